@@ -1,0 +1,186 @@
+/*
+ * libspca -- alternating maximization (AM) for single-loading-vector sparse
+ * PCA on AMD Instinct MI355X (gfx950).
+ *
+ * The method is Algorithm 2 of Richtarik, Jahani, Ahipasaoglu and Takac,
+ * "Alternating maximization: unifying framework for 8 sparse PCA
+ * formulations and efficient parallel codes" (arXiv:1212.4137), run from r
+ * starting points at once (the batched scheme of Section 4, where the r
+ * matrix-vector products of an iteration form one matrix product).
+ *
+ * Conventions shared by every entry point
+ *   - A is n x p, column-major with leading dimension lda >= n (column a_i
+ *     contiguous, Section 1: n samples of p variables), FP32, in device
+ *     memory.  The library never writes to it.
+ *   - Starting points X0 are r x p, start-major: row j (p contiguous floats)
+ *     is x^(0) of start j, in device memory.
+ *   - Every buffer passed in is owned by the caller and must stay valid until
+ *     the call returns.  The library owns its workspace (inside spca_ctx).
+ *   - Return value: SPCA_OK (0) or a negative SPCA_E* code; the message of
+ *     the last failure on the calling thread is spca_last_error().  No C++
+ *     exception crosses this boundary.  Argument checks happen before any
+ *     device work.
+ *   - Calls are synchronous with respect to the stream they are given.
+ */
+#ifndef SPCA_H
+#define SPCA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Formulations, numbered as in Table 1 (variance norm x sparsity norm x
+ * constraint or penalty).  The parameter s_or_gamma is the sparsity level s
+ * for 1-4 (L0: ||x||_0 <= s, s integral in [1, p]; L1: ||x||_1 <= sqrt(s),
+ * real s >= 1) and the penalty weight gamma >= 0 for 5-8.                  */
+enum {
+  SPCA_L2_L0_CON = 1, /* max ||Ax||_2   s.t. ||x||_2 <= 1, ||x||_0 <= s    */
+  SPCA_L1_L0_CON = 2, /* max ||Ax||_1   s.t. ||x||_2 <= 1, ||x||_0 <= s    */
+  SPCA_L2_L1_CON = 3, /* max ||Ax||_2   s.t. ||x||_2 <= 1, ||x||_1 <= vs   */
+  SPCA_L1_L1_CON = 4, /* max ||Ax||_1   s.t. ||x||_2 <= 1, ||x||_1 <= vs   */
+  SPCA_L2_L0_PEN = 5, /* max ||Ax||_2^2 - gamma ||x||_0, ||x||_2 <= 1     */
+  SPCA_L1_L0_PEN = 6, /* max ||Ax||_1^2 - gamma ||x||_0, ||x||_2 <= 1     */
+  SPCA_L2_L1_PEN = 7, /* max ||Ax||_2   - gamma ||x||_1, ||x||_2 <= 1     */
+  SPCA_L1_L1_PEN = 8  /* max ||Ax||_1   - gamma ||x||_1, ||x||_2 <= 1     */
+};
+
+/* Return codes */
+#define SPCA_OK 0
+#define SPCA_EINVAL (-1) /* bad argument (nothing was launched)            */
+#define SPCA_ENOMEM (-2) /* workspace would exceed the context's budget    */
+#define SPCA_EHIP (-3)   /* a HIP runtime call failed                      */
+
+/* Per-start status (and spca_result.status of the best start) */
+#define SPCA_CONVERGED 0  /* phi_k <= (1 + tol) phi_{k-1} (Section 2.2)     */
+#define SPCA_MAXIT 1      /* maxit x-updates without meeting the stop test  */
+#define SPCA_DEGENERATE 2 /* A x = 0 (excluded by Theorem 1): x = 0, f = 0  */
+#define SPCA_ZERO 3       /* the x-operator returned 0: x = 0, f = 0         */
+
+/* Arithmetic of the iterations */
+#define SPCA_PREC_FP32 0        /* A, X, Y in FP32, FP32 MFMA accumulation   */
+#define SPCA_PREC_BF16_POLISH 1 /* A, X, Y operands in BF16, FP32 accumulation,
+                                   then FP32 AM iterations restricted to the
+                                   final support ("polish")                  */
+
+typedef struct {
+  double objective;      /* f(x) of Table 1 at the returned x, FP64         */
+  double explained_var;  /* ||Ax||_2^2 (L2 variance) or ||Ax||_1 (L1), FP64 */
+  double phi;            /* last in-loop phi of the best start (Table 3)    */
+  double iters_x_starts; /* AM iterations summed over all starts            */
+  int32_t best_start;    /* index of the start with the largest objective   */
+  int32_t nnz;           /* |support|                                       */
+  int32_t iters;         /* x-updates done by the best start                */
+  int32_t status;        /* SPCA_CONVERGED .. SPCA_ZERO of the best start   */
+} spca_result;
+
+/* ---------------------------------------------------------------------- */
+/* One-call solve (Algorithm 2 from r starts, Section 4; best start kept).
+ *
+ * A        device, FP32, n x p column-major, lda >= n.
+ * formulation 1..8 (Table 1); s_or_gamma as described above.
+ * X0       device, FP32, r x p start-major; or NULL with r == 1, which starts
+ *          from x0 = e_i for the column i of A with the largest 2-norm (ties
+ *          to the lowest i), so that y0 is that column normalised.
+ * tol      stop test phi_k <= (1 + tol) phi_{k-1}; tol < 0 disables it.
+ * maxit    >= 1, maximum number of x-updates per start.
+ * x_out    host, p doubles: the loading vector of the best start, normalised
+ *          in FP64 (or all zero if every start ended DEGENERATE or ZERO).
+ * support_out host, capacity p int32: the sorted indices of the nonzeros of
+ *          x_out; res->nnz of them are written.
+ * res      host.
+ * Uses a per-device default context and the null stream.
+ * Errors: SPCA_EINVAL if n, p or r < 1, lda < n, formulation outside 1..8,
+ * s outside [1, p] (L0 constraint) or < 1 (L1 constraint), gamma < 0 or not
+ * finite, maxit < 1, a NULL pointer, X0 NULL with r != 1.                  */
+int spca_am_solve(const float* A, int64_t n, int64_t p, int64_t lda,
+                  int formulation, double s_or_gamma, const float* X0,
+                  int32_t r, double tol, int32_t maxit, double* x_out,
+                  int32_t* support_out, spca_result* res);
+
+/* ---------------------------------------------------------------------- */
+/* Context: device binding, workspace and HBM budget.                      */
+typedef struct spca_ctx spca_ctx;
+
+/* device: HIP device ordinal.  hbm_budget_bytes: upper bound on the
+ * workspace the context may hold (0 = no limit beyond the device).       */
+int spca_ctx_create(spca_ctx** ctx, int device, size_t hbm_budget_bytes);
+int spca_ctx_destroy(spca_ctx* ctx);
+/* Bytes of workspace a solve of this shape needs (for admission control). */
+size_t spca_workspace_bytes(int64_t n, int64_t p, int32_t r, int precision);
+
+typedef struct {
+  const float* A; /* device, FP32, n x p column-major                        */
+  int64_t n, p, lda;
+  int32_t formulation;
+  double s_or_gamma;
+} spca_problem;
+
+typedef struct {
+  const float* X0;      /* device r x p start-major, or NULL (needs r == 1) */
+  int32_t r;
+  double tol;
+  int32_t maxit;
+  int32_t precision;    /* SPCA_PREC_FP32 or SPCA_PREC_BF16_POLISH          */
+  int32_t polish_maxit; /* FP32 iterations on the final support (BF16 mode) */
+  int32_t check_every;  /* iterations between polls of the active count     */
+  int32_t flags;        /* SPCA_FLAG_* below                                */
+} spca_solve_opts;
+
+#define SPCA_FLAG_GRAPH 1        /* replay check_every iterations as a graph */
+#define SPCA_FLAG_CHECK_FINITE 2 /* reject A holding NaN or Inf (EINVAL)     */
+#define SPCA_FLAG_DENSE_ONLY 4   /* never use the sparse A x product         */
+
+typedef struct {
+  double* x;           /* host, p doubles (see spca_am_solve), or NULL      */
+  int32_t* support;    /* host, capacity p, or NULL                         */
+  spca_result* res;    /* host, required                                    */
+  /* optional host arrays of length r (NULL to skip)                        */
+  double* f_per_start;     /* f(x_j) of Table 1, FP64                       */
+  double* ev_per_start;    /* explained variance of x_j, FP64               */
+  double* phi_per_start;   /* last in-loop phi                              */
+  int32_t* iters_per_start;
+  int32_t* status_per_start;
+  int32_t* nnz_per_start;
+  float* X_final;      /* optional device r x p: final iterates (FP32)      */
+} spca_outputs;
+
+/* Full solve on a caller-chosen context and HIP stream (hipStream_t passed
+ * as void*; NULL = null stream).  Same semantics as spca_am_solve.
+ * Additional errors: SPCA_ENOMEM when the workspace exceeds the budget;
+ * SPCA_EINVAL for precision outside {0, 1}, check_every < 1 and, with
+ * SPCA_FLAG_CHECK_FINITE, a non-finite entry of A.                         */
+int spca_am_solve_ex(spca_ctx* ctx, void* stream, const spca_problem* prob,
+                     const spca_solve_opts* opts, spca_outputs* out);
+
+/* Thread-local message of the last failure ("" if none).                 */
+const char* spca_last_error(void);
+
+/* ---------------------------------------------------------------------- */
+/* Building blocks of one AM iteration, exported for testing and tuning.   */
+
+/* C = P * Q^T in FP32 with FP32 MFMA accumulation (the two products of an
+ * AM iteration, Section 4: U^T = X^T A^T and V^T = Y^T A).  P is M x K,
+ * Q is N x K, C is M x N, all row-major in device memory with leading
+ * dimensions ldp, ldq >= K and ldc >= N.  ldp and ldq must be multiples of
+ * 4 and P, Q 16-byte aligned (SPCA_EINVAL otherwise).                    */
+int spca_gemm_nt_f32(void* stream, const float* P, int64_t ldp, const float* Q,
+                     int64_t ldq, float* C, int64_t ldc, int64_t M, int64_t N,
+                     int64_t K);
+
+/* The x-update of Algorithm 2 for formulation fid applied to each row of V
+ * (r x p row-major, ldv >= p, device): X_j = op(V_j) / ||op(V_j)||_2 with op
+ * T_s, V_{lambda_s}, U_gamma or V_gamma (Table 3, rows S3-S6).  Writes X
+ * (r x p, ldx >= p, device), phi (r doubles, device: the subproblem optimum
+ * of Table 3) and nnz (r int32, device).  A zero image gives X_j = 0.
+ * Same parameter checks as spca_am_solve.                                 */
+int spca_x_update(void* stream, int formulation, const float* V, int64_t ldv,
+                  int64_t r, int64_t p, double s_or_gamma, float* X,
+                  int64_t ldx, double* phi, int32_t* nnz);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SPCA_H */

@@ -1,0 +1,13 @@
+"""MI355X-native alternating maximization (AM) for sparse PCA.
+
+Implements the batched AM iteration (Algorithm 2 of arXiv:1212.4137 run from
+many starting points at once, Section 4) for the 8 formulations of Table 1 as
+HIP kernels for gfx950 behind the C-ABI of ``include/spca.h``.  This package
+is the thin Python binding; see ``_lib`` for the functions.
+"""
+from ._lib import (  # noqa: F401
+    CONVERGED, DEGENERATE, EXPORTED, FLAG_CHECK_FINITE, FLAG_DENSE_ONLY, FLAG_GRAPH,
+    LIB_PATH, MAXIT, PREC_BF16_POLISH, PREC_FP32, ZERO, Context, SpcaError, am_solve,
+    am_solve_simple, colmajor_view, default_context, gemm_nt, load, workspace_bytes,
+    x_update,
+)

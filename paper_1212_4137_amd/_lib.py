@@ -1,0 +1,282 @@
+"""ctypes binding of ``libspca.so`` (argument marshalling only).
+
+Every step of the AM iteration runs in the HIP library; this module only
+turns torch tensors into pointers and host arrays back into numpy.  It never
+falls back to a CPU implementation: if the library is missing or the device
+is not a GPU, it raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libspca.so")
+
+SPCA_OK, SPCA_EINVAL, SPCA_ENOMEM, SPCA_EHIP = 0, -1, -2, -3
+CONVERGED, MAXIT, DEGENERATE, ZERO = 0, 1, 2, 3
+PREC_FP32, PREC_BF16_POLISH = 0, 1
+FLAG_GRAPH, FLAG_CHECK_FINITE, FLAG_DENSE_ONLY = 1, 2, 4
+
+EXPORTED = ("spca_am_solve", "spca_am_solve_ex", "spca_ctx_create",
+            "spca_ctx_destroy", "spca_workspace_bytes", "spca_last_error",
+            "spca_gemm_nt_f32", "spca_x_update")
+
+
+class SpcaError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libspca error {code}: {msg}")
+        self.code = code
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("objective", ctypes.c_double), ("explained_var", ctypes.c_double),
+                ("phi", ctypes.c_double), ("iters_x_starts", ctypes.c_double),
+                ("best_start", ctypes.c_int32), ("nnz", ctypes.c_int32),
+                ("iters", ctypes.c_int32), ("status", ctypes.c_int32)]
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("A", ctypes.c_void_p), ("n", ctypes.c_int64), ("p", ctypes.c_int64),
+                ("lda", ctypes.c_int64), ("formulation", ctypes.c_int32),
+                ("s_or_gamma", ctypes.c_double)]
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [("X0", ctypes.c_void_p), ("r", ctypes.c_int32), ("tol", ctypes.c_double),
+                ("maxit", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("polish_maxit", ctypes.c_int32), ("check_every", ctypes.c_int32),
+                ("flags", ctypes.c_int32)]
+
+
+class Outputs(ctypes.Structure):
+    _fields_ = [("x", ctypes.c_void_p), ("support", ctypes.c_void_p),
+                ("res", ctypes.POINTER(Result)),
+                ("f_per_start", ctypes.c_void_p), ("ev_per_start", ctypes.c_void_p),
+                ("phi_per_start", ctypes.c_void_p), ("iters_per_start", ctypes.c_void_p),
+                ("status_per_start", ctypes.c_void_p), ("nnz_per_start", ctypes.c_void_p),
+                ("X_final", ctypes.c_void_p)]
+
+
+_lib = None
+_lock = threading.Lock()
+
+
+def load():
+    """Loads libspca.so; raises if it has not been built."""
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_1212_4137_amd.build` (no CPU fallback)")
+        lib = ctypes.CDLL(LIB_PATH)
+        P, i64, i32, d = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
+        lib.spca_last_error.restype = ctypes.c_char_p
+        lib.spca_last_error.argtypes = []
+        lib.spca_ctx_create.argtypes = [ctypes.POINTER(P), ctypes.c_int, ctypes.c_size_t]
+        lib.spca_ctx_create.restype = ctypes.c_int
+        lib.spca_ctx_destroy.argtypes = [P]
+        lib.spca_ctx_destroy.restype = ctypes.c_int
+        lib.spca_workspace_bytes.argtypes = [i64, i64, i32, ctypes.c_int]
+        lib.spca_workspace_bytes.restype = ctypes.c_size_t
+        lib.spca_am_solve.argtypes = [P, i64, i64, i64, ctypes.c_int, d, P, i32, d, i32,
+                                      P, P, ctypes.POINTER(Result)]
+        lib.spca_am_solve.restype = ctypes.c_int
+        lib.spca_am_solve_ex.argtypes = [P, P, ctypes.POINTER(Problem),
+                                         ctypes.POINTER(SolveOpts), ctypes.POINTER(Outputs)]
+        lib.spca_am_solve_ex.restype = ctypes.c_int
+        lib.spca_gemm_nt_f32.argtypes = [P, P, i64, P, i64, P, i64, i64, i64, i64]
+        lib.spca_gemm_nt_f32.restype = ctypes.c_int
+        lib.spca_x_update.argtypes = [P, ctypes.c_int, P, i64, i64, i64, d, P, i64, P, P]
+        lib.spca_x_update.restype = ctypes.c_int
+        _lib = lib
+        return lib
+
+
+def _check(code):
+    if code != SPCA_OK:
+        raise SpcaError(code, load().spca_last_error().decode())
+
+
+def _np_ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p) if a is not None else None
+
+
+def _require_gpu_tensor(t, name, dtype=None):
+    import torch
+
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a torch tensor on the GPU")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+
+
+def _stream_ptr(stream):
+    import torch
+
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Context:
+    """An ``spca_ctx``: device binding, workspace and HBM budget."""
+
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 0):
+        lib = load()
+        h = ctypes.c_void_p()
+        _check(lib.spca_ctx_create(ctypes.byref(h), int(device), int(hbm_budget_bytes)))
+        self._h = h
+        self.device = device
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h:
+            load().spca_ctx_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_default_ctx = {}
+
+
+def default_context(device: int = 0) -> Context:
+    if device not in _default_ctx:
+        _default_ctx[device] = Context(device)
+    return _default_ctx[device]
+
+
+def workspace_bytes(n, p, r, precision=PREC_FP32):
+    return int(load().spca_workspace_bytes(int(n), int(p), int(r), int(precision)))
+
+
+def colmajor_view(A):
+    """(n, p, lda) of a torch tensor holding A column-major: shape (n, p) with
+    strides (1, lda)."""
+    n, p = A.shape
+    if A.stride(0) != 1 or (p > 1 and A.stride(1) < n):
+        raise ValueError("A must be column-major: shape (n, p), strides (1, lda>=n)")
+    lda = A.stride(1) if p > 1 else max(n, 1)
+    return n, p, lda
+
+
+def am_solve(A, formulation, s_or_gamma, X0=None, tol=1e-8, maxit=200, *,
+             precision=PREC_FP32, polish_maxit=0, check_every=8, flags=0,
+             ctx=None, stream=None, return_X=False):
+    """Batched AM solve (``spca_am_solve_ex``).
+
+    A : torch.float32 GPU tensor (n, p), column-major (strides (1, lda)).
+    X0: torch.float32 GPU tensor (r, p), contiguous, one start per row; or
+        None for the single start e_i at the column of largest norm.
+    Returns a dict of host (numpy) results.
+    """
+    import torch
+
+    _require_gpu_tensor(A, "A", torch.float32)
+    n, p, lda = colmajor_view(A)
+    if X0 is not None:
+        _require_gpu_tensor(X0, "X0", torch.float32)
+        if X0.dim() != 2 or X0.shape[1] != p or not X0.is_contiguous():
+            raise ValueError("X0 must be a contiguous (r, p) tensor")
+        r = X0.shape[0]
+    else:
+        r = 1
+    ctx = ctx or default_context(A.device.index or 0)
+    x = np.zeros(p, dtype=np.float64)
+    sup = np.zeros(p, dtype=np.int32)
+    res = Result()
+    f = np.zeros(r)
+    ev = np.zeros(r)
+    phi = np.zeros(r)
+    iters = np.zeros(r, dtype=np.int32)
+    status = np.zeros(r, dtype=np.int32)
+    nnz = np.zeros(r, dtype=np.int32)
+    Xf = torch.empty((r, p), dtype=torch.float32, device=A.device) if return_X else None
+    prob = Problem(A.data_ptr(), n, p, lda, int(formulation), float(s_or_gamma))
+    opts = SolveOpts(X0.data_ptr() if X0 is not None else None, r, float(tol), int(maxit),
+                     int(precision), int(polish_maxit), int(check_every), int(flags))
+    out = Outputs(_np_ptr(x), _np_ptr(sup), ctypes.pointer(res), _np_ptr(f), _np_ptr(ev),
+                  _np_ptr(phi), _np_ptr(iters), _np_ptr(status), _np_ptr(nnz),
+                  Xf.data_ptr() if Xf is not None else None)
+    _check(load().spca_am_solve_ex(ctx.handle, _stream_ptr(stream), ctypes.byref(prob),
+                                   ctypes.byref(opts), ctypes.byref(out)))
+    return {"x": x, "support": sup[: res.nnz].copy(), "objective": res.objective,
+            "explained_variance": res.explained_var, "phi": res.phi,
+            "best_start": res.best_start, "nnz": res.nnz, "iters": res.iters,
+            "status": res.status, "iters_x_starts": res.iters_x_starts,
+            "f_per_start": f, "ev_per_start": ev, "phi_per_start": phi,
+            "iters_per_start": iters, "status_per_start": status,
+            "nnz_per_start": nnz, "X_final": Xf}
+
+
+def am_solve_simple(A, formulation, s_or_gamma, X0=None, tol=1e-8, maxit=200):
+    """The one-call entry point ``spca_am_solve`` (default context, null
+    stream)."""
+    import torch
+
+    _require_gpu_tensor(A, "A", torch.float32)
+    n, p, lda = colmajor_view(A)
+    r = 1 if X0 is None else X0.shape[0]
+    x = np.zeros(p, dtype=np.float64)
+    sup = np.zeros(p, dtype=np.int32)
+    res = Result()
+    torch.cuda.synchronize()
+    _check(load().spca_am_solve(ctypes.c_void_p(A.data_ptr()), n, p, lda, int(formulation),
+                                float(s_or_gamma),
+                                ctypes.c_void_p(X0.data_ptr()) if X0 is not None else None,
+                                r, float(tol), int(maxit), _np_ptr(x), _np_ptr(sup),
+                                ctypes.byref(res)))
+    return {"x": x, "support": sup[: res.nnz].copy(), "objective": res.objective,
+            "explained_variance": res.explained_var, "best_start": res.best_start,
+            "nnz": res.nnz, "iters": res.iters, "status": res.status}
+
+
+def gemm_nt(P, Q, stream=None):
+    """C = P Q^T on the MFMA kernel (``spca_gemm_nt_f32``)."""
+    import torch
+
+    _require_gpu_tensor(P, "P", torch.float32)
+    _require_gpu_tensor(Q, "Q", torch.float32)
+    M, K = P.shape
+    N, K2 = Q.shape
+    if K2 != K:
+        raise ValueError("inner dimensions differ")
+    if P.stride(1) != 1 or Q.stride(1) != 1:
+        raise ValueError("P and Q must be row-major")
+    C = torch.empty((M, N), dtype=torch.float32, device=P.device)
+    _check(load().spca_gemm_nt_f32(_stream_ptr(stream), ctypes.c_void_p(P.data_ptr()),
+                                   P.stride(0), ctypes.c_void_p(Q.data_ptr()), Q.stride(0),
+                                   ctypes.c_void_p(C.data_ptr()), N, M, N, K))
+    return C
+
+
+def x_update(formulation, V, s_or_gamma, stream=None):
+    """The x-update operator on each row of V (``spca_x_update``); returns
+    (X, phi, nnz) as GPU tensors."""
+    import torch
+
+    _require_gpu_tensor(V, "V", torch.float32)
+    r, p = V.shape
+    if V.stride(1) != 1:
+        raise ValueError("V must be row-major")
+    X = torch.empty((r, p), dtype=torch.float32, device=V.device)
+    phi = torch.empty(r, dtype=torch.float64, device=V.device)
+    nnz = torch.empty(r, dtype=torch.int32, device=V.device)
+    _check(load().spca_x_update(_stream_ptr(stream), int(formulation),
+                                ctypes.c_void_p(V.data_ptr()), V.stride(0), r, p,
+                                float(s_or_gamma), ctypes.c_void_p(X.data_ptr()), p,
+                                ctypes.c_void_p(phi.data_ptr()),
+                                ctypes.c_void_p(nnz.data_ptr())))
+    return X, phi, nnz

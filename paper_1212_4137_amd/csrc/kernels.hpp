@@ -1,0 +1,102 @@
+// Launchers of the HIP kernels that make up one AM iteration.  All take a
+// stream and device pointers; none allocates or synchronises.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace spca {
+
+// x-operator kinds (Table 3): constraint L0 -> T_s, constraint L1 ->
+// V_{lambda_s}, penalty L0 -> U_gamma, penalty L1 -> V_gamma.
+enum XKind { kTopS = 0, kLambdaS = 1, kHardGamma = 2, kSoftGamma = 3 };
+
+inline XKind xkind_of(int fid) {
+  return fid <= 2 ? kTopS : fid <= 4 ? kLambdaS : fid <= 6 ? kHardGamma : kSoftGamma;
+}
+inline bool l1_variance(int fid) { return fid % 2 == 0; }
+
+// Per-start iteration state, device arrays of length r.
+struct StartState {
+  double* phi;       // phi after the last x-update (Table 3 optimum)
+  double* phi_prev;  // phi after the one before
+  int32_t* nnz;      // nonzeros of the current x
+  int32_t* iters;    // x-updates done
+  int32_t* status;   // kRunning or a SPCA_* status
+};
+
+// Sparse-product mode word written by the planner: 1 = the next A x uses
+// the compacted lists, 0 = the dense MFMA product.
+struct Plan {
+  int32_t sparse;
+  int32_t active;       // starts still running
+  int64_t total_nnz;    // sum of nnz over running starts
+};
+
+// C (M x N, ldc) = P (M x K, ldp) * Q (N x K, ldq)^T, FP32 MFMA.  When
+// gate != nullptr the kernel returns at once if *gate == gate_skip.
+void gemm_nt_f32(hipStream_t st, const float* P, int64_t ldp, const float* Q,
+                 int64_t ldq, float* C, int64_t ldc, int64_t M, int64_t N,
+                 int64_t K, const int32_t* gate, int32_t gate_skip);
+
+// Row-major copy: At[i * ldat + k] = A[i + k * lda] (i < n, k < p).
+void transpose_f32(hipStream_t st, const float* A, int64_t lda, float* At,
+                   int64_t ldat, int64_t n, int64_t p);
+
+// Column-major copy with a new leading dimension.
+void copy_columns_f32(hipStream_t st, const float* A, int64_t lda, float* B,
+                      int64_t ldb, int64_t n, int64_t p);
+
+// Counts non-finite entries of A into *count (device int32, zeroed first by
+// the caller).
+void count_nonfinite(hipStream_t st, const float* A, int64_t lda, int64_t n,
+                     int64_t p, int32_t* count);
+
+// x0 = e_{i*}, i* = argmax_i ||a_i||_2 (ties to the lowest i), written to
+// row 0 of X (ldx); colsq is p doubles of scratch.
+void max_norm_column_start(hipStream_t st, const float* A, int64_t lda,
+                           int64_t n, int64_t p, double* colsq, float* X,
+                           int64_t ldx);
+
+// Builds the compacted (index, value) lists of the rows of X, nnz per row.
+void compact_rows(hipStream_t st, const float* X, int64_t ldx, int64_t r,
+                  int64_t p, int32_t* list_idx, float* list_val, int64_t ldl,
+                  int32_t* nnz, const int32_t* status);
+
+// Resets the per-start state for a new solve.
+void init_state(hipStream_t st, StartState s, int64_t r);
+
+// Chooses the product mode for the next A x and counts running starts.
+void plan_next(hipStream_t st, StartState s, int64_t r, int64_t p,
+               double sparse_fraction, int dense_only, Plan* plan);
+
+// y-update of Algorithm 2 from a dense U (r x n): Y = sgn(U) (L1 variance)
+// or U / ||U||_2 per row (L2 variance); a zero row ends its start as
+// DEGENERATE.  Skipped when plan->sparse != 0.
+void y_update(hipStream_t st, int fid, const float* U, float* Y, int64_t ldu,
+              int64_t r, int64_t n, StartState s, const Plan* plan);
+
+// Sparse A x from the lists followed by the y-update, one block per start.
+// Skipped when plan->sparse == 0.
+void sparse_ax_y_update(hipStream_t st, int fid, const float* A, int64_t lda,
+                        int64_t n, const int32_t* list_idx,
+                        const float* list_val, int64_t ldl, float* Y,
+                        int64_t ldu, int64_t r, StartState s, const Plan* plan);
+
+// x-update of Algorithm 2 on the rows of V with the stop test of Section
+// 2.2.  When s.status is null every row is processed and no stop test or
+// counters are touched (operator-only mode used by spca_x_update).
+void x_update(hipStream_t st, int fid, double s_or_gamma, const float* V,
+              int64_t ldv, int64_t r, int64_t p, float* X, int64_t ldx,
+              int32_t* list_idx, float* list_val, int64_t ldl, StartState s,
+              double tol, int32_t maxit);
+
+// FP64 finalisation: per start, x64 = x / ||x||_2 from the lists, f(x64)
+// of Table 1 and the explained variance; then the best start.
+void finalize(hipStream_t st, int fid, double s_or_gamma, const float* A,
+              int64_t lda, int64_t n, int64_t p, const int32_t* list_idx,
+              const float* list_val, int64_t ldl, StartState s, int64_t r,
+              double* partial, double* f, double* ev, double* xnorm,
+              int32_t* best, double* x_out, int32_t* support_out);
+
+}  // namespace spca

@@ -1,0 +1,434 @@
+// C-ABI of libspca: argument checks, the per-device context and workspace,
+// and the host driver of the batched AM iteration (Algorithm 2 run from r
+// starts at once, Section 4).  One iteration is
+//   [dense]  U = X A^T (MFMA GEMM)  ->  y-update kernel
+//   [sparse] list-based A x fused with the y-update      (one of the two runs;
+//                                                         the planner decides
+//                                                         on the device)
+//   V = Y A (MFMA GEMM)  ->  x-update + stop test  ->  planner
+// The host only polls the count of running starts every check_every
+// iterations; everything else stays on the device.
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/spca.h"
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace spca {
+
+static thread_local std::string g_last_error;
+void set_error(const std::string& msg) { g_last_error = msg; }
+const char* last_error() { return g_last_error.c_str(); }
+
+namespace {
+
+constexpr double kSparseFraction = 0.04;  // list product when nnz <= 4% dense
+
+struct Layout {
+  int64_t n, p, r;
+  int64_t ldx, ldu, ldat, ldac;
+  bool copy_a;
+  size_t off_At, off_Ac, off_X, off_U, off_Y, off_V, off_li, off_lv;
+  size_t off_phi, off_phip, off_nnz, off_it, off_st, off_plan, off_part,
+      off_f, off_ev, off_xn, off_best, off_xout, off_sup, off_colsq, off_bad;
+  size_t total;
+  int nchunks;
+};
+
+size_t carve(size_t* cur, size_t bytes) {
+  size_t o = (*cur + 255) / 256 * 256;
+  *cur = o + bytes;
+  return o;
+}
+
+Layout make_layout(int64_t n, int64_t p, int64_t r, bool copy_a) {
+  Layout L;
+  L.n = n;
+  L.p = p;
+  L.r = r;
+  L.ldx = round_up(p, 4);
+  L.ldu = round_up(n, 4);
+  L.ldat = round_up(p, 4);
+  L.ldac = round_up(n, 4);
+  L.copy_a = copy_a;
+  L.nchunks = (int)ceil_div(n, 256);
+  size_t c = 0;
+  L.off_At = carve(&c, sizeof(float) * (size_t)n * L.ldat);
+  L.off_Ac = carve(&c, copy_a ? sizeof(float) * (size_t)p * L.ldac : 0);
+  L.off_X = carve(&c, sizeof(float) * (size_t)r * L.ldx);
+  L.off_U = carve(&c, sizeof(float) * (size_t)r * L.ldu);
+  L.off_Y = carve(&c, sizeof(float) * (size_t)r * L.ldu);
+  L.off_V = carve(&c, sizeof(float) * (size_t)r * L.ldx);
+  L.off_li = carve(&c, sizeof(int32_t) * (size_t)r * L.ldx);
+  L.off_lv = carve(&c, sizeof(float) * (size_t)r * L.ldx);
+  L.off_phi = carve(&c, sizeof(double) * r);
+  L.off_phip = carve(&c, sizeof(double) * r);
+  L.off_nnz = carve(&c, sizeof(int32_t) * r);
+  L.off_it = carve(&c, sizeof(int32_t) * r);
+  L.off_st = carve(&c, sizeof(int32_t) * r);
+  L.off_plan = carve(&c, sizeof(Plan));
+  L.off_part = carve(&c, sizeof(double) * 2 * (size_t)r * L.nchunks);
+  L.off_f = carve(&c, sizeof(double) * r);
+  L.off_ev = carve(&c, sizeof(double) * r);
+  L.off_xn = carve(&c, sizeof(double) * 2 * r);
+  L.off_best = carve(&c, sizeof(int32_t) * 2);
+  L.off_xout = carve(&c, sizeof(double) * p);
+  L.off_sup = carve(&c, sizeof(int32_t) * p);
+  L.off_colsq = carve(&c, sizeof(double) * p);
+  L.off_bad = carve(&c, sizeof(int32_t));
+  L.total = c;
+  return L;
+}
+
+int check_problem(int64_t n, int64_t p, int64_t lda, int fid, double sg,
+                  int64_t r, double tol, int32_t maxit) {
+  (void)tol;
+  SPCA_REQUIRE(n >= 1 && p >= 1, "n and p must be >= 1");
+  SPCA_REQUIRE(r >= 1, "r (number of starts) must be >= 1");
+  SPCA_REQUIRE(lda >= n, "lda must be >= n");
+  SPCA_REQUIRE(fid >= 1 && fid <= 8, "formulation must be in 1..8 (Table 1)");
+  SPCA_REQUIRE(maxit >= 1, "maxit must be >= 1");
+  SPCA_REQUIRE(p <= INT32_MAX && n <= INT32_MAX && r <= INT32_MAX,
+               "n, p and r must fit in int32");
+  SPCA_REQUIRE(isfinite(sg), "s_or_gamma must be finite");
+  if (fid <= 2) {
+    SPCA_REQUIRE(sg >= 1.0 && sg <= (double)p && sg == floor(sg),
+                 "L0 constraint needs an integral s in [1, p]");
+  } else if (fid <= 4) {
+    SPCA_REQUIRE(sg >= 1.0, "L1 constraint needs s >= 1");
+  } else {
+    SPCA_REQUIRE(sg >= 0.0, "penalty gamma must be >= 0");
+  }
+  return SPCA_OK;
+}
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev)
+      (void)hipSetDevice(prev);
+  }
+};
+
+}  // namespace
+}  // namespace spca
+
+struct spca_ctx {
+  int device = 0;
+  size_t budget = 0;
+  void* ws = nullptr;
+  size_t ws_cap = 0;
+  int32_t* host_poll = nullptr;  // pinned
+  std::mutex mu;
+};
+
+using namespace spca;
+
+extern "C" {
+
+const char* spca_last_error(void) { return spca::last_error(); }
+
+size_t spca_workspace_bytes(int64_t n, int64_t p, int32_t r, int precision) {
+  (void)precision;
+  if (n < 1 || p < 1 || r < 1) return 0;
+  return make_layout(n, p, r, true).total;
+}
+
+int spca_ctx_create(spca_ctx** ctx, int device, size_t hbm_budget_bytes) {
+  SPCA_REQUIRE(ctx != nullptr, "ctx must not be NULL");
+  int ndev = 0;
+  SPCA_HIP_TRY(hipGetDeviceCount(&ndev));
+  SPCA_REQUIRE(device >= 0 && device < ndev, "device ordinal out of range");
+  spca_ctx* c = new spca_ctx();
+  c->device = device;
+  c->budget = hbm_budget_bytes;
+  {
+    DeviceGuard g(device);
+    hipError_t e = hipHostMalloc((void**)&c->host_poll, sizeof(int32_t) * 4,
+                                 hipHostMallocDefault);
+    if (e != hipSuccess) {
+      set_error(std::string("hipHostMalloc: ") + hipGetErrorString(e));
+      delete c;
+      return SPCA_EHIP;
+    }
+  }
+  *ctx = c;
+  return SPCA_OK;
+}
+
+int spca_ctx_destroy(spca_ctx* ctx) {
+  if (ctx == nullptr) return SPCA_OK;
+  {
+    DeviceGuard g(ctx->device);
+    if (ctx->ws) {
+      (void)hipDeviceSynchronize();
+      (void)hipFree(ctx->ws);
+    }
+    if (ctx->host_poll) (void)hipHostFree(ctx->host_poll);
+  }
+  delete ctx;
+  return SPCA_OK;
+}
+
+static int ensure_workspace(spca_ctx* ctx, hipStream_t st, size_t bytes) {
+  if (ctx->budget != 0 && bytes > ctx->budget) {
+    set_error("workspace of " + std::to_string(bytes) +
+              " bytes exceeds the context budget of " +
+              std::to_string(ctx->budget));
+    return SPCA_ENOMEM;
+  }
+  if (bytes <= ctx->ws_cap) return SPCA_OK;
+  if (ctx->ws) {
+    SPCA_HIP_TRY(hipStreamSynchronize(st));
+    SPCA_HIP_TRY(hipFree(ctx->ws));
+    ctx->ws = nullptr;
+    ctx->ws_cap = 0;
+  }
+  hipError_t e = hipMalloc(&ctx->ws, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    set_error("hipMalloc of " + std::to_string(bytes) + " bytes: " +
+              hipGetErrorString(e));
+    return e == hipErrorOutOfMemory ? SPCA_ENOMEM : SPCA_EHIP;
+  }
+  ctx->ws_cap = bytes;
+  return SPCA_OK;
+}
+
+int spca_am_solve_ex(spca_ctx* ctx, void* stream, const spca_problem* prob,
+                     const spca_solve_opts* opts, spca_outputs* out) {
+  SPCA_REQUIRE(ctx && prob && opts && out && out->res,
+               "ctx, prob, opts, out and out->res must not be NULL");
+  SPCA_REQUIRE(prob->A != nullptr, "A must not be NULL");
+  const int64_t n = prob->n, p = prob->p, lda = prob->lda;
+  const int fid = prob->formulation;
+  const double sg = prob->s_or_gamma;
+  const int64_t r = opts->r;
+  int rc = check_problem(n, p, lda, fid, sg, r, opts->tol, opts->maxit);
+  if (rc != SPCA_OK) return rc;
+  SPCA_REQUIRE(opts->X0 != nullptr || r == 1,
+               "X0 may be NULL only with r == 1 (start e_i at the largest column)");
+  SPCA_REQUIRE(opts->precision == SPCA_PREC_FP32 ||
+                   opts->precision == SPCA_PREC_BF16_POLISH,
+               "precision must be SPCA_PREC_FP32 or SPCA_PREC_BF16_POLISH");
+  SPCA_REQUIRE(opts->precision == SPCA_PREC_FP32,
+               "SPCA_PREC_BF16_POLISH is not available in this build");
+  SPCA_REQUIRE(opts->check_every >= 1, "check_every must be >= 1");
+
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  DeviceGuard g(ctx->device);
+  hipStream_t st = (hipStream_t)stream;
+
+  const bool copy_a = (lda % 4) != 0 || ((uintptr_t)prob->A % 16) != 0;
+  const Layout L = make_layout(n, p, r, copy_a);
+  rc = ensure_workspace(ctx, st, L.total);
+  if (rc != SPCA_OK) return rc;
+  char* base = (char*)ctx->ws;
+  float* At = (float*)(base + L.off_At);
+  float* X = (float*)(base + L.off_X);
+  float* U = (float*)(base + L.off_U);
+  float* Y = (float*)(base + L.off_Y);
+  float* V = (float*)(base + L.off_V);
+  int32_t* li = (int32_t*)(base + L.off_li);
+  float* lv = (float*)(base + L.off_lv);
+  Plan* plan = (Plan*)(base + L.off_plan);
+  StartState s{(double*)(base + L.off_phi), (double*)(base + L.off_phip),
+               (int32_t*)(base + L.off_nnz), (int32_t*)(base + L.off_it),
+               (int32_t*)(base + L.off_st)};
+  double* partial = (double*)(base + L.off_part);
+  double* fj = (double*)(base + L.off_f);
+  double* evj = (double*)(base + L.off_ev);
+  double* xnorm = (double*)(base + L.off_xn);
+  int32_t* best = (int32_t*)(base + L.off_best);
+  double* xout = (double*)(base + L.off_xout);
+  int32_t* sup = (int32_t*)(base + L.off_sup);
+  double* colsq = (double*)(base + L.off_colsq);
+  int32_t* bad = (int32_t*)(base + L.off_bad);
+
+  // a0: stage A (aligned column-major copy only when needed) and its
+  // row-major twin used by the dense A x.
+  const float* A = prob->A;
+  int64_t ldA = lda;
+  if (copy_a) {
+    float* Ac = (float*)(base + L.off_Ac);
+    copy_columns_f32(st, prob->A, lda, Ac, L.ldac, n, p);
+    A = Ac;
+    ldA = L.ldac;
+  }
+  if (opts->flags & SPCA_FLAG_CHECK_FINITE) {
+    SPCA_HIP_TRY(hipMemsetAsync(bad, 0, sizeof(int32_t), st));
+    count_nonfinite(st, A, ldA, n, p, bad);
+    SPCA_HIP_TRY(hipMemcpyAsync(ctx->host_poll, bad, sizeof(int32_t),
+                                hipMemcpyDeviceToHost, st));
+    SPCA_HIP_TRY(hipStreamSynchronize(st));
+    SPCA_REQUIRE(ctx->host_poll[0] == 0, "A holds NaN or Inf entries");
+  }
+  transpose_f32(st, A, ldA, At, L.ldat, n, p);
+  SPCA_LAUNCH_CHECK("transpose");
+
+  // starting points
+  if (opts->X0 != nullptr) {
+    SPCA_HIP_TRY(hipMemcpy2DAsync(X, sizeof(float) * L.ldx, opts->X0,
+                                  sizeof(float) * p, sizeof(float) * p, r,
+                                  hipMemcpyDeviceToDevice, st));
+  } else {
+    max_norm_column_start(st, A, ldA, n, p, colsq, X, L.ldx);
+  }
+  init_state(st, s, r);
+  compact_rows(st, X, L.ldx, r, p, li, lv, L.ldx, s.nnz, s.status);
+  const int dense_only = (opts->flags & SPCA_FLAG_DENSE_ONLY) ? 1 : 0;
+  plan_next(st, s, r, p, kSparseFraction, dense_only, plan);
+  SPCA_LAUNCH_CHECK("staging");
+
+  const int32_t maxit = opts->maxit;
+  for (int32_t it = 0; it < maxit; ++it) {
+    // u = A x and the y-update
+    gemm_nt_f32(st, X, L.ldx, At, L.ldat, U, L.ldu, r, n, p, &plan->sparse, 1);
+    y_update(st, fid, U, Y, L.ldu, r, n, s, plan);
+    sparse_ax_y_update(st, fid, A, ldA, n, li, lv, L.ldx, Y, L.ldu, r, s, plan);
+    // v = A^T y and the x-update with the stop test
+    gemm_nt_f32(st, Y, L.ldu, A, ldA, V, L.ldx, r, p, n, nullptr, 0);
+    x_update(st, fid, sg, V, L.ldx, r, p, X, L.ldx, li, lv, L.ldx, s,
+             opts->tol, maxit);
+    plan_next(st, s, r, p, kSparseFraction, dense_only, plan);
+    SPCA_LAUNCH_CHECK("AM iteration");
+    if ((it + 1) % opts->check_every == 0 && it + 1 < maxit) {
+      SPCA_HIP_TRY(hipMemcpyAsync(ctx->host_poll, &plan->active, sizeof(int32_t),
+                                  hipMemcpyDeviceToHost, st));
+      SPCA_HIP_TRY(hipStreamSynchronize(st));
+      if (ctx->host_poll[0] == 0) break;
+    }
+  }
+
+  // a6: FP64 objective, explained variance, best start, output vector
+  finalize(st, fid, sg, A, ldA, n, p, li, lv, L.ldx, s, r, partial, fj, evj,
+           xnorm, best, xout, sup);
+  SPCA_LAUNCH_CHECK("finalize");
+
+  int32_t hb[2];
+  SPCA_HIP_TRY(hipMemcpyAsync(hb, best, sizeof(hb), hipMemcpyDeviceToHost, st));
+  SPCA_HIP_TRY(hipStreamSynchronize(st));
+  const int32_t jb = hb[0], nnzb = hb[1];
+  std::vector<double> f_all(r), ev_all(r), phi_all(r);
+  std::vector<int32_t> it_all(r), st_all(r), nnz_all(r);
+  SPCA_HIP_TRY(hipMemcpyAsync(f_all.data(), fj, sizeof(double) * r,
+                              hipMemcpyDeviceToHost, st));
+  SPCA_HIP_TRY(hipMemcpyAsync(ev_all.data(), evj, sizeof(double) * r,
+                              hipMemcpyDeviceToHost, st));
+  SPCA_HIP_TRY(hipMemcpyAsync(phi_all.data(), s.phi, sizeof(double) * r,
+                              hipMemcpyDeviceToHost, st));
+  SPCA_HIP_TRY(hipMemcpyAsync(it_all.data(), s.iters, sizeof(int32_t) * r,
+                              hipMemcpyDeviceToHost, st));
+  SPCA_HIP_TRY(hipMemcpyAsync(st_all.data(), s.status, sizeof(int32_t) * r,
+                              hipMemcpyDeviceToHost, st));
+  SPCA_HIP_TRY(hipMemcpyAsync(nnz_all.data(), s.nnz, sizeof(int32_t) * r,
+                              hipMemcpyDeviceToHost, st));
+  if (out->x)
+    SPCA_HIP_TRY(hipMemcpyAsync(out->x, xout, sizeof(double) * p,
+                                hipMemcpyDeviceToHost, st));
+  if (out->support && nnzb > 0)
+    SPCA_HIP_TRY(hipMemcpyAsync(out->support, sup, sizeof(int32_t) * nnzb,
+                                hipMemcpyDeviceToHost, st));
+  if (out->X_final)
+    SPCA_HIP_TRY(hipMemcpy2DAsync(out->X_final, sizeof(float) * p, X,
+                                  sizeof(float) * L.ldx, sizeof(float) * p, r,
+                                  hipMemcpyDeviceToDevice, st));
+  SPCA_HIP_TRY(hipStreamSynchronize(st));
+
+  double total_iters = 0.0;
+  for (int64_t j = 0; j < r; ++j) total_iters += it_all[j];
+  spca_result* res = out->res;
+  res->objective = f_all[jb];
+  res->explained_var = ev_all[jb];
+  res->phi = phi_all[jb];
+  res->iters_x_starts = total_iters;
+  res->best_start = jb;
+  res->nnz = nnzb;
+  res->iters = it_all[jb];
+  res->status = st_all[jb];
+  for (int64_t j = 0; j < r; ++j) {
+    if (out->f_per_start) out->f_per_start[j] = f_all[j];
+    if (out->ev_per_start) out->ev_per_start[j] = ev_all[j];
+    if (out->phi_per_start) out->phi_per_start[j] = phi_all[j];
+    if (out->iters_per_start) out->iters_per_start[j] = it_all[j];
+    if (out->status_per_start) out->status_per_start[j] = st_all[j];
+    if (out->nnz_per_start) out->nnz_per_start[j] = nnz_all[j];
+  }
+  return SPCA_OK;
+}
+
+static std::mutex g_default_mu;
+static std::vector<spca_ctx*> g_default_ctx;
+
+int spca_am_solve(const float* A, int64_t n, int64_t p, int64_t lda,
+                  int formulation, double s_or_gamma, const float* X0,
+                  int32_t r, double tol, int32_t maxit, double* x_out,
+                  int32_t* support_out, spca_result* res) {
+  SPCA_REQUIRE(A && x_out && support_out && res,
+               "A, x_out, support_out and res must not be NULL");
+  int rc = check_problem(n, p, lda, formulation, s_or_gamma, r, tol, maxit);
+  if (rc != SPCA_OK) return rc;
+  int dev = 0;
+  SPCA_HIP_TRY(hipGetDevice(&dev));
+  spca_ctx* ctx = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_default_mu);
+    if ((int)g_default_ctx.size() <= dev) g_default_ctx.resize(dev + 1, nullptr);
+    if (g_default_ctx[dev] == nullptr) {
+      rc = spca_ctx_create(&g_default_ctx[dev], dev, 0);
+      if (rc != SPCA_OK) return rc;
+    }
+    ctx = g_default_ctx[dev];
+  }
+  spca_problem prob{A, n, p, lda, formulation, s_or_gamma};
+  spca_solve_opts opts{X0, r, tol, maxit, SPCA_PREC_FP32, 0, 8, 0};
+  spca_outputs out{};
+  out.x = x_out;
+  out.support = support_out;
+  out.res = res;
+  return spca_am_solve_ex(ctx, nullptr, &prob, &opts, &out);
+}
+
+int spca_gemm_nt_f32(void* stream, const float* P, int64_t ldp, const float* Q,
+                     int64_t ldq, float* C, int64_t ldc, int64_t M, int64_t N,
+                     int64_t K) {
+  SPCA_REQUIRE(P && Q && C, "P, Q and C must not be NULL");
+  SPCA_REQUIRE(M >= 0 && N >= 0 && K >= 0, "sizes must be >= 0");
+  SPCA_REQUIRE(M <= INT32_MAX && N <= INT32_MAX && K <= INT32_MAX,
+               "sizes must fit in int32");
+  SPCA_REQUIRE(ldp >= K && ldq >= K && ldc >= N, "leading dimensions too small");
+  SPCA_REQUIRE(ldp % 4 == 0 && ldq % 4 == 0,
+               "ldp and ldq must be multiples of 4");
+  SPCA_REQUIRE((uintptr_t)P % 16 == 0 && (uintptr_t)Q % 16 == 0,
+               "P and Q must be 16-byte aligned");
+  gemm_nt_f32((hipStream_t)stream, P, ldp, Q, ldq, C, ldc, M, N, K, nullptr, 0);
+  SPCA_LAUNCH_CHECK("gemm_nt_f32");
+  return SPCA_OK;
+}
+
+int spca_x_update(void* stream, int formulation, const float* V, int64_t ldv,
+                  int64_t r, int64_t p, double s_or_gamma, float* X,
+                  int64_t ldx, double* phi, int32_t* nnz) {
+  SPCA_REQUIRE(V && X && phi && nnz, "V, X, phi and nnz must not be NULL");
+  int rc = check_problem(1, p, 1, formulation, s_or_gamma, r, 0.0, 1);
+  if (rc != SPCA_OK) return rc;
+  SPCA_REQUIRE(ldv >= p && ldx >= p, "leading dimensions too small");
+  StartState s{phi, nullptr, nnz, nullptr, nullptr};
+  x_update((hipStream_t)stream, formulation, s_or_gamma, V, ldv, r, p, X, ldx,
+           nullptr, nullptr, 0, s, -1.0, 1);
+  SPCA_LAUNCH_CHECK("x_update");
+  return SPCA_OK;
+}
+
+}  // extern "C"

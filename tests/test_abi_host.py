@@ -1,0 +1,91 @@
+"""Host-only checks of the C-ABI: the library loads, exports every function
+declared in include/spca.h, and rejects bad arguments before any device work
+(these calls never reach HIP, so they run without a GPU)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+import paper_1212_4137_amd as spca
+from paper_1212_4137_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "spca.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(spca_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_the_binding_names():
+    assert sorted(_declared()) == sorted(_lib.EXPORTED)
+
+
+def test_library_exports_every_declared_symbol():
+    out = subprocess.run(["nm", "-D", "--defined-only", spca.LIB_PATH],
+                         capture_output=True, text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (spca_\w+)", out))
+    missing = set(_declared()) - exported
+    assert not missing, missing
+    lib = spca.load()
+    for name in _declared():
+        assert hasattr(lib, name)
+
+
+FAKE = ctypes.c_void_p(4096)  # never dereferenced: validation fails first
+
+
+def _solve(**kw):
+    args = dict(A=FAKE, n=10, p=20, lda=10, fid=1, sg=3.0, X0=FAKE, r=2, tol=1e-6,
+                maxit=10)
+    args.update(kw)
+    x = (ctypes.c_double * 32)()
+    sup = (ctypes.c_int32 * 32)()
+    res = _lib.Result()
+    lib = spca.load()
+    rc = lib.spca_am_solve(args["A"], args["n"], args["p"], args["lda"], args["fid"],
+                           args["sg"], args["X0"], args["r"], args["tol"], args["maxit"],
+                           ctypes.cast(x, ctypes.c_void_p), ctypes.cast(sup, ctypes.c_void_p),
+                           ctypes.byref(res))
+    return rc, lib.spca_last_error().decode()
+
+
+@pytest.mark.parametrize("kw,msg", [
+    (dict(n=0), "n and p"), (dict(p=0), "n and p"), (dict(r=0), "r "),
+    (dict(lda=5), "lda"), (dict(fid=0), "formulation"), (dict(fid=9), "formulation"),
+    (dict(maxit=0), "maxit"), (dict(sg=0.0), "L0 constraint"), (dict(sg=21.0), "L0"),
+    (dict(sg=2.5), "integral"), (dict(fid=3, sg=0.5), "L1 constraint"),
+    (dict(fid=5, sg=-1.0), "gamma"), (dict(fid=7, sg=float("nan")), "finite"),
+    (dict(fid=8, sg=float("inf")), "finite"), (dict(A=None), "NULL"),
+])
+def test_argument_validation(kw, msg):
+    rc, err = _solve(**kw)
+    assert rc == _lib.SPCA_EINVAL
+    assert msg in err
+
+
+def test_gemm_argument_validation():
+    lib = spca.load()
+    rc = lib.spca_gemm_nt_f32(None, FAKE, 6, FAKE, 8, FAKE, 8, 4, 4, 6)
+    assert rc == _lib.SPCA_EINVAL and "multiples of 4" in lib.spca_last_error().decode()
+    rc = lib.spca_gemm_nt_f32(None, FAKE, 4, FAKE, 8, FAKE, 8, 4, 4, 6)
+    assert rc == _lib.SPCA_EINVAL and "leading" in lib.spca_last_error().decode()
+
+
+def test_x_update_argument_validation():
+    lib = spca.load()
+    rc = lib.spca_x_update(None, 1, FAKE, 20, 3, 20, 0.0, FAKE, 20, FAKE, FAKE)
+    assert rc == _lib.SPCA_EINVAL
+    rc = lib.spca_x_update(None, 9, FAKE, 20, 3, 20, 1.0, FAKE, 20, FAKE, FAKE)
+    assert rc == _lib.SPCA_EINVAL
+
+
+def test_workspace_bytes_is_monotone():
+    a = spca.workspace_bytes(100, 500, 1)
+    b = spca.workspace_bytes(1000, 10000, 1024)
+    assert 0 < a < b
+    assert spca.workspace_bytes(0, 5, 1) == 0

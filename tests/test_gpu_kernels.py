@@ -1,0 +1,139 @@
+"""Kernel-level parity on the GPU: the MFMA GEMM against an FP64 host
+product, and the x-update operators against the FP64 oracle operators on the
+same FP32 inputs (Table 3, rows S3-S6)."""
+import numpy as np
+import pytest
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def spca():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1212_4137_amd as m
+
+    m.load()
+    return m
+
+
+def _padded(rows, cols, rng, scale=1.0):
+    """Row-major FP32 (rows x cols) on the GPU with a leading dimension that is
+    a multiple of 4, plus its FP64 host copy."""
+    ld = (cols + 3) // 4 * 4
+    h = (rng.standard_normal((rows, cols)) * scale).astype(np.float32)
+    buf = torch.zeros((rows, ld), dtype=torch.float32)
+    buf[:, :cols] = torch.from_numpy(h)
+    return buf.cuda()[:, :cols], h.astype(np.float64)
+
+
+GEMM_SHAPES = [(1, 1, 1), (3, 130, 37), (32, 128, 32), (33, 129, 33), (64, 257, 1001),
+               (100, 1000, 513), (129, 200, 64), (300, 77, 1500), (1024, 300, 96),
+               (40, 1500, 300), (7, 5, 4099)]
+
+
+@pytest.mark.parametrize("M,N,K", GEMM_SHAPES)
+def test_gemm_nt_matches_fp64(spca, M, N, K):
+    print(f"gemm case M={M} N={N} K={K}", flush=True)
+    rng = np.random.default_rng(M * 131 + N * 7 + K)
+    P, P64 = _padded(M, K, rng)
+    Q, Q64 = _padded(N, K, rng)
+    C = spca.gemm_nt(P, Q)
+    torch.cuda.synchronize()
+    ref = P64 @ Q64.T
+    bound = (np.abs(P64) @ np.abs(Q64).T) * (K * 2.0 ** -24) * 1.01 + 1e-30
+    err = np.abs(C.cpu().numpy().astype(np.float64) - ref)
+    assert np.all(err <= bound), float(np.max(err / bound))
+
+
+def _oracle_rows(fid, V64, par):
+    X, phi, nnz = [], [], []
+    for v in V64:
+        w, ph = oracle.x_operator(fid, v, par)
+        nrm = np.linalg.norm(w)
+        X.append(w / nrm if nrm > 0 else w)
+        phi.append(ph)
+        nnz.append(int(np.count_nonzero(w)))
+    return np.array(X), np.array(phi), np.array(nnz)
+
+
+def _check_xupdate(spca, fid, V_h, par, exact_support=True):
+    V = torch.from_numpy(V_h).cuda()
+    X, phi, nnz = spca.x_update(fid, V, par)
+    torch.cuda.synchronize()
+    X = X.cpu().numpy().astype(np.float64)
+    phi = phi.cpu().numpy()
+    nnz = nnz.cpu().numpy()
+    Xr, phir, nnzr = _oracle_rows(fid, V_h.astype(np.float64), par)
+    np.testing.assert_allclose(phi, phir, rtol=1e-11, atol=1e-300)
+    if exact_support:
+        np.testing.assert_array_equal(nnz, nnzr)
+        np.testing.assert_array_equal(X != 0, Xr != 0)
+    np.testing.assert_allclose(X, Xr, rtol=0, atol=2e-7)
+    return X, phi, nnz
+
+
+@pytest.mark.parametrize("p", [37, 1500, 20000])
+@pytest.mark.parametrize("fid", [1, 3, 5, 7])
+def test_x_update_random(spca, fid, p):
+    print(f"x_update case fid={fid} p={p}", flush=True)
+    rng = np.random.default_rng(fid * 1000 + p)
+    V_h = (rng.standard_normal((6, p)) * 3).astype(np.float32)
+    par = {1: min(10, p), 3: 7.3, 5: 4.0, 7: 1.5}[fid]
+    _check_xupdate(spca, fid, V_h, par)
+    # L1-variance twins share the operator
+    _check_xupdate(spca, fid + 1, V_h, par)
+
+
+def test_x_update_T_s_ties_and_edges(spca):
+    p = 300
+    V_h = np.zeros((6, p), np.float32)
+    V_h[0, [5, 17, 40, 41, 250]] = [2.0, -2.0, 2.0, 1.0, -2.0]  # ties at |2|
+    V_h[1, :] = 1.0                                                # all equal
+    V_h[2, [3]] = -4.0                                             # fewer nonzeros than s
+    # row 3: all zero
+    V_h[4, :] = np.arange(p, dtype=np.float32)
+    V_h[5, :] = -np.arange(p, dtype=np.float32)[::-1]
+    X, phi, nnz = _check_xupdate(spca, 1, V_h, 3)
+    assert np.flatnonzero(X[0]).tolist() == [5, 17, 40]     # lowest indices win
+    assert np.flatnonzero(X[1]).tolist() == [0, 1, 2]
+    assert np.flatnonzero(X[2]).tolist() == [3] and nnz[3] == 0 and phi[3] == 0
+    # s = 1 and s = p
+    _check_xupdate(spca, 1, V_h, 1)
+    _check_xupdate(spca, 2, V_h, p)
+
+
+def test_x_update_gamma_boundaries(spca):
+    rng = np.random.default_rng(5)
+    V_h = (rng.standard_normal((4, 513)) * 2).astype(np.float32)
+    g = float(np.float64(V_h[0, 7]) ** 2)  # v_7^2 == gamma exactly: dropped
+    X, _, _ = _check_xupdate(spca, 5, V_h, g)
+    assert X[0, 7] == 0
+    _check_xupdate(spca, 5, V_h, 0.0)
+    big = float(np.max(np.abs(V_h).astype(np.float64)) ** 2)
+    X, phi, nnz = _check_xupdate(spca, 6, V_h, big)
+    assert np.all(nnz == 0) and np.all(X == 0) and np.all(phi == 0)
+    gs = float(abs(np.float64(V_h[1, 9])))
+    X, _, _ = _check_xupdate(spca, 7, V_h, gs)
+    assert X[1, 9] == 0
+    _check_xupdate(spca, 8, V_h, 0.0)
+    X, phi, nnz = _check_xupdate(spca, 7, V_h, float(np.max(np.abs(V_h))))
+    assert np.all(nnz == 0)
+
+
+@pytest.mark.parametrize("s", [1.0, 1.7, 12.0, 99.5, 5000.0])
+def test_x_update_lambda_s_regimes(spca, s):
+    rng = np.random.default_rng(int(s * 10))
+    V_h = (rng.standard_normal((5, 2049)) * 10).astype(np.float32)
+    V_h[4, 100:] = 0.0
+    X, phi, nnz = _check_xupdate(spca, 3, V_h, s, exact_support=False)
+    if s >= 5000:  # inactive constraint: x = v / ||v||
+        Vn = V_h.astype(np.float64)
+        np.testing.assert_allclose(X, Vn / np.linalg.norm(Vn, axis=1, keepdims=True),
+                                   atol=2e-7)
+    if s == 1.0:
+        assert np.all(nnz == 1)
