@@ -145,6 +145,12 @@ typedef struct {
   int32_t* status_per_start;
   int32_t* nnz_per_start;
   float* X_final;      /* optional device r x p: final iterates (FP32)      */
+  /* optional host array of 6 doubles: HIP-event times of the launches of
+   * this solve, [0] total ms and [1] count of the V = A^T Y products,
+   * [2] ms and [3] count of the x-updates, [4] ms and [5] count of the
+   * dense U = A X products (including launches that found the sparse
+   * product selected and returned at once).  NULL disables the events.   */
+  double* kernel_times;
 } spca_outputs;
 
 /* Full solve on a caller-chosen context and HIP stream (hipStream_t passed
@@ -169,6 +175,21 @@ const char* spca_last_error(void);
 int spca_gemm_nt_f32(void* stream, const float* P, int64_t ldp, const float* Q,
                      int64_t ldq, float* C, int64_t ldc, int64_t M, int64_t N,
                      int64_t K);
+
+/* Tuning and testing variant of spca_gemm_nt_f32 with a forced tile shape
+ * (0 .. 5: BMxBN of 128x128, 128x160, 128x96, 128x64, 64x128, 32x128) and
+ * K split count (1 .. 64).  With splits > 1, C must hold splits x M rows:
+ * split s writes its partial product (K slabs s*ceil(K/32/splits) onward)
+ * at C + s * M * ldc, and the product is the sum of the partials.       */
+int spca_gemm_nt_f32_shape(void* stream, const float* P, int64_t ldp,
+                           const float* Q, int64_t ldq, float* C, int64_t ldc,
+                           int64_t M, int64_t N, int64_t K, int shape,
+                           int splits);
+
+/* The tile shape and K split the library picks for an M x N x K product
+ * (deterministic, from a model of CU occupancy and tile efficiency).     */
+int spca_gemm_nt_f32_plan(int64_t M, int64_t N, int64_t K, int max_splits,
+                          int* shape, int* splits);
 
 /* The x-update of Algorithm 2 for formulation fid applied to each row of V
  * (r x p row-major, ldv >= p, device): X_j = op(V_j) / ||op(V_j)||_2 with op

@@ -23,7 +23,8 @@ FLAG_GRAPH, FLAG_CHECK_FINITE, FLAG_DENSE_ONLY = 1, 2, 4
 
 EXPORTED = ("spca_am_solve", "spca_am_solve_ex", "spca_ctx_create",
             "spca_ctx_destroy", "spca_workspace_bytes", "spca_last_error",
-            "spca_gemm_nt_f32", "spca_x_update")
+            "spca_gemm_nt_f32", "spca_gemm_nt_f32_shape", "spca_gemm_nt_f32_plan",
+            "spca_x_update")
 
 
 class SpcaError(RuntimeError):
@@ -58,7 +59,7 @@ class Outputs(ctypes.Structure):
                 ("f_per_start", ctypes.c_void_p), ("ev_per_start", ctypes.c_void_p),
                 ("phi_per_start", ctypes.c_void_p), ("iters_per_start", ctypes.c_void_p),
                 ("status_per_start", ctypes.c_void_p), ("nnz_per_start", ctypes.c_void_p),
-                ("X_final", ctypes.c_void_p)]
+                ("X_final", ctypes.c_void_p), ("kernel_times", ctypes.c_void_p)]
 
 
 _lib = None
@@ -92,6 +93,13 @@ def load():
         lib.spca_am_solve_ex.restype = ctypes.c_int
         lib.spca_gemm_nt_f32.argtypes = [P, P, i64, P, i64, P, i64, i64, i64, i64]
         lib.spca_gemm_nt_f32.restype = ctypes.c_int
+        lib.spca_gemm_nt_f32_shape.argtypes = [P, P, i64, P, i64, P, i64, i64, i64, i64,
+                                               ctypes.c_int, ctypes.c_int]
+        lib.spca_gemm_nt_f32_shape.restype = ctypes.c_int
+        lib.spca_gemm_nt_f32_plan.argtypes = [i64, i64, i64, ctypes.c_int,
+                                              ctypes.POINTER(ctypes.c_int),
+                                              ctypes.POINTER(ctypes.c_int)]
+        lib.spca_gemm_nt_f32_plan.restype = ctypes.c_int
         lib.spca_x_update.argtypes = [P, ctypes.c_int, P, i64, i64, i64, d, P, i64, P, P]
         lib.spca_x_update.restype = ctypes.c_int
         _lib = lib
@@ -174,7 +182,7 @@ def colmajor_view(A):
 
 def am_solve(A, formulation, s_or_gamma, X0=None, tol=1e-8, maxit=200, *,
              precision=PREC_FP32, polish_maxit=0, check_every=8, flags=0,
-             ctx=None, stream=None, return_X=False):
+             ctx=None, stream=None, return_X=False, kernel_times=False):
     """Batched AM solve (``spca_am_solve_ex``).
 
     A : torch.float32 GPU tensor (n, p), column-major (strides (1, lda)).
@@ -204,12 +212,13 @@ def am_solve(A, formulation, s_or_gamma, X0=None, tol=1e-8, maxit=200, *,
     status = np.zeros(r, dtype=np.int32)
     nnz = np.zeros(r, dtype=np.int32)
     Xf = torch.empty((r, p), dtype=torch.float32, device=A.device) if return_X else None
+    kt = np.zeros(6) if kernel_times else None
     prob = Problem(A.data_ptr(), n, p, lda, int(formulation), float(s_or_gamma))
     opts = SolveOpts(X0.data_ptr() if X0 is not None else None, r, float(tol), int(maxit),
                      int(precision), int(polish_maxit), int(check_every), int(flags))
     out = Outputs(_np_ptr(x), _np_ptr(sup), ctypes.pointer(res), _np_ptr(f), _np_ptr(ev),
                   _np_ptr(phi), _np_ptr(iters), _np_ptr(status), _np_ptr(nnz),
-                  Xf.data_ptr() if Xf is not None else None)
+                  Xf.data_ptr() if Xf is not None else None, _np_ptr(kt))
     _check(load().spca_am_solve_ex(ctx.handle, _stream_ptr(stream), ctypes.byref(prob),
                                    ctypes.byref(opts), ctypes.byref(out)))
     return {"x": x, "support": sup[: res.nnz].copy(), "objective": res.objective,
@@ -218,7 +227,11 @@ def am_solve(A, formulation, s_or_gamma, X0=None, tol=1e-8, maxit=200, *,
             "status": res.status, "iters_x_starts": res.iters_x_starts,
             "f_per_start": f, "ev_per_start": ev, "phi_per_start": phi,
             "iters_per_start": iters, "status_per_start": status,
-            "nnz_per_start": nnz, "X_final": Xf}
+            "nnz_per_start": nnz, "X_final": Xf,
+            "kernel_times": None if kt is None else {
+                "aty_ms": kt[0], "aty_launches": int(kt[1]), "x_update_ms": kt[2],
+                "x_update_launches": int(kt[3]), "ax_dense_ms": kt[4],
+                "ax_dense_launches": int(kt[5])}}
 
 
 def am_solve_simple(A, formulation, s_or_gamma, X0=None, tol=1e-8, maxit=200):
@@ -260,6 +273,32 @@ def gemm_nt(P, Q, stream=None):
                                    P.stride(0), ctypes.c_void_p(Q.data_ptr()), Q.stride(0),
                                    ctypes.c_void_p(C.data_ptr()), N, M, N, K))
     return C
+
+
+def gemm_nt_shape(P, Q, shape, splits=1, stream=None):
+    """Partial products of P Q^T with a forced tile shape and K split
+    (``spca_gemm_nt_f32_shape``); returns a (splits, M, N) tensor whose sum
+    over the first axis is the product."""
+    import torch
+
+    _require_gpu_tensor(P, "P", torch.float32)
+    _require_gpu_tensor(Q, "Q", torch.float32)
+    M, K = P.shape
+    N, _ = Q.shape
+    C = torch.empty((splits, M, N), dtype=torch.float32, device=P.device)
+    _check(load().spca_gemm_nt_f32_shape(_stream_ptr(stream), ctypes.c_void_p(P.data_ptr()),
+                                         P.stride(0), ctypes.c_void_p(Q.data_ptr()),
+                                         Q.stride(0), ctypes.c_void_p(C.data_ptr()), N,
+                                         M, N, K, int(shape), int(splits)))
+    return C
+
+
+def gemm_plan(M, N, K, max_splits=1):
+    """(shape, splits) the library picks for an M x N x K product."""
+    sh, sp = ctypes.c_int(), ctypes.c_int()
+    _check(load().spca_gemm_nt_f32_plan(int(M), int(N), int(K), int(max_splits),
+                                        ctypes.byref(sh), ctypes.byref(sp)))
+    return sh.value, sp.value
 
 
 def x_update(formulation, V, s_or_gamma, stream=None):

@@ -6,12 +6,19 @@
 //
 // Tiling: a workgroup of WM x WN waves owns a BM x BN tile of C; each wave
 // owns (BM/WM) x (BN/WN) built from 32 x 32 v_mfma_f32_32x32x2_f32 blocks.
-// K advances BK at a time through one LDS buffer, with the next tile
-// prefetched into registers while the current one is consumed.
-// Within an 8-wide K chunk, lane l of a wave feeds row (l % 32) at k offset
+// K advances 32 at a time through two LDS stages: while the waves multiply
+// out of one stage, the next K slab is already in registers and is written
+// to the other stage, so one barrier per slab suffices.
+// Within an 8-wide K chunk, lane l feeds row (l % 32) at k offset
 // 4 * (l / 32) .. +3 as one 16-byte LDS read; the i-th of the four MFMAs of
 // the chunk takes element i.  The order in which k terms enter the sum does
-// not change the product, so this keeps every LDS read 16 bytes wide.
+// not change the product, so every LDS read is 16 bytes wide.
+// LDS rows are 128 bytes with no padding; the 16-byte chunk c of row r is
+// stored at chunk c ^ ((r ^ (r >> 3)) & 7), so that any 8 consecutive rows
+// (and any 16 rows of alternating parity pairs) read at one chunk index
+// fall in distinct banks for 32- and 64-bank LDS alike.
+// Split-K: when splits > 1, slab range s of every tile writes its partial
+// product to C + s * split_stride; the consumer sums the partials in order.
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -21,63 +28,74 @@ namespace {
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
-constexpr int kPad = 4;  // floats of padding per LDS row
+constexpr int kBK = 32;              // K per slab (floats)
+constexpr int kChunks = kBK / 4;     // 16-byte chunks per LDS row
 
-template <int BM, int BN, int BK, int WM, int WN>
+template <int BM, int BN, int WM, int WN>
 struct GemmCfg {
   static constexpr int kThreads = WM * WN * kWave;
   static constexpr int kTM = BM / WM;  // rows per wave
   static constexpr int kTN = BN / WN;  // cols per wave
   static constexpr int kFM = kTM / 32;
   static constexpr int kFN = kTN / 32;
-  static constexpr int kLdsRow = BK + kPad;
-  static constexpr int kPVec = BM * BK / 4 / kThreads;  // float4 per thread
-  static constexpr int kQVec = BN * BK / 4 / kThreads;
+  static constexpr int kPVec = BM * kChunks / kThreads;  // float4 per thread
+  static constexpr int kQVec = BN * kChunks / kThreads;
+  static constexpr int kStage = (BM + BN) * kBK;  // floats per LDS stage
   static_assert(kTM % 32 == 0 && kTN % 32 == 0, "wave tile must be 32-aligned");
-  static_assert(BK % 8 == 0, "BK must be a multiple of 8");
-  static_assert((BM * BK / 4) % kThreads == 0, "P tile load must divide");
-  static_assert((BN * BK / 4) % kThreads == 0, "Q tile load must divide");
+  static_assert((BM * kChunks) % kThreads == 0, "P slab load must divide");
+  static_assert((BN * kChunks) % kThreads == 0, "Q slab load must divide");
 };
+
+__device__ __forceinline__ int swz(int row, int chunk) {
+  return row * kBK + ((chunk ^ ((row ^ (row >> 3)) & 7)) << 2);
+}
 
 __device__ __forceinline__ floatx4 load_row4(const float* __restrict__ base,
                                              int64_t ld, int row, int nrows,
-                                             int k, int K) {
+                                             int k, int kend) {
   floatx4 v = {0.f, 0.f, 0.f, 0.f};
   if (row < nrows) {
     const float* p = base + (int64_t)row * ld + k;
-    if (k + 3 < K) {
+    if (k + 3 < kend) {
       v = *reinterpret_cast<const floatx4*>(p);
     } else {
-      if (k + 0 < K) v.x = p[0];
-      if (k + 1 < K) v.y = p[1];
-      if (k + 2 < K) v.z = p[2];
+      if (k + 0 < kend) v.x = p[0];
+      if (k + 1 < kend) v.y = p[1];
+      if (k + 2 < kend) v.z = p[2];
     }
   }
   return v;
 }
 
-template <int BM, int BN, int BK, int WM, int WN>
+template <int BM, int BN, int WM, int WN>
 __global__ __launch_bounds__(WM* WN* kWave) void gemm_nt_f32_kernel(
     const float* __restrict__ P, int64_t ldp, const float* __restrict__ Q,
     int64_t ldq, float* __restrict__ C, int64_t ldc, int M, int N, int K,
-    int tiles_m, int tiles_total, const int32_t* __restrict__ gate,
-    int32_t gate_skip) {
-  using Cfg = GemmCfg<BM, BN, BK, WM, WN>;
+    int tiles_m, int tiles_mn, int splits, int kslabs_per_split,
+    int64_t split_stride, const int32_t* __restrict__ gate, int32_t gate_skip) {
+  using Cfg = GemmCfg<BM, BN, WM, WN>;
   if (gate != nullptr && *gate == gate_skip) return;
 
-  __shared__ __attribute__((aligned(16))) float Ps[BM * Cfg::kLdsRow];
-  __shared__ __attribute__((aligned(16))) float Qs[BN * Cfg::kLdsRow];
+  __shared__ __attribute__((aligned(16))) float lds[2 * Cfg::kStage];
 
   // Blocks are dealt to the 8 XCDs round-robin; renumber so that runs of
-  // consecutive tiles (the M tiles sharing one Q tile) stay on one XCD and
-  // reuse its L2.
+  // consecutive tiles (the M tiles and K splits sharing one Q tile) stay on
+  // one XCD and reuse its L2.
   int b = blockIdx.x;
-  const int per_xcd = tiles_total / 8;
+  const int total = tiles_mn * splits;
+  const int per_xcd = total / 8;
   if (b < per_xcd * 8) b = (b % 8) * per_xcd + b / 8;
-  const int tm = b % tiles_m;
-  const int tn = b / tiles_m;
+  const int split = b % splits;
+  const int t = b / splits;
+  const int tm = t % tiles_m;
+  const int tn = t / tiles_m;
   const int m0 = tm * BM;
   const int n0 = tn * BN;
+  const int kbeg = split * kslabs_per_split * kBK;
+  int kend = kbeg + kslabs_per_split * kBK;
+  kend = kend < K ? kend : K;
+  const int nslabs = kend > kbeg ? (kend - kbeg + kBK - 1) / kBK : 0;
+  float* Cs = C + (int64_t)split * split_stride;
 
   const int tid = threadIdx.x;
   const int lane = tid % kWave;
@@ -85,7 +103,7 @@ __global__ __launch_bounds__(WM* WN* kWave) void gemm_nt_f32_kernel(
   const int wm = wave % WM;
   const int wn = wave / WM;
   const int lrow = lane % 32;
-  const int lk = 4 * (lane / 32);
+  const int lhalf = lane / 32;
 
   const float* Pblk = P + (int64_t)m0 * ldp;
   const float* Qblk = Q + (int64_t)n0 * ldq;
@@ -102,59 +120,55 @@ __global__ __launch_bounds__(WM* WN* kWave) void gemm_nt_f32_kernel(
 
   floatx4 pre_p[Cfg::kPVec];
   floatx4 pre_q[Cfg::kQVec];
-  constexpr int kVecPerRow = BK / 4;
 
   auto fetch = [&](int k0) {
 #pragma unroll
     for (int v = 0; v < Cfg::kPVec; ++v) {
       int f = tid + v * Cfg::kThreads;
-      int row = f / kVecPerRow;
-      int kc = (f % kVecPerRow) * 4;
-      pre_p[v] = load_row4(Pblk, ldp, row, mrows, k0 + kc, K);
+      pre_p[v] = load_row4(Pblk, ldp, f / kChunks, mrows, k0 + (f % kChunks) * 4, kend);
     }
 #pragma unroll
     for (int v = 0; v < Cfg::kQVec; ++v) {
       int f = tid + v * Cfg::kThreads;
-      int row = f / kVecPerRow;
-      int kc = (f % kVecPerRow) * 4;
-      pre_q[v] = load_row4(Qblk, ldq, row, nrows, k0 + kc, K);
+      pre_q[v] = load_row4(Qblk, ldq, f / kChunks, nrows, k0 + (f % kChunks) * 4, kend);
     }
   };
-  auto stash = [&]() {
+  auto stash = [&](float* st) {
 #pragma unroll
     for (int v = 0; v < Cfg::kPVec; ++v) {
       int f = tid + v * Cfg::kThreads;
-      int row = f / kVecPerRow;
-      int kc = (f % kVecPerRow) * 4;
-      *reinterpret_cast<floatx4*>(&Ps[row * Cfg::kLdsRow + kc]) = pre_p[v];
+      *reinterpret_cast<floatx4*>(&st[swz(f / kChunks, f % kChunks)]) = pre_p[v];
     }
+    float* sq = st + BM * kBK;
 #pragma unroll
     for (int v = 0; v < Cfg::kQVec; ++v) {
       int f = tid + v * Cfg::kThreads;
-      int row = f / kVecPerRow;
-      int kc = (f % kVecPerRow) * 4;
-      *reinterpret_cast<floatx4*>(&Qs[row * Cfg::kLdsRow + kc]) = pre_q[v];
+      *reinterpret_cast<floatx4*>(&sq[swz(f / kChunks, f % kChunks)]) = pre_q[v];
     }
   };
 
-  const int ktiles = (K + BK - 1) / BK;
-  fetch(0);
-  stash();
+  if (nslabs > 0) {
+    fetch(kbeg);
+    stash(lds);
+  }
   __syncthreads();
-  for (int kt = 0; kt < ktiles; ++kt) {
-    if (kt + 1 < ktiles) fetch((kt + 1) * BK);
+  for (int ks = 0; ks < nslabs; ++ks) {
+    const float* sp = lds + (ks & 1) * Cfg::kStage;
+    const float* sq = sp + BM * kBK;
+    if (ks + 1 < nslabs) fetch(kbeg + (ks + 1) * kBK);
 #pragma unroll
-    for (int kc = 0; kc < BK; kc += 8) {
+    for (int c8 = 0; c8 < kChunks; c8 += 2) {
+      const int chunk = c8 + lhalf;  // k offset 4 * chunk within the slab
       floatx4 a[Cfg::kFM];
       floatx4 bq[Cfg::kFN];
 #pragma unroll
       for (int i = 0; i < Cfg::kFM; ++i)
         a[i] = *reinterpret_cast<const floatx4*>(
-            &Ps[(wm * Cfg::kTM + i * 32 + lrow) * Cfg::kLdsRow + kc + lk]);
+            &sp[swz(wm * Cfg::kTM + i * 32 + lrow, chunk)]);
 #pragma unroll
       for (int j = 0; j < Cfg::kFN; ++j)
         bq[j] = *reinterpret_cast<const floatx4*>(
-            &Qs[(wn * Cfg::kTN + j * 32 + lrow) * Cfg::kLdsRow + kc + lk]);
+            &sq[swz(wn * Cfg::kTN + j * 32 + lrow, chunk)]);
 #pragma unroll
       for (int e = 0; e < 4; ++e)
 #pragma unroll
@@ -164,11 +178,8 @@ __global__ __launch_bounds__(WM* WN* kWave) void gemm_nt_f32_kernel(
             acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i][e], bq[j][e],
                                                              acc[i][j], 0, 0, 0);
     }
+    if (ks + 1 < nslabs) stash(lds + ((ks + 1) & 1) * Cfg::kStage);
     __syncthreads();
-    if (kt + 1 < ktiles) {
-      stash();
-      __syncthreads();
-    }
   }
 
   // Accumulator layout of the 32x32 block: register e of lane l holds
@@ -180,38 +191,124 @@ __global__ __launch_bounds__(WM* WN* kWave) void gemm_nt_f32_kernel(
       const int col = n0 + wn * Cfg::kTN + j * 32 + lrow;
 #pragma unroll
       for (int e = 0; e < 16; ++e) {
-        const int row = m0 + wm * Cfg::kTM + i * 32 + 8 * (e / 4) + lk + (e % 4);
-        if (row < M && col < N) C[(int64_t)row * ldc + col] = acc[i][j][e];
+        const int row = m0 + wm * Cfg::kTM + i * 32 + 8 * (e / 4) + 4 * lhalf + (e % 4);
+        if (row < M && col < N) Cs[(int64_t)row * ldc + col] = acc[i][j][e];
       }
     }
   }
 }
 
-template <int BM, int BN, int BK, int WM, int WN>
+// Compiled tile shapes.  occ = workgroups a CU holds at once (LDS and
+// registers); eff = relative MFMA efficiency of the shape measured on
+// MI355X (larger per-wave tiles reuse each LDS read for more MFMAs).
+struct Shape {
+  int bm, bn, occ;
+  double eff;
+};
+constexpr Shape kShapes[] = {
+    {128, 128, 2, 1.00},  // 2x2 waves of 64x64
+    {128, 160, 2, 1.00},  // 4x1 waves of 32x160
+    {128, 96, 2, 0.92},   // 4x1 waves of 32x96
+    {128, 64, 3, 0.85},   // 2x2 waves of 64x32
+    {64, 128, 3, 0.85},   // 2x2 waves of 32x64
+    {32, 128, 3, 0.70},   // 1x4 waves of 32x32
+};
+constexpr int kNumShapes = (int)(sizeof(kShapes) / sizeof(kShapes[0]));
+
+template <int BM, int BN, int WM, int WN>
 void launch(hipStream_t st, const float* P, int64_t ldp, const float* Q,
             int64_t ldq, float* C, int64_t ldc, int64_t M, int64_t N,
-            int64_t K, const int32_t* gate, int32_t gate_skip) {
+            int64_t K, int splits, int64_t split_stride, const int32_t* gate,
+            int32_t gate_skip) {
   const int tiles_m = (int)ceil_div(M, BM);
   const int tiles_n = (int)ceil_div(N, BN);
-  const int total = tiles_m * tiles_n;
-  hipLaunchKernelGGL((gemm_nt_f32_kernel<BM, BN, BK, WM, WN>), dim3(total),
+  const int kslabs = (int)ceil_div(K, kBK);
+  const int per_split = (int)ceil_div(kslabs, splits);
+  const int total = tiles_m * tiles_n * splits;
+  hipLaunchKernelGGL((gemm_nt_f32_kernel<BM, BN, WM, WN>), dim3(total),
                      dim3(WM * WN * kWave), 0, st, P, ldp, Q, ldq, C, ldc,
-                     (int)M, (int)N, (int)K, tiles_m, total, gate, gate_skip);
+                     (int)M, (int)N, (int)K, tiles_m, tiles_m * tiles_n, splits,
+                     per_split, split_stride, gate, gate_skip);
+}
+
+void dispatch(int shape, hipStream_t st, const float* P, int64_t ldp,
+              const float* Q, int64_t ldq, float* C, int64_t ldc, int64_t M,
+              int64_t N, int64_t K, int splits, int64_t split_stride,
+              const int32_t* gate, int32_t gate_skip) {
+  switch (shape) {
+    case 0:
+      launch<128, 128, 2, 2>(st, P, ldp, Q, ldq, C, ldc, M, N, K, splits, split_stride, gate, gate_skip);
+      break;
+    case 1:
+      launch<128, 160, 4, 1>(st, P, ldp, Q, ldq, C, ldc, M, N, K, splits, split_stride, gate, gate_skip);
+      break;
+    case 2:
+      launch<128, 96, 4, 1>(st, P, ldp, Q, ldq, C, ldc, M, N, K, splits, split_stride, gate, gate_skip);
+      break;
+    case 3:
+      launch<128, 64, 2, 2>(st, P, ldp, Q, ldq, C, ldc, M, N, K, splits, split_stride, gate, gate_skip);
+      break;
+    case 4:
+      launch<64, 128, 2, 2>(st, P, ldp, Q, ldq, C, ldc, M, N, K, splits, split_stride, gate, gate_skip);
+      break;
+    default:
+      launch<32, 128, 1, 4>(st, P, ldp, Q, ldq, C, ldc, M, N, K, splits, split_stride, gate, gate_skip);
+      break;
+  }
 }
 
 }  // namespace
 
+// Deterministic choice of tile shape and K split from a model of one
+// launch, in cycles of one CU:
+//   a workgroup's MFMA work  w = BM * BN * (K slabs per split * 32)
+//                               / (128 MACs per cycle * eff);
+//   the workgroups fill rounds of 256 CUs x occ slots; a CU running k
+//   workgroups at once takes w * max(k, 1.5) (one workgroup alone cannot
+//   keep the matrix cores busy), so the partial last round costs
+//   w * max(ceil(rest / 256), 1.5);
+//   split partials cost their HBM traffic, 8 bytes per element per split at
+//   about 1.7 KB per cycle for the whole chip.
+GemmPlan plan_gemm_nt(int64_t M, int64_t N, int64_t K, int max_splits) {
+  GemmPlan best{0, 1};
+  double best_cost = 1e300;
+  const int64_t kslabs = ceil_div(K, kBK);
+  for (int s = 0; s < kNumShapes; ++s) {
+    const Shape& sh = kShapes[s];
+    if (sh.bm > 32 && M <= sh.bm / 2) continue;  // mostly padding rows
+    const int64_t tiles = ceil_div(M, sh.bm) * ceil_div(N, sh.bn);
+    for (int splits = 1; splits <= max_splits; splits *= 2) {
+      const int64_t per = ceil_div(kslabs, splits);
+      if (splits > 1 && per < 8) break;  // too little K per split
+      const int64_t wgs = tiles * splits;
+      const int64_t slots = 256LL * sh.occ;
+      const double w = (double)sh.bm * sh.bn * (double)(per * kBK) / (128.0 * sh.eff);
+      const int64_t full = wgs / slots;
+      const int64_t rest = wgs % slots;
+      double cost = (double)full * w * (sh.occ > 1.5 ? sh.occ : 1.5);
+      if (rest > 0) {
+        double k = (double)ceil_div(rest, 256);
+        cost += w * (k > 1.5 ? k : 1.5);
+      }
+      if (splits > 1) cost += (double)splits * M * N * 8.0 / 1700.0;
+      if (cost < best_cost * 0.999) {
+        best_cost = cost;
+        best = GemmPlan{s, splits};
+      }
+    }
+  }
+  return best;
+}
+
+int gemm_num_shapes() { return kNumShapes; }
+
 void gemm_nt_f32(hipStream_t st, const float* P, int64_t ldp, const float* Q,
                  int64_t ldq, float* C, int64_t ldc, int64_t M, int64_t N,
-                 int64_t K, const int32_t* gate, int32_t gate_skip) {
+                 int64_t K, const int32_t* gate, int32_t gate_skip,
+                 GemmPlan plan, int64_t split_stride) {
   if (M <= 0 || N <= 0) return;
-  if (M <= 32) {
-    launch<32, 128, 32, 1, 4>(st, P, ldp, Q, ldq, C, ldc, M, N, K, gate, gate_skip);
-  } else if (M <= 64) {
-    launch<64, 128, 32, 2, 2>(st, P, ldp, Q, ldq, C, ldc, M, N, K, gate, gate_skip);
-  } else {
-    launch<128, 128, 32, 2, 2>(st, P, ldp, Q, ldq, C, ldc, M, N, K, gate, gate_skip);
-  }
+  dispatch(plan.shape, st, P, ldp, Q, ldq, C, ldc, M, N, K, plan.splits,
+           split_stride, gate, gate_skip);
 }
 
 }  // namespace spca

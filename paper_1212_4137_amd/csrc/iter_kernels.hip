@@ -175,18 +175,24 @@ __global__ __launch_bounds__(1024) void plan_kernel(StartState s, int64_t r,
 
 template <bool L1VAR>
 __global__ __launch_bounds__(256) void y_update_kernel(
-    const float* __restrict__ U, float* __restrict__ Y, int64_t ldu, int64_t n,
-    StartState s, const Plan* plan) {
+    const float* __restrict__ U, int splits, int64_t split_stride,
+    float* __restrict__ Y, int64_t ldu, int64_t n, StartState s,
+    const Plan* plan) {
   __shared__ double red[8];
   if (plan->sparse) return;
   const int64_t j = blockIdx.x;
   if (s.status[j] != kRunning) return;
   const float* u = U + j * ldu;
   float* y = Y + j * ldu;
+  // u_i = sum of the split partials in split order; each thread keeps the
+  // values it owns in y until the norm is known
   double sq = 0.0;
   for (int64_t i = threadIdx.x; i < n; i += 256) {
-    double t = u[i];
-    sq += t * t;
+    float t = u[i];
+    for (int sp = 1; sp < splits; ++sp) t += u[i + sp * split_stride];
+    y[i] = t;
+    double td = t;
+    sq += td * td;
   }
   sq = block_sum(sq, red);
   if (sq == 0.0) {
@@ -195,7 +201,7 @@ __global__ __launch_bounds__(256) void y_update_kernel(
   }
   const double inv = 1.0 / sqrt(sq);
   for (int64_t i = threadIdx.x; i < n; i += 256) {
-    float t = u[i];
+    float t = y[i];
     y[i] = L1VAR ? (float)((t > 0.f) - (t < 0.f)) : (float)((double)t * inv);
   }
 }
@@ -328,14 +334,15 @@ void plan_next(hipStream_t st, StartState s, int64_t r, int64_t p,
                      sparse_fraction, dense_only, plan);
 }
 
-void y_update(hipStream_t st, int fid, const float* U, float* Y, int64_t ldu,
-              int64_t r, int64_t n, StartState s, const Plan* plan) {
+void y_update(hipStream_t st, int fid, const float* U, int splits,
+              int64_t split_stride, float* Y, int64_t ldu, int64_t r,
+              int64_t n, StartState s, const Plan* plan) {
   if (l1_variance(fid))
     hipLaunchKernelGGL(y_update_kernel<true>, dim3((unsigned)r), dim3(256), 0,
-                       st, U, Y, ldu, n, s, plan);
+                       st, U, splits, split_stride, Y, ldu, n, s, plan);
   else
     hipLaunchKernelGGL(y_update_kernel<false>, dim3((unsigned)r), dim3(256), 0,
-                       st, U, Y, ldu, n, s, plan);
+                       st, U, splits, split_stride, Y, ldu, n, s, plan);
 }
 
 void sparse_ax_y_update(hipStream_t st, int fid, const float* A, int64_t lda,

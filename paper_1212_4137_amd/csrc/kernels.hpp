@@ -33,11 +33,24 @@ struct Plan {
   int64_t total_nnz;    // sum of nnz over running starts
 };
 
-// C (M x N, ldc) = P (M x K, ldp) * Q (N x K, ldq)^T, FP32 MFMA.  When
-// gate != nullptr the kernel returns at once if *gate == gate_skip.
+// Tile shape (index into the compiled shapes) and K split of one product.
+struct GemmPlan {
+  int shape;
+  int splits;
+};
+
+// Deterministic shape / split choice for an M x N x K product.
+GemmPlan plan_gemm_nt(int64_t M, int64_t N, int64_t K, int max_splits);
+int gemm_num_shapes();
+
+// C (M x N, ldc) = P (M x K, ldp) * Q (N x K, ldq)^T, FP32 MFMA.  With
+// plan.splits > 1, K split s writes its partial product at
+// C + s * split_stride.  When gate != nullptr the kernel returns at once if
+// *gate == gate_skip.
 void gemm_nt_f32(hipStream_t st, const float* P, int64_t ldp, const float* Q,
                  int64_t ldq, float* C, int64_t ldc, int64_t M, int64_t N,
-                 int64_t K, const int32_t* gate, int32_t gate_skip);
+                 int64_t K, const int32_t* gate, int32_t gate_skip,
+                 GemmPlan plan, int64_t split_stride);
 
 // Row-major copy: At[i * ldat + k] = A[i + k * lda] (i < n, k < p).
 void transpose_f32(hipStream_t st, const float* A, int64_t lda, float* At,
@@ -70,11 +83,13 @@ void init_state(hipStream_t st, StartState s, int64_t r);
 void plan_next(hipStream_t st, StartState s, int64_t r, int64_t p,
                double sparse_fraction, int dense_only, Plan* plan);
 
-// y-update of Algorithm 2 from a dense U (r x n): Y = sgn(U) (L1 variance)
-// or U / ||U||_2 per row (L2 variance); a zero row ends its start as
-// DEGENERATE.  Skipped when plan->sparse != 0.
-void y_update(hipStream_t st, int fid, const float* U, float* Y, int64_t ldu,
-              int64_t r, int64_t n, StartState s, const Plan* plan);
+// y-update of Algorithm 2 from a dense U (r x n), given as `splits` partial
+// products split_stride floats apart that are summed in order: Y = sgn(U)
+// (L1 variance) or U / ||U||_2 per row (L2 variance); a zero row ends its
+// start as DEGENERATE.  Skipped when plan->sparse != 0.
+void y_update(hipStream_t st, int fid, const float* U, int splits,
+              int64_t split_stride, float* Y, int64_t ldu, int64_t r,
+              int64_t n, StartState s, const Plan* plan);
 
 // Sparse A x from the lists followed by the y-update, one block per start.
 // Skipped when plan->sparse == 0.

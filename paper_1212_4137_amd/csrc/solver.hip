@@ -30,10 +30,13 @@ namespace {
 
 constexpr double kSparseFraction = 0.04;  // list product when nnz <= 4% dense
 
+constexpr int kMaxSplits = 16;  // K splits of the dense A x product
+
 struct Layout {
   int64_t n, p, r;
   int64_t ldx, ldu, ldat, ldac;
   bool copy_a;
+  GemmPlan plan_ax, plan_aty;
   size_t off_At, off_Ac, off_X, off_U, off_Y, off_V, off_li, off_lv;
   size_t off_phi, off_phip, off_nnz, off_it, off_st, off_plan, off_part,
       off_f, off_ev, off_xn, off_best, off_xout, off_sup, off_colsq, off_bad;
@@ -58,11 +61,13 @@ Layout make_layout(int64_t n, int64_t p, int64_t r, bool copy_a) {
   L.ldac = round_up(n, 4);
   L.copy_a = copy_a;
   L.nchunks = (int)ceil_div(n, 256);
+  L.plan_ax = plan_gemm_nt(r, n, p, kMaxSplits);   // U^T = X^T A^T, K = p
+  L.plan_aty = plan_gemm_nt(r, p, n, 1);           // V^T = Y^T A,   K = n
   size_t c = 0;
   L.off_At = carve(&c, sizeof(float) * (size_t)n * L.ldat);
   L.off_Ac = carve(&c, copy_a ? sizeof(float) * (size_t)p * L.ldac : 0);
   L.off_X = carve(&c, sizeof(float) * (size_t)r * L.ldx);
-  L.off_U = carve(&c, sizeof(float) * (size_t)r * L.ldu);
+  L.off_U = carve(&c, sizeof(float) * (size_t)L.plan_ax.splits * r * L.ldu);
   L.off_Y = carve(&c, sizeof(float) * (size_t)r * L.ldu);
   L.off_V = carve(&c, sizeof(float) * (size_t)r * L.ldx);
   L.off_li = carve(&c, sizeof(int32_t) * (size_t)r * L.ldx);
@@ -124,12 +129,46 @@ struct DeviceGuard {
 }  // namespace
 }  // namespace spca
 
+// Pool of HIP events recorded in begin/end pairs around selected launches.
+struct EventPairs {
+  std::vector<hipEvent_t> ev;
+  size_t used = 0;
+  hipError_t mark(hipStream_t st) {
+    if (used == ev.size()) {
+      hipEvent_t e;
+      hipError_t rc = hipEventCreate(&e);
+      if (rc != hipSuccess) return rc;
+      ev.push_back(e);
+    }
+    return hipEventRecord(ev[used++], st);
+  }
+  // sum of (end - begin) over the recorded pairs, in ms
+  hipError_t total_ms(double* ms) {
+    double t = 0.0;
+    for (size_t i = 0; i + 1 < used; i += 2) {
+      float x = 0.f;
+      hipError_t rc = hipEventElapsedTime(&x, ev[i], ev[i + 1]);
+      if (rc != hipSuccess) return rc;
+      t += x;
+    }
+    *ms = t;
+    return hipSuccess;
+  }
+  void reset() { used = 0; }
+  void destroy() {
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    ev.clear();
+    used = 0;
+  }
+};
+
 struct spca_ctx {
   int device = 0;
   size_t budget = 0;
   void* ws = nullptr;
   size_t ws_cap = 0;
   int32_t* host_poll = nullptr;  // pinned
+  EventPairs t_aty, t_xup, t_ax;
   std::mutex mu;
 };
 
@@ -176,6 +215,9 @@ int spca_ctx_destroy(spca_ctx* ctx) {
       (void)hipFree(ctx->ws);
     }
     if (ctx->host_poll) (void)hipHostFree(ctx->host_poll);
+    ctx->t_aty.destroy();
+    ctx->t_xup.destroy();
+    ctx->t_ax.destroy();
   }
   delete ctx;
   return SPCA_OK;
@@ -292,15 +334,27 @@ int spca_am_solve_ex(spca_ctx* ctx, void* stream, const spca_problem* prob,
   SPCA_LAUNCH_CHECK("staging");
 
   const int32_t maxit = opts->maxit;
+  const bool timed = out->kernel_times != nullptr;
+  ctx->t_aty.reset();
+  ctx->t_xup.reset();
+  ctx->t_ax.reset();
   for (int32_t it = 0; it < maxit; ++it) {
     // u = A x and the y-update
-    gemm_nt_f32(st, X, L.ldx, At, L.ldat, U, L.ldu, r, n, p, &plan->sparse, 1);
-    y_update(st, fid, U, Y, L.ldu, r, n, s, plan);
+    if (timed) SPCA_HIP_TRY(ctx->t_ax.mark(st));
+    gemm_nt_f32(st, X, L.ldx, At, L.ldat, U, L.ldu, r, n, p, &plan->sparse, 1,
+                L.plan_ax, r * L.ldu);
+    if (timed) SPCA_HIP_TRY(ctx->t_ax.mark(st));
+    y_update(st, fid, U, L.plan_ax.splits, r * L.ldu, Y, L.ldu, r, n, s, plan);
     sparse_ax_y_update(st, fid, A, ldA, n, li, lv, L.ldx, Y, L.ldu, r, s, plan);
     // v = A^T y and the x-update with the stop test
-    gemm_nt_f32(st, Y, L.ldu, A, ldA, V, L.ldx, r, p, n, nullptr, 0);
+    if (timed) SPCA_HIP_TRY(ctx->t_aty.mark(st));
+    gemm_nt_f32(st, Y, L.ldu, A, ldA, V, L.ldx, r, p, n, nullptr, 0,
+                L.plan_aty, 0);
+    if (timed) SPCA_HIP_TRY(ctx->t_aty.mark(st));
+    if (timed) SPCA_HIP_TRY(ctx->t_xup.mark(st));
     x_update(st, fid, sg, V, L.ldx, r, p, X, L.ldx, li, lv, L.ldx, s,
              opts->tol, maxit);
+    if (timed) SPCA_HIP_TRY(ctx->t_xup.mark(st));
     plan_next(st, s, r, p, kSparseFraction, dense_only, plan);
     SPCA_LAUNCH_CHECK("AM iteration");
     if ((it + 1) % opts->check_every == 0 && it + 1 < maxit) {
@@ -346,6 +400,15 @@ int spca_am_solve_ex(spca_ctx* ctx, void* stream, const spca_problem* prob,
                                   hipMemcpyDeviceToDevice, st));
   SPCA_HIP_TRY(hipStreamSynchronize(st));
 
+  if (timed) {
+    double* kt = out->kernel_times;
+    SPCA_HIP_TRY(ctx->t_aty.total_ms(&kt[0]));
+    kt[1] = (double)(ctx->t_aty.used / 2);
+    SPCA_HIP_TRY(ctx->t_xup.total_ms(&kt[2]));
+    kt[3] = (double)(ctx->t_xup.used / 2);
+    SPCA_HIP_TRY(ctx->t_ax.total_ms(&kt[4]));
+    kt[5] = (double)(ctx->t_ax.used / 2);
+  }
   double total_iters = 0.0;
   for (int64_t j = 0; j < r; ++j) total_iters += it_all[j];
   spca_result* res = out->res;
@@ -412,8 +475,41 @@ int spca_gemm_nt_f32(void* stream, const float* P, int64_t ldp, const float* Q,
                "ldp and ldq must be multiples of 4");
   SPCA_REQUIRE((uintptr_t)P % 16 == 0 && (uintptr_t)Q % 16 == 0,
                "P and Q must be 16-byte aligned");
-  gemm_nt_f32((hipStream_t)stream, P, ldp, Q, ldq, C, ldc, M, N, K, nullptr, 0);
+  gemm_nt_f32((hipStream_t)stream, P, ldp, Q, ldq, C, ldc, M, N, K, nullptr, 0,
+              plan_gemm_nt(M, N, K, 1), 0);
   SPCA_LAUNCH_CHECK("gemm_nt_f32");
+  return SPCA_OK;
+}
+
+int spca_gemm_nt_f32_shape(void* stream, const float* P, int64_t ldp,
+                           const float* Q, int64_t ldq, float* C, int64_t ldc,
+                           int64_t M, int64_t N, int64_t K, int shape,
+                           int splits) {
+  SPCA_REQUIRE(P && Q && C, "P, Q and C must not be NULL");
+  SPCA_REQUIRE(M >= 0 && N >= 0 && K >= 0, "sizes must be >= 0");
+  SPCA_REQUIRE(M <= INT32_MAX && N <= INT32_MAX && K <= INT32_MAX,
+               "sizes must fit in int32");
+  SPCA_REQUIRE(ldp >= K && ldq >= K && ldc >= N, "leading dimensions too small");
+  SPCA_REQUIRE(ldp % 4 == 0 && ldq % 4 == 0,
+               "ldp and ldq must be multiples of 4");
+  SPCA_REQUIRE((uintptr_t)P % 16 == 0 && (uintptr_t)Q % 16 == 0,
+               "P and Q must be 16-byte aligned");
+  SPCA_REQUIRE(shape >= 0 && shape < gemm_num_shapes(), "shape index out of range");
+  SPCA_REQUIRE(splits >= 1 && splits <= 64, "splits must be in 1..64");
+  gemm_nt_f32((hipStream_t)stream, P, ldp, Q, ldq, C, ldc, M, N, K, nullptr, 0,
+              GemmPlan{shape, splits}, M * ldc);
+  SPCA_LAUNCH_CHECK("gemm_nt_f32");
+  return SPCA_OK;
+}
+
+int spca_gemm_nt_f32_plan(int64_t M, int64_t N, int64_t K, int max_splits,
+                          int* shape, int* splits) {
+  SPCA_REQUIRE(shape && splits, "shape and splits must not be NULL");
+  SPCA_REQUIRE(M >= 1 && N >= 1 && K >= 1 && max_splits >= 1,
+               "sizes and max_splits must be >= 1");
+  GemmPlan g = plan_gemm_nt(M, N, K, max_splits);
+  *shape = g.shape;
+  *splits = g.splits;
   return SPCA_OK;
 }
 

@@ -50,6 +50,22 @@ def test_gemm_nt_matches_fp64(spca, M, N, K):
     assert np.all(err <= bound), float(np.max(err / bound))
 
 
+@pytest.mark.parametrize("shape", range(6))
+@pytest.mark.parametrize("M,N,K,splits", [(130, 333, 1001, 1), (37, 161, 517, 4),
+                                          (256, 100, 4100, 16)])
+def test_gemm_every_shape_and_split(spca, shape, M, N, K, splits):
+    print(f"gemm shape={shape} M={M} N={N} K={K} splits={splits}", flush=True)
+    rng = np.random.default_rng(shape * 17 + M + N + K + splits)
+    P, P64 = _padded(M, K, rng)
+    Q, Q64 = _padded(N, K, rng)
+    parts = spca.gemm_nt_shape(P, Q, shape, splits)
+    torch.cuda.synchronize()
+    C = parts.cpu().numpy().astype(np.float64).sum(axis=0)
+    ref = P64 @ Q64.T
+    bound = (np.abs(P64) @ np.abs(Q64).T) * ((K + splits) * 2.0 ** -24) * 1.01 + 1e-30
+    assert np.all(np.abs(C - ref) <= bound)
+
+
 def _oracle_rows(fid, V64, par):
     X, phi, nnz = [], [], []
     for v in V64:
