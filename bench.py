@@ -90,6 +90,8 @@ def main():
     ctx = spca.Context(0)
     stream = torch.cuda.current_stream()
 
+    modes = {}
+
     def step(timing):
         work = 0.0
         kt = {}
@@ -102,6 +104,8 @@ def main():
             if timing:
                 for k, v in res["kernel_times"].items():
                     kt[k] = kt.get(k, 0) + v
+                t = res["kernel_times"]
+                modes[fid] = (t["iters_dense"], t["iters_list"], t["iters_union"])
         return work, kt, nnz
 
     for _ in range(args.warmup):
@@ -131,7 +135,8 @@ def main():
                 "launches": int(launches)}
     other = {"x_update_avg_ms": round(kt_all["x_update_ms"] / kt_all["x_update_launches"], 5),
              "ax_dense_avg_ms": round(kt_all["ax_dense_ms"] / kt_all["ax_dense_launches"], 5),
-             "mean_nnz_per_start": nnz}
+             "mean_nnz_per_start": nnz,
+             "ax_modes_dense_list_union": modes}
 
     rec = {
         "metric": "AM iters x starts/sec",

@@ -145,11 +145,13 @@ typedef struct {
   int32_t* status_per_start;
   int32_t* nnz_per_start;
   float* X_final;      /* optional device r x p: final iterates (FP32)      */
-  /* optional host array of 6 doubles: HIP-event times of the launches of
+  /* optional host array of 9 doubles: HIP-event times of the launches of
    * this solve, [0] total ms and [1] count of the V = A^T Y products,
    * [2] ms and [3] count of the x-updates, [4] ms and [5] count of the
-   * dense U = A X products (including launches that found the sparse
-   * product selected and returned at once).  NULL disables the events.   */
+   * dense U = A X products (including launches that found another product
+   * selected and returned at once); [6], [7], [8] the iterations whose A x
+   * used the dense product, the per-start lists, and the product over the
+   * union of the supports.  NULL disables the events.                     */
   double* kernel_times;
 } spca_outputs;
 

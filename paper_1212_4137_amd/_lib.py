@@ -212,7 +212,7 @@ def am_solve(A, formulation, s_or_gamma, X0=None, tol=1e-8, maxit=200, *,
     status = np.zeros(r, dtype=np.int32)
     nnz = np.zeros(r, dtype=np.int32)
     Xf = torch.empty((r, p), dtype=torch.float32, device=A.device) if return_X else None
-    kt = np.zeros(6) if kernel_times else None
+    kt = np.zeros(9) if kernel_times else None
     prob = Problem(A.data_ptr(), n, p, lda, int(formulation), float(s_or_gamma))
     opts = SolveOpts(X0.data_ptr() if X0 is not None else None, r, float(tol), int(maxit),
                      int(precision), int(polish_maxit), int(check_every), int(flags))
@@ -231,7 +231,8 @@ def am_solve(A, formulation, s_or_gamma, X0=None, tol=1e-8, maxit=200, *,
             "kernel_times": None if kt is None else {
                 "aty_ms": kt[0], "aty_launches": int(kt[1]), "x_update_ms": kt[2],
                 "x_update_launches": int(kt[3]), "ax_dense_ms": kt[4],
-                "ax_dense_launches": int(kt[5])}}
+                "ax_dense_launches": int(kt[5]), "iters_dense": int(kt[6]),
+                "iters_list": int(kt[7]), "iters_union": int(kt[8])}}
 
 
 def am_solve_simple(A, formulation, s_or_gamma, X0=None, tol=1e-8, maxit=200):

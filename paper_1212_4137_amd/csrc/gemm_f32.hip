@@ -72,9 +72,14 @@ __global__ __launch_bounds__(WM* WN* kWave) void gemm_nt_f32_kernel(
     const float* __restrict__ P, int64_t ldp, const float* __restrict__ Q,
     int64_t ldq, float* __restrict__ C, int64_t ldc, int M, int N, int K,
     int tiles_m, int tiles_mn, int splits, int kslabs_per_split,
-    int64_t split_stride, const int32_t* __restrict__ gate, int32_t gate_skip) {
+    int64_t split_stride, const int32_t* __restrict__ gate, int32_t gate_run,
+    const int32_t* __restrict__ kdev) {
   using Cfg = GemmCfg<BM, BN, WM, WN>;
-  if (gate != nullptr && *gate == gate_skip) return;
+  if (gate != nullptr && *gate != gate_run) return;
+  if (kdev != nullptr) {
+    K = *kdev;
+    kslabs_per_split = (K + kBK - 1) / kBK;
+  }
 
   __shared__ __attribute__((aligned(16))) float lds[2 * Cfg::kStage];
 
@@ -219,7 +224,7 @@ template <int BM, int BN, int WM, int WN>
 void launch(hipStream_t st, const float* P, int64_t ldp, const float* Q,
             int64_t ldq, float* C, int64_t ldc, int64_t M, int64_t N,
             int64_t K, int splits, int64_t split_stride, const int32_t* gate,
-            int32_t gate_skip) {
+            int32_t gate_run, const int32_t* kdev) {
   const int tiles_m = (int)ceil_div(M, BM);
   const int tiles_n = (int)ceil_div(N, BN);
   const int kslabs = (int)ceil_div(K, kBK);
@@ -228,31 +233,31 @@ void launch(hipStream_t st, const float* P, int64_t ldp, const float* Q,
   hipLaunchKernelGGL((gemm_nt_f32_kernel<BM, BN, WM, WN>), dim3(total),
                      dim3(WM * WN * kWave), 0, st, P, ldp, Q, ldq, C, ldc,
                      (int)M, (int)N, (int)K, tiles_m, tiles_m * tiles_n, splits,
-                     per_split, split_stride, gate, gate_skip);
+                     per_split, split_stride, gate, gate_run, kdev);
 }
 
 void dispatch(int shape, hipStream_t st, const float* P, int64_t ldp,
               const float* Q, int64_t ldq, float* C, int64_t ldc, int64_t M,
               int64_t N, int64_t K, int splits, int64_t split_stride,
-              const int32_t* gate, int32_t gate_skip) {
+              const int32_t* gate, int32_t gate_run, const int32_t* kdev) {
   switch (shape) {
     case 0:
-      launch<128, 128, 2, 2>(st, P, ldp, Q, ldq, C, ldc, M, N, K, splits, split_stride, gate, gate_skip);
+      launch<128, 128, 2, 2>(st, P, ldp, Q, ldq, C, ldc, M, N, K, splits, split_stride, gate, gate_run, kdev);
       break;
     case 1:
-      launch<128, 160, 4, 1>(st, P, ldp, Q, ldq, C, ldc, M, N, K, splits, split_stride, gate, gate_skip);
+      launch<128, 160, 4, 1>(st, P, ldp, Q, ldq, C, ldc, M, N, K, splits, split_stride, gate, gate_run, kdev);
       break;
     case 2:
-      launch<128, 96, 4, 1>(st, P, ldp, Q, ldq, C, ldc, M, N, K, splits, split_stride, gate, gate_skip);
+      launch<128, 96, 4, 1>(st, P, ldp, Q, ldq, C, ldc, M, N, K, splits, split_stride, gate, gate_run, kdev);
       break;
     case 3:
-      launch<128, 64, 2, 2>(st, P, ldp, Q, ldq, C, ldc, M, N, K, splits, split_stride, gate, gate_skip);
+      launch<128, 64, 2, 2>(st, P, ldp, Q, ldq, C, ldc, M, N, K, splits, split_stride, gate, gate_run, kdev);
       break;
     case 4:
-      launch<64, 128, 2, 2>(st, P, ldp, Q, ldq, C, ldc, M, N, K, splits, split_stride, gate, gate_skip);
+      launch<64, 128, 2, 2>(st, P, ldp, Q, ldq, C, ldc, M, N, K, splits, split_stride, gate, gate_run, kdev);
       break;
     default:
-      launch<32, 128, 1, 4>(st, P, ldp, Q, ldq, C, ldc, M, N, K, splits, split_stride, gate, gate_skip);
+      launch<32, 128, 1, 4>(st, P, ldp, Q, ldq, C, ldc, M, N, K, splits, split_stride, gate, gate_run, kdev);
       break;
   }
 }
@@ -304,11 +309,12 @@ int gemm_num_shapes() { return kNumShapes; }
 
 void gemm_nt_f32(hipStream_t st, const float* P, int64_t ldp, const float* Q,
                  int64_t ldq, float* C, int64_t ldc, int64_t M, int64_t N,
-                 int64_t K, const int32_t* gate, int32_t gate_skip,
-                 GemmPlan plan, int64_t split_stride) {
+                 int64_t K, const int32_t* gate, int32_t gate_run,
+                 GemmPlan plan, int64_t split_stride, const int32_t* kdev) {
   if (M <= 0 || N <= 0) return;
+  if (kdev != nullptr) plan.splits = 1;
   dispatch(plan.shape, st, P, ldp, Q, ldq, C, ldc, M, N, K, plan.splits,
-           split_stride, gate, gate_skip);
+           split_stride, gate, gate_run, kdev);
 }
 
 }  // namespace spca

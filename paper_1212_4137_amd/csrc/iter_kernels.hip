@@ -116,10 +116,12 @@ __global__ __launch_bounds__(1024) void argmax_start_kernel(
 
 __global__ __launch_bounds__(1024) void compact_rows_kernel(
     const float* __restrict__ X, int64_t ldx, int64_t p, int32_t* list_idx,
-    float* list_val, int64_t ldl, int32_t* nnz, const int32_t* status) {
+    float* list_val, int64_t ldl, int32_t* nnz, const int32_t* status,
+    int32_t* colmark, const Plan* plan) {
   __shared__ int scan[20];
   const int64_t j = blockIdx.x;
   if (status != nullptr && status[j] != kRunning) return;
+  const int32_t epoch = colmark != nullptr ? plan->epoch : 0;
   const float* x = X + j * ldx;
   const int64_t chunk = ceil_div(p, blockDim.x);
   const int64_t b = threadIdx.x * chunk;
@@ -134,6 +136,7 @@ __global__ __launch_bounds__(1024) void compact_rows_kernel(
       list_idx[j * ldl + off] = (int32_t)i;
       list_val[j * ldl + off] = v;
       ++off;
+      if (colmark != nullptr) colmark[i] = epoch;
     }
   }
   if (threadIdx.x == 0) nnz[j] = total;
@@ -148,24 +151,129 @@ __global__ void init_state_kernel(StartState s, int64_t r) {
   s.status[j] = kRunning;
 }
 
-// One block: count running starts and their nonzeros, pick the product.
-__global__ __launch_bounds__(1024) void plan_kernel(StartState s, int64_t r,
-                                                    int64_t p, double frac,
-                                                    int dense_only, Plan* plan) {
+// One block: count running starts and their nonzeros, gather the union of
+// their supports, pick the product for the next A x.
+//
+// Cost model of the three ways to form U = X A^T (r x n), in microseconds on
+// MI355X: the dense MFMA product runs at about 100 TFLOP/s over all p
+// columns; the union product at about 80 TFLOP/s over the u union columns
+// plus its gathers (about 2 TB/s) and a fixed 6 us; the list product reads
+// a column of A per list entry from cache at about 12 TB/s.
+// The union is only gathered when the last x-update marked columns: while
+// the union product wins, every iteration, otherwise every 16th (a probe).
+__global__ __launch_bounds__(1024) void plan_kernel(
+    StartState s, int64_t r, int64_t n, int64_t p, int list_cap,
+    int dense_only, int dense_splits, int64_t ucap,
+    const int32_t* __restrict__ colmark, int32_t* __restrict__ ulist,
+    Plan* plan) {
   __shared__ int64_t red[2 * 17];
+  __shared__ int32_t mred[17];
+  __shared__ int scan[20];
   int64_t v[2] = {0, 0};
+  int32_t mx = 0;
   for (int64_t j = threadIdx.x; j < r; j += blockDim.x) {
     if (s.status[j] == kRunning) {
       v[0] += 1;
       v[1] += s.nnz[j];
+      mx = s.nnz[j] > mx ? s.nnz[j] : mx;
     }
   }
   block_sum_n<int64_t, 2>(v, red);
+  mx = block_max(mx, mred);
+  // union of the marked columns, in index order
+  const int32_t epoch = plan->epoch;
+  const bool marked = colmark != nullptr && plan->mark != 0;
+  int u = -1;
+  if (marked) {
+    const int64_t chunk = ceil_div(p, blockDim.x);
+    const int64_t b = threadIdx.x * chunk < p ? threadIdx.x * chunk : p;
+    const int64_t e = b + chunk < p ? b + chunk : p;
+    int cnt = 0;
+    for (int64_t i = b; i < e; ++i) cnt += colmark[i] == epoch;
+    int off = block_exclusive_scan(cnt, scan, &u);
+    for (int64_t i = b; i < e; ++i)
+      if (colmark[i] == epoch) ulist[off++] = (int32_t)i;
+  }
   if (threadIdx.x == 0) {
     plan->active = (int32_t)v[0];
     plan->total_nnz = v[1];
-    const double dense_work = (double)p * (double)v[0];
-    plan->sparse = (!dense_only && (double)v[1] <= frac * dense_work) ? 1 : 0;
+    plan->max_nnz = mx;
+    plan->union_size = u < 0 ? 0 : u;
+    const double rd = (double)r, nd = (double)n;
+    const double dense_us = 2.0 * rd * nd * (double)p / 1.0e8;
+    const double union_us = u >= 0 && u <= ucap
+                                ? 2.0 * rd * nd * u / 0.8e8 + 6.0 +
+                                      (rd + nd) * u * 8.0 / 2.0e6
+                                : 1e300;
+    const double list_us = mx <= list_cap ? (double)v[1] * nd * 4.0 / 12.0e6 + 3.0 : 1e300;
+    int mode = kAxDense;
+    double best = dense_us;
+    if (!dense_only) {
+      if (union_us < best) {
+        best = union_us;
+        mode = kAxUnion;
+      }
+      if (list_us < best) {
+        best = list_us;
+        mode = kAxList;
+      }
+    }
+    plan->mode = mode;
+    plan->ax_splits = mode == kAxDense ? dense_splits : 1;
+    plan->mode_count[mode] += v[0] > 0 ? 1 : 0;
+    plan->epoch = epoch + 1;
+    const int32_t it = plan->iter + 1;
+    plan->iter = it;
+    plan->mark = (colmark != nullptr && !dense_only && (mode == kAxUnion || it % 16 == 0)) ? 1 : 0;
+  }
+}
+
+__global__ void init_plan_kernel(Plan* plan, int dense_splits) {
+  plan->mode = kAxDense;
+  plan->active = 0;
+  plan->total_nnz = 0;
+  plan->max_nnz = 0;
+  plan->union_size = 0;
+  plan->epoch = 1;
+  plan->ax_splits = dense_splits;
+  plan->mark = 1;
+  plan->iter = 0;
+  plan->mode_count[0] = plan->mode_count[1] = plan->mode_count[2] = 0;
+}
+
+// Union gathers: blocks [0, r) copy the union columns of the rows of X;
+// the remaining blocks transpose 64 x 64 tiles of A's union columns into
+// the row-major Qc.
+constexpr int kGT = 64;
+__global__ __launch_bounds__(256) void union_gather_kernel(
+    const float* __restrict__ X, int64_t ldx, int64_t r,
+    const float* __restrict__ A, int64_t lda, int64_t n,
+    const int32_t* __restrict__ ulist, const Plan* plan, float* __restrict__ Xc,
+    int64_t ldxc, float* __restrict__ Qc, int64_t ldqc) {
+  __shared__ float tile[kGT][kGT + 1];
+  if (plan->mode != kAxUnion) return;
+  const int u = plan->union_size;
+  if ((int64_t)blockIdx.x < r) {
+    const int64_t j = blockIdx.x;
+    for (int c = threadIdx.x; c < u; c += 256) Xc[j * ldxc + c] = X[j * ldx + ulist[c]];
+    return;
+  }
+  const int64_t tiles_i = ceil_div(n, kGT);
+  const int64_t tiles = tiles_i * ceil_div(u, kGT);
+  const int tx = threadIdx.x % kGT, ty = threadIdx.x / kGT;  // ty in 0..3
+  for (int64_t t = (int64_t)blockIdx.x - r; t < tiles; t += (int64_t)gridDim.x - r) {
+    const int64_t i0 = (t % tiles_i) * kGT;
+    const int64_t c0 = (t / tiles_i) * kGT;
+    __syncthreads();
+    for (int cc = ty; cc < kGT; cc += 4) {
+      const int64_t c = c0 + cc, i = i0 + tx;
+      tile[cc][tx] = (c < u && i < n) ? A[i + (int64_t)ulist[c] * lda] : 0.f;
+    }
+    __syncthreads();
+    for (int ii = ty; ii < kGT; ii += 4) {
+      const int64_t i = i0 + ii, c = c0 + tx;
+      if (i < n && c < u) Qc[i * ldqc + c] = tile[tx][ii];
+    }
   }
 }
 
@@ -175,11 +283,11 @@ __global__ __launch_bounds__(1024) void plan_kernel(StartState s, int64_t r,
 
 template <bool L1VAR>
 __global__ __launch_bounds__(256) void y_update_kernel(
-    const float* __restrict__ U, int splits, int64_t split_stride,
-    float* __restrict__ Y, int64_t ldu, int64_t n, StartState s,
-    const Plan* plan) {
+    const float* __restrict__ U, int64_t split_stride, float* __restrict__ Y,
+    int64_t ldu, int64_t n, StartState s, const Plan* plan) {
   __shared__ double red[8];
-  if (plan->sparse) return;
+  if (plan->mode == kAxList) return;
+  const int splits = plan->ax_splits;
   const int64_t j = blockIdx.x;
   if (s.status[j] != kRunning) return;
   const float* u = U + j * ldu;
@@ -207,60 +315,116 @@ __global__ __launch_bounds__(256) void y_update_kernel(
 }
 
 // Sparse A x (x given by its list) fused with the y-update; one block per
-// start, rows of A strided over the threads so that every term reads a
-// contiguous run of a column.  FP64 accumulation.
+// start.  Thread t owns groups of 4 consecutive rows (one 16-byte load per
+// list entry and group), so a column of A is read with 16-byte loads; list
+// entries are taken four at a time so that 4 R independent loads are in
+// flight.  FP64 accumulation.  Needs lda % 4 == 0 and a 16-byte aligned A.
 constexpr int kSpThreads = 256;
-constexpr int kSpRows = 8;      // rows per thread per sweep of the list
 constexpr int kSpStage = 256;   // list entries staged in LDS at a time
+typedef float floatx4_t __attribute__((ext_vector_type(4)));
 
-template <bool L1VAR>
+template <bool L1VAR, int R>
 __global__ __launch_bounds__(kSpThreads) void sparse_ax_y_kernel(
     const float* __restrict__ A, int64_t lda, int64_t n,
     const int32_t* __restrict__ list_idx, const float* __restrict__ list_val,
     int64_t ldl, float* __restrict__ Y, int64_t ldu, StartState s,
     const Plan* plan) {
   __shared__ int32_t sidx[kSpStage];
-  __shared__ float sval[kSpStage];
+  __shared__ double sval[kSpStage];
   __shared__ double red[8];
-  if (!plan->sparse) return;
+  if (plan->mode != kAxList) return;
   const int64_t j = blockIdx.x;
   if (s.status[j] != kRunning) return;
   const int32_t cnt = s.nnz[j];
   const int32_t* li = list_idx + j * ldl;
   const float* lv = list_val + j * ldl;
   float* y = Y + j * ldu;
+  const int64_t groups = ceil_div(n, 4);
 
   double sq = 0.0;
-  for (int64_t base = 0; base < n; base += (int64_t)kSpThreads * kSpRows) {
-    double acc[kSpRows];
+  for (int64_t gbase = 0; gbase < groups; gbase += (int64_t)kSpThreads * R) {
+    double acc[R][4];
+    int64_t g[R];
+    bool ok[R];
 #pragma unroll
-    for (int q = 0; q < kSpRows; ++q) acc[q] = 0.0;
+    for (int q = 0; q < R; ++q) {
+      g[q] = gbase + q * kSpThreads + threadIdx.x;
+      ok[q] = g[q] < groups;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) acc[q][e] = 0.0;
+    }
     for (int32_t t0 = 0; t0 < cnt; t0 += kSpStage) {
       const int32_t m = cnt - t0 < kSpStage ? cnt - t0 : kSpStage;
       __syncthreads();
       if (threadIdx.x < m) {
         sidx[threadIdx.x] = li[t0 + threadIdx.x];
-        sval[threadIdx.x] = lv[t0 + threadIdx.x];
+        sval[threadIdx.x] = (double)lv[t0 + threadIdx.x];
       }
       __syncthreads();
-      for (int32_t t = 0; t < m; ++t) {
-        const float* col = A + (int64_t)sidx[t] * lda;
-        const double xv = sval[t];
+      int32_t t = 0;
+      for (; t + 4 <= m; t += 4) {
+        const float* c[4];
+        double xv[4];
 #pragma unroll
-        for (int q = 0; q < kSpRows; ++q) {
-          int64_t i = base + q * kSpThreads + threadIdx.x;
-          if (i < n) acc[q] += (double)col[i] * xv;
+        for (int e = 0; e < 4; ++e) {
+          c[e] = A + (int64_t)sidx[t + e] * lda;
+          xv[e] = sval[t + e];
+        }
+        floatx4_t a[4][R];
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+#pragma unroll
+          for (int q = 0; q < R; ++q) {
+            if (ok[q]) {
+              const int64_t row = 4 * g[q];
+              if (row + 3 < n) {
+                a[e][q] = *reinterpret_cast<const floatx4_t*>(c[e] + row);
+              } else {
+                floatx4_t z = {0.f, 0.f, 0.f, 0.f};
+                if (row < n) z.x = c[e][row];
+                if (row + 1 < n) z.y = c[e][row + 1];
+                if (row + 2 < n) z.z = c[e][row + 2];
+                a[e][q] = z;
+              }
+            } else {
+              a[e][q] = floatx4_t{0.f, 0.f, 0.f, 0.f};
+            }
+          }
+#pragma unroll
+        for (int q = 0; q < R; ++q)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            acc[q][0] += (double)a[e][q].x * xv[e];
+            acc[q][1] += (double)a[e][q].y * xv[e];
+            acc[q][2] += (double)a[e][q].z * xv[e];
+            acc[q][3] += (double)a[e][q].w * xv[e];
+          }
+      }
+      for (; t < m; ++t) {
+        const float* c0 = A + (int64_t)sidx[t] * lda;
+        const double x0 = sval[t];
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+          if (!ok[q]) continue;
+          const int64_t row = 4 * g[q];
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            if (row + e < n) acc[q][e] += (double)c0[row + e] * x0;
         }
       }
     }
 #pragma unroll
-    for (int q = 0; q < kSpRows; ++q) {
-      int64_t i = base + q * kSpThreads + threadIdx.x;
-      if (i < n) {
-        float u = (float)acc[q];
-        y[i] = u;  // u for now; scaled below once ||u|| is known
-        double uu = u;
-        sq += uu * uu;
+    for (int q = 0; q < R; ++q) {
+      if (!ok[q]) continue;
+      const int64_t row = 4 * g[q];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        if (row + e < n) {
+          float u = (float)acc[q][e];
+          y[row + e] = u;  // u for now; scaled below once ||u|| is known
+          double uu = u;
+          sq += uu * uu;
+        }
       }
     }
   }
@@ -271,16 +435,33 @@ __global__ __launch_bounds__(kSpThreads) void sparse_ax_y_kernel(
   }
   const double inv = 1.0 / sqrt(sq);
   // each thread rescales exactly the entries it wrote
-  for (int64_t base = 0; base < n; base += (int64_t)kSpThreads * kSpRows) {
+  for (int64_t gbase = 0; gbase < groups; gbase += (int64_t)kSpThreads * R) {
 #pragma unroll
-    for (int q = 0; q < kSpRows; ++q) {
-      int64_t i = base + q * kSpThreads + threadIdx.x;
-      if (i < n) {
-        float t = y[i];
-        y[i] = L1VAR ? (float)((t > 0.f) - (t < 0.f)) : (float)((double)t * inv);
+    for (int q = 0; q < R; ++q) {
+      const int64_t gq = gbase + q * kSpThreads + threadIdx.x;
+      if (gq >= groups) continue;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t i = 4 * gq + e;
+        if (i < n) {
+          float t = y[i];
+          y[i] = L1VAR ? (float)((t > 0.f) - (t < 0.f)) : (float)((double)t * inv);
+        }
       }
     }
   }
+}
+
+template <bool L1VAR>
+void launch_sparse(hipStream_t st, const float* A, int64_t lda, int64_t n,
+                   const int32_t* li, const float* lv, int64_t ldl, float* Y,
+                   int64_t ldu, int64_t r, StartState s, const Plan* plan) {
+  const int64_t per = ceil_div(ceil_div(n, 4), kSpThreads);
+  dim3 g((unsigned)r), b(kSpThreads);
+  if (per <= 1)
+    hipLaunchKernelGGL((sparse_ax_y_kernel<L1VAR, 1>), g, b, 0, st, A, lda, n, li, lv, ldl, Y, ldu, s, plan);
+  else
+    hipLaunchKernelGGL((sparse_ax_y_kernel<L1VAR, 2>), g, b, 0, st, A, lda, n, li, lv, ldl, Y, ldu, s, plan);
 }
 
 }  // namespace
@@ -318,9 +499,11 @@ void max_norm_column_start(hipStream_t st, const float* A, int64_t lda,
 
 void compact_rows(hipStream_t st, const float* X, int64_t ldx, int64_t r,
                   int64_t p, int32_t* list_idx, float* list_val, int64_t ldl,
-                  int32_t* nnz, const int32_t* status) {
+                  int32_t* nnz, const int32_t* status, int32_t* colmark,
+                  const Plan* plan) {
   hipLaunchKernelGGL(compact_rows_kernel, dim3((unsigned)r), dim3(1024), 0, st,
-                     X, ldx, p, list_idx, list_val, ldl, nnz, status);
+                     X, ldx, p, list_idx, list_val, ldl, nnz, status, colmark,
+                     plan);
 }
 
 void init_state(hipStream_t st, StartState s, int64_t r) {
@@ -328,21 +511,37 @@ void init_state(hipStream_t st, StartState s, int64_t r) {
                      dim3(256), 0, st, s, r);
 }
 
-void plan_next(hipStream_t st, StartState s, int64_t r, int64_t p,
-               double sparse_fraction, int dense_only, Plan* plan) {
-  hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(1024), 0, st, s, r, p,
-                     sparse_fraction, dense_only, plan);
+void plan_next(hipStream_t st, StartState s, int64_t r, int64_t n, int64_t p,
+               int list_cap, int dense_only, int dense_splits, int64_t ucap,
+               const int32_t* colmark, int32_t* ulist, Plan* plan) {
+  hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(1024), 0, st, s, r, n, p,
+                     list_cap, dense_only, dense_splits, ucap, colmark, ulist,
+                     plan);
 }
 
-void y_update(hipStream_t st, int fid, const float* U, int splits,
-              int64_t split_stride, float* Y, int64_t ldu, int64_t r,
-              int64_t n, StartState s, const Plan* plan) {
+void init_plan(hipStream_t st, Plan* plan, int dense_splits) {
+  hipLaunchKernelGGL(init_plan_kernel, dim3(1), dim3(1), 0, st, plan, dense_splits);
+}
+
+void union_gather(hipStream_t st, const float* X, int64_t ldx, int64_t r,
+                  const float* A, int64_t lda, int64_t n,
+                  const int32_t* ulist, const Plan* plan, float* Xc,
+                  int64_t ldxc, float* Qc, int64_t ldqc) {
+  const unsigned tile_blocks = 512;
+  hipLaunchKernelGGL(union_gather_kernel, dim3((unsigned)r + tile_blocks),
+                     dim3(256), 0, st, X, ldx, r, A, lda, n, ulist, plan, Xc,
+                     ldxc, Qc, ldqc);
+}
+
+void y_update(hipStream_t st, int fid, const float* U, int64_t split_stride,
+              float* Y, int64_t ldu, int64_t r, int64_t n, StartState s,
+              const Plan* plan) {
   if (l1_variance(fid))
     hipLaunchKernelGGL(y_update_kernel<true>, dim3((unsigned)r), dim3(256), 0,
-                       st, U, splits, split_stride, Y, ldu, n, s, plan);
+                       st, U, split_stride, Y, ldu, n, s, plan);
   else
     hipLaunchKernelGGL(y_update_kernel<false>, dim3((unsigned)r), dim3(256), 0,
-                       st, U, splits, split_stride, Y, ldu, n, s, plan);
+                       st, U, split_stride, Y, ldu, n, s, plan);
 }
 
 void sparse_ax_y_update(hipStream_t st, int fid, const float* A, int64_t lda,
@@ -350,13 +549,9 @@ void sparse_ax_y_update(hipStream_t st, int fid, const float* A, int64_t lda,
                         const float* list_val, int64_t ldl, float* Y,
                         int64_t ldu, int64_t r, StartState s, const Plan* plan) {
   if (l1_variance(fid))
-    hipLaunchKernelGGL(sparse_ax_y_kernel<true>, dim3((unsigned)r),
-                       dim3(kSpThreads), 0, st, A, lda, n, list_idx, list_val,
-                       ldl, Y, ldu, s, plan);
+    launch_sparse<true>(st, A, lda, n, list_idx, list_val, ldl, Y, ldu, r, s, plan);
   else
-    hipLaunchKernelGGL(sparse_ax_y_kernel<false>, dim3((unsigned)r),
-                       dim3(kSpThreads), 0, st, A, lda, n, list_idx, list_val,
-                       ldl, Y, ldu, s, plan);
+    launch_sparse<false>(st, A, lda, n, list_idx, list_val, ldl, Y, ldu, r, s, plan);
 }
 
 }  // namespace spca

@@ -25,12 +25,24 @@ struct StartState {
   int32_t* status;   // kRunning or a SPCA_* status
 };
 
-// Sparse-product mode word written by the planner: 1 = the next A x uses
-// the compacted lists, 0 = the dense MFMA product.
+// How the next product A x is formed (chosen on the device by the planner):
+//   kAxDense  MFMA GEMM over all p columns (split-K partials),
+//   kAxList   per-start sums over each start's (index, value) list,
+//   kAxUnion  MFMA GEMM over the union of the running starts' supports,
+//             with X and A gathered onto those columns.
+enum AxMode { kAxDense = 0, kAxList = 1, kAxUnion = 2 };
+
 struct Plan {
-  int32_t sparse;
+  int32_t mode;         // AxMode of the next A x
   int32_t active;       // starts still running
   int64_t total_nnz;    // sum of nnz over running starts
+  int32_t max_nnz;      // largest nnz over running starts
+  int32_t union_size;   // columns used by the running starts (kAxUnion's K)
+  int32_t epoch;        // column marks of the current x-update carry this
+  int32_t ax_splits;    // K partials the y-update sums (dense mode)
+  int32_t mark;         // the next x-update marks its columns
+  int32_t iter;         // planner calls so far
+  int32_t mode_count[3];  // iterations run in each mode (statistics)
 };
 
 // Tile shape (index into the compiled shapes) and K split of one product.
@@ -45,12 +57,14 @@ int gemm_num_shapes();
 
 // C (M x N, ldc) = P (M x K, ldp) * Q (N x K, ldq)^T, FP32 MFMA.  With
 // plan.splits > 1, K split s writes its partial product at
-// C + s * split_stride.  When gate != nullptr the kernel returns at once if
-// *gate == gate_skip.
+// C + s * split_stride.  When gate != nullptr the kernel runs only if
+// *gate == gate_run.  When kdev != nullptr, K is read from *kdev on the
+// device (plan.splits must then be 1).
 void gemm_nt_f32(hipStream_t st, const float* P, int64_t ldp, const float* Q,
                  int64_t ldq, float* C, int64_t ldc, int64_t M, int64_t N,
-                 int64_t K, const int32_t* gate, int32_t gate_skip,
-                 GemmPlan plan, int64_t split_stride);
+                 int64_t K, const int32_t* gate, int32_t gate_run,
+                 GemmPlan plan, int64_t split_stride,
+                 const int32_t* kdev = nullptr);
 
 // Row-major copy: At[i * ldat + k] = A[i + k * lda] (i < n, k < p).
 void transpose_f32(hipStream_t st, const float* A, int64_t lda, float* At,
@@ -71,40 +85,60 @@ void max_norm_column_start(hipStream_t st, const float* A, int64_t lda,
                            int64_t n, int64_t p, double* colsq, float* X,
                            int64_t ldx);
 
-// Builds the compacted (index, value) lists of the rows of X, nnz per row.
+// Builds the compacted (index, value) lists of the rows of X, nnz per row;
+// with colmark != nullptr also marks every used column with plan->epoch.
 void compact_rows(hipStream_t st, const float* X, int64_t ldx, int64_t r,
                   int64_t p, int32_t* list_idx, float* list_val, int64_t ldl,
-                  int32_t* nnz, const int32_t* status);
+                  int32_t* nnz, const int32_t* status, int32_t* colmark,
+                  const Plan* plan);
 
 // Resets the per-start state for a new solve.
 void init_state(hipStream_t st, StartState s, int64_t r);
 
-// Chooses the product mode for the next A x and counts running starts.
-void plan_next(hipStream_t st, StartState s, int64_t r, int64_t p,
-               double sparse_fraction, int dense_only, Plan* plan);
+// Counts the running starts, gathers the union of their supports (columns
+// marked with the current epoch) into ulist, and chooses the product mode
+// for the next A x from a cost model; the list mode needs every running
+// start to have at most list_cap nonzeros (only those keep lists).
+void plan_next(hipStream_t st, StartState s, int64_t r, int64_t n, int64_t p,
+               int list_cap, int dense_only, int dense_splits, int64_t ucap,
+               const int32_t* colmark, int32_t* ulist, Plan* plan);
 
-// y-update of Algorithm 2 from a dense U (r x n), given as `splits` partial
-// products split_stride floats apart that are summed in order: Y = sgn(U)
-// (L1 variance) or U / ||U||_2 per row (L2 variance); a zero row ends its
-// start as DEGENERATE.  Skipped when plan->sparse != 0.
-void y_update(hipStream_t st, int fid, const float* U, int splits,
-              int64_t split_stride, float* Y, int64_t ldu, int64_t r,
-              int64_t n, StartState s, const Plan* plan);
+// Resets the plan (epoch 1, dense mode, zero statistics).
+void init_plan(hipStream_t st, Plan* plan, int dense_splits);
+
+// For kAxUnion: Xc[j][c] = X[j][ulist[c]] (r x u) and Qc[i][c] =
+// A[i, ulist[c]] (n x u, row-major), u = plan->union_size.
+void union_gather(hipStream_t st, const float* X, int64_t ldx, int64_t r,
+                  const float* A, int64_t lda, int64_t n,
+                  const int32_t* ulist, const Plan* plan, float* Xc,
+                  int64_t ldxc, float* Qc, int64_t ldqc);
+
+// y-update of Algorithm 2 from a dense U (r x n), given as plan->ax_splits
+// partial products split_stride floats apart that are summed in order:
+// Y = sgn(U) (L1 variance) or U / ||U||_2 per row (L2 variance); a zero row
+// ends its start as DEGENERATE.  Skipped in list mode.
+void y_update(hipStream_t st, int fid, const float* U, int64_t split_stride,
+              float* Y, int64_t ldu, int64_t r, int64_t n, StartState s,
+              const Plan* plan);
 
 // Sparse A x from the lists followed by the y-update, one block per start.
-// Skipped when plan->sparse == 0.
+// Runs only in list mode.
 void sparse_ax_y_update(hipStream_t st, int fid, const float* A, int64_t lda,
                         int64_t n, const int32_t* list_idx,
                         const float* list_val, int64_t ldl, float* Y,
                         int64_t ldu, int64_t r, StartState s, const Plan* plan);
 
 // x-update of Algorithm 2 on the rows of V with the stop test of Section
-// 2.2.  When s.status is null every row is processed and no stop test or
+// 2.2.  Rows with at most list_cap nonzeros also get their (index, value)
+// list.  When s.status is null every row is processed and no stop test or
 // counters are touched (operator-only mode used by spca_x_update).
+// Every kept column of a processed row is marked colmark[i] = plan->epoch
+// (colmark may be null).
 void x_update(hipStream_t st, int fid, double s_or_gamma, const float* V,
               int64_t ldv, int64_t r, int64_t p, float* X, int64_t ldx,
-              int32_t* list_idx, float* list_val, int64_t ldl, StartState s,
-              double tol, int32_t maxit);
+              int32_t* list_idx, float* list_val, int64_t ldl, int list_cap,
+              StartState s, double tol, int32_t maxit, int32_t* colmark,
+              const Plan* plan);
 
 // FP64 finalisation: per start, x64 = x / ||x||_2 from the lists, f(x64)
 // of Table 1 and the explained variance; then the best start.

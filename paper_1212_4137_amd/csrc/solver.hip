@@ -28,7 +28,13 @@ const char* last_error() { return g_last_error.c_str(); }
 
 namespace {
 
-constexpr double kSparseFraction = 0.04;  // list product when nnz <= 4% dense
+// The list-based A x is possible when every running start has at most
+// max(32, p / 8) nonzeros; only those starts keep (index, value) lists.
+constexpr double kSparseFraction = 0.125;
+inline int list_cap_of(int64_t p) {
+  int64_t c = (int64_t)(kSparseFraction * (double)p);
+  return (int)(c < 32 ? (p < 32 ? p : 32) : c);
+}
 
 constexpr int kMaxSplits = 16;  // K splits of the dense A x product
 
@@ -40,6 +46,9 @@ struct Layout {
   size_t off_At, off_Ac, off_X, off_U, off_Y, off_V, off_li, off_lv;
   size_t off_phi, off_phip, off_nnz, off_it, off_st, off_plan, off_part,
       off_f, off_ev, off_xn, off_best, off_xout, off_sup, off_colsq, off_bad;
+  size_t off_mark, off_ulist, off_Xc, off_Qc;
+  int64_t ucap;  // largest support union the union product can hold
+  GemmPlan plan_union;
   size_t total;
   int nchunks;
 };
@@ -63,6 +72,11 @@ Layout make_layout(int64_t n, int64_t p, int64_t r, bool copy_a) {
   L.nchunks = (int)ceil_div(n, 256);
   L.plan_ax = plan_gemm_nt(r, n, p, kMaxSplits);   // U^T = X^T A^T, K = p
   L.plan_aty = plan_gemm_nt(r, p, n, 1);           // V^T = Y^T A,   K = n
+  // union product: K = u <= ucap columns, gathered A is n x ucap (<= 256 MB)
+  L.ucap = p;
+  const int64_t mem_cap = (int64_t)(64LL << 20) / (n > 0 ? n : 1);
+  if (L.ucap > mem_cap) L.ucap = mem_cap < 1024 ? (p < 1024 ? p : 1024) : mem_cap;
+  L.plan_union = plan_gemm_nt(r, n, L.ucap < 256 ? L.ucap : 256, 1);
   size_t c = 0;
   L.off_At = carve(&c, sizeof(float) * (size_t)n * L.ldat);
   L.off_Ac = carve(&c, copy_a ? sizeof(float) * (size_t)p * L.ldac : 0);
@@ -87,6 +101,10 @@ Layout make_layout(int64_t n, int64_t p, int64_t r, bool copy_a) {
   L.off_sup = carve(&c, sizeof(int32_t) * p);
   L.off_colsq = carve(&c, sizeof(double) * p);
   L.off_bad = carve(&c, sizeof(int32_t));
+  L.off_mark = carve(&c, sizeof(int32_t) * p);
+  L.off_ulist = carve(&c, sizeof(int32_t) * p);
+  L.off_Xc = carve(&c, sizeof(float) * (size_t)r * round_up(L.ucap, 4));
+  L.off_Qc = carve(&c, sizeof(float) * (size_t)n * round_up(L.ucap, 4));
   L.total = c;
   return L;
 }
@@ -297,6 +315,11 @@ int spca_am_solve_ex(spca_ctx* ctx, void* stream, const spca_problem* prob,
   int32_t* sup = (int32_t*)(base + L.off_sup);
   double* colsq = (double*)(base + L.off_colsq);
   int32_t* bad = (int32_t*)(base + L.off_bad);
+  int32_t* colmark = (int32_t*)(base + L.off_mark);
+  int32_t* ulist = (int32_t*)(base + L.off_ulist);
+  float* Xc = (float*)(base + L.off_Xc);
+  float* Qc = (float*)(base + L.off_Qc);
+  const int64_t ldc_u = round_up(L.ucap, 4);
 
   // a0: stage A (aligned column-major copy only when needed) and its
   // row-major twin used by the dense A x.
@@ -328,9 +351,18 @@ int spca_am_solve_ex(spca_ctx* ctx, void* stream, const spca_problem* prob,
     max_norm_column_start(st, A, ldA, n, p, colsq, X, L.ldx);
   }
   init_state(st, s, r);
-  compact_rows(st, X, L.ldx, r, p, li, lv, L.ldx, s.nnz, s.status);
+  init_plan(st, plan, L.plan_ax.splits);
+  SPCA_HIP_TRY(hipMemsetAsync(colmark, 0, sizeof(int32_t) * p, st));
+  compact_rows(st, X, L.ldx, r, p, li, lv, L.ldx, s.nnz, s.status, colmark, plan);
   const int dense_only = (opts->flags & SPCA_FLAG_DENSE_ONLY) ? 1 : 0;
-  plan_next(st, s, r, p, kSparseFraction, dense_only, plan);
+  const int list_cap = list_cap_of(p);
+  // the union product is offered only while the union fits its buffers
+  // (at most ucap columns)
+  auto plan_iter = [&]() {
+    plan_next(st, s, r, n, p, list_cap, dense_only, L.plan_ax.splits, L.ucap,
+              colmark, ulist, plan);
+  };
+  plan_iter();
   SPCA_LAUNCH_CHECK("staging");
 
   const int32_t maxit = opts->maxit;
@@ -341,10 +373,13 @@ int spca_am_solve_ex(spca_ctx* ctx, void* stream, const spca_problem* prob,
   for (int32_t it = 0; it < maxit; ++it) {
     // u = A x and the y-update
     if (timed) SPCA_HIP_TRY(ctx->t_ax.mark(st));
-    gemm_nt_f32(st, X, L.ldx, At, L.ldat, U, L.ldu, r, n, p, &plan->sparse, 1,
-                L.plan_ax, r * L.ldu);
+    gemm_nt_f32(st, X, L.ldx, At, L.ldat, U, L.ldu, r, n, p, &plan->mode,
+                kAxDense, L.plan_ax, r * L.ldu);
     if (timed) SPCA_HIP_TRY(ctx->t_ax.mark(st));
-    y_update(st, fid, U, L.plan_ax.splits, r * L.ldu, Y, L.ldu, r, n, s, plan);
+    union_gather(st, X, L.ldx, r, A, ldA, n, ulist, plan, Xc, ldc_u, Qc, ldc_u);
+    gemm_nt_f32(st, Xc, ldc_u, Qc, ldc_u, U, L.ldu, r, n, L.ucap, &plan->mode,
+                kAxUnion, L.plan_union, 0, &plan->union_size);
+    y_update(st, fid, U, r * L.ldu, Y, L.ldu, r, n, s, plan);
     sparse_ax_y_update(st, fid, A, ldA, n, li, lv, L.ldx, Y, L.ldu, r, s, plan);
     // v = A^T y and the x-update with the stop test
     if (timed) SPCA_HIP_TRY(ctx->t_aty.mark(st));
@@ -352,10 +387,10 @@ int spca_am_solve_ex(spca_ctx* ctx, void* stream, const spca_problem* prob,
                 L.plan_aty, 0);
     if (timed) SPCA_HIP_TRY(ctx->t_aty.mark(st));
     if (timed) SPCA_HIP_TRY(ctx->t_xup.mark(st));
-    x_update(st, fid, sg, V, L.ldx, r, p, X, L.ldx, li, lv, L.ldx, s,
-             opts->tol, maxit);
+    x_update(st, fid, sg, V, L.ldx, r, p, X, L.ldx, li, lv, L.ldx, list_cap, s,
+             opts->tol, maxit, colmark, plan);
     if (timed) SPCA_HIP_TRY(ctx->t_xup.mark(st));
-    plan_next(st, s, r, p, kSparseFraction, dense_only, plan);
+    plan_iter();
     SPCA_LAUNCH_CHECK("AM iteration");
     if ((it + 1) % opts->check_every == 0 && it + 1 < maxit) {
       SPCA_HIP_TRY(hipMemcpyAsync(ctx->host_poll, &plan->active, sizeof(int32_t),
@@ -365,13 +400,17 @@ int spca_am_solve_ex(spca_ctx* ctx, void* stream, const spca_problem* prob,
     }
   }
 
-  // a6: FP64 objective, explained variance, best start, output vector
+  // a6: FP64 objective, explained variance, best start, output vector; the
+  // lists are rebuilt from the final dense iterates (dense starts keep none)
+  compact_rows(st, X, L.ldx, r, p, li, lv, L.ldx, s.nnz, nullptr, nullptr, nullptr);
   finalize(st, fid, sg, A, ldA, n, p, li, lv, L.ldx, s, r, partial, fj, evj,
            xnorm, best, xout, sup);
   SPCA_LAUNCH_CHECK("finalize");
 
   int32_t hb[2];
+  Plan hplan;
   SPCA_HIP_TRY(hipMemcpyAsync(hb, best, sizeof(hb), hipMemcpyDeviceToHost, st));
+  SPCA_HIP_TRY(hipMemcpyAsync(&hplan, plan, sizeof(Plan), hipMemcpyDeviceToHost, st));
   SPCA_HIP_TRY(hipStreamSynchronize(st));
   const int32_t jb = hb[0], nnzb = hb[1];
   std::vector<double> f_all(r), ev_all(r), phi_all(r);
@@ -408,6 +447,9 @@ int spca_am_solve_ex(spca_ctx* ctx, void* stream, const spca_problem* prob,
     kt[3] = (double)(ctx->t_xup.used / 2);
     SPCA_HIP_TRY(ctx->t_ax.total_ms(&kt[4]));
     kt[5] = (double)(ctx->t_ax.used / 2);
+    kt[6] = hplan.mode_count[kAxDense];
+    kt[7] = hplan.mode_count[kAxList];
+    kt[8] = hplan.mode_count[kAxUnion];
   }
   double total_iters = 0.0;
   for (int64_t j = 0; j < r; ++j) total_iters += it_all[j];
@@ -522,7 +564,7 @@ int spca_x_update(void* stream, int formulation, const float* V, int64_t ldv,
   SPCA_REQUIRE(ldv >= p && ldx >= p, "leading dimensions too small");
   StartState s{phi, nullptr, nnz, nullptr, nullptr};
   x_update((hipStream_t)stream, formulation, s_or_gamma, V, ldv, r, p, X, ldx,
-           nullptr, nullptr, 0, s, -1.0, 1);
+           nullptr, nullptr, 0, 0, s, -1.0, 1, nullptr, nullptr);
   SPCA_LAUNCH_CHECK("x_update");
   return SPCA_OK;
 }

@@ -6,17 +6,25 @@
 //   L1 penalty     x = V_g(v) / ||V_g(v)||             phi = ||V_g(v)||
 // followed by the ratio stop test of Section 2.2.
 //
-// Selection without sorting.  The bit pattern of a non-negative float is
-// monotone in its value, so thresholds are searched over the 31-bit keys of
-// |v_i|.  Each step tests kNC thresholds at once with one deterministic
-// block reduction (an 8-ary search, 11 steps for 31 bits):
+// Selection without a full sort.  The bit pattern of a non-negative float
+// is monotone in its value, so thresholds are searched over the 31-bit keys
+// of |v_i|.  Counting searches test kNC thresholds per step with wave
+// ballots (one compare and one scalar popcount per element and threshold),
+// a 16-ary search that needs 8 steps for 31 bits.
 //   T_s       largest key t with #{key >= t} >= s; ties at that key go to the
 //             lowest indices (a block-wide prefix count finds the cut index).
 //   lambda_s  the derivative of l sqrt(s) + ||V_l(v)|| is sqrt(s) - rho(l)
-//             with rho = ||V_l||_1 / ||V_l||_2 non-increasing, so the search
-//             finds the float interval [t, t+) holding the root; on it the
-//             active set is fixed and the root has the closed form
-//             l = (S1 - sqrt(s (k S2 - S1^2) / (k - s))) / k.
+//             with rho = ||V_l||_1 / ||V_l||_2 non-increasing, so lambda = 0
+//             when rho(0) <= sqrt(s), and otherwise the root lies in the
+//             first segment [c_{k+1}, c_k] (k > s, c sorted descending) whose
+//             lower end already has rho >= sqrt(s), with the closed form
+//             l = (S1_k - sqrt(s (k S2_k - S1_k^2) / (k - s))) / k.
+//             Fast path: the M largest |v_i| (M from the previous support
+//             size) are gathered, sorted in LDS and scanned for that segment,
+//             after checking rho >= sqrt(s) at their smallest key (so the
+//             root cannot lie below them).  Otherwise a search over keys with
+//             FP64 sums of (|v| - t)_+ and its square finds the float interval
+//             holding the root, on which the active set is fixed.
 // Comparisons that decide membership use FP64 on the FP32 inputs (squares
 // and differences of floats are exact or correctly rounded there).
 #include "../../include/spca.h"
@@ -28,7 +36,9 @@ namespace {
 
 constexpr int kXT = 1024;  // threads per start
 constexpr int kNW = kXT / kWave;
-constexpr int kNC = 7;     // thresholds per search step
+constexpr int kNC = 15;    // thresholds per counting step (ballots)
+constexpr int kNCd = 7;    // thresholds per FP64 search step
+constexpr int kMaxCand = 2048;        // lambda_s candidates sorted in LDS
 constexpr int64_t kStageMax = 12288;  // p staged in LDS up to this size
 
 __device__ __forceinline__ uint32_t key_of(float v) {
@@ -36,25 +46,151 @@ __device__ __forceinline__ uint32_t key_of(float v) {
 }
 
 struct XSmem {
-  double dred[2 * kNC * (kNW + 1)];
+  double dred[2 * kNCd * (kNW + 1)];
   int32_t ired[kNC * (kNW + 1)];
   uint32_t ured[kNW + 1];
   int scan[kNW + 1];
-  int64_t cut;  // last index kept among the ties (T_s)
+  double dscan[2 * (kNW + 1)];
+  float cand[kMaxCand];
+  int ncand;
+  int kbest;
+  int64_t cut;
+  double seg[4];  // S1, S2, lower end, upper end of the chosen segment
 };
+
+// Thresholds strictly inside (lo, hi), spread evenly; unused slots get hi.
+template <int NC>
+__device__ __forceinline__ void spread(uint32_t lo, uint32_t hi, uint32_t (&t)[NC]) {
+  const uint32_t span = hi - lo;
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    uint32_t d = span > NC + 1
+                     ? (uint32_t)(((uint64_t)span * (uint64_t)(c + 1)) / (NC + 1))
+                     : (uint32_t)(c + 1);
+    t[c] = d < span ? lo + d : hi;
+  }
+}
+
+// #{i : key_i >= t} for kNC thresholds, every thread gets the totals.
+template <typename ValF>
+__device__ __forceinline__ void count_ge(ValF val, int p, const uint32_t (&t)[kNC],
+                                         int (&cnt)[kNC], int32_t* ired) {
+  const int lane = threadIdx.x % kWave;
+  const int wave = threadIdx.x / kWave;
+#pragma unroll
+  for (int c = 0; c < kNC; ++c) cnt[c] = 0;
+  for (int base = wave * kWave; base < p; base += kXT) {
+    const int i = base + lane;
+    const uint32_t k = i < p ? key_of(val(i)) : 0u;
+#pragma unroll
+    for (int c = 0; c < kNC; ++c) cnt[c] += __popcll(__ballot(k >= t[c]));
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int c = 0; c < kNC; ++c) ired[wave * kNC + c] = cnt[c];
+  }
+  __syncthreads();
+  if (threadIdx.x < kNC) {
+    int a = 0;
+    for (int w = 0; w < kNW; ++w) a += ired[w * kNC + threadIdx.x];
+    ired[kNW * kNC + threadIdx.x] = a;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < kNC; ++c) cnt[c] = ired[kNW * kNC + c];
+  __syncthreads();
+}
+
+// Largest key t in [lo, hi) with #{key >= t} >= need, given that this holds
+// at lo and fails at hi.
+template <typename ValF>
+__device__ uint32_t search_count(ValF val, int p, uint32_t lo, uint32_t hi,
+                                 int64_t need, int32_t* ired) {
+  while (hi - lo > 1) {
+    uint32_t t[kNC];
+    spread<kNC>(lo, hi, t);
+    int cnt[kNC];
+    count_ge(val, p, t, cnt, ired);
+    uint32_t nlo = lo, nhi = hi;
+#pragma unroll
+    for (int c = 0; c < kNC; ++c) {
+      if (t[c] >= hi) continue;
+      if (cnt[c] >= need)
+        nlo = t[c] > nlo ? t[c] : nlo;
+      else
+        nhi = t[c] < nhi ? t[c] : nhi;
+    }
+    lo = nlo;
+    hi = nhi;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ int count_ge1(uint32_t t, int p, const float* vs,
+                                         const float* vg, bool staged,
+                                         int32_t* ired) {
+  uint32_t tt[kNC];
+#pragma unroll
+  for (int c = 0; c < kNC; ++c) tt[c] = t;
+  int cnt[kNC];
+  auto val = [&](int i) -> float { return staged ? vs[i] : vg[i]; };
+  count_ge(val, p, tt, cnt, ired);
+  return cnt[0];
+}
+
+// Exclusive prefix sums of two doubles per thread in thread order.
+__device__ __forceinline__ void block_exclusive_scan2(double (&v)[2], double* scratch,
+                                                     double (&total)[2]) {
+  const int lane = threadIdx.x % kWave;
+  const int wave = threadIdx.x / kWave;
+  double inc[2] = {v[0], v[1]};
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      double o = __shfl_up(inc[c], off, kWave);
+      if (lane >= off) inc[c] += o;
+    }
+  }
+  if (lane == kWave - 1) {
+    scratch[2 * wave] = inc[0];
+    scratch[2 * wave + 1] = inc[1];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r0 = 0.0, r1 = 0.0;
+    for (int w = 0; w < kNW; ++w) {
+      double a = scratch[2 * w], b = scratch[2 * w + 1];
+      scratch[2 * w] = r0;
+      scratch[2 * w + 1] = r1;
+      r0 += a;
+      r1 += b;
+    }
+    scratch[2 * kNW] = r0;
+    scratch[2 * kNW + 1] = r1;
+  }
+  __syncthreads();
+  const double b0 = scratch[2 * wave], b1 = scratch[2 * wave + 1];
+  total[0] = scratch[2 * kNW];
+  total[1] = scratch[2 * kNW + 1];
+  v[0] = b0 + inc[0] - v[0];
+  v[1] = b1 + inc[1] - v[1];
+  __syncthreads();
+}
 
 template <int KIND, bool STAGED>
 __global__ __launch_bounds__(kXT) void x_update_kernel(
     const float* __restrict__ V, int64_t ldv, int p, double param,
     float* __restrict__ X, int64_t ldx, int32_t* __restrict__ list_idx,
-    float* __restrict__ list_val, int64_t ldl, StartState s, double tol,
-    int maxit) {
+    float* __restrict__ list_val, int64_t ldl, int list_cap, StartState s,
+    double tol, int maxit, int32_t* __restrict__ colmark, const Plan* plan) {
   extern __shared__ __attribute__((aligned(16))) float vstage[];
   __shared__ XSmem sm;
   const int64_t j = blockIdx.x;
   const bool full = s.status != nullptr;
   if (full && s.status[j] != kRunning) return;
   const int tid = threadIdx.x;
+  const int lane = tid % kWave;
   const float* vg = V + j * ldv;
   if (STAGED) {
     for (int i = tid; i < p; i += kXT) vstage[i] = vg[i];
@@ -79,53 +215,15 @@ __global__ __launch_bounds__(kXT) void x_update_kernel(
     mk = block_max(mk, sm.ured);
     const double s_par = param;
     const double rs = sqrt(s_par);
-    bool search = true;
-    uint32_t lo = 0, hi = mk + 1;
     if (KIND == kTopS) {
       const int64_t s_int = (int64_t)s_par < (int64_t)p ? (int64_t)s_par : (int64_t)p;
-      // pred(t) = #{key >= t} >= s ; pred(0) holds, pred(mk + 1) fails
-      while (hi - lo > 1) {
-        uint32_t t[kNC];
-        const uint32_t span = hi - lo;
-#pragma unroll
-        for (int c = 0; c < kNC; ++c) {
-          uint32_t d = span > kNC + 1
-                           ? (uint32_t)(((uint64_t)span * (uint64_t)(c + 1)) / (kNC + 1))
-                           : (uint32_t)(c + 1);
-          t[c] = d < span ? lo + d : hi;
-        }
-        int cnt[kNC];
-#pragma unroll
-        for (int c = 0; c < kNC; ++c) cnt[c] = 0;
-        for (int i = tid; i < p; i += kXT) {
-          uint32_t k = key_of(val(i));
-#pragma unroll
-          for (int c = 0; c < kNC; ++c) cnt[c] += k >= t[c];
-        }
-        block_sum_n<int, kNC>(cnt, sm.ired);
-        uint32_t nlo = lo, nhi = hi;
-#pragma unroll
-        for (int c = 0; c < kNC; ++c) {
-          if (t[c] >= hi) continue;
-          if (cnt[c] >= s_int) {
-            nlo = t[c] > nlo ? t[c] : nlo;
-          } else {
-            nhi = t[c] < nhi ? t[c] : nhi;
-          }
-        }
-        lo = nlo;
-        hi = nhi;
-      }
-      thr_key = lo;
+      // #{key >= 0} = p >= s and #{key >= mk + 1} = 0 < s
+      thr_key = search_count(val, p, 0u, mk + 1, s_int, sm.ired);
       // ties at thr_key: keep the first (s - #{key > thr_key}) in index order
       if (tid == 0) sm.cut = -1;
-      int gt = 0, eq = 0;
-      for (int i = tid; i < p; i += kXT) {
-        uint32_t k = key_of(val(i));
-        gt += k > thr_key;
-      }
+      const int gt = count_ge1(thr_key + 1, p, vstage, vg, STAGED, sm.ired);
+      int eq = 0;
       for (int i = cb; i < ce; ++i) eq += key_of(val(i)) == thr_key;
-      gt = block_sum(gt, sm.ired);
       int eq_total;
       int eq_off = block_exclusive_scan(eq, sm.scan, &eq_total);
       const int need = (int)s_int - gt;  // >= 1
@@ -143,7 +241,6 @@ __global__ __launch_bounds__(kXT) void x_update_kernel(
       }
       __syncthreads();
       cut = sm.cut;
-      search = false;
     }
     if (KIND == kLambdaS) {
       // constraint inactive when ||v||_1 <= sqrt(s) ||v||_2: lambda = 0
@@ -154,51 +251,159 @@ __global__ __launch_bounds__(kXT) void x_update_kernel(
         a0[1] += a * a;
       }
       block_sum_n<double, 2>(a0, sm.dred);
-      search = a0[0] > rs * sqrt(a0[1]);
-      if (!search) lam = 0.0;
-      hi = mk;  // no entry exceeds max |v|: rho undefined, pred false
-      while (search && hi - lo > 1) {
-        uint32_t t[kNC];
-        const uint32_t span = hi - lo;
-#pragma unroll
-        for (int c = 0; c < kNC; ++c) {
-          uint32_t d = span > kNC + 1
-                           ? (uint32_t)(((uint64_t)span * (uint64_t)(c + 1)) / (kNC + 1))
-                           : (uint32_t)(c + 1);
-          t[c] = d < span ? lo + d : hi;
-        }
-        double acc[2 * kNC];
-#pragma unroll
-        for (int c = 0; c < 2 * kNC; ++c) acc[c] = 0.0;
-        double tf[kNC];
-#pragma unroll
-        for (int c = 0; c < kNC; ++c) tf[c] = (double)__uint_as_float(t[c]);
+      const bool active = a0[0] > rs * sqrt(a0[1]);
+      bool done = !active;
+      if (active) {
+        // ---- fast path: the M largest entries ----
+        int64_t m0 = full ? 2 * (int64_t)s.nnz[j] + 32 : 4 * (int64_t)ceil(s_par) + 64;
+        const int64_t smin = (int64_t)floor(s_par) + 2;
+        m0 = m0 < smin ? smin : m0;
+        m0 = m0 > kMaxCand ? kMaxCand : m0;
+        m0 = m0 > p ? p : m0;
+        uint32_t t0 = search_count(val, p, 0u, mk + 1, m0, sm.ired);
+        t0 = t0 < 1u ? 1u : t0;  // zeros never enter
+        const double t0f = (double)__uint_as_float(t0);
+        double a1[2] = {0.0, 0.0};
+        int mine = 0;
         for (int i = tid; i < p; i += kXT) {
           double a = fabs((double)val(i));
-#pragma unroll
-          for (int c = 0; c < kNC; ++c) {
-            double d = a - tf[c];
-            d = d > 0.0 ? d : 0.0;
-            acc[2 * c] += d;
-            acc[2 * c + 1] += d * d;
-          }
+          if (key_of(val(i)) >= t0) ++mine;
+          double d = a - t0f;
+          d = d > 0.0 ? d : 0.0;
+          a1[0] += d;
+          a1[1] += d * d;
         }
-        block_sum_n<double, 2 * kNC>(acc, sm.dred);
-        uint32_t nlo = lo, nhi = hi;
-#pragma unroll
-        for (int c = 0; c < kNC; ++c) {
-          if (t[c] >= hi) continue;
-          bool pred = acc[2 * c + 1] > 0.0 && acc[2 * c] >= rs * sqrt(acc[2 * c + 1]);
-          if (pred) {
-            nlo = t[c] > nlo ? t[c] : nlo;
-          } else {
-            nhi = t[c] < nhi ? t[c] : nhi;
+        block_sum_n<double, 2>(a1, sm.dred);
+        const int ncand = block_sum(mine, sm.ired);
+        // rho(t0) >= sqrt(s): the root is >= t0 and only candidates matter
+        const bool ok = ncand <= kMaxCand && a1[1] > 0.0 && a1[0] >= rs * sqrt(a1[1]);
+        if (ok) {
+          if (tid == 0) sm.ncand = 0;
+          __syncthreads();
+          for (int base = (tid / kWave) * kWave; base < p; base += kXT) {
+            const int i = base + lane;
+            const float v = i < p ? val(i) : 0.f;
+            const bool in = i < p && key_of(v) >= t0;
+            const unsigned long long mask = __ballot(in);
+            int wbase = 0;
+            if (lane == 0 && mask) wbase = atomicAdd(&sm.ncand, (int)__popcll(mask));
+            wbase = __shfl(wbase, 0, kWave);
+            if (in) {
+              const unsigned long long below = mask & ((1ull << lane) - 1ull);
+              sm.cand[wbase + __popcll(below)] = fabsf(v);
+            }
           }
+          __syncthreads();
+          int np2 = 2;
+          while (np2 < ncand) np2 <<= 1;
+          for (int i = ncand + tid; i < np2; i += kXT) sm.cand[i] = -1.f;
+          // bitonic sort, descending
+          for (int size = 2; size <= np2; size <<= 1) {
+            for (int stride = size >> 1; stride > 0; stride >>= 1) {
+              __syncthreads();
+              for (int t = tid; t < np2 / 2; t += kXT) {
+                const int pos = 2 * stride * (t / stride) + (t % stride);
+                const int partner = pos + stride;
+                const bool desc = (pos & size) == 0;
+                const float x0 = sm.cand[pos], x1 = sm.cand[partner];
+                if ((x0 < x1) == desc) {
+                  sm.cand[pos] = x1;
+                  sm.cand[partner] = x0;
+                }
+              }
+            }
+          }
+          __syncthreads();
+          // prefix sums of c and c^2; thread t owns sorted positions 2t, 2t+1
+          const int q0 = 2 * tid, q1 = 2 * tid + 1;
+          const double c0 = q0 < ncand ? (double)sm.cand[q0] : 0.0;
+          const double c1 = q1 < ncand ? (double)sm.cand[q1] : 0.0;
+          double pre[2] = {c0 + c1, c0 * c0 + c1 * c1};
+          double tot[2];
+          block_exclusive_scan2(pre, sm.dscan, tot);
+          if (tid == 0) sm.kbest = INT32_MAX;
+          __syncthreads();
+          double S1 = pre[0], S2 = pre[1];
+          int myk = INT32_MAX;
+          double seg[4] = {0, 0, 0, 0};
+          for (int e = 0; e < 2; ++e) {
+            const int q = q0 + e;
+            if (q >= ncand) break;
+            const double c = e == 0 ? c0 : c1;
+            S1 += c;
+            S2 += c * c;
+            const int k = q + 1;  // top-k prefix
+            if ((double)k <= s_par) continue;
+            const double lo = k < ncand ? (double)sm.cand[k] : t0f;
+            const double l1 = S1 - (double)k * lo;
+            const double l2 = S2 - 2.0 * lo * S1 + (double)k * lo * lo;
+            if (l2 > 0.0 && l1 >= rs * sqrt(l2) && k < myk) {
+              myk = k;
+              seg[0] = S1;
+              seg[1] = S2;
+              seg[2] = lo;
+              seg[3] = c;
+            }
+          }
+          if (myk != INT32_MAX) atomicMin(&sm.kbest, myk);
+          __syncthreads();
+          const int kb = sm.kbest;
+          if (myk == kb && kb != INT32_MAX) {
+            sm.seg[0] = seg[0];
+            sm.seg[1] = seg[1];
+            sm.seg[2] = seg[2];
+            sm.seg[3] = seg[3];
+          }
+          __syncthreads();
+          if (kb != INT32_MAX) {
+            const double k = (double)kb, S1b = sm.seg[0], S2b = sm.seg[1];
+            double disc = k * S2b - S1b * S1b;
+            disc = disc > 0.0 ? disc : 0.0;
+            double l = (S1b - sqrt(s_par * disc / (k - s_par))) / k;
+            l = l < sm.seg[2] ? sm.seg[2] : l;
+            l = l > sm.seg[3] ? sm.seg[3] : l;
+            lam = l;
+            done = true;
+          }
+          __syncthreads();
         }
-        lo = nlo;
-        hi = nhi;
       }
-      if (search) {
+      if (!done) {
+        // ---- fallback: FP64 search of the float interval holding the root ----
+        uint32_t lo = 0, hi = mk;  // rho(0) > sqrt(s); nothing exceeds mk
+        while (hi - lo > 1) {
+          uint32_t t[kNCd];
+          spread<kNCd>(lo, hi, t);
+          double acc[2 * kNCd];
+#pragma unroll
+          for (int c = 0; c < 2 * kNCd; ++c) acc[c] = 0.0;
+          double tf[kNCd];
+#pragma unroll
+          for (int c = 0; c < kNCd; ++c) tf[c] = (double)__uint_as_float(t[c]);
+          for (int i = tid; i < p; i += kXT) {
+            double a = fabs((double)val(i));
+#pragma unroll
+            for (int c = 0; c < kNCd; ++c) {
+              double d = a - tf[c];
+              d = d > 0.0 ? d : 0.0;
+              acc[2 * c] += d;
+              acc[2 * c + 1] += d * d;
+            }
+          }
+          block_sum_n<double, 2 * kNCd>(acc, sm.dred);
+          uint32_t nlo = lo, nhi = hi;
+#pragma unroll
+          for (int c = 0; c < kNCd; ++c) {
+            if (t[c] >= hi) continue;
+            bool pred = acc[2 * c + 1] > 0.0 && acc[2 * c] >= rs * sqrt(acc[2 * c + 1]);
+            if (pred)
+              nlo = t[c] > nlo ? t[c] : nlo;
+            else
+              nhi = t[c] < nhi ? t[c] : nhi;
+          }
+          lo = nlo;
+          hi = nhi;
+        }
         const double tl = (double)__uint_as_float(lo);
         const double th = (double)__uint_as_float(hi);
         double ks[3] = {0.0, 0.0, 0.0};
@@ -270,7 +475,7 @@ __global__ __launch_bounds__(kXT) void x_update_kernel(
   const double inv = zero ? 0.0 : 1.0 / nrm;
 
   // ---------------- write x (list and dense row) ----------------
-  if (list_idx != nullptr && !zero) {
+  if (list_idx != nullptr && !zero && total <= list_cap) {
     int32_t* li = list_idx + j * ldl;
     float* lv = list_val + j * ldl;
     for (int i = cb; i < ce; ++i) {
@@ -284,11 +489,14 @@ __global__ __launch_bounds__(kXT) void x_update_kernel(
     }
   }
   float* x = X + j * ldx;
+  const bool marking = colmark != nullptr && !zero && plan->mark != 0;
+  const int32_t epoch = marking ? plan->epoch : 0;
   for (int i = tid; i < p; i += kXT) {
     float v = val(i);
     double w;
     bool k = kept(i, v, &w);
     x[i] = (k && !zero) ? (float)(w * inv) : 0.f;
+    if (k && marking) colmark[i] = epoch;
   }
 
   // ---------------- state and stop test (Section 2.2) ----------------
@@ -314,19 +522,526 @@ __global__ __launch_bounds__(kXT) void x_update_kernel(
   }
 }
 
+
+// ---------------------------------------------------------------------------
+// Register-resident variant for p <= 256 * NPT.  A 256-thread block per
+// start, thread t holding the contiguous entries [t NPT, (t+1) NPT) of the
+// row (16-byte loads), so that every pass is register arithmetic, index
+// order is thread order for the prefix counts, and all starts of a batch
+// are resident on the chip at once.  Keys are selected by radix select:
+// three histogram passes over 11, 11 and 9 bits of the 31-bit key with
+// integer LDS atomics (exact and order-independent).
+// ---------------------------------------------------------------------------
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+constexpr int kRT = 256;  // threads per start
+constexpr int kRW = kRT / kWave;
+constexpr int kBins = 2048;
+
+struct RSmem {
+  uint32_t hist[kBins];
+  double dred[2 * kNCd * (kRW + 1)];
+  int32_t ired[16 * (kRW + 1)];
+  uint32_t ured[kRW + 1];
+  int scan[kRW + 1];
+  double dscan[2 * (kRW + 1)];
+  float cand[kMaxCand];
+  int ncand;
+  int kbest;
+  int64_t cut;
+  uint32_t sel[2];  // selected bin, count above it
+  double seg[4];
+};
+
+// Exclusive prefix sums of two doubles per thread in thread order (kRT).
+__device__ __forceinline__ void rscan2(double (&v)[2], double* scratch) {
+  const int lane = threadIdx.x % kWave;
+  const int wave = threadIdx.x / kWave;
+  double inc[2] = {v[0], v[1]};
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      double o = __shfl_up(inc[c], off, kWave);
+      if (lane >= off) inc[c] += o;
+    }
+  }
+  if (lane == kWave - 1) {
+    scratch[2 * wave] = inc[0];
+    scratch[2 * wave + 1] = inc[1];
+  }
+  __syncthreads();
+  double b0 = 0.0, b1 = 0.0;
+  for (int w = 0; w < wave; ++w) {
+    b0 += scratch[2 * w];
+    b1 += scratch[2 * w + 1];
+  }
+  v[0] = b0 + inc[0] - v[0];
+  v[1] = b1 + inc[1] - v[1];
+  __syncthreads();
+}
+
+// The need-th largest key (1 <= need <= number of entries) and the number of
+// keys strictly above it.  Entries beyond p are zero keys.
+// Marks a register value as changed, so that the compiler recomputes what
+// it derives from it (keys, bins) instead of holding copies across passes.
+__device__ __forceinline__ void reload(float& x) { asm volatile("" : "+v"(x)); }
+
+template <int NPT>
+__device__ void radix_select(float (&v)[NPT], uint32_t need, RSmem& sm,
+                             uint32_t* key_out, uint32_t* above_out) {
+  const int tid = threadIdx.x;
+  uint32_t prefix = 0;      // selected high bits so far
+  uint32_t above = 0;       // keys strictly above the selected prefix range
+  // (shift, bits) of the three passes over the 31-bit key
+  const int shifts[3] = {20, 9, 0};
+  const int widths[3] = {11, 11, 9};
+#pragma unroll 1
+  for (int pass = 0; pass < 3; ++pass) {
+    const int sh = shifts[pass];
+    const uint32_t nb = 1u << widths[pass];
+    const uint32_t hi_mask = pass == 0 ? 0u : (0x7fffffffu >> (sh + widths[pass])) << (sh + widths[pass]);
+    for (int i = tid; i < kBins; i += kRT) sm.hist[i] = 0u;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) {
+      reload(v[k]);
+      const uint32_t key = key_of(v[k]);
+      if ((key & hi_mask) == prefix) atomicAdd(&sm.hist[(key >> sh) & (nb - 1)], 1u);
+    }
+    __syncthreads();
+    // bins from the top: thread t owns bins nb-1-8t .. nb-8-8t
+    constexpr int kPer = kBins / kRT;  // 8
+    uint32_t local = 0;
+    int first = (int)nb - 1 - kPer * tid;
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      int bin = first - q;
+      local += bin >= 0 ? sm.hist[bin] : 0u;
+    }
+    int total;
+    const uint32_t before = (uint32_t)block_exclusive_scan((int)local, sm.scan, &total);
+    const uint32_t rem = need - above;
+    if (before < rem && rem <= before + local) {
+      uint32_t run = before;
+#pragma unroll
+      for (int q = 0; q < kPer; ++q) {
+        int bin = first - q;
+        uint32_t h = bin >= 0 ? sm.hist[bin] : 0u;
+        if (run < rem && rem <= run + h) {
+          sm.sel[0] = (uint32_t)bin;
+          sm.sel[1] = run;
+        }
+        run += h;
+      }
+    }
+    __syncthreads();
+    prefix |= sm.sel[0] << sh;
+    above += sm.sel[1];
+    __syncthreads();
+  }
+  *key_out = prefix;
+  *above_out = above;
+}
+
+template <int KIND, int NPT>
+__global__ __launch_bounds__(kRT) void x_update_reg_kernel(
+    const float* __restrict__ V, int64_t ldv, int p, double param,
+    float* __restrict__ X, int64_t ldx, int32_t* __restrict__ list_idx,
+    float* __restrict__ list_val, int64_t ldl, int list_cap, StartState s,
+    double tol, int maxit, int32_t* __restrict__ colmark, const Plan* plan) {
+  static_assert(NPT % 4 == 0, "NPT must be a multiple of 4");
+  __shared__ RSmem sm;
+  const int64_t j = blockIdx.x;
+  const bool full = s.status != nullptr;
+  if (full && s.status[j] != kRunning) return;
+  const int tid = threadIdx.x;
+  const int lane = tid % kWave;
+  const int base = tid * NPT;
+  const float* vg = V + j * ldv;
+  float v[NPT];
+#pragma unroll
+  for (int q = 0; q < NPT; q += 4) {
+    const int i = base + q;
+    if (i + 3 < p) {
+      const floatx4 t = *reinterpret_cast<const floatx4*>(vg + i);
+      v[q] = t.x;
+      v[q + 1] = t.y;
+      v[q + 2] = t.z;
+      v[q + 3] = t.w;
+    } else {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) v[q + e] = i + e < p ? vg[i + e] : 0.f;
+    }
+  }
+
+  uint32_t thr_key = 0;
+  int64_t cut = -1;
+  double lam = 0.0;
+  if (KIND == kTopS) {
+    const uint32_t s_int = (uint32_t)((int64_t)param < (int64_t)p ? (int64_t)param : (int64_t)p);
+    uint32_t above;
+    radix_select<NPT>(v, s_int, sm, &thr_key, &above);
+    // ties at thr_key: keep the first (s - #{key > thr_key}) in index order
+    if (tid == 0) sm.cut = -1;
+    int eq = 0;
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) {
+      reload(v[k]);
+      eq += key_of(v[k]) == thr_key && base + k < p;
+    }
+    int eq_total;
+    const int eq_off = block_exclusive_scan(eq, sm.scan, &eq_total);
+    const int need = (int)s_int - (int)above;  // >= 1
+    if (eq_off < need && need <= eq_off + eq) {
+      int seen = eq_off;
+#pragma unroll
+      for (int k = 0; k < NPT; ++k) {
+        if (key_of(v[k]) == thr_key && base + k < p) {
+          ++seen;
+          if (seen == need) sm.cut = base + k;
+        }
+      }
+    }
+    __syncthreads();
+    cut = sm.cut;
+  } else if (KIND == kLambdaS) {
+    const double s_par = param;
+    const double rs = sqrt(s_par);
+    double a0[2] = {0.0, 0.0};
+    uint32_t mk = 0;
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) {
+      double a = fabs((double)v[k]);
+      a0[0] += a;
+      a0[1] += a * a;
+      uint32_t key = key_of(v[k]);
+      mk = key > mk ? key : mk;
+    }
+    block_sum_n<double, 2>(a0, sm.dred);
+    const bool active = a0[0] > rs * sqrt(a0[1]);
+    bool done = !active;
+    if (active) {
+      mk = block_max(mk, sm.ured);
+      int64_t m0 = full ? 2 * (int64_t)s.nnz[j] + 32 : 4 * (int64_t)ceil(s_par) + 64;
+      const int64_t smin = (int64_t)floor(s_par) + 2;
+      m0 = m0 < smin ? smin : m0;
+      m0 = m0 > kMaxCand ? kMaxCand : m0;
+      m0 = m0 > p ? p : m0;
+      uint32_t t0, above0;
+      radix_select<NPT>(v, (uint32_t)m0, sm, &t0, &above0);
+      t0 = t0 < 1u ? 1u : t0;  // zeros never enter
+      const double t0f = (double)__uint_as_float(t0);
+      double a1[2] = {0.0, 0.0};
+      int mine = 0;
+#pragma unroll
+      for (int k = 0; k < NPT; ++k) {
+        mine += key_of(v[k]) >= t0;
+        double d = fabs((double)v[k]) - t0f;
+        d = d > 0.0 ? d : 0.0;
+        a1[0] += d;
+        a1[1] += d * d;
+      }
+      block_sum_n<double, 2>(a1, sm.dred);
+      const int ncand = block_sum(mine, sm.ired);
+      // rho(t0) >= sqrt(s): the root is >= t0 and only candidates matter
+      const bool ok = ncand <= kMaxCand && a1[1] > 0.0 && a1[0] >= rs * sqrt(a1[1]);
+      if (ok) {
+        if (tid == 0) sm.ncand = 0;
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < NPT; ++k) {
+          const bool in = key_of(v[k]) >= t0;
+          const unsigned long long mask = __ballot(in);
+          int wbase = 0;
+          if (lane == 0 && mask) wbase = atomicAdd(&sm.ncand, (int)__popcll(mask));
+          wbase = __shfl(wbase, 0, kWave);
+          if (in) {
+            const unsigned long long below = mask & ((1ull << lane) - 1ull);
+            sm.cand[wbase + __popcll(below)] = fabsf(v[k]);
+          }
+        }
+        __syncthreads();
+        int np2 = 2;
+        while (np2 < ncand) np2 <<= 1;
+        for (int i = ncand + tid; i < np2; i += kRT) sm.cand[i] = -1.f;
+        // bitonic sort, descending
+        for (int size = 2; size <= np2; size <<= 1) {
+          for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            __syncthreads();
+            for (int t = tid; t < np2 / 2; t += kRT) {
+              const int pos = 2 * stride * (t / stride) + (t % stride);
+              const int partner = pos + stride;
+              const bool desc = (pos & size) == 0;
+              const float x0 = sm.cand[pos], x1 = sm.cand[partner];
+              if ((x0 < x1) == desc) {
+                sm.cand[pos] = x1;
+                sm.cand[partner] = x0;
+              }
+            }
+          }
+        }
+        __syncthreads();
+        // prefix sums of c and c^2; thread t owns sorted positions [8t, 8t+8)
+        constexpr int kCP = kMaxCand / kRT;
+        double cv[kCP];
+        double pre[2] = {0.0, 0.0};
+#pragma unroll
+        for (int e = 0; e < kCP; ++e) {
+          const int q = kCP * tid + e;
+          cv[e] = q < ncand ? (double)sm.cand[q] : 0.0;
+          pre[0] += cv[e];
+          pre[1] += cv[e] * cv[e];
+        }
+        rscan2(pre, sm.dscan);
+        if (tid == 0) sm.kbest = INT32_MAX;
+        __syncthreads();
+        double S1 = pre[0], S2 = pre[1];
+        int myk = INT32_MAX;
+        double seg[4] = {0, 0, 0, 0};
+#pragma unroll
+        for (int e = 0; e < kCP; ++e) {
+          const int q = kCP * tid + e;
+          S1 += cv[e];
+          S2 += cv[e] * cv[e];
+          const int k = q + 1;  // top-k prefix
+          if (q >= ncand || (double)k <= s_par || myk != INT32_MAX) continue;
+          const double lo = k < ncand ? (double)sm.cand[k] : t0f;
+          const double l1 = S1 - (double)k * lo;
+          const double l2 = S2 - 2.0 * lo * S1 + (double)k * lo * lo;
+          if (l2 > 0.0 && l1 >= rs * sqrt(l2)) {
+            myk = k;
+            seg[0] = S1;
+            seg[1] = S2;
+            seg[2] = lo;
+            seg[3] = cv[e];
+          }
+        }
+        if (myk != INT32_MAX) atomicMin(&sm.kbest, myk);
+        __syncthreads();
+        const int kb = sm.kbest;
+        if (myk == kb && kb != INT32_MAX) {
+          sm.seg[0] = seg[0];
+          sm.seg[1] = seg[1];
+          sm.seg[2] = seg[2];
+          sm.seg[3] = seg[3];
+        }
+        __syncthreads();
+        if (kb != INT32_MAX) {
+          const double k = (double)kb, S1b = sm.seg[0], S2b = sm.seg[1];
+          double disc = k * S2b - S1b * S1b;
+          disc = disc > 0.0 ? disc : 0.0;
+          double l = (S1b - sqrt(s_par * disc / (k - s_par))) / k;
+          l = l < sm.seg[2] ? sm.seg[2] : l;
+          l = l > sm.seg[3] ? sm.seg[3] : l;
+          lam = l;
+          done = true;
+        }
+        __syncthreads();
+      }
+    }
+    if (!done) {
+      // fallback: FP64 search of the float interval holding the root; reads
+      // the row from memory so that the fast path keeps its registers
+      uint32_t lo = 0, hi = mk;
+      while (hi - lo > 1) {
+        uint32_t t[kNCd];
+        spread<kNCd>(lo, hi, t);
+        double acc[2 * kNCd];
+#pragma unroll
+        for (int c = 0; c < 2 * kNCd; ++c) acc[c] = 0.0;
+        double tf[kNCd];
+#pragma unroll
+        for (int c = 0; c < kNCd; ++c) tf[c] = (double)__uint_as_float(t[c]);
+#pragma unroll 1
+        for (int i = tid; i < p; i += kRT) {
+          const double a = fabs((double)vg[i]);
+#pragma unroll
+          for (int c = 0; c < kNCd; ++c) {
+            double d = a - tf[c];
+            d = d > 0.0 ? d : 0.0;
+            acc[2 * c] += d;
+            acc[2 * c + 1] += d * d;
+          }
+        }
+        block_sum_n<double, 2 * kNCd>(acc, sm.dred);
+        uint32_t nlo = lo, nhi = hi;
+#pragma unroll
+        for (int c = 0; c < kNCd; ++c) {
+          if (t[c] >= hi) continue;
+          bool pred = acc[2 * c + 1] > 0.0 && acc[2 * c] >= rs * sqrt(acc[2 * c + 1]);
+          if (pred)
+            nlo = t[c] > nlo ? t[c] : nlo;
+          else
+            nhi = t[c] < nhi ? t[c] : nhi;
+        }
+        lo = nlo;
+        hi = nhi;
+      }
+      const double tl = (double)__uint_as_float(lo);
+      const double th = (double)__uint_as_float(hi);
+      double ks[3] = {0.0, 0.0, 0.0};
+#pragma unroll 1
+      for (int i = tid; i < p; i += kRT) {
+        const double a = fabs((double)vg[i]);
+        if (a > tl) {
+          ks[0] += 1.0;
+          ks[1] += a;
+          ks[2] += a * a;
+        }
+      }
+      block_sum_n<double, 3>(ks, sm.dred);
+      const double k = ks[0], S1 = ks[1], S2 = ks[2];
+      double l = tl;
+      if (k > s_par) {
+        double disc = k * S2 - S1 * S1;
+        disc = disc > 0.0 ? disc : 0.0;
+        l = (S1 - sqrt(s_par * disc / (k - s_par))) / k;
+      }
+      l = l < tl ? tl : l;
+      l = l > th ? th : l;
+      lam = l;
+    }
+  } else {
+    lam = param;
+  }
+
+  auto kept = [&](int i, float vv, double* w) -> bool {
+    if (KIND == kTopS) {
+      uint32_t k = key_of(vv);
+      *w = (double)vv;
+      return k != 0 && (k > thr_key || (k == thr_key && (int64_t)i <= cut));
+    } else if (KIND == kHardGamma) {
+      *w = (double)vv;
+      return (double)vv * (double)vv > lam;
+    } else {
+      double a = fabs((double)vv);
+      *w = vv > 0.f ? a - lam : lam - a;
+      return a > lam;
+    }
+  };
+
+  int cnt = 0;
+  double acc[2] = {0.0, 0.0};
+#pragma unroll
+  for (int k = 0; k < NPT; ++k) {
+    double w;
+    if (kept(base + k, v[k], &w)) {
+      ++cnt;
+      acc[0] += w * w;
+      if (KIND == kHardGamma) acc[1] += w * w - lam;
+    }
+  }
+  block_sum_n<double, 2>(acc, sm.dred);
+  int total;
+  int off = block_exclusive_scan(cnt, sm.scan, &total);
+  const double nrm = sqrt(acc[0]);
+  double phi;
+  if (KIND == kHardGamma)
+    phi = acc[1];
+  else if (KIND == kLambdaS)
+    phi = lam * sqrt(param) + nrm;
+  else
+    phi = nrm;
+  const bool zero = !(nrm > 0.0);
+  const double inv = zero ? 0.0 : 1.0 / nrm;
+
+  // the list is written only when it can serve the list-based product
+  const bool listed = list_idx != nullptr && !zero && total <= list_cap;
+  const bool marking = colmark != nullptr && !zero && plan->mark != 0;
+  const int32_t epoch = marking ? plan->epoch : 0;
+  int32_t* li = listed ? list_idx + j * ldl : nullptr;
+  float* lv = listed ? list_val + j * ldl : nullptr;
+  float* x = X + j * ldx;
+#pragma unroll
+  for (int q = 0; q < NPT; q += 4) {
+    float xo[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      double w;
+      const bool kp = kept(base + q + e, v[q + e], &w) && !zero;
+      xo[e] = kp ? (float)(w * inv) : 0.f;
+      if (kp && li != nullptr) {
+        li[off] = base + q + e;
+        lv[off] = xo[e];
+        ++off;
+      }
+      if (kp && marking) colmark[base + q + e] = epoch;
+    }
+    const int i = base + q;
+    if (i + 3 < p) {
+      floatx4 t = {xo[0], xo[1], xo[2], xo[3]};
+      *reinterpret_cast<floatx4*>(x + i) = t;
+    } else {
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        if (i + e < p) x[i + e] = xo[e];
+    }
+  }
+
+  if (tid == 0) {
+    if (!full) {
+      s.phi[j] = phi;
+      s.nnz[j] = zero ? 0 : total;
+    } else {
+      const int it = s.iters[j] + 1;
+      const double prev = s.phi[j];
+      s.iters[j] = it;
+      s.phi_prev[j] = prev;
+      s.phi[j] = phi;
+      s.nnz[j] = zero ? 0 : total;
+      if (zero)
+        s.status[j] = SPCA_ZERO;
+      else if (it >= 2 && tol >= 0.0 && phi <= (1.0 + tol) * prev)
+        s.status[j] = SPCA_CONVERGED;
+      else if (it >= maxit)
+        s.status[j] = SPCA_MAXIT;
+    }
+  }
+}
+
+template <int KIND, int NPT>
+void launch_reg(hipStream_t st, double param, const float* V, int64_t ldv,
+                int64_t r, int64_t p, float* X, int64_t ldx, int32_t* li,
+                float* lv, int64_t ldl, int list_cap, StartState s, double tol,
+                int maxit, int32_t* colmark, const Plan* plan) {
+  hipLaunchKernelGGL((x_update_reg_kernel<KIND, NPT>), dim3((unsigned)r),
+                     dim3(kRT), 0, st, V, ldv, (int)p, param, X, ldx, li, lv,
+                     ldl, list_cap, s, tol, maxit, colmark, plan);
+}
+
 template <int KIND>
 void launch_kind(hipStream_t st, double param, const float* V, int64_t ldv,
                  int64_t r, int64_t p, float* X, int64_t ldx, int32_t* li,
-                 float* lv, int64_t ldl, StartState s, double tol, int maxit) {
+                 float* lv, int64_t ldl, int list_cap, StartState s, double tol,
+                 int maxit, int32_t* colmark, const Plan* plan) {
+  const bool aligned = ldv % 4 == 0 && ldx % 4 == 0 &&
+                       (uintptr_t)V % 16 == 0 && (uintptr_t)X % 16 == 0;
+  const int64_t per = ceil_div(p, kRT);
+  if (aligned && per <= 48) {
+    if (per <= 8)
+      launch_reg<KIND, 8>(st, param, V, ldv, r, p, X, ldx, li, lv, ldl, list_cap, s, tol, maxit, colmark, plan);
+    else if (per <= 16)
+      launch_reg<KIND, 16>(st, param, V, ldv, r, p, X, ldx, li, lv, ldl, list_cap, s, tol, maxit, colmark, plan);
+    else if (per <= 24)
+      launch_reg<KIND, 24>(st, param, V, ldv, r, p, X, ldx, li, lv, ldl, list_cap, s, tol, maxit, colmark, plan);
+    else if (per <= 32)
+      launch_reg<KIND, 32>(st, param, V, ldv, r, p, X, ldx, li, lv, ldl, list_cap, s, tol, maxit, colmark, plan);
+    else if (per <= 40)
+      launch_reg<KIND, 40>(st, param, V, ldv, r, p, X, ldx, li, lv, ldl, list_cap, s, tol, maxit, colmark, plan);
+    else
+      launch_reg<KIND, 48>(st, param, V, ldv, r, p, X, ldx, li, lv, ldl, list_cap, s, tol, maxit, colmark, plan);
+    return;
+  }
   if (p <= kStageMax) {
     size_t shm = (size_t)p * sizeof(float);
     hipLaunchKernelGGL((x_update_kernel<KIND, true>), dim3((unsigned)r),
                        dim3(kXT), shm, st, V, ldv, (int)p, param, X, ldx, li,
-                       lv, ldl, s, tol, maxit);
+                       lv, ldl, list_cap, s, tol, maxit, colmark, plan);
   } else {
     hipLaunchKernelGGL((x_update_kernel<KIND, false>), dim3((unsigned)r),
                        dim3(kXT), 0, st, V, ldv, (int)p, param, X, ldx, li, lv,
-                       ldl, s, tol, maxit);
+                       ldl, list_cap, s, tol, maxit, colmark, plan);
   }
 }
 
@@ -334,24 +1049,25 @@ void launch_kind(hipStream_t st, double param, const float* V, int64_t ldv,
 
 void x_update(hipStream_t st, int fid, double s_or_gamma, const float* V,
               int64_t ldv, int64_t r, int64_t p, float* X, int64_t ldx,
-              int32_t* list_idx, float* list_val, int64_t ldl, StartState s,
-              double tol, int32_t maxit) {
+              int32_t* list_idx, float* list_val, int64_t ldl, int list_cap,
+              StartState s, double tol, int32_t maxit, int32_t* colmark,
+              const Plan* plan) {
   switch (xkind_of(fid)) {
     case kTopS:
       launch_kind<kTopS>(st, s_or_gamma, V, ldv, r, p, X, ldx, list_idx,
-                         list_val, ldl, s, tol, maxit);
+                         list_val, ldl, list_cap, s, tol, maxit, colmark, plan);
       break;
     case kLambdaS:
       launch_kind<kLambdaS>(st, s_or_gamma, V, ldv, r, p, X, ldx, list_idx,
-                            list_val, ldl, s, tol, maxit);
+                            list_val, ldl, list_cap, s, tol, maxit, colmark, plan);
       break;
     case kHardGamma:
       launch_kind<kHardGamma>(st, s_or_gamma, V, ldv, r, p, X, ldx, list_idx,
-                              list_val, ldl, s, tol, maxit);
+                              list_val, ldl, list_cap, s, tol, maxit, colmark, plan);
       break;
     case kSoftGamma:
       launch_kind<kSoftGamma>(st, s_or_gamma, V, ldv, r, p, X, ldx, list_idx,
-                              list_val, ldl, s, tol, maxit);
+                              list_val, ldl, list_cap, s, tol, maxit, colmark, plan);
       break;
   }
 }
