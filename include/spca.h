@@ -62,8 +62,10 @@ enum {
 /* Arithmetic of the iterations */
 #define SPCA_PREC_FP32 0        /* A, X, Y in FP32, FP32 MFMA accumulation   */
 #define SPCA_PREC_BF16_POLISH 1 /* A, X, Y operands in BF16, FP32 accumulation,
-                                   then FP32 AM iterations restricted to the
-                                   final support ("polish")                  */
+                                   then up to polish_maxit FP32 AM iterations
+                                   on the caller's FP32 A from the best
+                                   start's iterate ("polish"); objective and
+                                   explained variance in FP64 on the FP32 A */
 
 typedef struct {
   double objective;      /* f(x) of Table 1 at the returned x, FP64         */
@@ -74,6 +76,11 @@ typedef struct {
   int32_t nnz;           /* |support|                                       */
   int32_t iters;         /* x-updates done by the best start                */
   int32_t status;        /* SPCA_CONVERGED .. SPCA_ZERO of the best start   */
+  double objective_pre_polish; /* BF16 mode: f of the best start before the
+                                  FP32 polish (FP64, on the FP32 A); equal to
+                                  objective otherwise                        */
+  int32_t polish_iters;  /* FP32 polish iterations run (BF16 mode)          */
+  int32_t reserved;
 } spca_result;
 
 /* ---------------------------------------------------------------------- */
@@ -177,6 +184,14 @@ const char* spca_last_error(void);
 int spca_gemm_nt_f32(void* stream, const float* P, int64_t ldp, const float* Q,
                      int64_t ldq, float* C, int64_t ldc, int64_t M, int64_t N,
                      int64_t K);
+
+/* The same product with BF16 operands (raw bfloat16 bit patterns), FP32
+ * accumulation and FP32 output (the products of the SPCA_PREC_BF16_POLISH
+ * iterations).  ldp and ldq must be multiples of 8, P and Q 16-byte
+ * aligned.                                                                */
+int spca_gemm_nt_bf16(void* stream, const uint16_t* P, int64_t ldp,
+                      const uint16_t* Q, int64_t ldq, float* C, int64_t ldc,
+                      int64_t M, int64_t N, int64_t K);
 
 /* Tuning and testing variant of spca_gemm_nt_f32 with a forced tile shape
  * (0 .. 5: BMxBN of 128x128, 128x160, 128x96, 128x64, 64x128, 32x128) and

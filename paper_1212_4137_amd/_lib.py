@@ -23,8 +23,8 @@ FLAG_GRAPH, FLAG_CHECK_FINITE, FLAG_DENSE_ONLY = 1, 2, 4
 
 EXPORTED = ("spca_am_solve", "spca_am_solve_ex", "spca_ctx_create",
             "spca_ctx_destroy", "spca_workspace_bytes", "spca_last_error",
-            "spca_gemm_nt_f32", "spca_gemm_nt_f32_shape", "spca_gemm_nt_f32_plan",
-            "spca_x_update")
+            "spca_gemm_nt_f32", "spca_gemm_nt_bf16", "spca_gemm_nt_f32_shape",
+            "spca_gemm_nt_f32_plan", "spca_x_update")
 
 
 class SpcaError(RuntimeError):
@@ -37,7 +37,9 @@ class Result(ctypes.Structure):
     _fields_ = [("objective", ctypes.c_double), ("explained_var", ctypes.c_double),
                 ("phi", ctypes.c_double), ("iters_x_starts", ctypes.c_double),
                 ("best_start", ctypes.c_int32), ("nnz", ctypes.c_int32),
-                ("iters", ctypes.c_int32), ("status", ctypes.c_int32)]
+                ("iters", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("objective_pre_polish", ctypes.c_double),
+                ("polish_iters", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class Problem(ctypes.Structure):
@@ -93,6 +95,8 @@ def load():
         lib.spca_am_solve_ex.restype = ctypes.c_int
         lib.spca_gemm_nt_f32.argtypes = [P, P, i64, P, i64, P, i64, i64, i64, i64]
         lib.spca_gemm_nt_f32.restype = ctypes.c_int
+        lib.spca_gemm_nt_bf16.argtypes = [P, P, i64, P, i64, P, i64, i64, i64, i64]
+        lib.spca_gemm_nt_bf16.restype = ctypes.c_int
         lib.spca_gemm_nt_f32_shape.argtypes = [P, P, i64, P, i64, P, i64, i64, i64, i64,
                                                ctypes.c_int, ctypes.c_int]
         lib.spca_gemm_nt_f32_shape.restype = ctypes.c_int
@@ -225,6 +229,8 @@ def am_solve(A, formulation, s_or_gamma, X0=None, tol=1e-8, maxit=200, *,
             "explained_variance": res.explained_var, "phi": res.phi,
             "best_start": res.best_start, "nnz": res.nnz, "iters": res.iters,
             "status": res.status, "iters_x_starts": res.iters_x_starts,
+            "objective_pre_polish": res.objective_pre_polish,
+            "polish_iters": res.polish_iters,
             "f_per_start": f, "ev_per_start": ev, "phi_per_start": phi,
             "iters_per_start": iters, "status_per_start": status,
             "nnz_per_start": nnz, "X_final": Xf,
@@ -273,6 +279,25 @@ def gemm_nt(P, Q, stream=None):
     _check(load().spca_gemm_nt_f32(_stream_ptr(stream), ctypes.c_void_p(P.data_ptr()),
                                    P.stride(0), ctypes.c_void_p(Q.data_ptr()), Q.stride(0),
                                    ctypes.c_void_p(C.data_ptr()), N, M, N, K))
+    return C
+
+
+def gemm_nt_bf16(P, Q, stream=None):
+    """C = P Q^T from BF16 operands with FP32 accumulation
+    (``spca_gemm_nt_bf16``); P and Q are torch.bfloat16 row-major tensors
+    whose leading dimensions are multiples of 8."""
+    import torch
+
+    _require_gpu_tensor(P, "P", torch.bfloat16)
+    _require_gpu_tensor(Q, "Q", torch.bfloat16)
+    M, K = P.shape
+    N, K2 = Q.shape
+    if K2 != K:
+        raise ValueError("inner dimensions differ")
+    C = torch.empty((M, N), dtype=torch.float32, device=P.device)
+    _check(load().spca_gemm_nt_bf16(_stream_ptr(stream), ctypes.c_void_p(P.data_ptr()),
+                                    P.stride(0), ctypes.c_void_p(Q.data_ptr()), Q.stride(0),
+                                    ctypes.c_void_p(C.data_ptr()), N, M, N, K))
     return C
 
 

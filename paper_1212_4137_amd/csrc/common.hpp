@@ -156,6 +156,17 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int* scratch,
   return res;
 }
 
+// FP32 -> BF16 bit pattern, round to nearest even (NaN stays NaN).
+__device__ __forceinline__ uint16_t f32_to_bf16(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) {
+  return __uint_as_float((uint32_t)h << 16);
+}
+
 // Per-start state machine shared by the iteration kernels.
 constexpr int32_t kRunning = -1;
 

@@ -19,6 +19,9 @@
 // fall in distinct banks for 32- and 64-bank LDS alike.
 // Split-K: when splits > 1, slab range s of every tile writes its partial
 // product to C + s * split_stride; the consumer sums the partials in order.
+// BF16 operands: the same 128-byte LDS rows hold 64 bf16 of K; each 16-byte
+// chunk (8 bf16 of one row) feeds one v_mfma_f32_32x32x16_bf16 instead of
+// four FP32 MFMAs, and the products accumulate in FP32.
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -27,9 +30,22 @@ namespace {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-constexpr int kBK = 32;              // K per slab (floats)
+constexpr int kBK = 32;              // floats per LDS row (128 bytes)
 constexpr int kChunks = kBK / 4;     // 16-byte chunks per LDS row
+
+// Element traits: how many K elements a 16-byte chunk holds.
+template <typename T>
+struct Elem;
+template <>
+struct Elem<float> {
+  static constexpr int kPerChunk = 4;
+};
+template <>
+struct Elem<uint16_t> {  // bf16 bit patterns
+  static constexpr int kPerChunk = 8;
+};
 
 template <int BM, int BN, int WM, int WN>
 struct GemmCfg {
@@ -50,35 +66,41 @@ __device__ __forceinline__ int swz(int row, int chunk) {
   return row * kBK + ((chunk ^ ((row ^ (row >> 3)) & 7)) << 2);
 }
 
-__device__ __forceinline__ floatx4 load_row4(const float* __restrict__ base,
-                                             int64_t ld, int row, int nrows,
-                                             int k, int kend) {
+// 16 bytes of row `row` starting at element k (zero past kend or nrows).
+template <typename T>
+__device__ __forceinline__ floatx4 load_chunk(const T* __restrict__ base,
+                                              int64_t ld, int row, int nrows,
+                                              int k, int kend) {
+  constexpr int E = Elem<T>::kPerChunk;
   floatx4 v = {0.f, 0.f, 0.f, 0.f};
   if (row < nrows) {
-    const float* p = base + (int64_t)row * ld + k;
-    if (k + 3 < kend) {
+    const T* p = base + (int64_t)row * ld + k;
+    if (k + E - 1 < kend) {
       v = *reinterpret_cast<const floatx4*>(p);
     } else {
-      if (k + 0 < kend) v.x = p[0];
-      if (k + 1 < kend) v.y = p[1];
-      if (k + 2 < kend) v.z = p[2];
+      T tmp[E];
+#pragma unroll
+      for (int e = 0; e < E; ++e) tmp[e] = k + e < kend ? p[e] : T(0);
+      v = *reinterpret_cast<const floatx4*>(tmp);
     }
   }
   return v;
 }
 
-template <int BM, int BN, int WM, int WN>
-__global__ __launch_bounds__(WM* WN* kWave) void gemm_nt_f32_kernel(
-    const float* __restrict__ P, int64_t ldp, const float* __restrict__ Q,
+template <typename T, int BM, int BN, int WM, int WN>
+__global__ __launch_bounds__(WM* WN* kWave) void gemm_nt_kernel(
+    const T* __restrict__ P, int64_t ldp, const T* __restrict__ Q,
     int64_t ldq, float* __restrict__ C, int64_t ldc, int M, int N, int K,
     int tiles_m, int tiles_mn, int splits, int kslabs_per_split,
     int64_t split_stride, const int32_t* __restrict__ gate, int32_t gate_run,
     const int32_t* __restrict__ kdev) {
   using Cfg = GemmCfg<BM, BN, WM, WN>;
+  constexpr int E = Elem<T>::kPerChunk;
+  constexpr int SK = kChunks * E;  // K elements per slab
   if (gate != nullptr && *gate != gate_run) return;
   if (kdev != nullptr) {
     K = *kdev;
-    kslabs_per_split = (K + kBK - 1) / kBK;
+    kslabs_per_split = (K + SK - 1) / SK;
   }
 
   __shared__ __attribute__((aligned(16))) float lds[2 * Cfg::kStage];
@@ -96,10 +118,10 @@ __global__ __launch_bounds__(WM* WN* kWave) void gemm_nt_f32_kernel(
   const int tn = t / tiles_m;
   const int m0 = tm * BM;
   const int n0 = tn * BN;
-  const int kbeg = split * kslabs_per_split * kBK;
-  int kend = kbeg + kslabs_per_split * kBK;
+  const int kbeg = split * kslabs_per_split * SK;
+  int kend = kbeg + kslabs_per_split * SK;
   kend = kend < K ? kend : K;
-  const int nslabs = kend > kbeg ? (kend - kbeg + kBK - 1) / kBK : 0;
+  const int nslabs = kend > kbeg ? (kend - kbeg + SK - 1) / SK : 0;
   float* Cs = C + (int64_t)split * split_stride;
 
   const int tid = threadIdx.x;
@@ -110,8 +132,8 @@ __global__ __launch_bounds__(WM* WN* kWave) void gemm_nt_f32_kernel(
   const int lrow = lane % 32;
   const int lhalf = lane / 32;
 
-  const float* Pblk = P + (int64_t)m0 * ldp;
-  const float* Qblk = Q + (int64_t)n0 * ldq;
+  const T* Pblk = P + (int64_t)m0 * ldp;
+  const T* Qblk = Q + (int64_t)n0 * ldq;
   const int mrows = M - m0;
   const int nrows = N - n0;
 
@@ -130,12 +152,12 @@ __global__ __launch_bounds__(WM* WN* kWave) void gemm_nt_f32_kernel(
 #pragma unroll
     for (int v = 0; v < Cfg::kPVec; ++v) {
       int f = tid + v * Cfg::kThreads;
-      pre_p[v] = load_row4(Pblk, ldp, f / kChunks, mrows, k0 + (f % kChunks) * 4, kend);
+      pre_p[v] = load_chunk<T>(Pblk, ldp, f / kChunks, mrows, k0 + (f % kChunks) * E, kend);
     }
 #pragma unroll
     for (int v = 0; v < Cfg::kQVec; ++v) {
       int f = tid + v * Cfg::kThreads;
-      pre_q[v] = load_row4(Qblk, ldq, f / kChunks, nrows, k0 + (f % kChunks) * 4, kend);
+      pre_q[v] = load_chunk<T>(Qblk, ldq, f / kChunks, nrows, k0 + (f % kChunks) * E, kend);
     }
   };
   auto stash = [&](float* st) {
@@ -160,7 +182,7 @@ __global__ __launch_bounds__(WM* WN* kWave) void gemm_nt_f32_kernel(
   for (int ks = 0; ks < nslabs; ++ks) {
     const float* sp = lds + (ks & 1) * Cfg::kStage;
     const float* sq = sp + BM * kBK;
-    if (ks + 1 < nslabs) fetch(kbeg + (ks + 1) * kBK);
+    if (ks + 1 < nslabs) fetch(kbeg + (ks + 1) * SK);
 #pragma unroll
     for (int c8 = 0; c8 < kChunks; c8 += 2) {
       const int chunk = c8 + lhalf;  // k offset 4 * chunk within the slab
@@ -174,14 +196,24 @@ __global__ __launch_bounds__(WM* WN* kWave) void gemm_nt_f32_kernel(
       for (int j = 0; j < Cfg::kFN; ++j)
         bq[j] = *reinterpret_cast<const floatx4*>(
             &sq[swz(wn * Cfg::kTN + j * 32 + lrow, chunk)]);
+      if constexpr (E == 4) {
 #pragma unroll
-      for (int e = 0; e < 4; ++e)
+        for (int e = 0; e < 4; ++e)
+#pragma unroll
+          for (int i = 0; i < Cfg::kFM; ++i)
+#pragma unroll
+            for (int j = 0; j < Cfg::kFN; ++j)
+              acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i][e], bq[j][e],
+                                                               acc[i][j], 0, 0, 0);
+      } else {
 #pragma unroll
         for (int i = 0; i < Cfg::kFM; ++i)
 #pragma unroll
           for (int j = 0; j < Cfg::kFN; ++j)
-            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i][e], bq[j][e],
-                                                             acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                __builtin_bit_cast(bf16x8, a[i]), __builtin_bit_cast(bf16x8, bq[j]),
+                acc[i][j], 0, 0, 0);
+      }
     }
     if (ks + 1 < nslabs) stash(lds + ((ks + 1) & 1) * Cfg::kStage);
     __syncthreads();
@@ -220,44 +252,45 @@ constexpr Shape kShapes[] = {
 };
 constexpr int kNumShapes = (int)(sizeof(kShapes) / sizeof(kShapes[0]));
 
-template <int BM, int BN, int WM, int WN>
-void launch(hipStream_t st, const float* P, int64_t ldp, const float* Q,
+template <typename T, int BM, int BN, int WM, int WN>
+void launch(hipStream_t st, const T* P, int64_t ldp, const T* Q,
             int64_t ldq, float* C, int64_t ldc, int64_t M, int64_t N,
             int64_t K, int splits, int64_t split_stride, const int32_t* gate,
             int32_t gate_run, const int32_t* kdev) {
   const int tiles_m = (int)ceil_div(M, BM);
   const int tiles_n = (int)ceil_div(N, BN);
-  const int kslabs = (int)ceil_div(K, kBK);
+  const int kslabs = (int)ceil_div(K, kChunks * Elem<T>::kPerChunk);
   const int per_split = (int)ceil_div(kslabs, splits);
   const int total = tiles_m * tiles_n * splits;
-  hipLaunchKernelGGL((gemm_nt_f32_kernel<BM, BN, WM, WN>), dim3(total),
+  hipLaunchKernelGGL((gemm_nt_kernel<T, BM, BN, WM, WN>), dim3(total),
                      dim3(WM * WN * kWave), 0, st, P, ldp, Q, ldq, C, ldc,
                      (int)M, (int)N, (int)K, tiles_m, tiles_m * tiles_n, splits,
                      per_split, split_stride, gate, gate_run, kdev);
 }
 
-void dispatch(int shape, hipStream_t st, const float* P, int64_t ldp,
-              const float* Q, int64_t ldq, float* C, int64_t ldc, int64_t M,
+template <typename T>
+void dispatch(int shape, hipStream_t st, const T* P, int64_t ldp,
+              const T* Q, int64_t ldq, float* C, int64_t ldc, int64_t M,
               int64_t N, int64_t K, int splits, int64_t split_stride,
               const int32_t* gate, int32_t gate_run, const int32_t* kdev) {
   switch (shape) {
     case 0:
-      launch<128, 128, 2, 2>(st, P, ldp, Q, ldq, C, ldc, M, N, K, splits, split_stride, gate, gate_run, kdev);
+      launch<T, 128, 128, 2, 2>(st, P, ldp, Q, ldq, C, ldc, M, N, K, splits, split_stride, gate, gate_run, kdev);
       break;
     case 1:
-      launch<128, 160, 4, 1>(st, P, ldp, Q, ldq, C, ldc, M, N, K, splits, split_stride, gate, gate_run, kdev);
+      launch<T, 128, 160, 4, 1>(st, P, ldp, Q, ldq, C, ldc, M, N, K, splits, split_stride, gate, gate_run, kdev);
       break;
     case 2:
-      launch<128, 96, 4, 1>(st, P, ldp, Q, ldq, C, ldc, M, N, K, splits, split_stride, gate, gate_run, kdev);
+      launch<T, 128, 96, 4, 1>(st, P, ldp, Q, ldq, C, ldc, M, N, K, splits, split_stride, gate, gate_run, kdev);
       break;
     case 3:
-      launch<128, 64, 2, 2>(st, P, ldp, Q, ldq, C, ldc, M, N, K, splits, split_stride, gate, gate_run, kdev);
+      launch<T, 128, 64, 2, 2>(st, P, ldp, Q, ldq, C, ldc, M, N, K, splits, split_stride, gate, gate_run, kdev);
       break;
     case 4:
-      launch<64, 128, 2, 2>(st, P, ldp, Q, ldq, C, ldc, M, N, K, splits, split_stride, gate, gate_run, kdev);
+      launch<T, 64, 128, 2, 2>(st, P, ldp, Q, ldq, C, ldc, M, N, K, splits, split_stride, gate, gate_run, kdev);
       break;
     default:
-      launch<32, 128, 1, 4>(st, P, ldp, Q, ldq, C, ldc, M, N, K, splits, split_stride, gate, gate_run, kdev);
+      launch<T, 32, 128, 1, 4>(st, P, ldp, Q, ldq, C, ldc, M, N, K, splits, split_stride, gate, gate_run, kdev);
       break;
   }
 }
@@ -274,10 +307,15 @@ void dispatch(int shape, hipStream_t st, const float* P, int64_t ldp,
 //   w * max(ceil(rest / 256), 1.5);
 //   split partials cost their HBM traffic, 8 bytes per element per split at
 //   about 1.7 KB per cycle for the whole chip.
-GemmPlan plan_gemm_nt(int64_t M, int64_t N, int64_t K, int max_splits) {
+GemmPlan plan_gemm_nt(int64_t M, int64_t N, int64_t K, int max_splits,
+                      int elem_bytes) {
   GemmPlan best{0, 1};
   double best_cost = 1e300;
-  const int64_t kslabs = ceil_div(K, kBK);
+  const int64_t slab_k = 128 / elem_bytes;
+  const int64_t kslabs = ceil_div(K, slab_k);
+  // MACs per cycle per CU: FP32 MFMA 128; BF16 operands are limited by LDS
+  // reads well below their MFMA rate, taken as 4x FP32
+  const double macs = elem_bytes == 4 ? 128.0 : 512.0;
   for (int s = 0; s < kNumShapes; ++s) {
     const Shape& sh = kShapes[s];
     if (sh.bm > 32 && M <= sh.bm / 2) continue;  // mostly padding rows
@@ -287,7 +325,7 @@ GemmPlan plan_gemm_nt(int64_t M, int64_t N, int64_t K, int max_splits) {
       if (splits > 1 && per < 8) break;  // too little K per split
       const int64_t wgs = tiles * splits;
       const int64_t slots = 256LL * sh.occ;
-      const double w = (double)sh.bm * sh.bn * (double)(per * kBK) / (128.0 * sh.eff);
+      const double w = (double)sh.bm * sh.bn * (double)(per * slab_k) / (macs * sh.eff);
       const int64_t full = wgs / slots;
       const int64_t rest = wgs % slots;
       double cost = (double)full * w * (sh.occ > 1.5 ? sh.occ : 1.5);
@@ -313,8 +351,17 @@ void gemm_nt_f32(hipStream_t st, const float* P, int64_t ldp, const float* Q,
                  GemmPlan plan, int64_t split_stride, const int32_t* kdev) {
   if (M <= 0 || N <= 0) return;
   if (kdev != nullptr) plan.splits = 1;
-  dispatch(plan.shape, st, P, ldp, Q, ldq, C, ldc, M, N, K, plan.splits,
-           split_stride, gate, gate_run, kdev);
+  dispatch<float>(plan.shape, st, P, ldp, Q, ldq, C, ldc, M, N, K, plan.splits,
+                  split_stride, gate, gate_run, kdev);
+}
+
+void gemm_nt_bf16(hipStream_t st, const uint16_t* P, int64_t ldp,
+                  const uint16_t* Q, int64_t ldq, float* C, int64_t ldc,
+                  int64_t M, int64_t N, int64_t K, const int32_t* gate,
+                  int32_t gate_run, GemmPlan plan, int64_t split_stride) {
+  if (M <= 0 || N <= 0) return;
+  dispatch<uint16_t>(plan.shape, st, P, ldp, Q, ldq, C, ldc, M, N, K,
+                     plan.splits, split_stride, gate, gate_run, nullptr);
 }
 
 }  // namespace spca

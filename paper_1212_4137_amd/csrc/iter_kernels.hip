@@ -34,6 +34,43 @@ __global__ __launch_bounds__(256) void transpose_kernel(
   }
 }
 
+// BF16 conversions of A.  Column-major: one block per column (grid-stride).
+__global__ __launch_bounds__(256) void to_bf16_col_kernel(
+    const float* __restrict__ A, int64_t lda, int64_t n, int64_t p,
+    uint16_t* __restrict__ Ab, int64_t ldab) {
+  for (int64_t k = blockIdx.x; k < p; k += gridDim.x)
+    for (int64_t i = threadIdx.x; i < ldab; i += 256)
+      Ab[i + k * ldab] = i < n ? f32_to_bf16(A[i + k * lda]) : (uint16_t)0;
+}
+
+// Row-major: 64 x 64 tiles transposed through LDS.
+__global__ __launch_bounds__(256) void to_bf16_row_kernel(
+    const float* __restrict__ A, int64_t lda, int64_t n, int64_t p,
+    uint16_t* __restrict__ Atb, int64_t ldatb) {
+  __shared__ float tile[64][65];
+  const int64_t i0 = (int64_t)blockIdx.x * 64;  // rows of A
+  const int64_t k0 = (int64_t)blockIdx.y * 64;  // columns of A
+  const int tx = threadIdx.x % 64, ty = threadIdx.x / 64;
+  for (int kk = ty; kk < 64; kk += 4) {
+    const int64_t i = i0 + tx, k = k0 + kk;
+    tile[kk][tx] = (i < n && k < p) ? A[i + k * lda] : 0.f;
+  }
+  __syncthreads();
+  for (int ii = ty; ii < 64; ii += 4) {
+    const int64_t i = i0 + ii, k = k0 + tx;
+    if (i < n && k < ldatb) Atb[i * ldatb + k] = k < p ? f32_to_bf16(tile[tx][ii]) : (uint16_t)0;
+  }
+}
+
+__global__ __launch_bounds__(256) void rows_to_bf16_kernel(
+    const float* __restrict__ X, int64_t ldx, int64_t p,
+    uint16_t* __restrict__ Xb, int64_t ldxb, const Plan* plan) {
+  if (plan != nullptr && plan->mode != kAxDense) return;
+  const int64_t j = blockIdx.x;
+  for (int64_t i = threadIdx.x; i < ldxb; i += 256)
+    Xb[j * ldxb + i] = i < p ? f32_to_bf16(X[j * ldx + i]) : (uint16_t)0;
+}
+
 // one block per column (grid-stride over columns)
 __global__ __launch_bounds__(256) void copy_columns_kernel(
     const float* __restrict__ A, int64_t lda, float* __restrict__ B,
@@ -241,9 +278,8 @@ __global__ void init_plan_kernel(Plan* plan, int dense_splits) {
   plan->mode_count[0] = plan->mode_count[1] = plan->mode_count[2] = 0;
 }
 
-// Union gathers: blocks [0, r) copy the union columns of the rows of X;
-// the remaining blocks transpose 64 x 64 tiles of A's union columns into
-// the row-major Qc.
+// Union gathers: the blocks copy the union columns of the rows of X, then
+// transpose 64 x 64 tiles of A's union columns into the row-major Qc.
 constexpr int kGT = 64;
 __global__ __launch_bounds__(256) void union_gather_kernel(
     const float* __restrict__ X, int64_t ldx, int64_t r,
@@ -253,15 +289,12 @@ __global__ __launch_bounds__(256) void union_gather_kernel(
   __shared__ float tile[kGT][kGT + 1];
   if (plan->mode != kAxUnion) return;
   const int u = plan->union_size;
-  if ((int64_t)blockIdx.x < r) {
-    const int64_t j = blockIdx.x;
+  for (int64_t j = blockIdx.x; j < r; j += gridDim.x)
     for (int c = threadIdx.x; c < u; c += 256) Xc[j * ldxc + c] = X[j * ldx + ulist[c]];
-    return;
-  }
   const int64_t tiles_i = ceil_div(n, kGT);
   const int64_t tiles = tiles_i * ceil_div(u, kGT);
   const int tx = threadIdx.x % kGT, ty = threadIdx.x / kGT;  // ty in 0..3
-  for (int64_t t = (int64_t)blockIdx.x - r; t < tiles; t += (int64_t)gridDim.x - r) {
+  for (int64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
     const int64_t i0 = (t % tiles_i) * kGT;
     const int64_t c0 = (t / tiles_i) * kGT;
     __syncthreads();
@@ -284,7 +317,8 @@ __global__ __launch_bounds__(256) void union_gather_kernel(
 template <bool L1VAR>
 __global__ __launch_bounds__(256) void y_update_kernel(
     const float* __restrict__ U, int64_t split_stride, float* __restrict__ Y,
-    int64_t ldu, int64_t n, StartState s, const Plan* plan) {
+    int64_t ldu, int64_t n, StartState s, const Plan* plan,
+    uint16_t* __restrict__ Yb, int64_t ldyb) {
   __shared__ double red[8];
   if (plan->mode == kAxList) return;
   const int splits = plan->ax_splits;
@@ -310,7 +344,9 @@ __global__ __launch_bounds__(256) void y_update_kernel(
   const double inv = 1.0 / sqrt(sq);
   for (int64_t i = threadIdx.x; i < n; i += 256) {
     float t = y[i];
-    y[i] = L1VAR ? (float)((t > 0.f) - (t < 0.f)) : (float)((double)t * inv);
+    const float o = L1VAR ? (float)((t > 0.f) - (t < 0.f)) : (float)((double)t * inv);
+    y[i] = o;
+    if (Yb != nullptr) Yb[j * ldyb + i] = f32_to_bf16(o);
   }
 }
 
@@ -323,12 +359,27 @@ constexpr int kSpThreads = 256;
 constexpr int kSpStage = 256;   // list entries staged in LDS at a time
 typedef float floatx4_t __attribute__((ext_vector_type(4)));
 
-template <bool L1VAR, int R>
+// four consecutive entries of a column as floats (FP32 or BF16 storage)
+__device__ __forceinline__ floatx4_t load4(const float* c, int64_t row) {
+  return *reinterpret_cast<const floatx4_t*>(c + row);
+}
+__device__ __forceinline__ floatx4_t load4(const uint16_t* c, int64_t row) {
+  const uint2 w = *reinterpret_cast<const uint2*>(c + row);
+  floatx4_t f = {__uint_as_float(w.x << 16), __uint_as_float(w.x & 0xffff0000u),
+                 __uint_as_float(w.y << 16), __uint_as_float(w.y & 0xffff0000u)};
+  return f;
+}
+__device__ __forceinline__ float load1(const float* c, int64_t row) { return c[row]; }
+__device__ __forceinline__ float load1(const uint16_t* c, int64_t row) {
+  return bf16_to_f32(c[row]);
+}
+
+template <bool L1VAR, int R, typename TA>
 __global__ __launch_bounds__(kSpThreads) void sparse_ax_y_kernel(
-    const float* __restrict__ A, int64_t lda, int64_t n,
+    const TA* __restrict__ A, int64_t lda, int64_t n,
     const int32_t* __restrict__ list_idx, const float* __restrict__ list_val,
     int64_t ldl, float* __restrict__ Y, int64_t ldu, StartState s,
-    const Plan* plan) {
+    const Plan* plan, uint16_t* __restrict__ Yb, int64_t ldyb) {
   __shared__ int32_t sidx[kSpStage];
   __shared__ double sval[kSpStage];
   __shared__ double red[8];
@@ -363,7 +414,7 @@ __global__ __launch_bounds__(kSpThreads) void sparse_ax_y_kernel(
       __syncthreads();
       int32_t t = 0;
       for (; t + 4 <= m; t += 4) {
-        const float* c[4];
+        const TA* c[4];
         double xv[4];
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
@@ -378,12 +429,12 @@ __global__ __launch_bounds__(kSpThreads) void sparse_ax_y_kernel(
             if (ok[q]) {
               const int64_t row = 4 * g[q];
               if (row + 3 < n) {
-                a[e][q] = *reinterpret_cast<const floatx4_t*>(c[e] + row);
+                a[e][q] = load4(c[e], row);
               } else {
                 floatx4_t z = {0.f, 0.f, 0.f, 0.f};
-                if (row < n) z.x = c[e][row];
-                if (row + 1 < n) z.y = c[e][row + 1];
-                if (row + 2 < n) z.z = c[e][row + 2];
+                if (row < n) z.x = load1(c[e], row);
+                if (row + 1 < n) z.y = load1(c[e], row + 1);
+                if (row + 2 < n) z.z = load1(c[e], row + 2);
                 a[e][q] = z;
               }
             } else {
@@ -401,7 +452,7 @@ __global__ __launch_bounds__(kSpThreads) void sparse_ax_y_kernel(
           }
       }
       for (; t < m; ++t) {
-        const float* c0 = A + (int64_t)sidx[t] * lda;
+        const TA* c0 = A + (int64_t)sidx[t] * lda;
         const double x0 = sval[t];
 #pragma unroll
         for (int q = 0; q < R; ++q) {
@@ -409,7 +460,7 @@ __global__ __launch_bounds__(kSpThreads) void sparse_ax_y_kernel(
           const int64_t row = 4 * g[q];
 #pragma unroll
           for (int e = 0; e < 4; ++e)
-            if (row + e < n) acc[q][e] += (double)c0[row + e] * x0;
+            if (row + e < n) acc[q][e] += (double)load1(c0, row + e) * x0;
         }
       }
     }
@@ -445,23 +496,26 @@ __global__ __launch_bounds__(kSpThreads) void sparse_ax_y_kernel(
         const int64_t i = 4 * gq + e;
         if (i < n) {
           float t = y[i];
-          y[i] = L1VAR ? (float)((t > 0.f) - (t < 0.f)) : (float)((double)t * inv);
+          const float o = L1VAR ? (float)((t > 0.f) - (t < 0.f)) : (float)((double)t * inv);
+          y[i] = o;
+          if (Yb != nullptr) Yb[j * ldyb + i] = f32_to_bf16(o);
         }
       }
     }
   }
 }
 
-template <bool L1VAR>
-void launch_sparse(hipStream_t st, const float* A, int64_t lda, int64_t n,
+template <bool L1VAR, typename TA>
+void launch_sparse(hipStream_t st, const TA* A, int64_t lda, int64_t n,
                    const int32_t* li, const float* lv, int64_t ldl, float* Y,
-                   int64_t ldu, int64_t r, StartState s, const Plan* plan) {
+                   int64_t ldu, int64_t r, StartState s, const Plan* plan,
+                   uint16_t* Yb, int64_t ldyb) {
   const int64_t per = ceil_div(ceil_div(n, 4), kSpThreads);
   dim3 g((unsigned)r), b(kSpThreads);
   if (per <= 1)
-    hipLaunchKernelGGL((sparse_ax_y_kernel<L1VAR, 1>), g, b, 0, st, A, lda, n, li, lv, ldl, Y, ldu, s, plan);
+    hipLaunchKernelGGL((sparse_ax_y_kernel<L1VAR, 1, TA>), g, b, 0, st, A, lda, n, li, lv, ldl, Y, ldu, s, plan, Yb, ldyb);
   else
-    hipLaunchKernelGGL((sparse_ax_y_kernel<L1VAR, 2>), g, b, 0, st, A, lda, n, li, lv, ldl, Y, ldu, s, plan);
+    hipLaunchKernelGGL((sparse_ax_y_kernel<L1VAR, 2, TA>), g, b, 0, st, A, lda, n, li, lv, ldl, Y, ldu, s, plan, Yb, ldyb);
 }
 
 }  // namespace
@@ -527,21 +581,58 @@ void union_gather(hipStream_t st, const float* X, int64_t ldx, int64_t r,
                   const float* A, int64_t lda, int64_t n,
                   const int32_t* ulist, const Plan* plan, float* Xc,
                   int64_t ldxc, float* Qc, int64_t ldqc) {
-  const unsigned tile_blocks = 512;
-  hipLaunchKernelGGL(union_gather_kernel, dim3((unsigned)r + tile_blocks),
+  const unsigned blocks = 512;
+  hipLaunchKernelGGL(union_gather_kernel, dim3(blocks),
                      dim3(256), 0, st, X, ldx, r, A, lda, n, ulist, plan, Xc,
                      ldxc, Qc, ldqc);
 }
 
 void y_update(hipStream_t st, int fid, const float* U, int64_t split_stride,
               float* Y, int64_t ldu, int64_t r, int64_t n, StartState s,
-              const Plan* plan) {
+              const Plan* plan, uint16_t* Yb, int64_t ldyb) {
   if (l1_variance(fid))
     hipLaunchKernelGGL(y_update_kernel<true>, dim3((unsigned)r), dim3(256), 0,
-                       st, U, split_stride, Y, ldu, n, s, plan);
+                       st, U, split_stride, Y, ldu, n, s, plan, Yb, ldyb);
   else
     hipLaunchKernelGGL(y_update_kernel<false>, dim3((unsigned)r), dim3(256), 0,
-                       st, U, split_stride, Y, ldu, n, s, plan);
+                       st, U, split_stride, Y, ldu, n, s, plan, Yb, ldyb);
+}
+
+void to_bf16_colmajor(hipStream_t st, const float* A, int64_t lda, int64_t n,
+                      int64_t p, uint16_t* Ab, int64_t ldab) {
+  hipLaunchKernelGGL(to_bf16_col_kernel, dim3((unsigned)(p < 65536 ? p : 65536)),
+                     dim3(256), 0, st, A, lda, n, p, Ab, ldab);
+}
+
+void to_bf16_rowmajor(hipStream_t st, const float* A, int64_t lda, int64_t n,
+                      int64_t p, uint16_t* Atb, int64_t ldatb) {
+  dim3 grid((unsigned)ceil_div(n, 64), (unsigned)ceil_div(ldatb, 64));
+  hipLaunchKernelGGL(to_bf16_row_kernel, grid, dim3(256), 0, st, A, lda, n, p,
+                     Atb, ldatb);
+}
+
+void rows_to_bf16(hipStream_t st, const float* X, int64_t ldx, int64_t r,
+                  int64_t p, uint16_t* Xb, int64_t ldxb, const Plan* plan) {
+  hipLaunchKernelGGL(rows_to_bf16_kernel, dim3((unsigned)r), dim3(256), 0, st,
+                     X, ldx, p, Xb, ldxb, plan);
+}
+
+__global__ __launch_bounds__(256) void gather_columns_kernel(
+    const float* __restrict__ A, int64_t lda, int64_t n,
+    const int32_t* __restrict__ idx, int64_t m, float* __restrict__ As,
+    int64_t ldas) {
+  for (int64_t t = blockIdx.x; t < m; t += gridDim.x) {
+    const float* col = A + (int64_t)idx[t] * lda;
+    for (int64_t i = threadIdx.x; i < ldas; i += 256)
+      As[t * ldas + i] = i < n ? col[i] : 0.f;
+  }
+}
+
+void gather_columns(hipStream_t st, const float* A, int64_t lda, int64_t n,
+                    const int32_t* idx, int64_t m, float* As, int64_t ldas) {
+  if (m <= 0) return;
+  hipLaunchKernelGGL(gather_columns_kernel, dim3((unsigned)(m < 65536 ? m : 65536)),
+                     dim3(256), 0, st, A, lda, n, idx, m, As, ldas);
 }
 
 void sparse_ax_y_update(hipStream_t st, int fid, const float* A, int64_t lda,
@@ -549,9 +640,20 @@ void sparse_ax_y_update(hipStream_t st, int fid, const float* A, int64_t lda,
                         const float* list_val, int64_t ldl, float* Y,
                         int64_t ldu, int64_t r, StartState s, const Plan* plan) {
   if (l1_variance(fid))
-    launch_sparse<true>(st, A, lda, n, list_idx, list_val, ldl, Y, ldu, r, s, plan);
+    launch_sparse<true, float>(st, A, lda, n, list_idx, list_val, ldl, Y, ldu, r, s, plan, nullptr, 0);
   else
-    launch_sparse<false>(st, A, lda, n, list_idx, list_val, ldl, Y, ldu, r, s, plan);
+    launch_sparse<false, float>(st, A, lda, n, list_idx, list_val, ldl, Y, ldu, r, s, plan, nullptr, 0);
+}
+
+void sparse_ax_y_update_bf16(hipStream_t st, int fid, const uint16_t* Ab,
+                             int64_t ldab, int64_t n, const int32_t* list_idx,
+                             const float* list_val, int64_t ldl, float* Y,
+                             int64_t ldu, uint16_t* Yb, int64_t ldyb, int64_t r,
+                             StartState s, const Plan* plan) {
+  if (l1_variance(fid))
+    launch_sparse<true, uint16_t>(st, Ab, ldab, n, list_idx, list_val, ldl, Y, ldu, r, s, plan, Yb, ldyb);
+  else
+    launch_sparse<false, uint16_t>(st, Ab, ldab, n, list_idx, list_val, ldl, Y, ldu, r, s, plan, Yb, ldyb);
 }
 
 }  // namespace spca

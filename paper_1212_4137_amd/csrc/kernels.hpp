@@ -51,8 +51,10 @@ struct GemmPlan {
   int splits;
 };
 
-// Deterministic shape / split choice for an M x N x K product.
-GemmPlan plan_gemm_nt(int64_t M, int64_t N, int64_t K, int max_splits);
+// Deterministic shape / split choice for an M x N x K product with
+// elem_bytes-byte operands (4: FP32, 2: BF16).
+GemmPlan plan_gemm_nt(int64_t M, int64_t N, int64_t K, int max_splits,
+                      int elem_bytes = 4);
 int gemm_num_shapes();
 
 // C (M x N, ldc) = P (M x K, ldp) * Q (N x K, ldq)^T, FP32 MFMA.  With
@@ -66,9 +68,31 @@ void gemm_nt_f32(hipStream_t st, const float* P, int64_t ldp, const float* Q,
                  GemmPlan plan, int64_t split_stride,
                  const int32_t* kdev = nullptr);
 
+// The same product with BF16 operands (bit patterns, ld multiple of 8 and
+// 16-byte aligned rows), FP32 accumulation and output.
+void gemm_nt_bf16(hipStream_t st, const uint16_t* P, int64_t ldp,
+                  const uint16_t* Q, int64_t ldq, float* C, int64_t ldc,
+                  int64_t M, int64_t N, int64_t K, const int32_t* gate,
+                  int32_t gate_run, GemmPlan plan, int64_t split_stride);
+
 // Row-major copy: At[i * ldat + k] = A[i + k * lda] (i < n, k < p).
 void transpose_f32(hipStream_t st, const float* A, int64_t lda, float* At,
                    int64_t ldat, int64_t n, int64_t p);
+
+// BF16 copies of A: column-major Ab (ldab, rows n..ldab zero) and row-major
+// Atb (ldatb, columns p..ldatb zero).
+void to_bf16_colmajor(hipStream_t st, const float* A, int64_t lda, int64_t n,
+                      int64_t p, uint16_t* Ab, int64_t ldab);
+void to_bf16_rowmajor(hipStream_t st, const float* A, int64_t lda, int64_t n,
+                      int64_t p, uint16_t* Atb, int64_t ldatb);
+// BF16 copy of the rows of a row-major FP32 matrix.
+// Runs only when plan is null or selects the dense product.
+void rows_to_bf16(hipStream_t st, const float* X, int64_t ldx, int64_t r,
+                  int64_t p, uint16_t* Xb, int64_t ldxb, const Plan* plan);
+
+// As[:, t] = A[:, idx[t]] for t < m (FP32, column-major, ldas).
+void gather_columns(hipStream_t st, const float* A, int64_t lda, int64_t n,
+                    const int32_t* idx, int64_t m, float* As, int64_t ldas);
 
 // Column-major copy with a new leading dimension.
 void copy_columns_f32(hipStream_t st, const float* A, int64_t lda, float* B,
@@ -117,9 +141,10 @@ void union_gather(hipStream_t st, const float* X, int64_t ldx, int64_t r,
 // partial products split_stride floats apart that are summed in order:
 // Y = sgn(U) (L1 variance) or U / ||U||_2 per row (L2 variance); a zero row
 // ends its start as DEGENERATE.  Skipped in list mode.
+// With Yb != nullptr the rows are also written as BF16 (ldyb).
 void y_update(hipStream_t st, int fid, const float* U, int64_t split_stride,
               float* Y, int64_t ldu, int64_t r, int64_t n, StartState s,
-              const Plan* plan);
+              const Plan* plan, uint16_t* Yb = nullptr, int64_t ldyb = 0);
 
 // Sparse A x from the lists followed by the y-update, one block per start.
 // Runs only in list mode.
@@ -127,6 +152,12 @@ void sparse_ax_y_update(hipStream_t st, int fid, const float* A, int64_t lda,
                         int64_t n, const int32_t* list_idx,
                         const float* list_val, int64_t ldl, float* Y,
                         int64_t ldu, int64_t r, StartState s, const Plan* plan);
+// The same with a BF16 column-major A (ldab % 4 == 0); Y also as BF16.
+void sparse_ax_y_update_bf16(hipStream_t st, int fid, const uint16_t* Ab,
+                             int64_t ldab, int64_t n, const int32_t* list_idx,
+                             const float* list_val, int64_t ldl, float* Y,
+                             int64_t ldu, uint16_t* Yb, int64_t ldyb, int64_t r,
+                             StartState s, const Plan* plan);
 
 // x-update of Algorithm 2 on the rows of V with the stop test of Section
 // 2.2.  Rows with at most list_cap nonzeros also get their (index, value)

@@ -12,6 +12,7 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <algorithm>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -37,11 +38,15 @@ inline int list_cap_of(int64_t p) {
 }
 
 constexpr int kMaxSplits = 16;  // K splits of the dense A x product
+constexpr int kPolishMax = 32;      // starts polished in FP32 (BF16 mode)
+constexpr double kPolishBand = 2e-3;  // relative band of polished starts
 
 struct Layout {
   int64_t n, p, r;
   int64_t ldx, ldu, ldat, ldac;
-  bool copy_a;
+  bool copy_a, bf16;
+  int64_t ldab, ldatb, ldyb, ldxb;
+  size_t off_Ab, off_Atb, off_Yb, off_Xb, off_Xp;
   GemmPlan plan_ax, plan_aty;
   size_t off_At, off_Ac, off_X, off_U, off_Y, off_V, off_li, off_lv;
   size_t off_phi, off_phip, off_nnz, off_it, off_st, off_plan, off_part,
@@ -59,7 +64,7 @@ size_t carve(size_t* cur, size_t bytes) {
   return o;
 }
 
-Layout make_layout(int64_t n, int64_t p, int64_t r, bool copy_a) {
+Layout make_layout(int64_t n, int64_t p, int64_t r, bool copy_a, bool bf16) {
   Layout L;
   L.n = n;
   L.p = p;
@@ -69,16 +74,29 @@ Layout make_layout(int64_t n, int64_t p, int64_t r, bool copy_a) {
   L.ldat = round_up(p, 4);
   L.ldac = round_up(n, 4);
   L.copy_a = copy_a;
+  L.bf16 = bf16;
+  L.ldab = round_up(n, 8);
+  L.ldatb = round_up(p, 8);
+  L.ldyb = round_up(n, 8);
+  L.ldxb = round_up(p, 8);
   L.nchunks = (int)ceil_div(n, 256);
-  L.plan_ax = plan_gemm_nt(r, n, p, kMaxSplits);   // U^T = X^T A^T, K = p
-  L.plan_aty = plan_gemm_nt(r, p, n, 1);           // V^T = Y^T A,   K = n
-  // union product: K = u <= ucap columns, gathered A is n x ucap (<= 256 MB)
-  L.ucap = p;
+  const int eb = bf16 ? 2 : 4;
+  L.plan_ax = plan_gemm_nt(r, n, p, kMaxSplits, eb);   // U^T = X^T A^T, K = p
+  L.plan_aty = plan_gemm_nt(r, p, n, 1, eb);           // V^T = Y^T A,   K = n
+  // union product (FP32 only): K = u <= ucap columns, gathered A is
+  // n x ucap (<= 256 MB)
+  L.ucap = bf16 ? 0 : p;
   const int64_t mem_cap = (int64_t)(64LL << 20) / (n > 0 ? n : 1);
   if (L.ucap > mem_cap) L.ucap = mem_cap < 1024 ? (p < 1024 ? p : 1024) : mem_cap;
-  L.plan_union = plan_gemm_nt(r, n, L.ucap < 256 ? L.ucap : 256, 1);
+  L.plan_union = plan_gemm_nt(r, n, L.ucap < 256 ? (L.ucap > 0 ? L.ucap : 1) : 256, 1);
   size_t c = 0;
-  L.off_At = carve(&c, sizeof(float) * (size_t)n * L.ldat);
+  L.off_At = carve(&c, bf16 ? 0 : sizeof(float) * (size_t)n * L.ldat);
+  L.off_Ab = carve(&c, bf16 ? sizeof(uint16_t) * (size_t)p * L.ldab : 0);
+  L.off_Atb = carve(&c, bf16 ? sizeof(uint16_t) * (size_t)n * L.ldatb : 0);
+  L.off_Yb = carve(&c, bf16 ? sizeof(uint16_t) * (size_t)r * L.ldyb : 0);
+  L.off_Xb = carve(&c, bf16 ? sizeof(uint16_t) * (size_t)r * L.ldxb : 0);
+  L.off_Xp = carve(&c, bf16 ? sizeof(float) * (size_t)kPolishMax * p : 0);
+
   L.off_Ac = carve(&c, copy_a ? sizeof(float) * (size_t)p * L.ldac : 0);
   L.off_X = carve(&c, sizeof(float) * (size_t)r * L.ldx);
   L.off_U = carve(&c, sizeof(float) * (size_t)L.plan_ax.splits * r * L.ldu);
@@ -187,6 +205,7 @@ struct spca_ctx {
   size_t ws_cap = 0;
   int32_t* host_poll = nullptr;  // pinned
   EventPairs t_aty, t_xup, t_ax;
+  spca_ctx* polish = nullptr;  // context of the FP32 polish sub-solves
   std::mutex mu;
 };
 
@@ -197,9 +216,8 @@ extern "C" {
 const char* spca_last_error(void) { return spca::last_error(); }
 
 size_t spca_workspace_bytes(int64_t n, int64_t p, int32_t r, int precision) {
-  (void)precision;
   if (n < 1 || p < 1 || r < 1) return 0;
-  return make_layout(n, p, r, true).total;
+  return make_layout(n, p, r, true, precision == SPCA_PREC_BF16_POLISH).total;
 }
 
 int spca_ctx_create(spca_ctx** ctx, int device, size_t hbm_budget_bytes) {
@@ -226,6 +244,7 @@ int spca_ctx_create(spca_ctx** ctx, int device, size_t hbm_budget_bytes) {
 
 int spca_ctx_destroy(spca_ctx* ctx) {
   if (ctx == nullptr) return SPCA_OK;
+  if (ctx->polish) spca_ctx_destroy(ctx->polish);
   {
     DeviceGuard g(ctx->device);
     if (ctx->ws) {
@@ -266,6 +285,46 @@ static int ensure_workspace(spca_ctx* ctx, hipStream_t st, size_t bytes) {
   return SPCA_OK;
 }
 
+// a7 polish: FP32 AM of the same formulation on the caller's FP32 A, run
+// as one batched solve from the BF16-phase iterates of the candidate starts
+// (rows of Xp), for at most polish_maxit iterations with the same stop
+// test.  Candidates are the starts whose BF16-phase objective lies within
+// the BF16 error band (2e-3 relative) of the best, since BF16 iterates
+// cannot rank starts closer than that.  Working on all of A (not only on
+// the BF16-phase supports) lets a column that BF16 rounding moved across a
+// selection threshold come back.  The best polished start replaces the
+// result when its FP64 objective does not decrease.
+
+static int polish_best(spca_ctx* ctx, hipStream_t st, const spca_problem* prob,
+                       const spca_solve_opts* opts, const float* Xp,
+                       int32_t nc, spca_outputs* out) {
+  if (ctx->polish == nullptr) {
+    int rc = spca_ctx_create(&ctx->polish, ctx->device, 0);
+    if (rc != SPCA_OK) return rc;
+  }
+  spca_problem sub = *prob;
+  spca_solve_opts so{Xp, nc, opts->tol, opts->polish_maxit, SPCA_PREC_FP32, 0,
+                     opts->check_every, opts->flags & ~SPCA_FLAG_GRAPH};
+  std::vector<double> xsub(prob->p);
+  std::vector<int32_t> ssub(prob->p);
+  spca_result rsub{};
+  spca_outputs o{};
+  o.x = xsub.data();
+  o.support = ssub.data();
+  o.res = &rsub;
+  int rc = spca_am_solve_ex(ctx->polish, st, &sub, &so, &o);
+  if (rc != SPCA_OK) return rc;
+  spca_result* res = out->res;
+  if (!(rsub.objective >= res->objective_pre_polish)) return SPCA_OK;
+  res->objective = rsub.objective;
+  res->explained_var = rsub.explained_var;
+  res->nnz = rsub.nnz;
+  res->polish_iters = rsub.iters;
+  if (out->x) std::copy(xsub.begin(), xsub.end(), out->x);
+  if (out->support) std::copy(ssub.begin(), ssub.begin() + rsub.nnz, out->support);
+  return SPCA_OK;
+}
+
 int spca_am_solve_ex(spca_ctx* ctx, void* stream, const spca_problem* prob,
                      const spca_solve_opts* opts, spca_outputs* out) {
   SPCA_REQUIRE(ctx && prob && opts && out && out->res,
@@ -282,16 +341,16 @@ int spca_am_solve_ex(spca_ctx* ctx, void* stream, const spca_problem* prob,
   SPCA_REQUIRE(opts->precision == SPCA_PREC_FP32 ||
                    opts->precision == SPCA_PREC_BF16_POLISH,
                "precision must be SPCA_PREC_FP32 or SPCA_PREC_BF16_POLISH");
-  SPCA_REQUIRE(opts->precision == SPCA_PREC_FP32,
-               "SPCA_PREC_BF16_POLISH is not available in this build");
+  SPCA_REQUIRE(opts->polish_maxit >= 0, "polish_maxit must be >= 0");
   SPCA_REQUIRE(opts->check_every >= 1, "check_every must be >= 1");
+  const bool bf16 = opts->precision == SPCA_PREC_BF16_POLISH;
 
   std::lock_guard<std::mutex> lock(ctx->mu);
   DeviceGuard g(ctx->device);
   hipStream_t st = (hipStream_t)stream;
 
   const bool copy_a = (lda % 4) != 0 || ((uintptr_t)prob->A % 16) != 0;
-  const Layout L = make_layout(n, p, r, copy_a);
+  const Layout L = make_layout(n, p, r, copy_a, bf16);
   rc = ensure_workspace(ctx, st, L.total);
   if (rc != SPCA_OK) return rc;
   char* base = (char*)ctx->ws;
@@ -320,6 +379,10 @@ int spca_am_solve_ex(spca_ctx* ctx, void* stream, const spca_problem* prob,
   float* Xc = (float*)(base + L.off_Xc);
   float* Qc = (float*)(base + L.off_Qc);
   const int64_t ldc_u = round_up(L.ucap, 4);
+  uint16_t* Ab = (uint16_t*)(base + L.off_Ab);
+  uint16_t* Atb = (uint16_t*)(base + L.off_Atb);
+  uint16_t* Yb = (uint16_t*)(base + L.off_Yb);
+  uint16_t* Xb = (uint16_t*)(base + L.off_Xb);
 
   // a0: stage A (aligned column-major copy only when needed) and its
   // row-major twin used by the dense A x.
@@ -339,8 +402,14 @@ int spca_am_solve_ex(spca_ctx* ctx, void* stream, const spca_problem* prob,
     SPCA_HIP_TRY(hipStreamSynchronize(st));
     SPCA_REQUIRE(ctx->host_poll[0] == 0, "A holds NaN or Inf entries");
   }
-  transpose_f32(st, A, ldA, At, L.ldat, n, p);
-  SPCA_LAUNCH_CHECK("transpose");
+  if (bf16) {
+    // a7: A in BF16, column-major (for A^T Y) and row-major (for A X)
+    to_bf16_colmajor(st, A, ldA, n, p, Ab, L.ldab);
+    to_bf16_rowmajor(st, A, ldA, n, p, Atb, L.ldatb);
+  } else {
+    transpose_f32(st, A, ldA, At, L.ldat, n, p);
+  }
+  SPCA_LAUNCH_CHECK("layout copies of A");
 
   // starting points
   if (opts->X0 != nullptr) {
@@ -363,6 +432,7 @@ int spca_am_solve_ex(spca_ctx* ctx, void* stream, const spca_problem* prob,
               colmark, ulist, plan);
   };
   plan_iter();
+  if (bf16) rows_to_bf16(st, X, L.ldx, r, p, Xb, L.ldxb, plan);
   SPCA_LAUNCH_CHECK("staging");
 
   const int32_t maxit = opts->maxit;
@@ -373,24 +443,40 @@ int spca_am_solve_ex(spca_ctx* ctx, void* stream, const spca_problem* prob,
   for (int32_t it = 0; it < maxit; ++it) {
     // u = A x and the y-update
     if (timed) SPCA_HIP_TRY(ctx->t_ax.mark(st));
-    gemm_nt_f32(st, X, L.ldx, At, L.ldat, U, L.ldu, r, n, p, &plan->mode,
-                kAxDense, L.plan_ax, r * L.ldu);
+    if (bf16)
+      gemm_nt_bf16(st, Xb, L.ldxb, Atb, L.ldatb, U, L.ldu, r, n, p, &plan->mode,
+                   kAxDense, L.plan_ax, r * L.ldu);
+    else
+      gemm_nt_f32(st, X, L.ldx, At, L.ldat, U, L.ldu, r, n, p, &plan->mode,
+                  kAxDense, L.plan_ax, r * L.ldu);
     if (timed) SPCA_HIP_TRY(ctx->t_ax.mark(st));
-    union_gather(st, X, L.ldx, r, A, ldA, n, ulist, plan, Xc, ldc_u, Qc, ldc_u);
-    gemm_nt_f32(st, Xc, ldc_u, Qc, ldc_u, U, L.ldu, r, n, L.ucap, &plan->mode,
-                kAxUnion, L.plan_union, 0, &plan->union_size);
-    y_update(st, fid, U, r * L.ldu, Y, L.ldu, r, n, s, plan);
-    sparse_ax_y_update(st, fid, A, ldA, n, li, lv, L.ldx, Y, L.ldu, r, s, plan);
+    if (!bf16) {
+      union_gather(st, X, L.ldx, r, A, ldA, n, ulist, plan, Xc, ldc_u, Qc, ldc_u);
+      gemm_nt_f32(st, Xc, ldc_u, Qc, ldc_u, U, L.ldu, r, n, L.ucap, &plan->mode,
+                  kAxUnion, L.plan_union, 0, &plan->union_size);
+    }
+    y_update(st, fid, U, r * L.ldu, Y, L.ldu, r, n, s, plan, bf16 ? Yb : nullptr,
+             L.ldyb);
+    if (bf16)
+      sparse_ax_y_update_bf16(st, fid, Ab, L.ldab, n, li, lv, L.ldx, Y, L.ldu, Yb,
+                              L.ldyb, r, s, plan);
+    else
+      sparse_ax_y_update(st, fid, A, ldA, n, li, lv, L.ldx, Y, L.ldu, r, s, plan);
     // v = A^T y and the x-update with the stop test
     if (timed) SPCA_HIP_TRY(ctx->t_aty.mark(st));
-    gemm_nt_f32(st, Y, L.ldu, A, ldA, V, L.ldx, r, p, n, nullptr, 0,
-                L.plan_aty, 0);
+    if (bf16)
+      gemm_nt_bf16(st, Yb, L.ldyb, Ab, L.ldab, V, L.ldx, r, p, n, nullptr, 0,
+                   L.plan_aty, 0);
+    else
+      gemm_nt_f32(st, Y, L.ldu, A, ldA, V, L.ldx, r, p, n, nullptr, 0,
+                  L.plan_aty, 0);
     if (timed) SPCA_HIP_TRY(ctx->t_aty.mark(st));
     if (timed) SPCA_HIP_TRY(ctx->t_xup.mark(st));
     x_update(st, fid, sg, V, L.ldx, r, p, X, L.ldx, li, lv, L.ldx, list_cap, s,
              opts->tol, maxit, colmark, plan);
     if (timed) SPCA_HIP_TRY(ctx->t_xup.mark(st));
     plan_iter();
+    if (bf16) rows_to_bf16(st, X, L.ldx, r, p, Xb, L.ldxb, plan);
     SPCA_LAUNCH_CHECK("AM iteration");
     if ((it + 1) % opts->check_every == 0 && it + 1 < maxit) {
       SPCA_HIP_TRY(hipMemcpyAsync(ctx->host_poll, &plan->active, sizeof(int32_t),
@@ -455,6 +541,8 @@ int spca_am_solve_ex(spca_ctx* ctx, void* stream, const spca_problem* prob,
   for (int64_t j = 0; j < r; ++j) total_iters += it_all[j];
   spca_result* res = out->res;
   res->objective = f_all[jb];
+  res->objective_pre_polish = f_all[jb];
+  res->polish_iters = 0;
   res->explained_var = ev_all[jb];
   res->phi = phi_all[jb];
   res->iters_x_starts = total_iters;
@@ -462,6 +550,25 @@ int spca_am_solve_ex(spca_ctx* ctx, void* stream, const spca_problem* prob,
   res->nnz = nnzb;
   res->iters = it_all[jb];
   res->status = st_all[jb];
+  if (bf16 && opts->polish_maxit > 0 && nnzb > 0) {
+    // candidates: best first, then by decreasing objective inside the band
+    std::vector<int32_t> order;
+    const double fb = f_all[jb];
+    const double floor_f = fb - kPolishBand * fabs(fb);
+    for (int64_t j = 0; j < r; ++j)
+      if (j != jb && nnz_all[j] > 0 && f_all[j] >= floor_f) order.push_back((int32_t)j);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int32_t a, int32_t b) { return f_all[a] > f_all[b]; });
+    order.insert(order.begin(), jb);
+    if ((int)order.size() > kPolishMax) order.resize(kPolishMax);
+    float* Xp = (float*)(base + L.off_Xp);
+    for (size_t c = 0; c < order.size(); ++c)
+      SPCA_HIP_TRY(hipMemcpyAsync(Xp + c * p, X + (int64_t)order[c] * L.ldx,
+                                  sizeof(float) * p, hipMemcpyDeviceToDevice, st));
+    // the context lock is held, so the workspace stays valid meanwhile
+    rc = polish_best(ctx, st, prob, opts, Xp, (int32_t)order.size(), out);
+    if (rc != SPCA_OK) return rc;
+  }
   for (int64_t j = 0; j < r; ++j) {
     if (out->f_per_start) out->f_per_start[j] = f_all[j];
     if (out->ev_per_start) out->ev_per_start[j] = ev_all[j];
@@ -541,6 +648,24 @@ int spca_gemm_nt_f32_shape(void* stream, const float* P, int64_t ldp,
   gemm_nt_f32((hipStream_t)stream, P, ldp, Q, ldq, C, ldc, M, N, K, nullptr, 0,
               GemmPlan{shape, splits}, M * ldc);
   SPCA_LAUNCH_CHECK("gemm_nt_f32");
+  return SPCA_OK;
+}
+
+int spca_gemm_nt_bf16(void* stream, const uint16_t* P, int64_t ldp,
+                      const uint16_t* Q, int64_t ldq, float* C, int64_t ldc,
+                      int64_t M, int64_t N, int64_t K) {
+  SPCA_REQUIRE(P && Q && C, "P, Q and C must not be NULL");
+  SPCA_REQUIRE(M >= 0 && N >= 0 && K >= 0, "sizes must be >= 0");
+  SPCA_REQUIRE(M <= INT32_MAX && N <= INT32_MAX && K <= INT32_MAX,
+               "sizes must fit in int32");
+  SPCA_REQUIRE(ldp >= K && ldq >= K && ldc >= N, "leading dimensions too small");
+  SPCA_REQUIRE(ldp % 8 == 0 && ldq % 8 == 0,
+               "ldp and ldq must be multiples of 8");
+  SPCA_REQUIRE((uintptr_t)P % 16 == 0 && (uintptr_t)Q % 16 == 0,
+               "P and Q must be 16-byte aligned");
+  gemm_nt_bf16((hipStream_t)stream, P, ldp, Q, ldq, C, ldc, M, N, K, nullptr, 0,
+               plan_gemm_nt(M, N, K, 1, 2), 0);
+  SPCA_LAUNCH_CHECK("gemm_nt_bf16");
   return SPCA_OK;
 }
 

@@ -644,8 +644,10 @@ __device__ void radix_select(float (&v)[NPT], uint32_t need, RSmem& sm,
   *above_out = above;
 }
 
+// Register budget: the top-s kernel keeps its keys live across the radix
+// passes and is left at 2 waves per SIMD; the others fit 4.
 template <int KIND, int NPT>
-__global__ __launch_bounds__(kRT) void x_update_reg_kernel(
+__global__ __launch_bounds__(kRT, KIND == kTopS ? 2 : 4) void x_update_reg_kernel(
     const float* __restrict__ V, int64_t ldv, int p, double param,
     float* __restrict__ X, int64_t ldx, int32_t* __restrict__ list_idx,
     float* __restrict__ list_val, int64_t ldl, int list_cap, StartState s,
