@@ -218,6 +218,24 @@ int spca_x_update(void* stream, int formulation, const float* V, int64_t ldv,
                   int64_t r, int64_t p, double s_or_gamma, float* X,
                   int64_t ldx, double* phi, int32_t* nnz);
 
+/* ---------------------------------------------------------------------- */
+/* Synthetic data (workload generation, not part of the method).           */
+
+/* Writes the n x p spiked matrix A = G + sum_k theta_k u_k v_k^T into A
+ * (device, FP32, column-major, lda >= n).  G[i, j] is a function of
+ * (seed, i, j) only: one Philox4x32-10 block (Salmon et al., SC'11) with
+ * counter (i, j, 0, 0) and key (seed & 0xffffffff, seed >> 32); with w_q the
+ * top 24 bits of its four outputs, G = ((w_0+w_1+w_2+w_3) 2^-24 - 2) sqrt(3)
+ * in FP64 (mean 0, variance 1).  The spikes are added in FP64 left to right
+ * in k, each term (theta_k U[i,k]) V[j,k], then rounded once to FP32.
+ * thetas: host, k values (0 <= k <= 16); U: device FP64 n x k column-major
+ * (ldu >= n); V: device FP64 p x k column-major (ldv >= p).  Enqueues on
+ * the stream and returns.                                                  */
+int spca_generate_spiked(void* stream, uint64_t seed, int64_t n, int64_t p,
+                         float* A, int64_t lda, int32_t k, const double* thetas,
+                         const double* U, int64_t ldu, const double* V,
+                         int64_t ldv);
+
 #ifdef __cplusplus
 }
 #endif

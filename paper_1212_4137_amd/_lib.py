@@ -24,7 +24,7 @@ FLAG_GRAPH, FLAG_CHECK_FINITE, FLAG_DENSE_ONLY = 1, 2, 4
 EXPORTED = ("spca_am_solve", "spca_am_solve_ex", "spca_ctx_create",
             "spca_ctx_destroy", "spca_workspace_bytes", "spca_last_error",
             "spca_gemm_nt_f32", "spca_gemm_nt_bf16", "spca_gemm_nt_f32_shape",
-            "spca_gemm_nt_f32_plan", "spca_x_update")
+            "spca_gemm_nt_f32_plan", "spca_x_update", "spca_generate_spiked")
 
 
 class SpcaError(RuntimeError):
@@ -97,6 +97,9 @@ def load():
         lib.spca_gemm_nt_f32.restype = ctypes.c_int
         lib.spca_gemm_nt_bf16.argtypes = [P, P, i64, P, i64, P, i64, i64, i64, i64]
         lib.spca_gemm_nt_bf16.restype = ctypes.c_int
+        lib.spca_generate_spiked.argtypes = [P, ctypes.c_uint64, i64, i64, P, i64, i32,
+                                             P, P, i64, P, i64]
+        lib.spca_generate_spiked.restype = ctypes.c_int
         lib.spca_gemm_nt_f32_shape.argtypes = [P, P, i64, P, i64, P, i64, i64, i64, i64,
                                                ctypes.c_int, ctypes.c_int]
         lib.spca_gemm_nt_f32_shape.restype = ctypes.c_int
@@ -280,6 +283,30 @@ def gemm_nt(P, Q, stream=None):
                                    P.stride(0), ctypes.c_void_p(Q.data_ptr()), Q.stride(0),
                                    ctypes.c_void_p(C.data_ptr()), N, M, N, K))
     return C
+
+
+def generate_spiked(seed, n, p, thetas=(), U=None, V=None, lda=None, device="cuda:0",
+                    stream=None):
+    """Device-generated spiked matrix (``spca_generate_spiked``) as a
+    column-major (n, p) float32 tensor.  U (n x k) and V (p x k) are host
+    float64 arrays of the spike directions."""
+    import torch
+
+    lda = lda or n
+    buf = torch.empty((p, lda), dtype=torch.float32, device=device)
+    k = len(thetas)
+    th = np.ascontiguousarray(np.asarray(thetas, dtype=np.float64))
+    Ud = Vd = None
+    if k:
+        Ud = torch.from_numpy(np.asfortranarray(U, dtype=np.float64).T.copy()).to(device)
+        Vd = torch.from_numpy(np.asfortranarray(V, dtype=np.float64).T.copy()).to(device)
+    _check(load().spca_generate_spiked(_stream_ptr(stream), int(seed), n, p,
+                                       ctypes.c_void_p(buf.data_ptr()), lda, k,
+                                       _np_ptr(th) if k else None,
+                                       ctypes.c_void_p(Ud.data_ptr()) if k else None, n,
+                                       ctypes.c_void_p(Vd.data_ptr()) if k else None, p))
+    torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
+    return buf[:, :n].t()
 
 
 def gemm_nt_bf16(P, Q, stream=None):
