@@ -56,26 +56,39 @@ def cpu_baseline(A_np, X0_np, params, maxit_sample=25):
                       f"{threads} threads over starts)"}
 
 
-def main():
-    ap = argparse.ArgumentParser(description=__doc__,
-                                 formatter_class=argparse.RawDescriptionHelpFormatter)
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--fids", default="1,2,3,4,5,6,7,8",
-                    help="formulations in a step (default: all 8)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported: "
-              "the batched AM path runs on a single MI355X", file=sys.stderr)
-        sys.exit(2)
+def _roofline_aty(kt, r, n, p, peak, unit_flops_name="TFLOP/s"):
+    """Roofline point of the dominant kernel, V = A^T Y: 2 r n p flops per
+    launch over the average launch time measured with HIP events."""
+    launches = kt["aty_launches"]
+    avg_ms = kt["aty_ms"] / launches
+    achieved = 2.0 * r * n * p / (avg_ms * 1e-3) / 1e12
+    return {"kernel": "gemm_nt (V = A^T Y)", "bound": "mfma",
+            "achieved": round(achieved, 2), "peak": peak, "unit": unit_flops_name,
+            "frac": round(achieved / peak, 4), "traffic": None,
+            "avg_launch_ms": round(avg_ms, 5), "launches": int(launches)}
 
+
+def _timed_steps(step, steps, warmup):
     import torch
 
-    import paper_1212_4137_amd as spca
+    for _ in range(warmup):
+        step(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    outs = [step(True) for _ in range(steps)]
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, outs
 
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
+
+def _sum_kt(outs):
+    kt = {}
+    for o in outs:
+        for k, v in o["kt"].items():
+            kt[k] = kt.get(k, 0) + v
+    return kt
+
+
+def bench_all8(args, spca, torch):
     dev = torch.device("cuda:0")
     cfg = workloads.SPIKED_ALL8
     n, p, r, maxit = cfg["n"], cfg["p"], cfg["r"], cfg["maxit"]
@@ -89,7 +102,6 @@ def main():
     X0 = torch.from_numpy(X0_np).to(dev)
     ctx = spca.Context(0)
     stream = torch.cuda.current_stream()
-
     modes = {}
 
     def step(timing):
@@ -98,7 +110,8 @@ def main():
         nnz = {}
         for fid in fids:
             res = spca.am_solve(A, fid, params[fid], X0, tol=-1.0, maxit=maxit,
-                                ctx=ctx, stream=stream, kernel_times=timing)
+                                ctx=ctx, stream=stream, kernel_times=timing,
+                                flags=args.flags)
             work += res["iters_x_starts"]
             nnz[fid] = float(np.mean(res["nnz_per_start"]))
             if timing:
@@ -106,38 +119,16 @@ def main():
                     kt[k] = kt.get(k, 0) + v
                 t = res["kernel_times"]
                 modes[fid] = (t["iters_dense"], t["iters_list"], t["iters_union"])
-        return work, kt, nnz
+        return {"work": work, "kt": kt, "nnz": nnz}
 
-    for _ in range(args.warmup):
-        step(False)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    work = 0.0
-    kt_all = {}
-    nnz = {}
-    for _ in range(args.steps):
-        w, kt, nnz = step(True)
-        work += w
-        for k, v in kt.items():
-            kt_all[k] = kt_all.get(k, 0) + v
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-
-    # dominant kernel: V = A^T Y, 2 r n p flops per launch (dense product)
-    launches = kt_all["aty_launches"]
-    avg_ms = kt_all["aty_ms"] / launches
-    flops = 2.0 * r * n * p
-    achieved = flops / (avg_ms * 1e-3) / 1e12
-    roofline = {"kernel": "gemm_nt_f32 (V = A^T Y)", "bound": "mfma",
-                "achieved": round(achieved, 2), "peak": PEAK_FP32_MFMA_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_MFMA_TFLOPS, 4),
-                "traffic": None, "avg_launch_ms": round(avg_ms, 5),
-                "launches": int(launches)}
+    dt, outs = _timed_steps(step, args.steps, args.warmup)
+    work = sum(o["work"] for o in outs)
+    kt_all = _sum_kt(outs)
+    roofline = _roofline_aty(kt_all, r, n, p, PEAK_FP32_MFMA_TFLOPS)
     other = {"x_update_avg_ms": round(kt_all["x_update_ms"] / kt_all["x_update_launches"], 5),
              "ax_dense_avg_ms": round(kt_all["ax_dense_ms"] / kt_all["ax_dense_launches"], 5),
-             "mean_nnz_per_start": nnz,
+             "mean_nnz_per_start": outs[-1]["nnz"],
              "ax_modes_dense_list_union": modes}
-
     rec = {
         "metric": "AM iters x starts/sec",
         "value": work / dt,
@@ -160,6 +151,141 @@ def main():
     }
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(A_np, X0_np, params)
+    return rec
+
+
+def bench_large(args, spca, torch):
+    """One-GPU large instance: 20000 x 200000 FP32 (16 GB) generated in HBM
+    by the counter-based generator, F1 with s = 200, 64 starts; a step is one
+    solve with the stop test disabled (fixed work of maxit iterations)."""
+    from workloads import counter
+
+    cfg = workloads.SPIKED_LARGE
+    n, p, r = cfg["n"], cfg["p"], cfg["r"]
+    maxit = args.maxit or 30
+    f = counter.spike_factors(cfg["seed"], n, p, cfg["thetas"], cfg["spike_nnz"])
+    A = spca.generate_spiked(cfg["seed"], n, p, cfg["thetas"], f.U, f.V)
+    X0 = torch.from_numpy(workloads.random_unit_starts(cfg["seed"] + 1000, r, p)).cuda()
+    ctx = spca.Context(0)
+    stream = torch.cuda.current_stream()
+    res_last = {}
+
+    def step(timing):
+        res = spca.am_solve(A, cfg["fid"], float(cfg["s"]), X0, tol=-1.0, maxit=maxit,
+                            ctx=ctx, stream=stream, kernel_times=timing, flags=args.flags)
+        res_last.update(res)
+        return {"work": res["iters_x_starts"], "kt": res["kernel_times"] if timing else {}}
+
+    dt, outs = _timed_steps(step, args.steps, args.warmup)
+    kt = _sum_kt(outs)
+    sup = set(res_last["support"].tolist())
+    recovered = [len(sup & set(s.tolist())) for s in f.supports]
+    return {
+        "metric": "AM iters x starts/sec",
+        "value": sum(o["work"] for o in outs) / dt,
+        "unit": "iter*start/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": dt / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (counter-based spiked model generated in HBM)",
+        "config": {"workload": cfg["name"], "n": n, "p": p, "starts": r, "formulation": 1,
+                   "s": cfg["s"], "maxit": maxit, "tol": "disabled (fixed work)",
+                   "spikes": list(cfg["thetas"]), "spike_nnz": cfg["spike_nnz"],
+                   "A_bytes": 4 * n * p},
+        "roofline": _roofline_aty(kt, r, n, p, PEAK_FP32_MFMA_TFLOPS),
+        "kernels": {"x_update_avg_ms": round(kt["x_update_ms"] / kt["x_update_launches"], 5),
+                    "ax_dense_avg_ms": round(kt["ax_dense_ms"] / max(1, kt["ax_dense_launches"]), 5),
+                    "ax_modes_dense_list_union": (kt["iters_dense"], kt["iters_list"],
+                                                  kt["iters_union"])},
+        "result": {"objective": res_last["objective"], "nnz": int(res_last["nnz"]),
+                   "support_overlap_with_spikes": recovered},
+    }
+
+
+def bench_precision(args, spca, torch):
+    """BF16 storage + FP32 polish against the FP32 path on the 5000 x 50000
+    spiked workload (F8 and F1, 256 starts, stop test on): solves/s of each
+    path and the relative gap of their final FP64 objectives."""
+    cfg = workloads.SPIKED_BF16
+    n, p, r = cfg["n"], cfg["p"], cfg["r"]
+    sp = workloads.spiked_matrix(cfg["seed"], n, p, cfg["thetas"], cfg["spike_nnz"])
+    A = torch.from_numpy(np.ascontiguousarray(sp.A.T)).cuda().t()
+    X0 = torch.from_numpy(workloads.random_unit_starts(cfg["seed"] + 1000, r, p)).cuda()
+    params = {fid: workloads.s_or_gamma_for(fid, sp.A, cfg["s"]) for fid in cfg["fids"]}
+    del sp
+    ctx = spca.Context(0)
+    stream = torch.cuda.current_stream()
+    out = {}
+    for prec in ("fp32", "bf16"):
+        last = {}
+
+        def step(timing, prec=prec, last=last):
+            for fid in cfg["fids"]:
+                last[fid] = spca.am_solve(A, fid, params[fid], X0, tol=1e-7,
+                                          maxit=cfg["maxit"], precision=prec,
+                                          polish_maxit=cfg["maxit"], ctx=ctx,
+                                          stream=stream, flags=args.flags)
+            return {"work": len(cfg["fids"]), "kt": {}}
+
+        dt, outs = _timed_steps(step, args.steps, args.warmup)
+        out[prec] = {"solves_per_s": args.steps * len(cfg["fids"]) / dt,
+                     "ms_per_step": dt / args.steps * 1e3,
+                     "per_fid": {fid: {"objective": v["objective"],
+                                       "objective_pre_polish": v["objective_pre_polish"],
+                                       "iters": int(v["iters"]), "nnz": int(v["nnz"]),
+                                       "polish_iters": int(v["polish_iters"])}
+                                 for fid, v in last.items()}}
+    gaps = {fid: abs(out["bf16"]["per_fid"][fid]["objective"] -
+                     out["fp32"]["per_fid"][fid]["objective"]) /
+            abs(out["fp32"]["per_fid"][fid]["objective"]) for fid in cfg["fids"]}
+    pre = {fid: abs(out["bf16"]["per_fid"][fid]["objective_pre_polish"] -
+                    out["fp32"]["per_fid"][fid]["objective"]) /
+           abs(out["fp32"]["per_fid"][fid]["objective"]) for fid in cfg["fids"]}
+    return {
+        "metric": "solves/s at equal post-polish accuracy",
+        "value": out["bf16"]["solves_per_s"], "unit": "solves/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": out["bf16"]["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "bf16 (FP32 accumulate, FP32 polish)",
+        "data": "synthetic",
+        "config": {"workload": cfg["name"], "n": n, "p": p, "starts": r,
+                   "formulations": list(cfg["fids"]), "s": cfg["s"], "tol": 1e-7,
+                   "maxit": cfg["maxit"]},
+        "fp32_solves_per_s": out["fp32"]["solves_per_s"],
+        "speedup_vs_fp32": out["bf16"]["solves_per_s"] / out["fp32"]["solves_per_s"],
+        "rel_gap_to_fp32_post_polish": gaps, "rel_gap_to_fp32_pre_polish": pre,
+        "paths": out,
+    }
+
+
+WORKLOADS = {"spiked-all8": bench_all8, "large": bench_large, "precision": bench_precision}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__,
+                                 formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="spiked-all8", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--fids", default="1,2,3,4,5,6,7,8",
+                    help="formulations in a step of spiked-all8 (default: all 8)")
+    ap.add_argument("--maxit", type=int, default=0, help="iterations per solve (large)")
+    ap.add_argument("--graph", action="store_true",
+                    help="replay the iterations from a captured HIP graph")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported: "
+              "the batched AM path runs on a single MI355X", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1212_4137_amd as spca
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    args.flags = spca.FLAG_GRAPH if args.graph else 0
+    rec = WORKLOADS[args.workload](args, spca, torch)
     print(json.dumps(rec), flush=True)
 
 

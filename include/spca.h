@@ -136,7 +136,12 @@ typedef struct {
   int32_t flags;        /* SPCA_FLAG_* below                                */
 } spca_solve_opts;
 
-#define SPCA_FLAG_GRAPH 1        /* replay check_every iterations as a graph */
+/* SPCA_FLAG_GRAPH: capture check_every iterations once per solve into a HIP
+ * graph (on a stream of the context) and replay it on the caller's stream
+ * between stop-test polls; the leftover maxit % check_every iterations run
+ * eagerly.  Results are identical to the eager path.  Ignored when
+ * kernel_times is requested.                                               */
+#define SPCA_FLAG_GRAPH 1
 #define SPCA_FLAG_CHECK_FINITE 2 /* reject A holding NaN or Inf (EINVAL)     */
 #define SPCA_FLAG_DENSE_ONLY 4   /* never use the sparse A x product         */
 
@@ -213,7 +218,9 @@ int spca_gemm_nt_f32_plan(int64_t M, int64_t N, int64_t K, int max_splits,
  * T_s, V_{lambda_s}, U_gamma or V_gamma (Table 3, rows S3-S6).  Writes X
  * (r x p, ldx >= p, device), phi (r doubles, device: the subproblem optimum
  * of Table 3) and nnz (r int32, device).  A zero image gives X_j = 0.
- * Same parameter checks as spca_am_solve.                                 */
+ * Same parameter checks as spca_am_solve.  For p > 12288 (except the L1
+ * constraint) the chunked kernels run on scratch that this call allocates
+ * and frees, so the call then synchronizes the stream before returning.   */
 int spca_x_update(void* stream, int formulation, const float* V, int64_t ldv,
                   int64_t r, int64_t p, double s_or_gamma, float* X,
                   int64_t ldx, double* phi, int32_t* nnz);

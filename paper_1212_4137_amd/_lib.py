@@ -193,12 +193,15 @@ def am_solve(A, formulation, s_or_gamma, X0=None, tol=1e-8, maxit=200, *,
     """Batched AM solve (``spca_am_solve_ex``).
 
     A : torch.float32 GPU tensor (n, p), column-major (strides (1, lda)).
+    precision: PREC_FP32 / PREC_BF16_POLISH, or "fp32" / "bf16".
     X0: torch.float32 GPU tensor (r, p), contiguous, one start per row; or
         None for the single start e_i at the column of largest norm.
     Returns a dict of host (numpy) results.
     """
     import torch
 
+    if isinstance(precision, str):
+        precision = {"fp32": PREC_FP32, "bf16": PREC_BF16_POLISH}[precision]
     _require_gpu_tensor(A, "A", torch.float32)
     n, p, lda = colmajor_view(A)
     if X0 is not None:

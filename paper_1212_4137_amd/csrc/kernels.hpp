@@ -165,11 +165,27 @@ void sparse_ax_y_update_bf16(hipStream_t st, int fid, const uint16_t* Ab,
 // counters are touched (operator-only mode used by spca_x_update).
 // Every kept column of a processed row is marked colmark[i] = plan->epoch
 // (colmark may be null).
+// Rows longer than kWideMinP use the chunked kernels when `wide` points to
+// x_update_wide_bytes(fid, r, p) bytes of scratch whose histogram part was
+// cleared by x_update_wide_reset (the kernels leave it cleared again).
 void x_update(hipStream_t st, int fid, double s_or_gamma, const float* V,
               int64_t ldv, int64_t r, int64_t p, float* X, int64_t ldx,
               int32_t* list_idx, float* list_val, int64_t ldl, int list_cap,
               StartState s, double tol, int32_t maxit, int32_t* colmark,
-              const Plan* plan);
+              const Plan* plan, void* wide = nullptr);
+
+constexpr int64_t kWideMinP = 12288;
+// scratch of the chunked x-update (0 when it does not apply: lambda_s, or
+// p <= kWideMinP); the size is the same for every other formulation
+size_t x_update_wide_bytes(int fid, int64_t r, int64_t p);
+hipError_t x_update_wide_reset(hipStream_t st, void* scratch, int64_t r);
+// launches the chunked x-update; false (nothing launched) when it does not
+// apply
+bool x_update_wide(hipStream_t st, int fid, double s_or_gamma, const float* V,
+                   int64_t ldv, int64_t r, int64_t p, float* X, int64_t ldx,
+                   int32_t* list_idx, float* list_val, int64_t ldl, int list_cap,
+                   StartState s, double tol, int32_t maxit, int32_t* colmark,
+                   const Plan* plan, void* scratch);
 
 // FP64 finalisation: per start, x64 = x / ||x||_2 from the lists, f(x64)
 // of Table 1 and the explained variance; then the best start.

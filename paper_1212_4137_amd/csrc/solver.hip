@@ -51,7 +51,8 @@ struct Layout {
   size_t off_At, off_Ac, off_X, off_U, off_Y, off_V, off_li, off_lv;
   size_t off_phi, off_phip, off_nnz, off_it, off_st, off_plan, off_part,
       off_f, off_ev, off_xn, off_best, off_xout, off_sup, off_colsq, off_bad;
-  size_t off_mark, off_ulist, off_Xc, off_Qc;
+  size_t off_mark, off_ulist, off_Xc, off_Qc, off_wide;
+  size_t wide_bytes;
   int64_t ucap;  // largest support union the union product can hold
   GemmPlan plan_union;
   size_t total;
@@ -123,6 +124,8 @@ Layout make_layout(int64_t n, int64_t p, int64_t r, bool copy_a, bool bf16) {
   L.off_ulist = carve(&c, sizeof(int32_t) * p);
   L.off_Xc = carve(&c, sizeof(float) * (size_t)r * round_up(L.ucap, 4));
   L.off_Qc = carve(&c, sizeof(float) * (size_t)n * round_up(L.ucap, 4));
+  L.wide_bytes = x_update_wide_bytes(1, r, p);
+  L.off_wide = carve(&c, L.wide_bytes);
   L.total = c;
   return L;
 }
@@ -206,8 +209,15 @@ struct spca_ctx {
   int32_t* host_poll = nullptr;  // pinned
   EventPairs t_aty, t_xup, t_ax;
   spca_ctx* polish = nullptr;  // context of the FP32 polish sub-solves
+  hipStream_t capture = nullptr;  // stream that graphs are captured on
   std::mutex mu;
 };
+
+static int ensure_capture_stream(spca_ctx* ctx) {
+  if (ctx->capture == nullptr)
+    SPCA_HIP_TRY(hipStreamCreateWithFlags(&ctx->capture, hipStreamNonBlocking));
+  return SPCA_OK;
+}
 
 using namespace spca;
 
@@ -252,6 +262,7 @@ int spca_ctx_destroy(spca_ctx* ctx) {
       (void)hipFree(ctx->ws);
     }
     if (ctx->host_poll) (void)hipHostFree(ctx->host_poll);
+    if (ctx->capture) (void)hipStreamDestroy(ctx->capture);
     ctx->t_aty.destroy();
     ctx->t_xup.destroy();
     ctx->t_ax.destroy();
@@ -304,7 +315,7 @@ static int polish_best(spca_ctx* ctx, hipStream_t st, const spca_problem* prob,
   }
   spca_problem sub = *prob;
   spca_solve_opts so{Xp, nc, opts->tol, opts->polish_maxit, SPCA_PREC_FP32, 0,
-                     opts->check_every, opts->flags & ~SPCA_FLAG_GRAPH};
+                     opts->check_every, opts->flags};
   std::vector<double> xsub(prob->p);
   std::vector<int32_t> ssub(prob->p);
   spca_result rsub{};
@@ -383,6 +394,7 @@ int spca_am_solve_ex(spca_ctx* ctx, void* stream, const spca_problem* prob,
   uint16_t* Atb = (uint16_t*)(base + L.off_Atb);
   uint16_t* Yb = (uint16_t*)(base + L.off_Yb);
   uint16_t* Xb = (uint16_t*)(base + L.off_Xb);
+  void* wide = L.wide_bytes ? (void*)(base + L.off_wide) : nullptr;
 
   // a0: stage A (aligned column-major copy only when needed) and its
   // row-major twin used by the dense A x.
@@ -421,6 +433,7 @@ int spca_am_solve_ex(spca_ctx* ctx, void* stream, const spca_problem* prob,
   }
   init_state(st, s, r);
   init_plan(st, plan, L.plan_ax.splits);
+  if (wide) SPCA_HIP_TRY(x_update_wide_reset(st, wide, r));
   SPCA_HIP_TRY(hipMemsetAsync(colmark, 0, sizeof(int32_t) * p, st));
   compact_rows(st, X, L.ldx, r, p, li, lv, L.ldx, s.nnz, s.status, colmark, plan);
   const int dense_only = (opts->flags & SPCA_FLAG_DENSE_ONLY) ? 1 : 0;
@@ -440,49 +453,108 @@ int spca_am_solve_ex(spca_ctx* ctx, void* stream, const spca_problem* prob,
   ctx->t_aty.reset();
   ctx->t_xup.reset();
   ctx->t_ax.reset();
-  for (int32_t it = 0; it < maxit; ++it) {
+  // One AM iteration (Algorithm 2, one pass of its loop), enqueued on `q`.
+  // Every launch reads its control data (mode, active starts, sizes) from
+  // the device-side plan, so the same sequence serves every iteration and
+  // can be captured once into a graph.
+  auto iteration = [&](hipStream_t q, bool tm) -> int {
     // u = A x and the y-update
-    if (timed) SPCA_HIP_TRY(ctx->t_ax.mark(st));
+    if (tm) SPCA_HIP_TRY(ctx->t_ax.mark(q));
     if (bf16)
-      gemm_nt_bf16(st, Xb, L.ldxb, Atb, L.ldatb, U, L.ldu, r, n, p, &plan->mode,
+      gemm_nt_bf16(q, Xb, L.ldxb, Atb, L.ldatb, U, L.ldu, r, n, p, &plan->mode,
                    kAxDense, L.plan_ax, r * L.ldu);
     else
-      gemm_nt_f32(st, X, L.ldx, At, L.ldat, U, L.ldu, r, n, p, &plan->mode,
+      gemm_nt_f32(q, X, L.ldx, At, L.ldat, U, L.ldu, r, n, p, &plan->mode,
                   kAxDense, L.plan_ax, r * L.ldu);
-    if (timed) SPCA_HIP_TRY(ctx->t_ax.mark(st));
+    if (tm) SPCA_HIP_TRY(ctx->t_ax.mark(q));
     if (!bf16) {
-      union_gather(st, X, L.ldx, r, A, ldA, n, ulist, plan, Xc, ldc_u, Qc, ldc_u);
-      gemm_nt_f32(st, Xc, ldc_u, Qc, ldc_u, U, L.ldu, r, n, L.ucap, &plan->mode,
+      union_gather(q, X, L.ldx, r, A, ldA, n, ulist, plan, Xc, ldc_u, Qc, ldc_u);
+      gemm_nt_f32(q, Xc, ldc_u, Qc, ldc_u, U, L.ldu, r, n, L.ucap, &plan->mode,
                   kAxUnion, L.plan_union, 0, &plan->union_size);
     }
-    y_update(st, fid, U, r * L.ldu, Y, L.ldu, r, n, s, plan, bf16 ? Yb : nullptr,
+    y_update(q, fid, U, r * L.ldu, Y, L.ldu, r, n, s, plan, bf16 ? Yb : nullptr,
              L.ldyb);
     if (bf16)
-      sparse_ax_y_update_bf16(st, fid, Ab, L.ldab, n, li, lv, L.ldx, Y, L.ldu, Yb,
+      sparse_ax_y_update_bf16(q, fid, Ab, L.ldab, n, li, lv, L.ldx, Y, L.ldu, Yb,
                               L.ldyb, r, s, plan);
     else
-      sparse_ax_y_update(st, fid, A, ldA, n, li, lv, L.ldx, Y, L.ldu, r, s, plan);
+      sparse_ax_y_update(q, fid, A, ldA, n, li, lv, L.ldx, Y, L.ldu, r, s, plan);
     // v = A^T y and the x-update with the stop test
-    if (timed) SPCA_HIP_TRY(ctx->t_aty.mark(st));
+    if (tm) SPCA_HIP_TRY(ctx->t_aty.mark(q));
     if (bf16)
-      gemm_nt_bf16(st, Yb, L.ldyb, Ab, L.ldab, V, L.ldx, r, p, n, nullptr, 0,
+      gemm_nt_bf16(q, Yb, L.ldyb, Ab, L.ldab, V, L.ldx, r, p, n, nullptr, 0,
                    L.plan_aty, 0);
     else
-      gemm_nt_f32(st, Y, L.ldu, A, ldA, V, L.ldx, r, p, n, nullptr, 0,
+      gemm_nt_f32(q, Y, L.ldu, A, ldA, V, L.ldx, r, p, n, nullptr, 0,
                   L.plan_aty, 0);
-    if (timed) SPCA_HIP_TRY(ctx->t_aty.mark(st));
-    if (timed) SPCA_HIP_TRY(ctx->t_xup.mark(st));
-    x_update(st, fid, sg, V, L.ldx, r, p, X, L.ldx, li, lv, L.ldx, list_cap, s,
-             opts->tol, maxit, colmark, plan);
-    if (timed) SPCA_HIP_TRY(ctx->t_xup.mark(st));
-    plan_iter();
-    if (bf16) rows_to_bf16(st, X, L.ldx, r, p, Xb, L.ldxb, plan);
+    if (tm) SPCA_HIP_TRY(ctx->t_aty.mark(q));
+    if (tm) SPCA_HIP_TRY(ctx->t_xup.mark(q));
+    x_update(q, fid, sg, V, L.ldx, r, p, X, L.ldx, li, lv, L.ldx, list_cap, s,
+             opts->tol, maxit, colmark, plan, wide);
+    if (tm) SPCA_HIP_TRY(ctx->t_xup.mark(q));
+    plan_next(q, s, r, n, p, list_cap, dense_only, L.plan_ax.splits, L.ucap,
+              colmark, ulist, plan);
+    if (bf16) rows_to_bf16(q, X, L.ldx, r, p, Xb, L.ldxb, plan);
     SPCA_LAUNCH_CHECK("AM iteration");
-    if ((it + 1) % opts->check_every == 0 && it + 1 < maxit) {
-      SPCA_HIP_TRY(hipMemcpyAsync(ctx->host_poll, &plan->active, sizeof(int32_t),
-                                  hipMemcpyDeviceToHost, st));
-      SPCA_HIP_TRY(hipStreamSynchronize(st));
-      if (ctx->host_poll[0] == 0) break;
+    return SPCA_OK;
+  };
+  // the host reads the number of active starts after every check_every
+  // iterations and stops once none is left
+  auto none_active = [&](bool* done) -> int {
+    SPCA_HIP_TRY(hipMemcpyAsync(ctx->host_poll, &plan->active, sizeof(int32_t),
+                                hipMemcpyDeviceToHost, st));
+    SPCA_HIP_TRY(hipStreamSynchronize(st));
+    *done = ctx->host_poll[0] == 0;
+    return SPCA_OK;
+  };
+  const int32_t every = opts->check_every;
+  int32_t it = 0;
+  bool done = false;
+  if ((opts->flags & SPCA_FLAG_GRAPH) && !timed && maxit >= every) {
+    // a8: capture check_every iterations once (on the context's own stream,
+    // since the legacy default stream cannot be captured) and replay the
+    // graph on the caller's stream.  The captured sequence holds kernel
+    // launches only.
+    rc = ensure_capture_stream(ctx);
+    if (rc != SPCA_OK) return rc;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    SPCA_HIP_TRY(hipStreamBeginCapture(ctx->capture, hipStreamCaptureModeThreadLocal));
+    int body_rc = SPCA_OK;
+    for (int32_t k = 0; k < every && body_rc == SPCA_OK; ++k)
+      body_rc = iteration(ctx->capture, false);
+    hipError_t end_rc = hipStreamEndCapture(ctx->capture, &graph);
+    if (body_rc != SPCA_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return body_rc;
+    }
+    SPCA_HIP_TRY(end_rc);
+    hipError_t inst_rc = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    SPCA_HIP_TRY(inst_rc);
+    int loop_rc = SPCA_OK;
+    while (!done && it + every <= maxit) {
+      hipError_t e = hipGraphLaunch(exec, st);
+      if (e != hipSuccess) {
+        set_error(std::string("hipGraphLaunch: ") + hipGetErrorString(e));
+        loop_rc = SPCA_EHIP;
+        break;
+      }
+      it += every;
+      if (it < maxit) {
+        loop_rc = none_active(&done);
+        if (loop_rc != SPCA_OK) break;
+      }
+    }
+    (void)hipGraphExecDestroy(exec);
+    if (loop_rc != SPCA_OK) return loop_rc;
+  }
+  for (; !done && it < maxit; ++it) {
+    rc = iteration(st, timed);
+    if (rc != SPCA_OK) return rc;
+    if ((it + 1) % every == 0 && it + 1 < maxit) {
+      rc = none_active(&done);
+      if (rc != SPCA_OK) return rc;
     }
   }
 
@@ -688,9 +760,30 @@ int spca_x_update(void* stream, int formulation, const float* V, int64_t ldv,
   if (rc != SPCA_OK) return rc;
   SPCA_REQUIRE(ldv >= p && ldx >= p, "leading dimensions too small");
   StartState s{phi, nullptr, nnz, nullptr, nullptr};
-  x_update((hipStream_t)stream, formulation, s_or_gamma, V, ldv, r, p, X, ldx,
-           nullptr, nullptr, 0, 0, s, -1.0, 1, nullptr, nullptr);
-  SPCA_LAUNCH_CHECK("x_update");
+  hipStream_t st = (hipStream_t)stream;
+  // long rows: the chunked kernels need scratch, held for this call only
+  const size_t wb = x_update_wide_bytes(formulation, r, p);
+  void* wide = nullptr;
+  if (wb) {
+    SPCA_HIP_TRY(hipMalloc(&wide, wb));
+    hipError_t e = x_update_wide_reset(st, wide, r);
+    if (e != hipSuccess) {
+      (void)hipFree(wide);
+      SPCA_HIP_TRY(e);
+    }
+  }
+  x_update(st, formulation, s_or_gamma, V, ldv, r, p, X, ldx, nullptr, nullptr, 0,
+           0, s, -1.0, 1, nullptr, nullptr, wide);
+  hipError_t le = hipGetLastError();
+  if (wide) {
+    hipError_t se = hipStreamSynchronize(st);
+    (void)hipFree(wide);
+    if (le == hipSuccess) le = se;
+  }
+  if (le != hipSuccess) {
+    set_error(std::string("x_update: ") + hipGetErrorString(le));
+    return SPCA_EHIP;
+  }
   return SPCA_OK;
 }
 

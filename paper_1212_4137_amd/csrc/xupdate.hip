@@ -1053,7 +1053,11 @@ void x_update(hipStream_t st, int fid, double s_or_gamma, const float* V,
               int64_t ldv, int64_t r, int64_t p, float* X, int64_t ldx,
               int32_t* list_idx, float* list_val, int64_t ldl, int list_cap,
               StartState s, double tol, int32_t maxit, int32_t* colmark,
-              const Plan* plan) {
+              const Plan* plan, void* wide) {
+  if (wide != nullptr &&
+      x_update_wide(st, fid, s_or_gamma, V, ldv, r, p, X, ldx, list_idx, list_val,
+                    ldl, list_cap, s, tol, maxit, colmark, plan, wide))
+    return;
   switch (xkind_of(fid)) {
     case kTopS:
       launch_kind<kTopS>(st, s_or_gamma, V, ldv, r, p, X, ldx, list_idx,

@@ -1,0 +1,462 @@
+// x-update for long rows (p beyond what one workgroup keeps in registers):
+// each row of V is cut into chunks of kWCH elements and every chunk gets its
+// own workgroup, so a launch has (chunks x starts) workgroups instead of one
+// per start.  Row-level decisions are taken by small per-row kernels between
+// the chunk passes; every sum is reduced in a fixed order, so results do not
+// depend on timing.  Operators (Table 3, rows S3, S5, S6):
+//   T_s   exact top-s by |v| with ties to the lowest index: a radix select
+//         over the 31-bit keys of |v| in three digit passes (11, 10, 10
+//         bits); each pass histograms the keys that share the prefix fixed
+//         so far (LDS histogram per chunk, integer atomics into one global
+//         histogram per row) and a per-row kernel picks the digit holding
+//         the s-th largest key.  When the s-th key is shared by more
+//         elements than are still needed, a counting pass gives each chunk
+//         the number of such ties before it.
+//   U_g   keep v_i with v_i^2 > g;  V_g  soft threshold at g.
+// Then: per-chunk FP64 partial sums (count, ||w||^2, sum (w^2 - g)), a
+// per-row kernel that adds them in chunk order, applies the stop test and
+// turns the counts into list offsets, and an emit pass that writes
+// x = w / ||w|| (and the index list and column marks).
+#include "../../include/spca.h"
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace spca {
+namespace {
+
+constexpr int kWT = 256;              // threads per chunk workgroup
+constexpr int kWN = 16;               // elements per thread
+constexpr int kWCH = kWT * kWN;       // chunk length
+constexpr int kWBins = 2048;          // largest digit (11 bits)
+constexpr int kNWv = kWT / kWave;
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+struct WRow {
+  uint32_t prefix;   // key bits fixed so far (the full key after pass 3)
+  int32_t need;      // elements still to take at or below the prefix
+  int32_t eq_total;  // elements whose key equals the final key
+  int32_t straddle;  // 1 when only part of those are taken
+  int32_t live;      // row processed in this x-update
+  int32_t listed;    // the index list is written
+  int32_t zero;      // w = 0
+  int32_t marking;   // kept columns get colmark = epoch
+  int32_t epoch;
+  int32_t pad;
+  double inv;        // 1 / ||w||
+};
+
+struct Wide {
+  uint32_t* ghist;  // r x kWBins
+  WRow* rows;       // r
+  int32_t* eqcnt;   // r x nch
+  int32_t* cnt;     // r x nch: kept count, then list offset
+  double* part;     // r x nch x 2
+  int nch;
+};
+
+Wide carve_wide(void* base, int64_t r, int64_t p) {
+  Wide w;
+  w.nch = (int)ceil_div(p, kWCH);
+  char* c = (char*)base;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    char* q = c + off;
+    off += (bytes + 255) / 256 * 256;
+    return q;
+  };
+  w.ghist = (uint32_t*)take(sizeof(uint32_t) * kWBins * r);
+  w.rows = (WRow*)take(sizeof(WRow) * r);
+  w.eqcnt = (int32_t*)take(sizeof(int32_t) * r * w.nch);
+  w.cnt = (int32_t*)take(sizeof(int32_t) * r * w.nch);
+  w.part = (double*)take(sizeof(double) * 2 * r * w.nch);
+  return w;
+}
+
+__device__ __forceinline__ uint32_t wkey(float v) {
+  return __float_as_uint(v) & 0x7fffffffu;
+}
+
+__device__ __forceinline__ bool row_live(const StartState& s, int64_t j) {
+  return s.status == nullptr || s.status[j] == kRunning;
+}
+
+__device__ __forceinline__ void load_chunk(const float* __restrict__ vg, int p,
+                                           int base, float (&v)[kWN]) {
+#pragma unroll
+  for (int q = 0; q < kWN; q += 4) {
+    const int i = base + q;
+    if (i + 3 < p) {
+      const floatx4 t = *reinterpret_cast<const floatx4*>(vg + i);
+      v[q] = t.x;
+      v[q + 1] = t.y;
+      v[q + 2] = t.z;
+      v[q + 3] = t.w;
+    } else {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) v[q + e] = i + e < p ? vg[i + e] : 0.f;
+    }
+  }
+}
+
+// digit pass PASS: bits [shift, shift + bits) of the key, among keys whose
+// higher bits equal the prefix
+template <int PASS>
+struct Digit {
+  static constexpr int kShift = PASS == 0 ? 20 : PASS == 1 ? 10 : 0;
+  static constexpr int kBits = PASS == 0 ? 11 : 10;
+  static constexpr int kBins = 1 << kBits;
+};
+
+template <int PASS>
+__global__ __launch_bounds__(kWT) void wide_hist_kernel(
+    const float* __restrict__ V, int64_t ldv, int p, StartState s, Wide w) {
+  using D = Digit<PASS>;
+  __shared__ uint32_t lh[D::kBins];
+  const int64_t j = blockIdx.y;
+  if (!row_live(s, j)) return;
+  const int tid = threadIdx.x;
+  for (int b = tid; b < D::kBins; b += kWT) lh[b] = 0u;
+  const uint32_t prefix = PASS == 0 ? 0u : w.rows[j].prefix;
+  __syncthreads();
+  const int base = blockIdx.x * kWCH + tid * kWN;
+  float v[kWN];
+  load_chunk(V + j * ldv, p, base, v);
+#pragma unroll
+  for (int k = 0; k < kWN; ++k) {
+    const uint32_t key = wkey(v[k]);
+    const bool in = base + k < p &&
+                    (PASS == 0 || (key >> (D::kShift + D::kBits)) == prefix);
+    if (in) atomicAdd(&lh[(key >> D::kShift) & (D::kBins - 1)], 1u);
+  }
+  __syncthreads();
+  uint32_t* gh = w.ghist + j * kWBins;
+  for (int b = tid; b < D::kBins; b += kWT)
+    if (lh[b] != 0u) atomicAdd(&gh[b], lh[b]);
+}
+
+// per row: the digit holding the need-th largest key; clears the histogram
+template <int PASS>
+__global__ __launch_bounds__(kWT) void wide_decide_kernel(StartState s, Wide w,
+                                                          int32_t s_need) {
+  using D = Digit<PASS>;
+  constexpr int kPer = D::kBins / kWT;
+  __shared__ int scan[kNWv + 1];
+  const int64_t j = blockIdx.x;
+  if (!row_live(s, j)) return;
+  const int tid = threadIdx.x;
+  WRow* R = w.rows + j;
+  const int need = PASS == 0 ? s_need : R->need;
+  const uint32_t prefix = PASS == 0 ? 0u : R->prefix;
+  uint32_t* gh = w.ghist + j * kWBins;
+  // thread 0 owns the highest bins
+  const int hi = D::kBins - kPer * tid;
+  int c[kPer];
+  int sum = 0;
+#pragma unroll
+  for (int e = 0; e < kPer; ++e) {
+    c[e] = (int)gh[hi - 1 - e];
+    sum += c[e];
+  }
+  int total;
+  int run = block_exclusive_scan(sum, scan, &total);
+#pragma unroll
+  for (int e = 0; e < kPer; ++e) {
+    if (run < need && need <= run + c[e]) {
+      const uint32_t key = (prefix << D::kBits) | (uint32_t)(hi - 1 - e);
+      R->prefix = key;
+      R->need = need - run;
+      if (PASS == 2) {
+        R->eq_total = c[e];
+        R->straddle = key != 0u && c[e] > need - run;
+      }
+    }
+    run += c[e];
+  }
+#pragma unroll
+  for (int e = 0; e < kPer; ++e) gh[hi - 1 - e] = 0u;
+}
+
+__global__ __launch_bounds__(kWT) void wide_eqcount_kernel(
+    const float* __restrict__ V, int64_t ldv, int p, StartState s, Wide w) {
+  __shared__ int red[kNWv + 1];
+  const int64_t j = blockIdx.y;
+  if (!row_live(s, j) || !w.rows[j].straddle) return;
+  const uint32_t t = w.rows[j].prefix;
+  const int base = blockIdx.x * kWCH + threadIdx.x * kWN;
+  float v[kWN];
+  load_chunk(V + j * ldv, p, base, v);
+  int eq = 0;
+#pragma unroll
+  for (int k = 0; k < kWN; ++k) eq += base + k < p && wkey(v[k]) == t;
+  eq = block_sum(eq, red);
+  if (threadIdx.x == 0) w.eqcnt[j * w.nch + blockIdx.x] = eq;
+}
+
+// Membership and value of each element of the thread's slice.  For T_s the
+// rank of an element among the ties at the final key decides (lowest
+// indices first).
+template <int KIND>
+struct Keep {
+  uint32_t t = 0;
+  int straddle = 0, need = 0, rank = 0;
+  double lam = 0.0;
+
+  __device__ void setup(const Wide& w, int64_t j, double param,
+                        const float (&v)[kWN], int base, int p, int* scan,
+                        int* red) {
+    if (KIND == kTopS) {
+      const WRow& R = w.rows[j];
+      t = R.prefix;
+      straddle = R.straddle;
+      need = R.need;
+      if (straddle) {
+        int before = 0;
+        for (int c = threadIdx.x; c < (int)blockIdx.x; c += kWT)
+          before += w.eqcnt[j * w.nch + c];
+        before = block_sum(before, red);
+        int eq = 0;
+#pragma unroll
+        for (int k = 0; k < kWN; ++k) eq += base + k < p && wkey(v[k]) == t;
+        int tot;
+        rank = before + block_exclusive_scan(eq, scan, &tot);
+      }
+    } else {
+      lam = param;
+    }
+  }
+
+  // call in element order over the slice
+  __device__ bool operator()(float vv, bool valid, double* wv) {
+    if (!valid) return false;
+    if (KIND == kTopS) {
+      const uint32_t k = wkey(vv);
+      *wv = (double)vv;
+      if (k == 0u || k < t) return false;
+      if (k > t || !straddle) return true;
+      return rank++ < need;
+    } else if (KIND == kHardGamma) {
+      *wv = (double)vv;
+      return (double)vv * (double)vv > lam;
+    } else {
+      const double a = fabs((double)vv);
+      *wv = vv > 0.f ? a - lam : lam - a;
+      return a > lam;
+    }
+  }
+};
+
+template <int KIND>
+__global__ __launch_bounds__(kWT) void wide_partial_kernel(
+    const float* __restrict__ V, int64_t ldv, int p, double param, StartState s,
+    Wide w) {
+  __shared__ int scan[kNWv + 1];
+  __shared__ int red[kNWv + 1];
+  __shared__ double dred[2 * (kNWv + 1)];
+  const int64_t j = blockIdx.y;
+  if (!row_live(s, j)) return;
+  const int base = blockIdx.x * kWCH + threadIdx.x * kWN;
+  float v[kWN];
+  load_chunk(V + j * ldv, p, base, v);
+  Keep<KIND> keep;
+  keep.setup(w, j, param, v, base, p, scan, red);
+  int cnt = 0;
+  double acc[2] = {0.0, 0.0};
+#pragma unroll
+  for (int k = 0; k < kWN; ++k) {
+    double wv;
+    if (keep(v[k], base + k < p, &wv)) {
+      ++cnt;
+      acc[0] += wv * wv;
+      if (KIND == kHardGamma) acc[1] += wv * wv - param;
+    }
+  }
+  block_sum_n<double, 2>(acc, dred);
+  cnt = block_sum(cnt, red);
+  if (threadIdx.x == 0) {
+    const int64_t c = j * w.nch + blockIdx.x;
+    w.cnt[c] = cnt;
+    w.part[2 * c] = acc[0];
+    w.part[2 * c + 1] = acc[1];
+  }
+}
+
+// one thread per row: chunk sums in chunk order, phi, the stop test (the
+// same state machine as the one-workgroup kernels) and list offsets
+template <int KIND>
+__global__ __launch_bounds__(64) void wide_row_kernel(
+    int64_t r, StartState s, double tol, int maxit, int list_cap, int have_list,
+    const Plan* plan, int have_marks, Wide w) {
+  const int64_t j = (int64_t)blockIdx.x * 64 + threadIdx.x;
+  if (j >= r) return;
+  WRow* R = w.rows + j;
+  const bool live = row_live(s, j);
+  R->live = live;
+  if (!live) return;
+  double a0 = 0.0, a1 = 0.0;
+  int total = 0;
+  for (int c = 0; c < w.nch; ++c) {
+    const int64_t q = j * w.nch + c;
+    a0 += w.part[2 * q];
+    a1 += w.part[2 * q + 1];
+    const int k = w.cnt[q];
+    w.cnt[q] = total;
+    total += k;
+  }
+  const double nrm = sqrt(a0);
+  const double phi = KIND == kHardGamma ? a1 : nrm;
+  const bool zero = !(nrm > 0.0);
+  R->zero = zero;
+  R->inv = zero ? 0.0 : 1.0 / nrm;
+  R->listed = have_list && !zero && total <= list_cap;
+  R->marking = have_marks && !zero && plan != nullptr && plan->mark != 0;
+  R->epoch = R->marking ? plan->epoch : 0;
+  if (s.status == nullptr) {
+    s.phi[j] = phi;
+    s.nnz[j] = zero ? 0 : total;
+  } else {
+    const int it = s.iters[j] + 1;
+    const double prev = s.phi[j];
+    s.iters[j] = it;
+    s.phi_prev[j] = prev;
+    s.phi[j] = phi;
+    s.nnz[j] = zero ? 0 : total;
+    if (zero)
+      s.status[j] = SPCA_ZERO;
+    else if (it >= 2 && tol >= 0.0 && phi <= (1.0 + tol) * prev)
+      s.status[j] = SPCA_CONVERGED;
+    else if (it >= maxit)
+      s.status[j] = SPCA_MAXIT;
+  }
+}
+
+template <int KIND>
+__global__ __launch_bounds__(kWT) void wide_emit_kernel(
+    const float* __restrict__ V, int64_t ldv, int p, double param,
+    float* __restrict__ X, int64_t ldx, int32_t* __restrict__ list_idx,
+    float* __restrict__ list_val, int64_t ldl, int32_t* __restrict__ colmark,
+    Wide w) {
+  __shared__ int scan[kNWv + 1];
+  __shared__ int red[kNWv + 1];
+  const int64_t j = blockIdx.y;
+  const WRow R = w.rows[j];
+  if (!R.live) return;
+  const int base = blockIdx.x * kWCH + threadIdx.x * kWN;
+  float v[kWN];
+  load_chunk(V + j * ldv, p, base, v);
+  Keep<KIND> keep;
+  keep.setup(w, j, param, v, base, p, scan, red);
+  float xo[kWN];
+  bool kp[kWN];
+  int cnt = 0;
+#pragma unroll
+  for (int k = 0; k < kWN; ++k) {
+    double wv = 0.0;
+    kp[k] = keep(v[k], base + k < p, &wv) && !R.zero;
+    xo[k] = kp[k] ? (float)(wv * R.inv) : 0.f;
+    cnt += kp[k];
+  }
+  if (R.listed) {
+    int tot;
+    int off = w.cnt[j * w.nch + blockIdx.x] + block_exclusive_scan(cnt, scan, &tot);
+    int32_t* li = list_idx + j * ldl;
+    float* lv = list_val + j * ldl;
+#pragma unroll
+    for (int k = 0; k < kWN; ++k) {
+      if (kp[k]) {
+        li[off] = base + k;
+        lv[off] = xo[k];
+        ++off;
+      }
+    }
+  }
+  if (R.marking) {
+#pragma unroll
+    for (int k = 0; k < kWN; ++k)
+      if (kp[k]) colmark[base + k] = R.epoch;
+  }
+  float* x = X + j * ldx;
+#pragma unroll
+  for (int q = 0; q < kWN; q += 4) {
+    const int i = base + q;
+    if (i + 3 < p) {
+      floatx4 t = {xo[q], xo[q + 1], xo[q + 2], xo[q + 3]};
+      *reinterpret_cast<floatx4*>(x + i) = t;
+    } else {
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        if (i + e < p) x[i + e] = xo[q + e];
+    }
+  }
+}
+
+template <int KIND>
+void launch_wide_kind(hipStream_t st, double param, const float* V,
+                      int64_t ldv, int64_t r, int64_t p, float* X, int64_t ldx,
+                      int32_t* li, float* lv, int64_t ldl, int list_cap,
+                      StartState s, double tol, int maxit, int32_t* colmark,
+                      const Plan* plan, const Wide& w) {
+  const dim3 g2((unsigned)w.nch, (unsigned)r);
+  const int ip = (int)p;
+  if (KIND == kTopS) {
+    const int32_t need = (int32_t)((int64_t)param < p ? (int64_t)param : p);
+    hipLaunchKernelGGL(wide_hist_kernel<0>, g2, dim3(kWT), 0, st, V, ldv, ip, s, w);
+    hipLaunchKernelGGL(wide_decide_kernel<0>, dim3((unsigned)r), dim3(kWT), 0, st, s, w, need);
+    hipLaunchKernelGGL(wide_hist_kernel<1>, g2, dim3(kWT), 0, st, V, ldv, ip, s, w);
+    hipLaunchKernelGGL(wide_decide_kernel<1>, dim3((unsigned)r), dim3(kWT), 0, st, s, w, need);
+    hipLaunchKernelGGL(wide_hist_kernel<2>, g2, dim3(kWT), 0, st, V, ldv, ip, s, w);
+    hipLaunchKernelGGL(wide_decide_kernel<2>, dim3((unsigned)r), dim3(kWT), 0, st, s, w, need);
+    hipLaunchKernelGGL(wide_eqcount_kernel, g2, dim3(kWT), 0, st, V, ldv, ip, s, w);
+  }
+  hipLaunchKernelGGL(wide_partial_kernel<KIND>, g2, dim3(kWT), 0, st, V, ldv, ip,
+                     param, s, w);
+  hipLaunchKernelGGL(wide_row_kernel<KIND>, dim3((unsigned)ceil_div(r, 64)), dim3(64),
+                     0, st, r, s, tol, maxit, list_cap, li != nullptr ? 1 : 0, plan,
+                     colmark != nullptr ? 1 : 0, w);
+  hipLaunchKernelGGL(wide_emit_kernel<KIND>, g2, dim3(kWT), 0, st, V, ldv, ip, param,
+                     X, ldx, li, lv, ldl, colmark, w);
+}
+
+}  // namespace
+
+size_t x_update_wide_bytes(int fid, int64_t r, int64_t p) {
+  if (xkind_of(fid) == kLambdaS || p <= kWideMinP || r < 1) return 0;
+  const int64_t nch = ceil_div(p, kWCH);
+  auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+  return up(sizeof(uint32_t) * kWBins * r) + up(sizeof(WRow) * r) +
+         2 * up(sizeof(int32_t) * r * nch) + up(sizeof(double) * 2 * r * nch);
+}
+
+hipError_t x_update_wide_reset(hipStream_t st, void* scratch, int64_t r) {
+  return hipMemsetAsync(scratch, 0, sizeof(uint32_t) * kWBins * r, st);
+}
+
+bool x_update_wide(hipStream_t st, int fid, double s_or_gamma, const float* V,
+                   int64_t ldv, int64_t r, int64_t p, float* X, int64_t ldx,
+                   int32_t* list_idx, float* list_val, int64_t ldl, int list_cap,
+                   StartState s, double tol, int32_t maxit, int32_t* colmark,
+                   const Plan* plan, void* scratch) {
+  const bool aligned = ldv % 4 == 0 && ldx % 4 == 0 && (uintptr_t)V % 16 == 0 &&
+                       (uintptr_t)X % 16 == 0;
+  if (scratch == nullptr || !aligned || x_update_wide_bytes(fid, r, p) == 0)
+    return false;
+  const Wide w = carve_wide(scratch, r, p);
+  switch (xkind_of(fid)) {
+    case kTopS:
+      launch_wide_kind<kTopS>(st, s_or_gamma, V, ldv, r, p, X, ldx, list_idx, list_val,
+                              ldl, list_cap, s, tol, maxit, colmark, plan, w);
+      return true;
+    case kHardGamma:
+      launch_wide_kind<kHardGamma>(st, s_or_gamma, V, ldv, r, p, X, ldx, list_idx,
+                                   list_val, ldl, list_cap, s, tol, maxit, colmark, plan, w);
+      return true;
+    case kSoftGamma:
+      launch_wide_kind<kSoftGamma>(st, s_or_gamma, V, ldv, r, p, X, ldx, list_idx,
+                                   list_val, ldl, list_cap, s, tol, maxit, colmark, plan, w);
+      return true;
+    default:
+      return false;
+  }
+}
+
+}  // namespace spca

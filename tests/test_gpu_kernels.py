@@ -93,13 +93,15 @@ def _check_xupdate(spca, fid, V_h, par, exact_support=True):
     return X, phi, nnz
 
 
-@pytest.mark.parametrize("p", [37, 1500, 20000])
+@pytest.mark.parametrize("p", [37, 1500, 20000, 60001, 200000])
 @pytest.mark.parametrize("fid", [1, 3, 5, 7])
 def test_x_update_random(spca, fid, p):
     print(f"x_update case fid={fid} p={p}", flush=True)
     rng = np.random.default_rng(fid * 1000 + p)
     V_h = (rng.standard_normal((6, p)) * 3).astype(np.float32)
-    par = {1: min(10, p), 3: 7.3, 5: 4.0, 7: 1.5}[fid]
+    par = {1: min(10 if p < 50000 else 200, p), 3: 7.3, 5: 4.0, 7: 1.5}[fid]
+    if p >= 50000 and fid >= 5:  # keep the penalised supports a few hundred wide
+        par = {5: 16.0, 7: 3.0}[fid] * 9 / 4
     _check_xupdate(spca, fid, V_h, par)
     # L1-variance twins share the operator
     _check_xupdate(spca, fid + 1, V_h, par)
@@ -153,3 +155,45 @@ def test_x_update_lambda_s_regimes(spca, s):
                                    atol=2e-7)
     if s == 1.0:
         assert np.all(nnz == 1)
+
+
+def test_x_update_chunked_ties_across_chunks(spca):
+    # p = 12800 (aligned, beyond the register-resident rows): the chunked
+    # kernels, with ties at the s-th key spread over several 4096-wide chunks
+    p = 12800
+    rng = np.random.default_rng(77)
+    V_h = (rng.standard_normal((6, p)) * 0.5).astype(np.float32)
+    tie_cols = [5, 4100, 4101, 8200, 12000, 12799]
+    V_h[0, tie_cols] = [3.0, -3.0, 3.0, 3.0, -3.0, 3.0]
+    V_h[0, [10, 9000]] = [4.0, -5.0]          # two above the tie value
+    V_h[1, :] = -2.0                          # every key equal
+    V_h[2, :] = 0.0
+    V_h[2, [7, 11111]] = [1.0, -1.0]          # fewer nonzeros than s
+    V_h[3, :] = 0.0                           # zero row
+    V_h[4, :] = np.float32(1e-30)             # tiny but nonzero
+    X, phi, nnz = _check_xupdate(spca, 1, V_h, 5)
+    assert np.flatnonzero(X[0]).tolist() == [5, 10, 4100, 4101, 9000]
+    assert np.flatnonzero(X[1]).tolist() == [0, 1, 2, 3, 4]
+    assert np.flatnonzero(X[2]).tolist() == [7, 11111]
+    assert nnz[3] == 0 and phi[3] == 0 and np.all(X[3] == 0)
+    assert np.flatnonzero(X[4]).tolist() == [0, 1, 2, 3, 4]
+    for s in (1, 4096, 4097, p):
+        _check_xupdate(spca, 2, V_h, s)
+
+
+@pytest.mark.parametrize("fid", [1, 2, 5, 6, 7, 8, 3])
+def test_solve_long_rows_match_oracle(spca, fid):
+    # p = 20000 > 12288: the chunked x-update inside the solve (the L1
+    # constraint keeps the one-workgroup kernel)
+    import workloads
+    from gpu_helpers import compare_solve, to_device_colmajor, to_device_rows
+
+    print(f"long-row solve fid={fid}", flush=True)
+    sp = workloads.spiked_matrix(41, 150, 20000, thetas=(80.0, 40.0), spike_nnz=30)
+    X0 = workloads.random_unit_starts(42, 6, 20000)
+    par = workloads.s_or_gamma_for(fid, sp.A, 30, "scaled" if fid in (6, 8) else "literal")
+    got = spca.am_solve(to_device_colmajor(sp.A), fid, par, to_device_rows(X0),
+                        tol=1e-8, maxit=300)
+    ref = oracle.am_multi(sp.A.astype(np.float64), fid, par, X0.astype(np.float64),
+                          1e-8, 300, nthreads=6)
+    compare_solve(got, ref, f"long rows F{fid}")
