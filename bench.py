@@ -257,7 +257,125 @@ def bench_precision(args, spca, torch):
     }
 
 
-WORKLOADS = {"spiked-all8": bench_all8, "large": bench_large, "precision": bench_precision}
+def serve_requests(count, seed, precision):
+    """The serving stream: n ~ U[200, 5000], p ~ U[1000, 50000], formulation
+    uniform over the 8, s ~ U[5, 200] (at most p) or gamma = 0.1 max_i
+    ||a_i||_2, r in {16, 64, 256}; A is the 3-spike model (thetas 60/40/25,
+    50 nonzeros per spike) generated on the device from the request's seed.
+    precision: "fp32", "bf16" or "mixed" (drawn per request)."""
+    from workloads import counter
+
+    rng = np.random.default_rng(seed)
+    specs = []
+    for i in range(count):
+        n = int(rng.integers(200, 5001))
+        p = int(rng.integers(1000, 50001))
+        fid = int(rng.integers(1, 9))
+        r = int(rng.choice([16, 64, 256]))
+        s = int(rng.integers(5, 201))
+        prec = precision if precision != "mixed" else ("bf16" if rng.random() < 0.5 else "fp32")
+        thetas = (60.0, 40.0, 25.0)
+        f = counter.spike_factors(seed + i, n, p, thetas, 50)
+        spec = dict(n=n, p=p, seed=seed + i, thetas=thetas, U=f.U, V=f.V,
+                    start_seed=seed + 100000 + i, formulation=fid, r=r, maxit=200,
+                    tol=1e-6, precision=prec, polish_maxit=200, flags=1)
+        if fid <= 4:
+            spec["s_or_gamma"] = float(min(s, p))
+        else:
+            spec["gamma_rel"] = 0.1
+        specs.append(spec)
+    return specs
+
+
+def run_stream(spca, specs, qps, workers, arena, seed):
+    """Submits the requests at Poisson arrival times and collects them."""
+    rng = np.random.default_rng(seed + 7)
+    gaps = rng.exponential(1.0 / qps, len(specs))
+    done = {}
+    with spca.Server(arena, workers=workers) as srv:
+        t0 = time.monotonic()
+        due = t0 + np.cumsum(gaps)
+        ids = {}
+        for i, spec in enumerate(specs):
+            while True:
+                wait = due[i] - time.monotonic()
+                if wait <= 0:
+                    break
+                for c in srv.poll(wait_ms=max(1, int(wait * 1000))):
+                    done[ids[c["id"]]] = c
+            ids[srv.submit(spec)] = i
+        while len(done) < len(specs):
+            for c in srv.poll(wait_ms=1000):
+                done[ids[c["id"]]] = c
+        stats = srv.stats()
+    comps = [done[i] for i in range(len(specs))]
+    bad = [c for c in comps if c["rc"] != 0]
+    if bad:
+        raise RuntimeError(f"{len(bad)} requests failed, first: {bad[0]['error']}")
+    lat = np.array([c["t_done"] - c["t_submit"] for c in comps])
+    first = min(c["t_submit"] for c in comps)
+    last = max(c["t_done"] for c in comps)
+    return {"solves_per_s": len(comps) / (last - first),
+            "p50_ms": float(np.percentile(lat, 50) * 1e3),
+            "p99_ms": float(np.percentile(lat, 99) * 1e3),
+            "mean_ms": float(lat.mean() * 1e3), "wall_s": last - first,
+            "peak_running": stats["peak_running"],
+            "peak_in_use_GB": stats["peak_in_use_bytes"] / 1e9}, comps
+
+
+def bench_serve(args, spca, torch):
+    """Serving: a Poisson stream of requests of mixed shape, formulation and
+    precision at a fixed rate, run three ways on the same stream:
+    continuous batching with per-request precision (the measured path),
+    continuous batching with FP32 only, and one request at a time in FP32
+    (the baseline)."""
+    count, qps = args.requests, args.qps
+    seed = workloads.SEED_BASE + 5
+    arena = int(args.arena_gb * (1 << 30))
+    runs = {}
+    comps = {}
+    # warm the library (kernels load on first use) outside the timed streams
+    warm = serve_requests(4, seed + 999, "mixed")
+    run_stream(spca, warm, 1000.0, args.workers, arena, seed)
+    for name, prec, workers in (("batched_mixed", "mixed", args.workers),
+                                ("batched_fp32", "fp32", args.workers),
+                                ("one_at_a_time_fp32", "fp32", 1)):
+        specs = serve_requests(count, seed, prec)
+        runs[name], comps[name] = run_stream(spca, specs, qps, workers, arena, seed)
+        print(json.dumps({name: runs[name]}), file=sys.stderr, flush=True)
+    # accuracy at equal settings: per request, the final objective of the
+    # served path against the FP32 one-at-a-time run of the same request
+    gaps = np.array([abs(a["objective"] - b["objective"]) / max(abs(b["objective"]), 1e-300)
+                     for a, b in zip(comps["batched_mixed"], comps["one_at_a_time_fp32"])])
+    same32 = all(a["objective"] == b["objective"]
+                 for a, b in zip(comps["batched_fp32"], comps["one_at_a_time_fp32"]))
+    m = runs["batched_mixed"]
+    base = runs["one_at_a_time_fp32"]
+    return {
+        "metric": "solves/s with p50/p99 latency (continuous batching)",
+        "value": m["solves_per_s"], "unit": "solves/s", "n_gpus": 1,
+        "steps": count, "warmup": 4, "ms_per_step": m["wall_s"] / count * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "mixed f32 / bf16+f32 polish",
+        "data": "synthetic (per-request spiked model generated in HBM)",
+        "config": {"workload": f"serve-poisson-{count}req-{qps}qps", "requests": count,
+                   "qps": qps, "workers": args.workers, "arena_GB": args.arena_gb,
+                   "n": "U[200,5000]", "p": "U[1000,50000]", "formulation": "U{1..8}",
+                   "s": "U[5,200]", "gamma": "0.1*max_i ||a_i||_2", "r": [16, 64, 256],
+                   "precision": "50% fp32, 50% bf16+polish", "tol": 1e-6, "maxit": 200},
+        "p50_ms": m["p50_ms"], "p99_ms": m["p99_ms"],
+        "speedup_vs_one_at_a_time_fp32": m["solves_per_s"] / base["solves_per_s"],
+        "runs": runs,
+        "fp32_batched_equals_one_at_a_time": same32,
+        "objective_rel_gap_vs_fp32": {"median": float(np.median(gaps)),
+                                      "p99": float(np.percentile(gaps, 99)),
+                                      "max": float(gaps.max()),
+                                      "frac_le_1e-5": float(np.mean(gaps <= 1e-5))},
+    }
+
+
+WORKLOADS = {"spiked-all8": bench_all8, "large": bench_large, "precision": bench_precision,
+             "serve": bench_serve}
 
 
 def main():
@@ -271,6 +389,10 @@ def main():
     ap.add_argument("--fids", default="1,2,3,4,5,6,7,8",
                     help="formulations in a step of spiked-all8 (default: all 8)")
     ap.add_argument("--maxit", type=int, default=0, help="iterations per solve (large)")
+    ap.add_argument("--requests", type=int, default=200, help="serve: requests")
+    ap.add_argument("--qps", type=float, default=10.0, help="serve: arrival rate")
+    ap.add_argument("--workers", type=int, default=4, help="serve: concurrent solves")
+    ap.add_argument("--arena-gb", type=float, default=64.0, help="serve: HBM arena")
     ap.add_argument("--graph", action="store_true",
                     help="replay the iterations from a captured HIP graph")
     args = ap.parse_args()

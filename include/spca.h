@@ -115,8 +115,15 @@ typedef struct spca_ctx spca_ctx;
  * workspace the context may hold (0 = no limit beyond the device).       */
 int spca_ctx_create(spca_ctx** ctx, int device, size_t hbm_budget_bytes);
 int spca_ctx_destroy(spca_ctx* ctx);
-/* Bytes of workspace a solve of this shape needs (for admission control). */
+/* Bytes of workspace a solve of this shape needs (for admission control);
+ * with SPCA_PREC_BF16_POLISH it includes the FP32 polish sub-solve.       */
 size_t spca_workspace_bytes(int64_t n, int64_t p, int32_t r, int precision);
+/* Makes the context use caller-owned device memory (256-byte aligned) as its
+ * workspace instead of allocating its own; a solve that needs more than
+ * `bytes` then fails with SPCA_ENOMEM.  NULL / 0 returns the context to
+ * allocating.  The memory must stay valid while solves run on the context;
+ * the context never frees it.                                              */
+int spca_ctx_set_workspace(spca_ctx* ctx, void* dev_ptr, size_t bytes);
 
 typedef struct {
   const float* A; /* device, FP32, n x p column-major                        */
@@ -224,6 +231,83 @@ int spca_gemm_nt_f32_plan(int64_t M, int64_t N, int64_t K, int max_splits,
 int spca_x_update(void* stream, int formulation, const float* V, int64_t ldv,
                   int64_t r, int64_t p, double s_or_gamma, float* X,
                   int64_t ldx, double* phi, int32_t* nnz);
+
+/* ---------------------------------------------------------------------- */
+/* Serving: continuous batching of independent solves on one GPU.         */
+
+/* One request.  A is either the caller's (device, column-major, lda >= n,
+ * kept valid until the request completes) or, with A == NULL, generated in
+ * the server's memory by spca_generate_spiked(seed, n, p, k, thetas, U, V).
+ * The r starts are always generated: row j of X0 is column j of the
+ * generator's p x r noise matrix for start_seed (the AM iteration does not
+ * depend on the scale of a start).  For penalties, gamma_rel > 0 sets
+ * gamma = gamma_rel * max_i ||a_i||_2 (computed on the device); otherwise
+ * s_or_gamma is used as given.  Host arrays (thetas, U, V) are copied at
+ * submission; x_out and support_out (host, p entries, or NULL) are written
+ * before the completion is posted and must stay valid until then.         */
+typedef struct {
+  const float* A;
+  int64_t n, p, lda;
+  uint64_t seed;
+  int32_t k;
+  int32_t formulation;
+  const double* thetas; /* k values */
+  const double* U;      /* n x k, column-major */
+  const double* V;      /* p x k, column-major */
+  uint64_t start_seed;
+  double s_or_gamma;
+  double gamma_rel;
+  int32_t r;
+  int32_t maxit;
+  double tol;
+  int32_t precision;
+  int32_t polish_maxit;
+  int32_t check_every;  /* 0: 8 */
+  int32_t flags;        /* SPCA_FLAG_* */
+  double* x_out;
+  int32_t* support_out;
+} spca_request;
+
+typedef struct {
+  int64_t id;
+  int32_t rc;           /* SPCA_OK or the solve's error code */
+  int32_t reserved;
+  spca_result res;
+  double s_or_gamma;    /* the parameter the solve used */
+  double t_submit, t_admit, t_done; /* seconds on the monotonic clock */
+  size_t footprint;     /* bytes of the server arena the request held */
+  char error[160];      /* message when rc != SPCA_OK */
+} spca_completion;
+
+typedef struct {
+  size_t arena_bytes, in_use_bytes, peak_in_use_bytes;
+  int64_t queued;
+  int32_t running, peak_running;
+  int64_t completed;
+  double now;           /* monotonic clock, seconds */
+} spca_server_stats_t;
+
+typedef struct spca_server spca_server;
+
+/* Bytes of server memory a request holds while it runs: its generated A,
+ * spike factors, starts and spca_workspace_bytes of the solve.            */
+size_t spca_request_footprint(const spca_request* req);
+/* Allocates an arena of hbm_bytes on the device and starts `workers` worker
+ * threads, each with its own stream and context.  Requests are admitted in
+ * arrival order when a worker is free and their footprint fits in the free
+ * part of the arena (first fit); admitted requests run concurrently.       */
+int spca_server_create(spca_server** srv, int device, size_t hbm_bytes,
+                       int32_t workers);
+/* Queues a request; EINVAL when its footprint exceeds the whole arena. */
+int spca_server_submit(spca_server* srv, const spca_request* req, int64_t* id);
+/* Moves up to max completions (in completion order) to out; waits up to
+ * wait_ms for the first one (0: no wait, < 0: until one arrives).          */
+int spca_server_poll(spca_server* srv, spca_completion* out, int32_t max,
+                     int32_t* count, int32_t wait_ms);
+int spca_server_stats(spca_server* srv, spca_server_stats_t* stats);
+/* Finishes every queued request, then stops the workers and frees the
+ * arena (completions not yet polled are dropped).                         */
+int spca_server_destroy(spca_server* srv);
 
 /* ---------------------------------------------------------------------- */
 /* Synthetic data (workload generation, not part of the method).           */

@@ -24,7 +24,10 @@ FLAG_GRAPH, FLAG_CHECK_FINITE, FLAG_DENSE_ONLY = 1, 2, 4
 EXPORTED = ("spca_am_solve", "spca_am_solve_ex", "spca_ctx_create",
             "spca_ctx_destroy", "spca_workspace_bytes", "spca_last_error",
             "spca_gemm_nt_f32", "spca_gemm_nt_bf16", "spca_gemm_nt_f32_shape",
-            "spca_gemm_nt_f32_plan", "spca_x_update", "spca_generate_spiked")
+            "spca_gemm_nt_f32_plan", "spca_x_update", "spca_generate_spiked",
+            "spca_ctx_set_workspace", "spca_request_footprint", "spca_server_create",
+            "spca_server_submit", "spca_server_poll", "spca_server_stats",
+            "spca_server_destroy")
 
 
 class SpcaError(RuntimeError):
@@ -62,6 +65,34 @@ class Outputs(ctypes.Structure):
                 ("phi_per_start", ctypes.c_void_p), ("iters_per_start", ctypes.c_void_p),
                 ("status_per_start", ctypes.c_void_p), ("nnz_per_start", ctypes.c_void_p),
                 ("X_final", ctypes.c_void_p), ("kernel_times", ctypes.c_void_p)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("A", ctypes.c_void_p), ("n", ctypes.c_int64), ("p", ctypes.c_int64),
+                ("lda", ctypes.c_int64), ("seed", ctypes.c_uint64), ("k", ctypes.c_int32),
+                ("formulation", ctypes.c_int32), ("thetas", ctypes.c_void_p),
+                ("U", ctypes.c_void_p), ("V", ctypes.c_void_p),
+                ("start_seed", ctypes.c_uint64), ("s_or_gamma", ctypes.c_double),
+                ("gamma_rel", ctypes.c_double), ("r", ctypes.c_int32),
+                ("maxit", ctypes.c_int32), ("tol", ctypes.c_double),
+                ("precision", ctypes.c_int32), ("polish_maxit", ctypes.c_int32),
+                ("check_every", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("x_out", ctypes.c_void_p), ("support_out", ctypes.c_void_p)]
+
+
+class Completion(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_int64), ("rc", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("res", Result), ("s_or_gamma", ctypes.c_double),
+                ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double),
+                ("t_done", ctypes.c_double), ("footprint", ctypes.c_size_t),
+                ("error", ctypes.c_char * 160)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("arena_bytes", ctypes.c_size_t), ("in_use_bytes", ctypes.c_size_t),
+                ("peak_in_use_bytes", ctypes.c_size_t), ("queued", ctypes.c_int64),
+                ("running", ctypes.c_int32), ("peak_running", ctypes.c_int32),
+                ("completed", ctypes.c_int64), ("now", ctypes.c_double)]
 
 
 _lib = None
@@ -109,6 +140,23 @@ def load():
         lib.spca_gemm_nt_f32_plan.restype = ctypes.c_int
         lib.spca_x_update.argtypes = [P, ctypes.c_int, P, i64, i64, i64, d, P, i64, P, P]
         lib.spca_x_update.restype = ctypes.c_int
+        lib.spca_ctx_set_workspace.argtypes = [P, P, ctypes.c_size_t]
+        lib.spca_ctx_set_workspace.restype = ctypes.c_int
+        lib.spca_request_footprint.argtypes = [ctypes.POINTER(Request)]
+        lib.spca_request_footprint.restype = ctypes.c_size_t
+        lib.spca_server_create.argtypes = [ctypes.POINTER(P), ctypes.c_int, ctypes.c_size_t,
+                                           i32]
+        lib.spca_server_create.restype = ctypes.c_int
+        lib.spca_server_submit.argtypes = [P, ctypes.POINTER(Request),
+                                           ctypes.POINTER(ctypes.c_int64)]
+        lib.spca_server_submit.restype = ctypes.c_int
+        lib.spca_server_poll.argtypes = [P, ctypes.POINTER(Completion), i32,
+                                         ctypes.POINTER(i32), i32]
+        lib.spca_server_poll.restype = ctypes.c_int
+        lib.spca_server_stats.argtypes = [P, ctypes.POINTER(ServerStats)]
+        lib.spca_server_stats.restype = ctypes.c_int
+        lib.spca_server_destroy.argtypes = [P]
+        lib.spca_server_destroy.restype = ctypes.c_int
         _lib = lib
         return lib
 
@@ -375,3 +423,109 @@ def x_update(formulation, V, s_or_gamma, stream=None):
                                 ctypes.c_void_p(phi.data_ptr()),
                                 ctypes.c_void_p(nnz.data_ptr())))
     return X, phi, nnz
+
+
+def _request(spec):
+    """spca_request from a dict; returns (Request, arrays to keep alive)."""
+    keep = []
+    q = Request()
+    A = spec.get("A")
+    if A is not None:
+        n, p, lda = colmajor_view(A)
+        q.A, q.n, q.p, q.lda = A.data_ptr(), n, p, lda
+        keep.append(A)
+    else:
+        q.n, q.p = int(spec["n"]), int(spec["p"])
+        q.seed = int(spec.get("seed", 0))
+        thetas = np.ascontiguousarray(spec.get("thetas", ()), dtype=np.float64)
+        q.k = len(thetas)
+        if q.k:
+            U = np.asfortranarray(spec["U"], dtype=np.float64)
+            V = np.asfortranarray(spec["V"], dtype=np.float64)
+            if U.shape != (q.n, q.k) or V.shape != (q.p, q.k):
+                raise ValueError("U must be (n, k) and V (p, k)")
+            keep += [thetas, U, V]
+            q.thetas, q.U, q.V = _np_ptr(thetas), _np_ptr(U), _np_ptr(V)
+    q.start_seed = int(spec.get("start_seed", 1))
+    q.formulation = int(spec["formulation"])
+    q.s_or_gamma = float(spec.get("s_or_gamma", 0.0))
+    q.gamma_rel = float(spec.get("gamma_rel", 0.0))
+    q.r = int(spec.get("r", 16))
+    q.maxit = int(spec.get("maxit", 200))
+    q.tol = float(spec.get("tol", 1e-6))
+    prec = spec.get("precision", PREC_FP32)
+    q.precision = {"fp32": PREC_FP32, "bf16": PREC_BF16_POLISH}.get(prec, prec)
+    q.polish_maxit = int(spec.get("polish_maxit", q.maxit))
+    q.check_every = int(spec.get("check_every", 8))
+    q.flags = int(spec.get("flags", 0))
+    if spec.get("want_x", False):
+        x = np.zeros(q.p, dtype=np.float64)
+        sup = np.zeros(q.p, dtype=np.int32)
+        keep += [x, sup]
+        q.x_out, q.support_out = _np_ptr(x), _np_ptr(sup)
+    return q, keep
+
+
+def request_footprint(spec):
+    """Bytes of server memory the request holds while it runs."""
+    q, _ = _request(spec)
+    return int(load().spca_request_footprint(ctypes.byref(q)))
+
+
+class Server:
+    """Continuous-batching request server (``spca_server_*``): an HBM arena
+    of ``hbm_bytes`` and ``workers`` concurrent solves.  ``submit`` takes a
+    dict with the fields of spca_request (``want_x=True`` asks for x and
+    the support); ``poll`` returns finished requests as dicts."""
+
+    def __init__(self, hbm_bytes, workers=4, device=0):
+        self.handle = ctypes.c_void_p()
+        _check(load().spca_server_create(ctypes.byref(self.handle), device,
+                                         int(hbm_bytes), int(workers)))
+        self._keep = {}
+
+    def submit(self, spec):
+        q, keep = _request(spec)
+        rid = ctypes.c_int64()
+        _check(load().spca_server_submit(self.handle, ctypes.byref(q), ctypes.byref(rid)))
+        self._keep[rid.value] = (q, keep)
+        return rid.value
+
+    def poll(self, wait_ms=0, max_items=256):
+        buf = (Completion * max_items)()
+        cnt = ctypes.c_int32()
+        _check(load().spca_server_poll(self.handle, buf, max_items, ctypes.byref(cnt),
+                                       int(wait_ms)))
+        out = []
+        for c in buf[: cnt.value]:
+            q, keep = self._keep.pop(c.id)
+            d = {"id": c.id, "rc": c.rc, "error": c.error.decode(errors="replace"),
+                 "objective": c.res.objective, "explained_variance": c.res.explained_var,
+                 "objective_pre_polish": c.res.objective_pre_polish,
+                 "nnz": c.res.nnz, "iters": c.res.iters, "status": c.res.status,
+                 "best_start": c.res.best_start, "iters_x_starts": c.res.iters_x_starts,
+                 "polish_iters": c.res.polish_iters, "s_or_gamma": c.s_or_gamma,
+                 "t_submit": c.t_submit, "t_admit": c.t_admit, "t_done": c.t_done,
+                 "footprint": c.footprint}
+            if q.x_out:
+                x, sup = keep[-2], keep[-1]
+                d["x"] = x
+                d["support"] = sup[: c.res.nnz].copy()
+            out.append(d)
+        return out
+
+    def stats(self):
+        st = ServerStats()
+        _check(load().spca_server_stats(self.handle, ctypes.byref(st)))
+        return {k: getattr(st, k) for k, _ in ServerStats._fields_}
+
+    def close(self):
+        if self.handle:
+            _check(load().spca_server_destroy(self.handle))
+            self.handle = ctypes.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -206,6 +206,7 @@ struct spca_ctx {
   size_t budget = 0;
   void* ws = nullptr;
   size_t ws_cap = 0;
+  bool ws_external = false;  // ws belongs to the caller
   int32_t* host_poll = nullptr;  // pinned
   EventPairs t_aty, t_xup, t_ax;
   spca_ctx* polish = nullptr;  // context of the FP32 polish sub-solves
@@ -225,9 +226,38 @@ extern "C" {
 
 const char* spca_last_error(void) { return spca::last_error(); }
 
+// Workspace of one solve: its layout, and for BF16 storage the layout of the
+// FP32 polish sub-solve after it (at most kPolishMax starts).
+static size_t solve_bytes(const Layout& L, int64_t n, int64_t p, int64_t r) {
+  size_t b = L.total;
+  if (L.bf16) {
+    const int64_t rp = r < kPolishMax ? r : kPolishMax;
+    b = (size_t)round_up((int64_t)b, 256) + make_layout(n, p, rp, true, false).total;
+  }
+  return b;
+}
+
 size_t spca_workspace_bytes(int64_t n, int64_t p, int32_t r, int precision) {
   if (n < 1 || p < 1 || r < 1) return 0;
-  return make_layout(n, p, r, true, precision == SPCA_PREC_BF16_POLISH).total;
+  const Layout L = make_layout(n, p, r, true, precision == SPCA_PREC_BF16_POLISH);
+  return solve_bytes(L, n, p, r);
+}
+
+int spca_ctx_set_workspace(spca_ctx* ctx, void* dev_ptr, size_t bytes) {
+  SPCA_REQUIRE(ctx != nullptr, "ctx must not be NULL");
+  SPCA_REQUIRE((dev_ptr == nullptr) == (bytes == 0),
+               "dev_ptr and bytes must be both set or both zero");
+  SPCA_REQUIRE((uintptr_t)dev_ptr % 256 == 0, "dev_ptr must be 256-byte aligned");
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  if (ctx->ws && !ctx->ws_external) {
+    DeviceGuard g(ctx->device);
+    SPCA_HIP_TRY(hipDeviceSynchronize());
+    SPCA_HIP_TRY(hipFree(ctx->ws));
+  }
+  ctx->ws = dev_ptr;
+  ctx->ws_cap = bytes;
+  ctx->ws_external = dev_ptr != nullptr;
+  return SPCA_OK;
 }
 
 int spca_ctx_create(spca_ctx** ctx, int device, size_t hbm_budget_bytes) {
@@ -257,7 +287,7 @@ int spca_ctx_destroy(spca_ctx* ctx) {
   if (ctx->polish) spca_ctx_destroy(ctx->polish);
   {
     DeviceGuard g(ctx->device);
-    if (ctx->ws) {
+    if (ctx->ws && !ctx->ws_external) {
       (void)hipDeviceSynchronize();
       (void)hipFree(ctx->ws);
     }
@@ -279,6 +309,11 @@ static int ensure_workspace(spca_ctx* ctx, hipStream_t st, size_t bytes) {
     return SPCA_ENOMEM;
   }
   if (bytes <= ctx->ws_cap) return SPCA_OK;
+  if (ctx->ws_external) {
+    set_error("workspace of " + std::to_string(bytes) +
+              " bytes exceeds the caller-provided " + std::to_string(ctx->ws_cap));
+    return SPCA_ENOMEM;
+  }
   if (ctx->ws) {
     SPCA_HIP_TRY(hipStreamSynchronize(st));
     SPCA_HIP_TRY(hipFree(ctx->ws));
@@ -308,9 +343,15 @@ static int ensure_workspace(spca_ctx* ctx, hipStream_t st, size_t bytes) {
 
 static int polish_best(spca_ctx* ctx, hipStream_t st, const spca_problem* prob,
                        const spca_solve_opts* opts, const float* Xp,
-                       int32_t nc, spca_outputs* out) {
+                       int32_t nc, size_t ws_off, spca_outputs* out) {
   if (ctx->polish == nullptr) {
     int rc = spca_ctx_create(&ctx->polish, ctx->device, 0);
+    if (rc != SPCA_OK) return rc;
+  }
+  // the sub-solve works in the tail of this solve's workspace
+  {
+    int rc = spca_ctx_set_workspace(ctx->polish, (char*)ctx->ws + ws_off,
+                                    ctx->ws_cap - ws_off);
     if (rc != SPCA_OK) return rc;
   }
   spca_problem sub = *prob;
@@ -362,7 +403,7 @@ int spca_am_solve_ex(spca_ctx* ctx, void* stream, const spca_problem* prob,
 
   const bool copy_a = (lda % 4) != 0 || ((uintptr_t)prob->A % 16) != 0;
   const Layout L = make_layout(n, p, r, copy_a, bf16);
-  rc = ensure_workspace(ctx, st, L.total);
+  rc = ensure_workspace(ctx, st, solve_bytes(L, n, p, r));
   if (rc != SPCA_OK) return rc;
   char* base = (char*)ctx->ws;
   float* At = (float*)(base + L.off_At);
@@ -638,7 +679,8 @@ int spca_am_solve_ex(spca_ctx* ctx, void* stream, const spca_problem* prob,
       SPCA_HIP_TRY(hipMemcpyAsync(Xp + c * p, X + (int64_t)order[c] * L.ldx,
                                   sizeof(float) * p, hipMemcpyDeviceToDevice, st));
     // the context lock is held, so the workspace stays valid meanwhile
-    rc = polish_best(ctx, st, prob, opts, Xp, (int32_t)order.size(), out);
+    rc = polish_best(ctx, st, prob, opts, Xp, (int32_t)order.size(),
+                     (size_t)round_up((int64_t)L.total, 256), out);
     if (rc != SPCA_OK) return rc;
   }
   for (int64_t j = 0; j < r; ++j) {

@@ -1,0 +1,130 @@
+"""Request server (spca_server_*): results are the same alone and in a mix
+of concurrent requests, match a direct solve and the FP64 oracle on the same
+generated inputs, admission respects the HBM arena, and a failing request
+does not disturb the others."""
+import numpy as np
+import pytest
+
+import oracle
+from workloads import counter
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def spca():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1212_4137_amd as m
+
+    m.load()
+    return m
+
+
+def _spec(i, n, p, fid, r, prec, s=20, maxit=150):
+    thetas = (60.0, 40.0, 25.0)
+    f = counter.spike_factors(1000 + i, n, p, thetas, 20)
+    spec = dict(n=n, p=p, seed=1000 + i, thetas=thetas, U=f.U, V=f.V, start_seed=5000 + i,
+                formulation=fid, r=r, maxit=maxit, tol=1e-7, precision=prec,
+                polish_maxit=maxit, want_x=True)
+    if fid <= 4:
+        spec["s_or_gamma"] = float(s)
+    else:
+        spec["gamma_rel"] = 0.1
+    return spec
+
+
+SPECS = [(0, 120, 1500, 1, 16, "fp32"), (1, 300, 2000, 2, 64, "fp32"),
+         (2, 200, 13000, 1, 16, "fp32"), (3, 150, 900, 3, 16, "fp32"),
+         (4, 256, 3000, 5, 64, "bf16"), (5, 100, 14000, 6, 16, "fp32"),
+         (6, 333, 1024, 7, 16, "bf16"), (7, 210, 4000, 8, 64, "fp32"),
+         (8, 180, 2500, 4, 16, "bf16"), (9, 260, 1800, 1, 64, "bf16")]
+
+
+def _run(spca, specs, workers, one_at_a_time, arena=2 << 30):
+    out = {}
+    with spca.Server(arena, workers=workers) as srv:
+        ids = {}
+        for k, sp in enumerate(specs):
+            ids[srv.submit(sp)] = k
+            if one_at_a_time:
+                for c in srv.poll(wait_ms=-1):
+                    out[ids[c["id"]]] = c
+        while len(out) < len(specs):
+            for c in srv.poll(wait_ms=60000):
+                out[ids[c["id"]]] = c
+        stats = srv.stats()
+    return out, stats
+
+
+def test_alone_and_in_the_mix_are_identical(spca):
+    specs = [_spec(*a) for a in SPECS]
+    alone, _ = _run(spca, specs, workers=1, one_at_a_time=True)
+    # the mix: the same requests interleaved with others, 4 running at once
+    extra = [_spec(20 + k, 240, 2200, 1 + k % 8, 64, "fp32") for k in range(6)]
+    mixed_specs = []
+    for k, sp in enumerate(specs):
+        mixed_specs.append(sp)
+        if k < len(extra):
+            mixed_specs.append(extra[k])
+    mix, stats = _run(spca, mixed_specs, workers=4, one_at_a_time=False)
+    assert stats["peak_running"] >= 2, stats
+    pos = {id(sp): k for k, sp in enumerate(mixed_specs)}
+    for k, sp in enumerate(specs):
+        a, m = alone[k], mix[pos[id(sp)]]
+        print("request", k, a["rc"], a["objective"], m["objective"], flush=True)
+        assert a["rc"] == 0 and m["rc"] == 0, (a["error"], m["error"])
+        assert a["objective"] == m["objective"]
+        assert a["s_or_gamma"] == m["s_or_gamma"]
+        assert a["iters"] == m["iters"] and a["best_start"] == m["best_start"]
+        assert np.array_equal(a["support"], m["support"])
+        assert np.array_equal(a["x"], m["x"])
+
+
+@pytest.mark.parametrize("fid", [1, 4, 6, 7])
+def test_served_result_matches_oracle(spca, fid):
+    n, p, r = 150, 1200, 8
+    sp = _spec(40 + fid, n, p, fid, r, "fp32", s=15, maxit=300)
+    sp["tol"] = 1e-8
+    with spca.Server(1 << 30, workers=2) as srv:
+        srv.submit(sp)
+        (c,) = srv.poll(wait_ms=60000)
+    assert c["rc"] == 0, c["error"]
+    f = counter.spike_factors(sp["seed"], n, p, sp["thetas"], 20)
+    A = counter.spiked_matrix(sp["seed"], n, p, f).astype(np.float64)
+    X0 = counter.gaussian_entries(sp["start_seed"], np.arange(p), np.arange(r)).T
+    par = c["s_or_gamma"]
+    if fid >= 5:  # the device value of 0.1 max_i ||a_i||_2 (FP64 sums)
+        ref_g = 0.1 * np.sqrt(np.max(np.sum(A * A, axis=0)))
+        assert abs(par - ref_g) <= 1e-12 * ref_g
+    ref = oracle.am_multi(A, fid, par, X0.astype(np.float64), 1e-8, 300, nthreads=4)
+    best = ref["f"][ref["best"]]
+    assert abs(c["objective"] - best) <= 1e-5 * abs(best), (c["objective"], best)
+
+
+def test_admission_by_footprint(spca):
+    specs = [_spec(60 + k, 400, 6000, 1 + k % 8, 64, "fp32") for k in range(6)]
+    fps = [spca.request_footprint(sp) for sp in specs]
+    arena = int(max(fps) * 1.6)  # room for one request at a time
+    out, stats = _run(spca, specs, workers=4, one_at_a_time=False, arena=arena)
+    assert all(c["rc"] == 0 for c in out.values())
+    assert stats["peak_in_use_bytes"] <= arena
+    assert stats["peak_running"] == 1, stats
+    # intervals of admitted requests never overlap when only one fits
+    spans = sorted((c["t_admit"], c["t_done"]) for c in out.values())
+    assert all(b[0] >= a[1] for a, b in zip(spans, spans[1:]))
+    with spca.Server(arena, workers=1) as srv:
+        big = _spec(99, 4000, 50000, 1, 256, "fp32")
+        with pytest.raises(spca.SpcaError):
+            srv.submit(big)
+
+
+def test_failing_request_is_isolated(spca):
+    good = [_spec(70 + k, 200, 1500, 1, 16, "fp32") for k in range(3)]
+    bad = _spec(80, 200, 1500, 1, 16, "fp32")
+    bad["s_or_gamma"] = 5000.0  # s > p: rejected by the solve
+    out, _ = _run(spca, good[:2] + [bad] + good[2:], workers=2, one_at_a_time=False)
+    assert out[2]["rc"] == -1 and "s" in out[2]["error"]
+    assert all(out[k]["rc"] == 0 for k in (0, 1, 3))
