@@ -32,6 +32,30 @@ import workloads  # noqa: E402
 PEAK_FP32_MFMA_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
 
+# HBM bytes per launch of the A^T Y product on the spiked-all8 workload, from
+# rocprofv3 FETCH_SIZE / WRITE_SIZE counter passes scaled by the same
+# counters on a 1 GiB copy (fetch x 2.0, write x 1.0); valid only for the
+# GEMM source they were taken on.
+TRAFFIC_ATY = {"gemm_source_sha256":
+               "efbb24c674842dd3cd7af298ad971b66e9aeacca1d3bffafd374fb5ac73ca5ea",
+               "read_bytes": 3.921e4 * 1024 * 2.0, "write_bytes": 4.184e4 * 1024 * 1.0,
+               "profile": "profiles/traffic_spiked-1000x10000-F1-r1024_fetch_write.md"}
+
+
+def traffic_aty():
+    """Measured traffic of the A^T Y product, or None once the GEMM source
+    differs from the one the counters were taken on."""
+    import hashlib
+
+    src = os.path.join(ROOT, "paper_1212_4137_amd", "csrc", "gemm_f32.hip")
+    with open(src, "rb") as f:
+        digest = hashlib.sha256(f.read()).hexdigest()
+    if digest != TRAFFIC_ATY["gemm_source_sha256"]:
+        return None
+    return {"bytes_per_launch": TRAFFIC_ATY["read_bytes"] + TRAFFIC_ATY["write_bytes"],
+            "read_bytes": TRAFFIC_ATY["read_bytes"], "write_bytes": TRAFFIC_ATY["write_bytes"],
+            "algorithmic_bytes": None, "source": TRAFFIC_ATY["profile"]}
+
 
 def cpu_baseline(A_np, X0_np, params, maxit_sample=25):
     """FP64 oracle on a bounded sample of the same workload: every
@@ -125,6 +149,12 @@ def bench_all8(args, spca, torch):
     work = sum(o["work"] for o in outs)
     kt_all = _sum_kt(outs)
     roofline = _roofline_aty(kt_all, r, n, p, PEAK_FP32_MFMA_TFLOPS)
+    tr = traffic_aty()
+    if tr is not None:
+        tr["algorithmic_bytes"] = 4.0 * (n * p + r * n + r * p)
+    roofline["traffic"] = tr["bytes_per_launch"] if tr else None
+    roofline["traffic_unit"] = "bytes per launch (HBM, FETCH_SIZE + WRITE_SIZE, calibrated)"
+    roofline["traffic_detail"] = tr
     other = {"x_update_avg_ms": round(kt_all["x_update_ms"] / kt_all["x_update_launches"], 5),
              "ax_dense_avg_ms": round(kt_all["ax_dense_ms"] / kt_all["ax_dense_launches"], 5),
              "mean_nnz_per_start": outs[-1]["nnz"],
@@ -266,6 +296,7 @@ def serve_requests(count, seed, precision):
     from workloads import counter
 
     rng = np.random.default_rng(seed)
+    prng = np.random.default_rng(seed + 1)  # precision draws: the shapes stay the same
     specs = []
     for i in range(count):
         n = int(rng.integers(200, 5001))
@@ -273,7 +304,8 @@ def serve_requests(count, seed, precision):
         fid = int(rng.integers(1, 9))
         r = int(rng.choice([16, 64, 256]))
         s = int(rng.integers(5, 201))
-        prec = precision if precision != "mixed" else ("bf16" if rng.random() < 0.5 else "fp32")
+        coin = prng.random()
+        prec = precision if precision != "mixed" else ("bf16" if coin < 0.5 else "fp32")
         thetas = (60.0, 40.0, 25.0)
         f = counter.spike_factors(seed + i, n, p, thetas, 50)
         spec = dict(n=n, p=p, seed=seed + i, thetas=thetas, U=f.U, V=f.V,
