@@ -36,21 +36,29 @@ PEAK_HBM_GBS = 8000.0
 # rocprofv3 FETCH_SIZE / WRITE_SIZE counter passes scaled by the same
 # counters on a 1 GiB copy (fetch x 2.0, write x 1.0); valid only for the
 # GEMM source they were taken on.
-TRAFFIC_ATY = {"gemm_source_sha256":
-               "efbb24c674842dd3cd7af298ad971b66e9aeacca1d3bffafd374fb5ac73ca5ea",
+TRAFFIC_ATY = {"gemm_kernel_sha256":
+               "04d6167979004eb3f586fdf107e9ea4d70d33c46395a5ecdd93384010eb8de2e",
                "read_bytes": 3.921e4 * 1024 * 2.0, "write_bytes": 4.184e4 * 1024 * 1.0,
                "profile": "profiles/traffic_spiked-1000x10000-F1-r1024_fetch_write.md"}
 
 
-def traffic_aty():
-    """Measured traffic of the A^T Y product, or None once the GEMM source
-    differs from the one the counters were taken on."""
+def gemm_kernel_digest():
+    """sha256 of the GEMM kernel's source (its tile configuration and the
+    kernel body, not the host-side planner in the same file)."""
     import hashlib
 
     src = os.path.join(ROOT, "paper_1212_4137_amd", "csrc", "gemm_f32.hip")
-    with open(src, "rb") as f:
-        digest = hashlib.sha256(f.read()).hexdigest()
-    if digest != TRAFFIC_ATY["gemm_source_sha256"]:
+    with open(src) as f:
+        text = f.read()
+    a = text.index("template <int BM, int BN, int WM, int WN>\nstruct GemmCfg")
+    b = text.index("// Compiled tile shapes.")
+    return hashlib.sha256(text[a:b].encode()).hexdigest()
+
+
+def traffic_aty():
+    """Measured traffic of the A^T Y product, or None once the GEMM kernel
+    differs from the one the counters were taken on."""
+    if gemm_kernel_digest() != TRAFFIC_ATY["gemm_kernel_sha256"]:
         return None
     return {"bytes_per_launch": TRAFFIC_ATY["read_bytes"] + TRAFFIC_ATY["write_bytes"],
             "read_bytes": TRAFFIC_ATY["read_bytes"], "write_bytes": TRAFFIC_ATY["write_bytes"],
@@ -145,6 +153,12 @@ def bench_all8(args, spca, torch):
                 modes[fid] = (t["iters_dense"], t["iters_list"], t["iters_union"])
         return {"work": work, "kt": kt, "nnz": nnz}
 
+    if args.autotune:
+        # a8: one tuned solve per formulation fills the tuning table before
+        # the timed steps (which then plan from it)
+        for fid in fids:
+            spca.am_solve(A, fid, params[fid], X0, tol=-1.0, maxit=2, ctx=ctx,
+                          stream=stream, flags=args.flags | spca.FLAG_AUTOTUNE)
     dt, outs = _timed_steps(step, args.steps, args.warmup)
     work = sum(o["work"] for o in outs)
     kt_all = _sum_kt(outs)
@@ -158,7 +172,10 @@ def bench_all8(args, spca, torch):
     other = {"x_update_avg_ms": round(kt_all["x_update_ms"] / kt_all["x_update_launches"], 5),
              "ax_dense_avg_ms": round(kt_all["ax_dense_ms"] / kt_all["ax_dense_launches"], 5),
              "mean_nnz_per_start": outs[-1]["nnz"],
-             "ax_modes_dense_list_union": modes}
+             "ax_modes_dense_list_union": modes,
+             "gemm_plans": {"aty": spca.gemm_plan(r, p, n, 1),
+                            "ax_dense": spca.gemm_plan(r, n, p, 16)},
+             "tuning_table": spca.tune_table_export()}
     rec = {
         "metric": "AM iters x starts/sec",
         "value": work / dt,
@@ -199,6 +216,9 @@ def bench_large(args, spca, torch):
     ctx = spca.Context(0)
     stream = torch.cuda.current_stream()
     res_last = {}
+    if args.autotune:
+        spca.am_solve(A, cfg["fid"], float(cfg["s"]), X0, tol=-1.0, maxit=2, ctx=ctx,
+                      stream=stream, flags=args.flags | spca.FLAG_AUTOTUNE)
 
     def step(timing):
         res = spca.am_solve(A, cfg["fid"], float(cfg["s"]), X0, tol=-1.0, maxit=maxit,
@@ -320,9 +340,10 @@ def serve_requests(count, seed, precision):
 
 
 def run_stream(spca, specs, qps, workers, arena, seed):
-    """Submits the requests at Poisson arrival times and collects them."""
+    """Submits the requests at Poisson arrival times (all at once when qps is
+    infinite) and collects them."""
     rng = np.random.default_rng(seed + 7)
-    gaps = rng.exponential(1.0 / qps, len(specs))
+    gaps = rng.exponential(1.0 / qps, len(specs)) if np.isfinite(qps) else np.zeros(len(specs))
     done = {}
     with spca.Server(arena, workers=workers) as srv:
         t0 = time.monotonic()
@@ -345,64 +366,88 @@ def run_stream(spca, specs, qps, workers, arena, seed):
     if bad:
         raise RuntimeError(f"{len(bad)} requests failed, first: {bad[0]['error']}")
     lat = np.array([c["t_done"] - c["t_submit"] for c in comps])
+    solve = np.array([c["t_done"] - c["t_solve"] for c in comps])
     first = min(c["t_submit"] for c in comps)
     last = max(c["t_done"] for c in comps)
-    return {"solves_per_s": len(comps) / (last - first),
+    return {"offered_qps": qps if np.isfinite(qps) else "all at t=0",
+            "solves_per_s": len(comps) / (last - first),
             "p50_ms": float(np.percentile(lat, 50) * 1e3),
             "p99_ms": float(np.percentile(lat, 99) * 1e3),
-            "mean_ms": float(lat.mean() * 1e3), "wall_s": last - first,
-            "peak_running": stats["peak_running"],
+            "solve_only_p50_ms": float(np.percentile(solve, 50) * 1e3),
+            "solve_only_p99_ms": float(np.percentile(solve, 99) * 1e3),
+            "wall_s": last - first, "peak_running": stats["peak_running"],
             "peak_in_use_GB": stats["peak_in_use_bytes"] / 1e9}, comps
 
 
 def bench_serve(args, spca, torch):
-    """Serving: a Poisson stream of requests of mixed shape, formulation and
-    precision at a fixed rate, run three ways on the same stream:
-    continuous batching with per-request precision (the measured path),
-    continuous batching with FP32 only, and one request at a time in FP32
-    (the baseline)."""
-    count, qps = args.requests, args.qps
+    """Serving: Poisson streams of requests of mixed shape, formulation and
+    precision.  First the saturation rate C of the baseline (one request at
+    a time, FP32, every request queued at t = 0) and of the batched paths;
+    then latency at offered loads of 0.5, 1 and 2 x C, continuous batching
+    with per-request precision against the baseline."""
+    count = args.requests
     seed = workloads.SEED_BASE + 5
     arena = int(args.arena_gb * (1 << 30))
     runs = {}
     comps = {}
-    # warm the library (kernels load on first use) outside the timed streams
     warm = serve_requests(4, seed + 999, "mixed")
-    run_stream(spca, warm, 1000.0, args.workers, arena, seed)
-    for name, prec, workers in (("batched_mixed", "mixed", args.workers),
-                                ("batched_fp32", "fp32", args.workers),
-                                ("one_at_a_time_fp32", "fp32", 1)):
+    run_stream(spca, warm, float("inf"), args.workers, arena, seed)
+
+    def go(name, prec, workers, qps):
         specs = serve_requests(count, seed, prec)
         runs[name], comps[name] = run_stream(spca, specs, qps, workers, arena, seed)
         print(json.dumps({name: runs[name]}), file=sys.stderr, flush=True)
-    # accuracy at equal settings: per request, the final objective of the
-    # served path against the FP32 one-at-a-time run of the same request
-    gaps = np.array([abs(a["objective"] - b["objective"]) / max(abs(b["objective"]), 1e-300)
-                     for a, b in zip(comps["batched_mixed"], comps["one_at_a_time_fp32"])])
+
+    go("saturated/one_at_a_time_fp32", "fp32", 1, float("inf"))
+    C = runs["saturated/one_at_a_time_fp32"]["solves_per_s"]
+    go("saturated/batched_fp32", "fp32", args.workers, float("inf"))
+    go("saturated/batched_mixed", "mixed", args.workers, float("inf"))
+    loads = [float(x) for x in args.loads.split(",")]
+    for mult in loads:
+        go(f"{mult}xC/batched_mixed", "mixed", args.workers, mult * C)
+        go(f"{mult}xC/one_at_a_time_fp32", "fp32", 1, mult * C)
+    # accuracy, request by request: the served precision mix against the
+    # FP32 one-at-a-time result of the same request
+    base = comps["saturated/one_at_a_time_fp32"]
+    mixed = comps["saturated/batched_mixed"]
+    specs = serve_requests(count, seed, "mixed")
+    bf = [i for i, sp in enumerate(specs) if sp["precision"] == "bf16"]
+    signed = np.array([(mixed[i]["objective"] - base[i]["objective"]) /
+                       max(abs(base[i]["objective"]), 1e-300) for i in bf])
+    gaps = np.abs(signed)
     same32 = all(a["objective"] == b["objective"]
-                 for a, b in zip(comps["batched_fp32"], comps["one_at_a_time_fp32"]))
-    m = runs["batched_mixed"]
-    base = runs["one_at_a_time_fp32"]
+                 for a, b in zip(comps["saturated/batched_fp32"], base))
+    ref = f"{loads[len(loads) // 2]}xC"
+    m = runs[f"{ref}/batched_mixed"]
     return {
         "metric": "solves/s with p50/p99 latency (continuous batching)",
-        "value": m["solves_per_s"], "unit": "solves/s", "n_gpus": 1,
-        "steps": count, "warmup": 4, "ms_per_step": m["wall_s"] / count * 1e3,
+        "value": runs["saturated/batched_mixed"]["solves_per_s"], "unit": "solves/s",
+        "n_gpus": 1, "steps": count, "warmup": 4,
+        "ms_per_step": runs["saturated/batched_mixed"]["wall_s"] / count * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "mixed f32 / bf16+f32 polish",
         "data": "synthetic (per-request spiked model generated in HBM)",
-        "config": {"workload": f"serve-poisson-{count}req-{qps}qps", "requests": count,
-                   "qps": qps, "workers": args.workers, "arena_GB": args.arena_gb,
+        "config": {"workload": f"serve-poisson-{count}req", "requests": count,
+                   "workers": args.workers, "arena_GB": args.arena_gb,
                    "n": "U[200,5000]", "p": "U[1000,50000]", "formulation": "U{1..8}",
                    "s": "U[5,200]", "gamma": "0.1*max_i ||a_i||_2", "r": [16, 64, 256],
-                   "precision": "50% fp32, 50% bf16+polish", "tol": 1e-6, "maxit": 200},
-        "p50_ms": m["p50_ms"], "p99_ms": m["p99_ms"],
-        "speedup_vs_one_at_a_time_fp32": m["solves_per_s"] / base["solves_per_s"],
-        "runs": runs,
+                   "precision": "50% fp32, 50% bf16+polish", "tol": 1e-6, "maxit": 200,
+                   "baseline_saturation_C_per_s": C, "loads_x_C": loads},
+        "p50_ms": m["p50_ms"], "p99_ms": m["p99_ms"], "latency_at": ref,
+        "baseline_p50_ms": runs[f"{ref}/one_at_a_time_fp32"]["p50_ms"],
+        "baseline_p99_ms": runs[f"{ref}/one_at_a_time_fp32"]["p99_ms"],
+        "speedup_vs_one_at_a_time_fp32": runs["saturated/batched_mixed"]["solves_per_s"] / C,
+        "batched_fp32_solves_per_s": runs["saturated/batched_fp32"]["solves_per_s"],
         "fp32_batched_equals_one_at_a_time": same32,
-        "objective_rel_gap_vs_fp32": {"median": float(np.median(gaps)),
-                                      "p99": float(np.percentile(gaps, 99)),
-                                      "max": float(gaps.max()),
-                                      "frac_le_1e-5": float(np.mean(gaps <= 1e-5))},
+        "bf16_requests_objective_rel_gap_vs_fp32": {
+            "count": len(bf), "median": float(np.median(gaps)),
+            "p90": float(np.percentile(gaps, 90)), "max": float(gaps.max()),
+            "frac_le_1e-5": float(np.mean(gaps <= 1e-5)),
+            "frac_le_1e-3": float(np.mean(gaps <= 1e-3)),
+            "frac_bf16_better": float(np.mean(signed > 1e-5)),
+            "frac_bf16_worse": float(np.mean(signed < -1e-5)),
+            "mean_signed": float(np.mean(signed))},
+        "runs": runs,
     }
 
 
@@ -422,9 +467,12 @@ def main():
                     help="formulations in a step of spiked-all8 (default: all 8)")
     ap.add_argument("--maxit", type=int, default=0, help="iterations per solve (large)")
     ap.add_argument("--requests", type=int, default=200, help="serve: requests")
-    ap.add_argument("--qps", type=float, default=10.0, help="serve: arrival rate")
+    ap.add_argument("--loads", default="0.5,1,2",
+                    help="serve: offered loads as multiples of the baseline saturation rate")
     ap.add_argument("--workers", type=int, default=4, help="serve: concurrent solves")
     ap.add_argument("--arena-gb", type=float, default=64.0, help="serve: HBM arena")
+    ap.add_argument("--autotune", action="store_true",
+                    help="time every tile shape and split first (spiked-all8, large)")
     ap.add_argument("--graph", action="store_true",
                     help="replay the iterations from a captured HIP graph")
     args = ap.parse_args()

@@ -151,6 +151,13 @@ typedef struct {
 #define SPCA_FLAG_GRAPH 1
 #define SPCA_FLAG_CHECK_FINITE 2 /* reject A holding NaN or Inf (EINVAL)     */
 #define SPCA_FLAG_DENSE_ONLY 4   /* never use the sparse A x product         */
+/* SPCA_FLAG_AUTOTUNE: before iterating, time every compiled tile shape and
+ * K split of the two products on this solve's own operands (products whose
+ * size bucket already has a tuning-table entry are skipped) and record the
+ * fastest in the process-wide tuning table, which later plans use.  A
+ * product's result depends on its K split, so tuned solves are
+ * reproducible given the table (see spca_tune_table_export).              */
+#define SPCA_FLAG_AUTOTUNE 8
 
 typedef struct {
   double* x;           /* host, p doubles (see spca_am_solve), or NULL      */
@@ -217,6 +224,19 @@ int spca_gemm_nt_f32_shape(void* stream, const float* P, int64_t ldp,
 
 /* The tile shape and K split the library picks for an M x N x K product
  * (deterministic, from a model of CU occupancy and tile efficiency).     */
+/* Tuning table of the product tiles: one line per entry,
+ *   "elem_bytes max_splits bucket(M) bucket(N) bucket(K) shape splits"
+ * with bucket(x) = round(2 log2 x).  Export writes the table as text into
+ * buf (cap bytes, NUL-terminated; *len = its length, also when buf is NULL
+ * or too small, in which case EINVAL is returned for the too-small buffer);
+ * import adds (or replaces) entries from such text (EINVAL on a malformed
+ * line, and then nothing is imported); clear removes every entry.  Plans
+ * (spca_gemm_nt_f32_plan and the solves) use an entry of their bucket
+ * before the cost model.  Host-only: no device is touched.                */
+int spca_tune_table_export(char* buf, size_t cap, size_t* len);
+int spca_tune_table_import(const char* text);
+int spca_tune_table_clear(void);
+
 int spca_gemm_nt_f32_plan(int64_t M, int64_t N, int64_t K, int max_splits,
                           int* shape, int* splits);
 
@@ -274,7 +294,10 @@ typedef struct {
   int32_t reserved;
   spca_result res;
   double s_or_gamma;    /* the parameter the solve used */
-  double t_submit, t_admit, t_done; /* seconds on the monotonic clock */
+  double t_submit;      /* seconds on the monotonic clock: submission,  */
+  double t_admit;       /* admission (memory and worker granted),       */
+  double t_solve;       /* inputs generated, solve starts,              */
+  double t_done;        /* result written                               */
   size_t footprint;     /* bytes of the server arena the request held */
   char error[160];      /* message when rc != SPCA_OK */
 } spca_completion;

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(PKG, "libspca.so")
 SPCA_OK, SPCA_EINVAL, SPCA_ENOMEM, SPCA_EHIP = 0, -1, -2, -3
 CONVERGED, MAXIT, DEGENERATE, ZERO = 0, 1, 2, 3
 PREC_FP32, PREC_BF16_POLISH = 0, 1
-FLAG_GRAPH, FLAG_CHECK_FINITE, FLAG_DENSE_ONLY = 1, 2, 4
+FLAG_GRAPH, FLAG_CHECK_FINITE, FLAG_DENSE_ONLY, FLAG_AUTOTUNE = 1, 2, 4, 8
 
 EXPORTED = ("spca_am_solve", "spca_am_solve_ex", "spca_ctx_create",
             "spca_ctx_destroy", "spca_workspace_bytes", "spca_last_error",
@@ -27,7 +27,8 @@ EXPORTED = ("spca_am_solve", "spca_am_solve_ex", "spca_ctx_create",
             "spca_gemm_nt_f32_plan", "spca_x_update", "spca_generate_spiked",
             "spca_ctx_set_workspace", "spca_request_footprint", "spca_server_create",
             "spca_server_submit", "spca_server_poll", "spca_server_stats",
-            "spca_server_destroy")
+            "spca_server_destroy", "spca_tune_table_export", "spca_tune_table_import",
+            "spca_tune_table_clear")
 
 
 class SpcaError(RuntimeError):
@@ -84,7 +85,7 @@ class Completion(ctypes.Structure):
     _fields_ = [("id", ctypes.c_int64), ("rc", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("res", Result), ("s_or_gamma", ctypes.c_double),
                 ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double),
-                ("t_done", ctypes.c_double), ("footprint", ctypes.c_size_t),
+                ("t_solve", ctypes.c_double), ("t_done", ctypes.c_double), ("footprint", ctypes.c_size_t),
                 ("error", ctypes.c_char * 160)]
 
 
@@ -140,6 +141,13 @@ def load():
         lib.spca_gemm_nt_f32_plan.restype = ctypes.c_int
         lib.spca_x_update.argtypes = [P, ctypes.c_int, P, i64, i64, i64, d, P, i64, P, P]
         lib.spca_x_update.restype = ctypes.c_int
+        lib.spca_tune_table_export.argtypes = [ctypes.c_char_p, ctypes.c_size_t,
+                                               ctypes.POINTER(ctypes.c_size_t)]
+        lib.spca_tune_table_export.restype = ctypes.c_int
+        lib.spca_tune_table_import.argtypes = [ctypes.c_char_p]
+        lib.spca_tune_table_import.restype = ctypes.c_int
+        lib.spca_tune_table_clear.argtypes = []
+        lib.spca_tune_table_clear.restype = ctypes.c_int
         lib.spca_ctx_set_workspace.argtypes = [P, P, ctypes.c_size_t]
         lib.spca_ctx_set_workspace.restype = ctypes.c_int
         lib.spca_request_footprint.argtypes = [ctypes.POINTER(Request)]
@@ -505,7 +513,8 @@ class Server:
                  "nnz": c.res.nnz, "iters": c.res.iters, "status": c.res.status,
                  "best_start": c.res.best_start, "iters_x_starts": c.res.iters_x_starts,
                  "polish_iters": c.res.polish_iters, "s_or_gamma": c.s_or_gamma,
-                 "t_submit": c.t_submit, "t_admit": c.t_admit, "t_done": c.t_done,
+                 "t_submit": c.t_submit, "t_admit": c.t_admit, "t_solve": c.t_solve,
+                 "t_done": c.t_done,
                  "footprint": c.footprint}
             if q.x_out:
                 x, sup = keep[-2], keep[-1]
@@ -529,3 +538,20 @@ class Server:
 
     def __exit__(self, *exc):
         self.close()
+
+
+def tune_table_export():
+    """The tuning table as text (``spca_tune_table_export``)."""
+    n = ctypes.c_size_t()
+    _check(load().spca_tune_table_export(None, 0, ctypes.byref(n)))
+    buf = ctypes.create_string_buffer(n.value + 1)
+    _check(load().spca_tune_table_export(buf, n.value + 1, ctypes.byref(n)))
+    return buf.value.decode()
+
+
+def tune_table_import(text):
+    _check(load().spca_tune_table_import(text.encode()))
+
+
+def tune_table_clear():
+    _check(load().spca_tune_table_clear())

@@ -22,6 +22,13 @@
 // BF16 operands: the same 128-byte LDS rows hold 64 bf16 of K; each 16-byte
 // chunk (8 bf16 of one row) feeds one v_mfma_f32_32x32x16_bf16 instead of
 // four FP32 MFMAs, and the products accumulate in FP32.
+#include <cmath>
+#include <cstdio>
+#include <map>
+#include <mutex>
+#include <sstream>
+#include <string>
+
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -297,8 +304,9 @@ void dispatch(int shape, hipStream_t st, const T* P, int64_t ldp,
 
 }  // namespace
 
-// Deterministic choice of tile shape and K split from a model of one
-// launch, in cycles of one CU:
+// Choice of tile shape and K split: a measured winner from the tuning table
+// when there is one, else the deterministic model below.
+// Model of one launch, in cycles of one CU:
 //   a workgroup's MFMA work  w = BM * BN * (K slabs per split * 32)
 //                               / (128 MACs per cycle * eff);
 //   the workgroups fill rounds of 256 CUs x occ slots; a CU running k
@@ -307,8 +315,102 @@ void dispatch(int shape, hipStream_t st, const T* P, int64_t ldp,
 //   w * max(ceil(rest / 256), 1.5);
 //   split partials cost their HBM traffic, 8 bytes per element per split at
 //   about 1.7 KB per cycle for the whole chip.
+// ---------------------------------------------------------------------------
+// Tuning table: measured winners keyed by element width, max splits and the
+// half-octave buckets of M, N and K (round(2 log2 x)).  Filled by the
+// autotuner of the solve (or imported as text); consulted before the model.
+// ---------------------------------------------------------------------------
+namespace {
+struct TuneKey {
+  int eb, ms, bm, bn, bk;
+  bool operator<(const TuneKey& o) const {
+    if (eb != o.eb) return eb < o.eb;
+    if (ms != o.ms) return ms < o.ms;
+    if (bm != o.bm) return bm < o.bm;
+    if (bn != o.bn) return bn < o.bn;
+    return bk < o.bk;
+  }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, GemmPlan> g_tune;
+
+int bucket(int64_t x) { return (int)std::lround(2.0 * std::log2((double)(x > 0 ? x : 1))); }
+TuneKey key_of(int64_t M, int64_t N, int64_t K, int ms, int eb) {
+  return TuneKey{eb, ms, bucket(M), bucket(N), bucket(K)};
+}
+}  // namespace
+
+bool tuned_plan(int64_t M, int64_t N, int64_t K, int max_splits, int elem_bytes,
+                GemmPlan* out) {
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  auto it = g_tune.find(key_of(M, N, K, max_splits, elem_bytes));
+  if (it == g_tune.end()) return false;
+  *out = it->second;
+  return true;
+}
+
+void record_tuned_plan(int64_t M, int64_t N, int64_t K, int max_splits,
+                       int elem_bytes, GemmPlan plan) {
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  g_tune[key_of(M, N, K, max_splits, elem_bytes)] = plan;
+}
+
+std::string tune_table_text() {
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  std::ostringstream os;
+  for (const auto& kv : g_tune)
+    os << kv.first.eb << ' ' << kv.first.ms << ' ' << kv.first.bm << ' ' << kv.first.bn
+       << ' ' << kv.first.bk << ' ' << kv.second.shape << ' ' << kv.second.splits << '\n';
+  return os.str();
+}
+
+bool tune_table_load(const char* text, std::string* err) {
+  std::map<TuneKey, GemmPlan> t;
+  std::istringstream is(text);
+  std::string line;
+  int ln = 0;
+  while (std::getline(is, line)) {
+    ++ln;
+    if (line.find_first_not_of(" \t\r") == std::string::npos) continue;
+    std::istringstream ls(line);
+    TuneKey k;
+    GemmPlan g;
+    if (!(ls >> k.eb >> k.ms >> k.bm >> k.bn >> k.bk >> g.shape >> g.splits) ||
+        (k.eb != 2 && k.eb != 4) || g.shape < 0 || g.shape >= gemm_num_shapes() ||
+        g.splits < 1 || g.splits > k.ms) {
+      *err = "bad tuning entry on line " + std::to_string(ln);
+      return false;
+    }
+    t[k] = g;
+  }
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  for (const auto& kv : t) g_tune[kv.first] = kv.second;
+  return true;
+}
+
+void tune_table_clear() {
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  g_tune.clear();
+}
+
+int max_feasible_splits(int64_t K, int max_splits, int elem_bytes) {
+  const int64_t kslabs = ceil_div(K, 128 / elem_bytes);
+  int s = 1;
+  while (s * 2 <= max_splits && ceil_div(kslabs, (int64_t)s * 2) >= 8) s *= 2;
+  return s;
+}
+
 GemmPlan plan_gemm_nt(int64_t M, int64_t N, int64_t K, int max_splits,
                       int elem_bytes) {
+  {
+    GemmPlan t;
+    if (tuned_plan(M, N, K, max_splits, elem_bytes, &t)) return t;
+  }
+  return model_plan_gemm_nt(M, N, K, max_splits, elem_bytes);
+}
+
+GemmPlan model_plan_gemm_nt(int64_t M, int64_t N, int64_t K, int max_splits,
+                            int elem_bytes) {
   GemmPlan best{0, 1};
   double best_cost = 1e300;
   const int64_t slab_k = 128 / elem_bytes;

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <string>
+
 namespace spca {
 
 // x-operator kinds (Table 3): constraint L0 -> T_s, constraint L1 ->
@@ -55,7 +57,21 @@ struct GemmPlan {
 // elem_bytes-byte operands (4: FP32, 2: BF16).
 GemmPlan plan_gemm_nt(int64_t M, int64_t N, int64_t K, int max_splits,
                       int elem_bytes = 4);
+// the cost model alone (no tuning table)
+GemmPlan model_plan_gemm_nt(int64_t M, int64_t N, int64_t K, int max_splits,
+                            int elem_bytes = 4);
 int gemm_num_shapes();
+// largest power-of-two split count (<= max_splits) that leaves every split
+// at least 8 K slabs
+int max_feasible_splits(int64_t K, int max_splits, int elem_bytes);
+// tuning table (process-wide, thread-safe)
+bool tuned_plan(int64_t M, int64_t N, int64_t K, int max_splits, int elem_bytes,
+                GemmPlan* out);
+void record_tuned_plan(int64_t M, int64_t N, int64_t K, int max_splits,
+                       int elem_bytes, GemmPlan plan);
+std::string tune_table_text();
+bool tune_table_load(const char* text, std::string* err);
+void tune_table_clear();
 
 // C (M x N, ldc) = P (M x K, ldp) * Q (N x K, ldq)^T, FP32 MFMA.  With
 // plan.splits > 1, K split s writes its partial product at

@@ -191,6 +191,9 @@ int run_job(spca_server* srv, Job& job, size_t off, hipStream_t st, spca_ctx* ct
     param = q.gamma_rel * sqrt(m2);
   }
   c->s_or_gamma = param;
+  // inputs are ready: what follows is the solve alone
+  SPCA_HIP_TRY(hipStreamSynchronize(st));
+  c->t_solve = now_s();
   rc = spca_ctx_set_workspace(ctx, ws, f.ws);
   if (rc != SPCA_OK) return rc;
   spca_problem prob{A, q.n, q.p, lda, q.formulation, param};

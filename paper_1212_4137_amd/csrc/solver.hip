@@ -13,6 +13,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cstring>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -48,6 +49,7 @@ struct Layout {
   int64_t ldab, ldatb, ldyb, ldxb;
   size_t off_Ab, off_Atb, off_Yb, off_Xb, off_Xp;
   GemmPlan plan_ax, plan_aty;
+  int ax_split_cap;
   size_t off_At, off_Ac, off_X, off_U, off_Y, off_V, off_li, off_lv;
   size_t off_phi, off_phip, off_nnz, off_it, off_st, off_plan, off_part,
       off_f, off_ev, off_xn, off_best, off_xout, off_sup, off_colsq, off_bad;
@@ -100,7 +102,10 @@ Layout make_layout(int64_t n, int64_t p, int64_t r, bool copy_a, bool bf16) {
 
   L.off_Ac = carve(&c, copy_a ? sizeof(float) * (size_t)p * L.ldac : 0);
   L.off_X = carve(&c, sizeof(float) * (size_t)r * L.ldx);
-  L.off_U = carve(&c, sizeof(float) * (size_t)L.plan_ax.splits * r * L.ldu);
+  // room for the largest split count a tuned plan may pick
+  L.ax_split_cap = max_feasible_splits(p, kMaxSplits, eb);
+  if (L.ax_split_cap < L.plan_ax.splits) L.ax_split_cap = L.plan_ax.splits;
+  L.off_U = carve(&c, sizeof(float) * (size_t)L.ax_split_cap * r * L.ldu);
   L.off_Y = carve(&c, sizeof(float) * (size_t)r * L.ldu);
   L.off_V = carve(&c, sizeof(float) * (size_t)r * L.ldx);
   L.off_li = carve(&c, sizeof(int32_t) * (size_t)r * L.ldx);
@@ -221,6 +226,50 @@ static int ensure_capture_stream(spca_ctx* ctx) {
 }
 
 using namespace spca;
+
+// Times `launch` for every compiled shape and every power-of-two split up to
+// split_cap (3 runs after 1 warm-up, HIP events on the stream) and records
+// the fastest in the tuning table under (M, N, K, max_splits).  Shapes whose
+// rows would be mostly padding are skipped, as in the model.
+template <typename F>
+static int autotune_product(hipStream_t st, int64_t M, int64_t N, int64_t K,
+                            int split_cap, int max_splits, int eb, F launch) {
+  static const int kBM[] = {128, 128, 128, 128, 64, 32};
+  hipEvent_t e0, e1;
+  SPCA_HIP_TRY(hipEventCreate(&e0));
+  hipError_t ce = hipEventCreate(&e1);
+  if (ce != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    SPCA_HIP_TRY(ce);
+  }
+  GemmPlan best = model_plan_gemm_nt(M, N, K, max_splits, eb);
+  float best_ms = 3.4e38f;
+  hipError_t err = hipSuccess;
+  const int cap = max_feasible_splits(K, split_cap, eb);
+  for (int shape = 0; shape < gemm_num_shapes() && err == hipSuccess; ++shape) {
+    if (kBM[shape] > 32 && M <= kBM[shape] / 2) continue;
+    for (int splits = 1; splits <= cap && err == hipSuccess; splits *= 2) {
+      const GemmPlan g{shape, splits};
+      launch(g);
+      err = hipEventRecord(e0, st);
+      for (int k = 0; k < 3 && err == hipSuccess; ++k) launch(g);
+      if (err == hipSuccess) err = hipEventRecord(e1, st);
+      if (err == hipSuccess) err = hipEventSynchronize(e1);
+      if (err == hipSuccess) err = hipGetLastError();
+      float ms = 0.f;
+      if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+      if (err == hipSuccess && ms < best_ms) {
+        best_ms = ms;
+        best = g;
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  SPCA_HIP_TRY(err);
+  record_tuned_plan(M, N, K, max_splits, eb, best);
+  return SPCA_OK;
+}
 
 extern "C" {
 
@@ -402,7 +451,7 @@ int spca_am_solve_ex(spca_ctx* ctx, void* stream, const spca_problem* prob,
   hipStream_t st = (hipStream_t)stream;
 
   const bool copy_a = (lda % 4) != 0 || ((uintptr_t)prob->A % 16) != 0;
-  const Layout L = make_layout(n, p, r, copy_a, bf16);
+  Layout L = make_layout(n, p, r, copy_a, bf16);
   rc = ensure_workspace(ctx, st, solve_bytes(L, n, p, r));
   if (rc != SPCA_OK) return rc;
   char* base = (char*)ctx->ws;
@@ -471,6 +520,39 @@ int spca_am_solve_ex(spca_ctx* ctx, void* stream, const spca_problem* prob,
                                   hipMemcpyDeviceToDevice, st));
   } else {
     max_norm_column_start(st, A, ldA, n, p, colsq, X, L.ldx);
+  }
+  if (opts->flags & SPCA_FLAG_AUTOTUNE) {
+    // a8: measure every tile shape and split on this solve's own operands
+    // for the products that have no entry in the tuning table yet
+    SPCA_HIP_TRY(hipMemsetAsync(Y, 0, sizeof(float) * r * L.ldu, st));
+    if (bf16) SPCA_HIP_TRY(hipMemsetAsync(Yb, 0, sizeof(uint16_t) * r * L.ldyb, st));
+    const int eb = bf16 ? 2 : 4;
+    GemmPlan tmp;
+    if (!tuned_plan(r, n, p, kMaxSplits, eb, &tmp)) {
+      if (bf16) rows_to_bf16(st, X, L.ldx, r, p, Xb, L.ldxb, nullptr);
+      auto run_ax = [&](GemmPlan g) {
+        if (bf16)
+          gemm_nt_bf16(st, Xb, L.ldxb, Atb, L.ldatb, U, L.ldu, r, n, p, nullptr, 0, g,
+                       r * L.ldu);
+        else
+          gemm_nt_f32(st, X, L.ldx, At, L.ldat, U, L.ldu, r, n, p, nullptr, 0, g,
+                      r * L.ldu);
+      };
+      rc = autotune_product(st, r, n, p, L.ax_split_cap, kMaxSplits, eb, run_ax);
+      if (rc != SPCA_OK) return rc;
+    }
+    if (!tuned_plan(r, p, n, 1, eb, &tmp)) {
+      auto run_aty = [&](GemmPlan g) {
+        if (bf16)
+          gemm_nt_bf16(st, Yb, L.ldyb, Ab, L.ldab, V, L.ldx, r, p, n, nullptr, 0, g, 0);
+        else
+          gemm_nt_f32(st, Y, L.ldu, A, ldA, V, L.ldx, r, p, n, nullptr, 0, g, 0);
+      };
+      rc = autotune_product(st, r, p, n, 1, 1, eb, run_aty);
+      if (rc != SPCA_OK) return rc;
+    }
+    L.plan_ax = plan_gemm_nt(r, n, p, kMaxSplits, eb);
+    L.plan_aty = plan_gemm_nt(r, p, n, 1, eb);
   }
   init_state(st, s, r);
   init_plan(st, plan, L.plan_ax.splits);
@@ -780,6 +862,31 @@ int spca_gemm_nt_bf16(void* stream, const uint16_t* P, int64_t ldp,
   gemm_nt_bf16((hipStream_t)stream, P, ldp, Q, ldq, C, ldc, M, N, K, nullptr, 0,
                plan_gemm_nt(M, N, K, 1, 2), 0);
   SPCA_LAUNCH_CHECK("gemm_nt_bf16");
+  return SPCA_OK;
+}
+
+int spca_tune_table_export(char* buf, size_t cap, size_t* len) {
+  SPCA_REQUIRE(len != nullptr, "len must not be NULL");
+  const std::string t = tune_table_text();
+  *len = t.size();
+  if (buf != nullptr && cap > 0) {
+    const size_t k = t.size() < cap - 1 ? t.size() : cap - 1;
+    std::memcpy(buf, t.data(), k);
+    buf[k] = '\0';
+    SPCA_REQUIRE(t.size() < cap, "buffer too small for the tuning table");
+  }
+  return SPCA_OK;
+}
+
+int spca_tune_table_import(const char* text) {
+  SPCA_REQUIRE(text != nullptr, "text must not be NULL");
+  std::string err;
+  SPCA_REQUIRE(tune_table_load(text, &err), err.c_str());
+  return SPCA_OK;
+}
+
+int spca_tune_table_clear(void) {
+  tune_table_clear();
   return SPCA_OK;
 }
 

@@ -89,3 +89,25 @@ def test_workspace_bytes_is_monotone():
     b = spca.workspace_bytes(1000, 10000, 1024)
     assert 0 < a < b
     assert spca.workspace_bytes(0, 5, 1) == 0
+
+
+def test_tuning_table_round_trip_and_plan_lookup():
+    import paper_1212_4137_amd as m
+
+    m.tune_table_clear()
+    assert m.tune_table_export() == ""
+    model = m.gemm_plan(1024, 10000, 1000, 1)
+    # bucket(x) = round(2 log2 x): 1024 -> 20, 10000 -> 27, 1000 -> 20
+    other = (model[0] + 1) % 6
+    m.tune_table_import(f"4 1 20 27 20 {other} 1\n")
+    assert m.gemm_plan(1024, 10000, 1000, 1) == (other, 1)
+    assert m.gemm_plan(1100, 10500, 1050, 1) == (other, 1)  # same buckets
+    assert m.gemm_plan(1024, 10000, 1000, 2) == m.gemm_plan(1024, 10000, 1000, 2)
+    text = m.tune_table_export()
+    assert text == f"4 1 20 27 20 {other} 1\n"
+    for bad in ("4 1 x", "3 1 20 27 20 0 1", "4 1 20 27 20 9 1", "4 1 20 27 20 0 2"):
+        with pytest.raises(m.SpcaError):
+            m.tune_table_import(bad)
+    assert m.tune_table_export() == text  # a rejected import changes nothing
+    m.tune_table_clear()
+    assert m.gemm_plan(1024, 10000, 1000, 1) == model

@@ -1,0 +1,61 @@
+"""Autotuned tile plans (SPCA_FLAG_AUTOTUNE): the tuner fills the table for
+both products of a solve, results keep parity with the oracle, and solves
+are bit-reproducible given the table (export, clear, import)."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from gpu_helpers import compare_solve, to_device_colmajor, to_device_rows
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def spca():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1212_4137_amd as m
+
+    m.load()
+    m.tune_table_clear()
+    yield m
+    m.tune_table_clear()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_autotune_fills_table_and_is_reproducible(spca, prec):
+    spca.tune_table_clear()
+    sp = workloads.spiked_matrix(51, 300, 3000, thetas=(60.0, 30.0), spike_nnz=20)
+    X0n = workloads.random_unit_starts(52, 128, 3000)
+    A, X0 = to_device_colmajor(sp.A), to_device_rows(X0n)
+    kw = dict(tol=1e-8, maxit=200, precision=prec, polish_maxit=100, return_X=True)
+    res = {}
+    for fid in (1, 5):
+        par = workloads.s_or_gamma_for(fid, sp.A, 20)
+        res[fid] = spca.am_solve(A, fid, par, X0, flags=spca.FLAG_AUTOTUNE, **kw)
+    lines = spca.tune_table_export().splitlines()
+    eb = "2" if prec == "bf16" else "4"
+    # the two products of the solve; a BF16 solve also tunes the FP32
+    # products of its polish sub-solve (fewer starts)
+    assert sum(ln.split()[0] == eb for ln in lines) == 2, lines
+    assert len(lines) == (4 if prec == "bf16" else 2), lines
+    if prec == "fp32":
+        for fid in (1, 5):
+            par = workloads.s_or_gamma_for(fid, sp.A, 20)
+            ref = oracle.am_multi(sp.A.astype(np.float64), fid, par, X0n.astype(np.float64),
+                                  1e-8, 200, nthreads=8)
+            compare_solve(res[fid], ref, f"autotuned F{fid}")
+    text = spca.tune_table_export()
+    spca.tune_table_clear()
+    spca.tune_table_import(text)
+    assert spca.tune_table_export() == text
+    for fid in (1, 5):
+        par = workloads.s_or_gamma_for(fid, sp.A, 20)
+        again = spca.am_solve(A, fid, par, X0, **kw)  # plans from the imported table
+        assert again["objective"] == res[fid]["objective"]
+        assert np.array_equal(again["f_per_start"], res[fid]["f_per_start"])
+        assert torch.equal(again["X_final"], res[fid]["X_final"])
+    spca.tune_table_clear()
