@@ -451,7 +451,63 @@ def bench_serve(args, spca, torch):
     }
 
 
-WORKLOADS = {"spiked-all8": bench_all8, "large": bench_large, "precision": bench_precision,
+def bench_otf(args, spca, torch):
+    """Section 4.3 on the spiked 1000 x 10000 model: 1024 starting points
+    (F1 and F5, tol 1e-6, maxit 200) solved all at once (1024 slots), in 16
+    sequential batches of 64, and with on-the-fly replacement through 64
+    slots.  A step is one solve of all 1024 starts in each of the three
+    ways; reported per way: ms per solve and iterations x starts/s."""
+    cfg = workloads.SPIKED_ALL8
+    n, p, l = cfg["n"], cfg["p"], cfg["r"]
+    slots = args.slots
+    sp = workloads.spiked_matrix(cfg["seed"], n, p, cfg["thetas"], cfg["spike_nnz"])
+    A = torch.from_numpy(np.ascontiguousarray(sp.A.T)).cuda().t()
+    X0 = torch.from_numpy(workloads.random_unit_starts(cfg["seed"] + 1000, l, p)).cuda()
+    ctx = spca.Context(0)
+    stream = torch.cuda.current_stream()
+    fids = (1, 5)
+    params = {fid: workloads.s_or_gamma_for(fid, sp.A, cfg["s"]) for fid in fids}
+    ways = {}
+
+    def all_at_once(fid):
+        return [spca.am_solve(A, fid, params[fid], X0, tol=1e-6, maxit=200, ctx=ctx,
+                              stream=stream, flags=args.flags)]
+
+    def batches(fid):
+        return [spca.am_solve(A, fid, params[fid], X0[b:b + slots].contiguous(), tol=1e-6,
+                              maxit=200, ctx=ctx, stream=stream, flags=args.flags)
+                for b in range(0, l, slots)]
+
+    def otf(fid):
+        return [spca.am_solve(A, fid, params[fid], X0, tol=1e-6, maxit=200, ctx=ctx,
+                              stream=stream, flags=args.flags, slots=slots)]
+
+    for name, fn in ((f"all_at_once_{l}", all_at_once), (f"batches_of_{slots}", batches),
+                     (f"otf_{slots}_slots", otf)):
+        for fid in fids:
+            def step(timing, fn=fn, fid=fid):
+                res = fn(fid)
+                return {"work": sum(r["iters_x_starts"] for r in res), "kt": {},
+                        "best": max(r["objective"] for r in res)}
+            dt, outs = _timed_steps(step, args.steps, args.warmup)
+            ways[f"{name}/F{fid}"] = {"ms_per_solve": dt / args.steps * 1e3,
+                                      "iter_x_starts_per_s": sum(o["work"] for o in outs) / dt,
+                                      "best_objective": outs[-1]["best"]}
+    key = f"otf_{slots}_slots/F1"
+    return {
+        "metric": "ms per solve of 1024 starting points",
+        "value": ways[key]["ms_per_solve"], "unit": "ms", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ways[key]["ms_per_solve"],
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"spiked-1000x10000-F1F5-l1024-otf{slots}", "n": n, "p": p,
+                   "starting_points": l, "slots": slots, "formulations": list(fids),
+                   "tol": 1e-6, "maxit": 200},
+        "ways": ways,
+    }
+
+
+WORKLOADS = {"spiked-all8": bench_all8, "otf": bench_otf, "large": bench_large, "precision": bench_precision,
              "serve": bench_serve}
 
 
@@ -466,6 +522,7 @@ def main():
     ap.add_argument("--fids", default="1,2,3,4,5,6,7,8",
                     help="formulations in a step of spiked-all8 (default: all 8)")
     ap.add_argument("--maxit", type=int, default=0, help="iterations per solve (large)")
+    ap.add_argument("--slots", type=int, default=64, help="otf: slots")
     ap.add_argument("--requests", type=int, default=200, help="serve: requests")
     ap.add_argument("--loads", default="0.5,1,2",
                     help="serve: offered loads as multiples of the baseline saturation rate")

@@ -141,6 +141,14 @@ typedef struct {
   int32_t polish_maxit; /* FP32 iterations on the final support (BF16 mode) */
   int32_t check_every;  /* iterations between polls of the active count     */
   int32_t flags;        /* SPCA_FLAG_* below                                */
+  /* On-the-fly replacement (Section 4.3): 0 or r runs the r starts of X0
+   * together.  A value l > r makes X0 hold l starts that flow through r
+   * slots: whenever a start stops, it is evaluated and the next start takes
+   * its slot, until all l have run (each for at most maxit iterations).
+   * Per-start outputs then have l entries; FP32 only; X_final must be NULL.
+   * The workspace grows by about 40 bytes per start beyond
+   * spca_workspace_bytes(n, p, r, ...) plus 4p bytes.                    */
+  int32_t total_starts;
 } spca_solve_opts;
 
 /* SPCA_FLAG_GRAPH: capture check_every iterations once per solve into a HIP

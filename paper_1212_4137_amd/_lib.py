@@ -56,7 +56,7 @@ class SolveOpts(ctypes.Structure):
     _fields_ = [("X0", ctypes.c_void_p), ("r", ctypes.c_int32), ("tol", ctypes.c_double),
                 ("maxit", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("polish_maxit", ctypes.c_int32), ("check_every", ctypes.c_int32),
-                ("flags", ctypes.c_int32)]
+                ("flags", ctypes.c_int32), ("total_starts", ctypes.c_int32)]
 
 
 class Outputs(ctypes.Structure):
@@ -245,8 +245,11 @@ def colmajor_view(A):
 
 def am_solve(A, formulation, s_or_gamma, X0=None, tol=1e-8, maxit=200, *,
              precision=PREC_FP32, polish_maxit=0, check_every=8, flags=0,
-             ctx=None, stream=None, return_X=False, kernel_times=False):
+             ctx=None, stream=None, return_X=False, kernel_times=False, slots=None):
     """Batched AM solve (``spca_am_solve_ex``).
+
+    slots: run the rows of X0 through this many slots with on-the-fly
+        replacement (``total_starts`` = rows of X0); None runs them all at once.
 
     A : torch.float32 GPU tensor (n, p), column-major (strides (1, lda)).
     precision: PREC_FP32 / PREC_BF16_POLISH, or "fp32" / "bf16".
@@ -267,21 +270,27 @@ def am_solve(A, formulation, s_or_gamma, X0=None, tol=1e-8, maxit=200, *,
         r = X0.shape[0]
     else:
         r = 1
+    total = r
+    if slots is not None and slots < r:
+        if return_X:
+            raise ValueError("return_X is not available with slots")
+        r = int(slots)
     ctx = ctx or default_context(A.device.index or 0)
     x = np.zeros(p, dtype=np.float64)
     sup = np.zeros(p, dtype=np.int32)
     res = Result()
-    f = np.zeros(r)
-    ev = np.zeros(r)
-    phi = np.zeros(r)
-    iters = np.zeros(r, dtype=np.int32)
-    status = np.zeros(r, dtype=np.int32)
-    nnz = np.zeros(r, dtype=np.int32)
+    f = np.zeros(total)
+    ev = np.zeros(total)
+    phi = np.zeros(total)
+    iters = np.zeros(total, dtype=np.int32)
+    status = np.zeros(total, dtype=np.int32)
+    nnz = np.zeros(total, dtype=np.int32)
     Xf = torch.empty((r, p), dtype=torch.float32, device=A.device) if return_X else None
     kt = np.zeros(9) if kernel_times else None
     prob = Problem(A.data_ptr(), n, p, lda, int(formulation), float(s_or_gamma))
     opts = SolveOpts(X0.data_ptr() if X0 is not None else None, r, float(tol), int(maxit),
-                     int(precision), int(polish_maxit), int(check_every), int(flags))
+                     int(precision), int(polish_maxit), int(check_every), int(flags),
+                     int(total if total > r else 0))
     out = Outputs(_np_ptr(x), _np_ptr(sup), ctypes.pointer(res), _np_ptr(f), _np_ptr(ev),
                   _np_ptr(phi), _np_ptr(iters), _np_ptr(status), _np_ptr(nnz),
                   Xf.data_ptr() if Xf is not None else None, _np_ptr(kt))

@@ -17,9 +17,10 @@ constexpr int kFStage = 256;   // list entries staged in LDS at a time
 
 __global__ __launch_bounds__(256) void x_norms_kernel(
     const float* __restrict__ list_val, int64_t ldl, StartState s, int64_t r,
-    double* xnorm) {
+    double* xnorm, const int32_t* only) {
   __shared__ double red[2 * 5];
   const int64_t j = blockIdx.x;
+  if (only != nullptr && only[j] == 0) return;
   const bool live = s.status[j] != SPCA_DEGENERATE && s.status[j] != SPCA_ZERO;
   const int32_t cnt = live ? s.nnz[j] : 0;
   double acc[2] = {0.0, 0.0};
@@ -40,12 +41,13 @@ __global__ __launch_bounds__(kFT) void final_matvec_kernel(
     const float* __restrict__ A, int64_t lda, int64_t n,
     const int32_t* __restrict__ list_idx, const float* __restrict__ list_val,
     int64_t ldl, StartState s, const double* __restrict__ xnorm,
-    double* partial, int nchunks) {
+    double* partial, int nchunks, const int32_t* only) {
   __shared__ int32_t sidx[kFStage];
   __shared__ double sval[kFStage];
   __shared__ double red[2 * 5];
   const int64_t j = blockIdx.x;
   const int c = blockIdx.y;
+  if (only != nullptr && only[j] == 0) return;
   const double nrm = xnorm[j];
   double* out = partial + ((int64_t)j * nchunks + c) * 2;
   if (!(nrm > 0.0)) {
@@ -84,9 +86,10 @@ __global__ __launch_bounds__(kFT) void final_matvec_kernel(
 __global__ void objective_kernel(int fid, double gamma, StartState s,
                                  int64_t r, const double* __restrict__ partial,
                                  int nchunks, const double* __restrict__ xnorm,
-                                 double* f, double* ev) {
+                                 double* f, double* ev, const int32_t* only) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= r) return;
+  if (only != nullptr && only[j] == 0) return;
   const bool live = s.status[j] != SPCA_DEGENERATE && s.status[j] != SPCA_ZERO &&
                     xnorm[j] > 0.0;
   if (!live) {
@@ -169,20 +172,29 @@ __global__ __launch_bounds__(1024) void best_kernel(
 
 }  // namespace
 
+void evaluate_rows(hipStream_t st, int fid, double s_or_gamma, const float* A,
+                   int64_t lda, int64_t n, const int32_t* list_idx,
+                   const float* list_val, int64_t ldl, StartState s, int64_t r,
+                   double* partial, double* f, double* ev, double* xnorm,
+                   const int32_t* only) {
+  const int nchunks = (int)ceil_div(n, kFT);
+  hipLaunchKernelGGL(x_norms_kernel, dim3((unsigned)r), dim3(256), 0, st,
+                     list_val, ldl, s, r, xnorm, only);
+  hipLaunchKernelGGL(final_matvec_kernel, dim3((unsigned)r, (unsigned)nchunks),
+                     dim3(kFT), 0, st, A, lda, n, list_idx, list_val, ldl, s,
+                     xnorm, partial, nchunks, only);
+  hipLaunchKernelGGL(objective_kernel, dim3((unsigned)ceil_div(r, 256)),
+                     dim3(256), 0, st, fid, s_or_gamma, s, r, partial, nchunks,
+                     xnorm, f, ev, only);
+}
+
 void finalize(hipStream_t st, int fid, double s_or_gamma, const float* A,
               int64_t lda, int64_t n, int64_t p, const int32_t* list_idx,
               const float* list_val, int64_t ldl, StartState s, int64_t r,
               double* partial, double* f, double* ev, double* xnorm,
               int32_t* best, double* x_out, int32_t* support_out) {
-  const int nchunks = (int)ceil_div(n, kFT);
-  hipLaunchKernelGGL(x_norms_kernel, dim3((unsigned)r), dim3(256), 0, st,
-                     list_val, ldl, s, r, xnorm);
-  hipLaunchKernelGGL(final_matvec_kernel, dim3((unsigned)r, (unsigned)nchunks),
-                     dim3(kFT), 0, st, A, lda, n, list_idx, list_val, ldl, s,
-                     xnorm, partial, nchunks);
-  hipLaunchKernelGGL(objective_kernel, dim3((unsigned)ceil_div(r, 256)),
-                     dim3(256), 0, st, fid, s_or_gamma, s, r, partial, nchunks,
-                     xnorm, f, ev);
+  evaluate_rows(st, fid, s_or_gamma, A, lda, n, list_idx, list_val, ldl, s, r,
+                partial, f, ev, xnorm, nullptr);
   hipLaunchKernelGGL(best_kernel, dim3(1), dim3(1024), 0, st, f, s, r, p,
                      list_idx, list_val, ldl, xnorm, best, x_out, support_out);
 }

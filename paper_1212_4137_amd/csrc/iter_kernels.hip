@@ -154,10 +154,11 @@ __global__ __launch_bounds__(1024) void argmax_start_kernel(
 __global__ __launch_bounds__(1024) void compact_rows_kernel(
     const float* __restrict__ X, int64_t ldx, int64_t p, int32_t* list_idx,
     float* list_val, int64_t ldl, int32_t* nnz, const int32_t* status,
-    int32_t* colmark, const Plan* plan) {
+    int32_t* colmark, const Plan* plan, const int32_t* only) {
   __shared__ int scan[20];
   const int64_t j = blockIdx.x;
   if (status != nullptr && status[j] != kRunning) return;
+  if (only != nullptr && only[j] == 0) return;
   const int32_t epoch = colmark != nullptr ? plan->epoch : 0;
   const float* x = X + j * ldx;
   const int64_t chunk = ceil_div(p, blockDim.x);
@@ -554,10 +555,10 @@ void max_norm_column_start(hipStream_t st, const float* A, int64_t lda,
 void compact_rows(hipStream_t st, const float* X, int64_t ldx, int64_t r,
                   int64_t p, int32_t* list_idx, float* list_val, int64_t ldl,
                   int32_t* nnz, const int32_t* status, int32_t* colmark,
-                  const Plan* plan) {
+                  const Plan* plan, const int32_t* only) {
   hipLaunchKernelGGL(compact_rows_kernel, dim3((unsigned)r), dim3(1024), 0, st,
                      X, ldx, p, list_idx, list_val, ldl, nnz, status, colmark,
-                     plan);
+                     plan, only);
 }
 
 void init_state(hipStream_t st, StartState s, int64_t r) {

@@ -127,10 +127,11 @@ void max_norm_column_start(hipStream_t st, const float* A, int64_t lda,
 
 // Builds the compacted (index, value) lists of the rows of X, nnz per row;
 // with colmark != nullptr also marks every used column with plan->epoch.
+// (only: when not null, rows j with only[j] == 0 are skipped)
 void compact_rows(hipStream_t st, const float* X, int64_t ldx, int64_t r,
                   int64_t p, int32_t* list_idx, float* list_val, int64_t ldl,
                   int32_t* nnz, const int32_t* status, int32_t* colmark,
-                  const Plan* plan);
+                  const Plan* plan, const int32_t* only = nullptr);
 
 // Resets the per-start state for a new solve.
 void init_state(hipStream_t st, StartState s, int64_t r);
@@ -210,5 +211,44 @@ void finalize(hipStream_t st, int fid, double s_or_gamma, const float* A,
               const float* list_val, int64_t ldl, StartState s, int64_t r,
               double* partial, double* f, double* ev, double* xnorm,
               int32_t* best, double* x_out, int32_t* support_out);
+// The FP64 objective and explained variance of the rows with only[j] != 0
+// (the first three steps of finalize); other rows are left untouched.
+void evaluate_rows(hipStream_t st, int fid, double s_or_gamma, const float* A,
+                   int64_t lda, int64_t n, const int32_t* list_idx,
+                   const float* list_val, int64_t ldl, StartState s, int64_t r,
+                   double* partial, double* f, double* ev, double* xnorm,
+                   const int32_t* only);
+
+// On-the-fly replacement of finished starts (Section 4.3): state of the
+// slots and of the total_starts starts that flow through them.
+struct Otf {
+  int32_t* slot_start;  // r: start held by the slot, -1 once empty
+  int32_t* retiring;    // r: the slot's start finished in this x-update
+  int32_t* refill;      // r: start loaded into the slot now, -1 none
+  int32_t* ctl;         // [0] next start to issue, [1] best start, [2] slot
+                        // holding the best start now (-1 none)
+  double* best_f;       // 1
+  float* best_x;        // p: the best start's final iterate
+  double* f;            // total: per start f, explained variance, phi
+  double* ev;
+  double* phi;
+  int32_t* iters;       // total: per start iterations, status, nnz
+  int32_t* status;
+  int32_t* nnz;
+  int64_t total;
+};
+// per iteration, after the x-update: mark finished slots, evaluate them,
+// record their results and the best so far, load the next starts
+// (X0 rows) into the freed slots and reset their state
+void otf_step(hipStream_t st, int fid, double s_or_gamma, const float* A,
+              int64_t lda, int64_t n, int64_t p, float* X, int64_t ldx,
+              const float* X0, int32_t* list_idx, float* list_val, int64_t ldl,
+              StartState s, int64_t r, double* partial, double* f, double* ev,
+              double* xnorm, Otf o, int force);
+void otf_init(hipStream_t st, Otf o, int64_t r);
+// x_out (FP64, unit norm) and the sorted support of the best start; writes
+// {best start, nnz} to best
+void otf_output(hipStream_t st, Otf o, int64_t p, int32_t* best, double* x_out,
+                int32_t* support_out);
 
 }  // namespace spca

@@ -135,6 +135,40 @@ Layout make_layout(int64_t n, int64_t p, int64_t r, bool copy_a, bool bf16) {
   return L;
 }
 
+// Buffers of on-the-fly replacement (slots r, starts l).
+size_t otf_bytes(int64_t r, int64_t p, int64_t l) {
+  size_t c = 0;
+  carve(&c, sizeof(int32_t) * 3 * r);
+  carve(&c, sizeof(int32_t) * 4);
+  carve(&c, sizeof(double));
+  carve(&c, sizeof(float) * p);
+  carve(&c, sizeof(double) * 3 * l);
+  carve(&c, sizeof(int32_t) * 3 * l);
+  return c;
+}
+
+Otf carve_otf(char* base, int64_t r, int64_t p, int64_t l) {
+  size_t c = 0;
+  Otf o;
+  int32_t* slots = (int32_t*)(base + carve(&c, sizeof(int32_t) * 3 * r));
+  o.slot_start = slots;
+  o.retiring = slots + r;
+  o.refill = slots + 2 * r;
+  o.ctl = (int32_t*)(base + carve(&c, sizeof(int32_t) * 4));
+  o.best_f = (double*)(base + carve(&c, sizeof(double)));
+  o.best_x = (float*)(base + carve(&c, sizeof(float) * p));
+  double* d = (double*)(base + carve(&c, sizeof(double) * 3 * l));
+  o.f = d;
+  o.ev = d + l;
+  o.phi = d + 2 * l;
+  int32_t* q = (int32_t*)(base + carve(&c, sizeof(int32_t) * 3 * l));
+  o.iters = q;
+  o.status = q + l;
+  o.nnz = q + 2 * l;
+  o.total = l;
+  return o;
+}
+
 int check_problem(int64_t n, int64_t p, int64_t lda, int fid, double sg,
                   int64_t r, double tol, int32_t maxit) {
   (void)tol;
@@ -445,6 +479,14 @@ int spca_am_solve_ex(spca_ctx* ctx, void* stream, const spca_problem* prob,
   SPCA_REQUIRE(opts->polish_maxit >= 0, "polish_maxit must be >= 0");
   SPCA_REQUIRE(opts->check_every >= 1, "check_every must be >= 1");
   const bool bf16 = opts->precision == SPCA_PREC_BF16_POLISH;
+  SPCA_REQUIRE(opts->total_starts >= 0, "total_starts must be >= 0");
+  const int64_t l = opts->total_starts > r ? opts->total_starts : r;
+  const bool otf = l > r;
+  if (otf) {
+    SPCA_REQUIRE(!bf16, "on-the-fly replacement runs in FP32 only");
+    SPCA_REQUIRE(opts->X0 != nullptr, "on-the-fly replacement needs X0 (total_starts rows)");
+    SPCA_REQUIRE(out->X_final == nullptr, "X_final is not available with total_starts > r");
+  }
 
   std::lock_guard<std::mutex> lock(ctx->mu);
   DeviceGuard g(ctx->device);
@@ -452,7 +494,8 @@ int spca_am_solve_ex(spca_ctx* ctx, void* stream, const spca_problem* prob,
 
   const bool copy_a = (lda % 4) != 0 || ((uintptr_t)prob->A % 16) != 0;
   Layout L = make_layout(n, p, r, copy_a, bf16);
-  rc = ensure_workspace(ctx, st, solve_bytes(L, n, p, r));
+  const size_t otf_off = (size_t)round_up((int64_t)solve_bytes(L, n, p, r), 256);
+  rc = ensure_workspace(ctx, st, otf ? otf_off + otf_bytes(r, p, l) : solve_bytes(L, n, p, r));
   if (rc != SPCA_OK) return rc;
   char* base = (char*)ctx->ws;
   float* At = (float*)(base + L.off_At);
@@ -485,6 +528,8 @@ int spca_am_solve_ex(spca_ctx* ctx, void* stream, const spca_problem* prob,
   uint16_t* Yb = (uint16_t*)(base + L.off_Yb);
   uint16_t* Xb = (uint16_t*)(base + L.off_Xb);
   void* wide = L.wide_bytes ? (void*)(base + L.off_wide) : nullptr;
+  Otf o{};
+  if (otf) o = carve_otf(base + otf_off, r, p, l);
 
   // a0: stage A (aligned column-major copy only when needed) and its
   // row-major twin used by the dense A x.
@@ -555,6 +600,7 @@ int spca_am_solve_ex(spca_ctx* ctx, void* stream, const spca_problem* prob,
     L.plan_aty = plan_gemm_nt(r, p, n, 1, eb);
   }
   init_state(st, s, r);
+  if (otf) otf_init(st, o, r);
   init_plan(st, plan, L.plan_ax.splits);
   if (wide) SPCA_HIP_TRY(x_update_wide_reset(st, wide, r));
   SPCA_HIP_TRY(hipMemsetAsync(colmark, 0, sizeof(int32_t) * p, st));
@@ -615,6 +661,9 @@ int spca_am_solve_ex(spca_ctx* ctx, void* stream, const spca_problem* prob,
     x_update(q, fid, sg, V, L.ldx, r, p, X, L.ldx, li, lv, L.ldx, list_cap, s,
              opts->tol, maxit, colmark, plan, wide);
     if (tm) SPCA_HIP_TRY(ctx->t_xup.mark(q));
+    if (otf)
+      otf_step(q, fid, sg, A, ldA, n, p, X, L.ldx, opts->X0, li, lv, L.ldx, s, r,
+               partial, fj, evj, xnorm, o, 0);
     plan_next(q, s, r, n, p, list_cap, dense_only, L.plan_ax.splits, L.ucap,
               colmark, ulist, plan);
     if (bf16) rows_to_bf16(q, X, L.ldx, r, p, Xb, L.ldxb, plan);
@@ -631,9 +680,13 @@ int spca_am_solve_ex(spca_ctx* ctx, void* stream, const spca_problem* prob,
     return SPCA_OK;
   };
   const int32_t every = opts->check_every;
+  // with replacement every slot runs its starts back to back, and all slots
+  // stay busy while starts remain, so maxit (l / r + 1) iterations suffice
+  const int64_t loop_max64 = otf ? (int64_t)maxit * (ceil_div(l, r) + 1) : maxit;
+  const int32_t loop_max = loop_max64 > INT32_MAX ? INT32_MAX : (int32_t)loop_max64;
   int32_t it = 0;
   bool done = false;
-  if ((opts->flags & SPCA_FLAG_GRAPH) && !timed && maxit >= every) {
+  if ((opts->flags & SPCA_FLAG_GRAPH) && !timed && loop_max >= every) {
     // a8: capture check_every iterations once (on the context's own stream,
     // since the legacy default stream cannot be captured) and replay the
     // graph on the caller's stream.  The captured sequence holds kernel
@@ -656,7 +709,7 @@ int spca_am_solve_ex(spca_ctx* ctx, void* stream, const spca_problem* prob,
     (void)hipGraphDestroy(graph);
     SPCA_HIP_TRY(inst_rc);
     int loop_rc = SPCA_OK;
-    while (!done && it + every <= maxit) {
+    while (!done && it + every <= loop_max) {
       hipError_t e = hipGraphLaunch(exec, st);
       if (e != hipSuccess) {
         set_error(std::string("hipGraphLaunch: ") + hipGetErrorString(e));
@@ -664,7 +717,7 @@ int spca_am_solve_ex(spca_ctx* ctx, void* stream, const spca_problem* prob,
         break;
       }
       it += every;
-      if (it < maxit) {
+      if (it < loop_max) {
         loop_rc = none_active(&done);
         if (loop_rc != SPCA_OK) break;
       }
@@ -672,10 +725,10 @@ int spca_am_solve_ex(spca_ctx* ctx, void* stream, const spca_problem* prob,
     (void)hipGraphExecDestroy(exec);
     if (loop_rc != SPCA_OK) return loop_rc;
   }
-  for (; !done && it < maxit; ++it) {
+  for (; !done && it < loop_max; ++it) {
     rc = iteration(st, timed);
     if (rc != SPCA_OK) return rc;
-    if ((it + 1) % every == 0 && it + 1 < maxit) {
+    if ((it + 1) % every == 0 && it + 1 < loop_max) {
       rc = none_active(&done);
       if (rc != SPCA_OK) return rc;
     }
@@ -683,9 +736,16 @@ int spca_am_solve_ex(spca_ctx* ctx, void* stream, const spca_problem* prob,
 
   // a6: FP64 objective, explained variance, best start, output vector; the
   // lists are rebuilt from the final dense iterates (dense starts keep none)
-  compact_rows(st, X, L.ldx, r, p, li, lv, L.ldx, s.nnz, nullptr, nullptr, nullptr);
-  finalize(st, fid, sg, A, ldA, n, p, li, lv, L.ldx, s, r, partial, fj, evj,
-           xnorm, best, xout, sup);
+  if (otf) {
+    // close what is still running, then the best start's vector
+    otf_step(st, fid, sg, A, ldA, n, p, X, L.ldx, opts->X0, li, lv, L.ldx, s, r,
+             partial, fj, evj, xnorm, o, 1);
+    otf_output(st, o, p, best, xout, sup);
+  } else {
+    compact_rows(st, X, L.ldx, r, p, li, lv, L.ldx, s.nnz, nullptr, nullptr, nullptr);
+    finalize(st, fid, sg, A, ldA, n, p, li, lv, L.ldx, s, r, partial, fj, evj,
+             xnorm, best, xout, sup);
+  }
   SPCA_LAUNCH_CHECK("finalize");
 
   int32_t hb[2];
@@ -694,20 +754,22 @@ int spca_am_solve_ex(spca_ctx* ctx, void* stream, const spca_problem* prob,
   SPCA_HIP_TRY(hipMemcpyAsync(&hplan, plan, sizeof(Plan), hipMemcpyDeviceToHost, st));
   SPCA_HIP_TRY(hipStreamSynchronize(st));
   const int32_t jb = hb[0], nnzb = hb[1];
-  std::vector<double> f_all(r), ev_all(r), phi_all(r);
-  std::vector<int32_t> it_all(r), st_all(r), nnz_all(r);
-  SPCA_HIP_TRY(hipMemcpyAsync(f_all.data(), fj, sizeof(double) * r,
+  // per-start results: the slots themselves, or with replacement the
+  // records of all l starts
+  std::vector<double> f_all(l), ev_all(l), phi_all(l);
+  std::vector<int32_t> it_all(l), st_all(l), nnz_all(l);
+  SPCA_HIP_TRY(hipMemcpyAsync(f_all.data(), otf ? o.f : fj, sizeof(double) * l,
                               hipMemcpyDeviceToHost, st));
-  SPCA_HIP_TRY(hipMemcpyAsync(ev_all.data(), evj, sizeof(double) * r,
+  SPCA_HIP_TRY(hipMemcpyAsync(ev_all.data(), otf ? o.ev : evj, sizeof(double) * l,
                               hipMemcpyDeviceToHost, st));
-  SPCA_HIP_TRY(hipMemcpyAsync(phi_all.data(), s.phi, sizeof(double) * r,
+  SPCA_HIP_TRY(hipMemcpyAsync(phi_all.data(), otf ? o.phi : s.phi, sizeof(double) * l,
                               hipMemcpyDeviceToHost, st));
-  SPCA_HIP_TRY(hipMemcpyAsync(it_all.data(), s.iters, sizeof(int32_t) * r,
-                              hipMemcpyDeviceToHost, st));
-  SPCA_HIP_TRY(hipMemcpyAsync(st_all.data(), s.status, sizeof(int32_t) * r,
-                              hipMemcpyDeviceToHost, st));
-  SPCA_HIP_TRY(hipMemcpyAsync(nnz_all.data(), s.nnz, sizeof(int32_t) * r,
-                              hipMemcpyDeviceToHost, st));
+  SPCA_HIP_TRY(hipMemcpyAsync(it_all.data(), otf ? o.iters : s.iters,
+                              sizeof(int32_t) * l, hipMemcpyDeviceToHost, st));
+  SPCA_HIP_TRY(hipMemcpyAsync(st_all.data(), otf ? o.status : s.status,
+                              sizeof(int32_t) * l, hipMemcpyDeviceToHost, st));
+  SPCA_HIP_TRY(hipMemcpyAsync(nnz_all.data(), otf ? o.nnz : s.nnz,
+                              sizeof(int32_t) * l, hipMemcpyDeviceToHost, st));
   if (out->x)
     SPCA_HIP_TRY(hipMemcpyAsync(out->x, xout, sizeof(double) * p,
                                 hipMemcpyDeviceToHost, st));
@@ -733,7 +795,7 @@ int spca_am_solve_ex(spca_ctx* ctx, void* stream, const spca_problem* prob,
     kt[8] = hplan.mode_count[kAxUnion];
   }
   double total_iters = 0.0;
-  for (int64_t j = 0; j < r; ++j) total_iters += it_all[j];
+  for (int64_t j = 0; j < l; ++j) total_iters += it_all[j];
   spca_result* res = out->res;
   res->objective = f_all[jb];
   res->objective_pre_polish = f_all[jb];
@@ -765,7 +827,7 @@ int spca_am_solve_ex(spca_ctx* ctx, void* stream, const spca_problem* prob,
                      (size_t)round_up((int64_t)L.total, 256), out);
     if (rc != SPCA_OK) return rc;
   }
-  for (int64_t j = 0; j < r; ++j) {
+  for (int64_t j = 0; j < l; ++j) {
     if (out->f_per_start) out->f_per_start[j] = f_all[j];
     if (out->ev_per_start) out->ev_per_start[j] = ev_all[j];
     if (out->phi_per_start) out->phi_per_start[j] = phi_all[j];

@@ -1,0 +1,81 @@
+"""On-the-fly replacement (total_starts > r, Section 4.3): every start that
+flows through the slots ends where the oracle's AM from the same start ends,
+fixed-work runs count exactly maxit iterations per start, graph replay is
+bit-identical, and the returned x is the best start's."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from gpu_helpers import compare_solve, to_device_colmajor, to_device_rows
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def spca():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1212_4137_amd as m
+
+    m.load()
+    return m
+
+
+@pytest.fixture(scope="module")
+def problem():
+    sp = workloads.spiked_matrix(61, 300, 1500, thetas=(50.0, 30.0), spike_nnz=20)
+    X0 = workloads.random_unit_starts(62, 96, 1500)
+    return sp.A, X0, to_device_colmajor(sp.A), to_device_rows(X0)
+
+
+@pytest.mark.parametrize("fid", range(1, 9))
+def test_replacement_matches_oracle(spca, problem, fid):
+    print(f"otf case fid={fid}", flush=True)
+    A_np, X0_np, A, X0 = problem
+    par = workloads.s_or_gamma_for(fid, A_np, 20, "scaled" if fid in (6, 8) else "literal")
+    got = spca.am_solve(A, fid, par, X0, tol=1e-8, maxit=300, slots=16)
+    assert len(got["f_per_start"]) == 96
+    ref = oracle.am_multi(A_np.astype(np.float64), fid, par, X0_np.astype(np.float64),
+                          1e-8, 300, nthreads=8)
+    compare_solve(got, ref, f"otf F{fid}")
+    # the reported vector is the best start's, evaluated in FP64
+    x = got["x"]
+    j = got["best_start"]
+    assert got["objective"] == got["f_per_start"][j] == np.max(got["f_per_start"])
+    if got["nnz"]:
+        assert abs(np.linalg.norm(x) - 1) < 1e-12
+        assert np.array_equal(got["support"], np.flatnonzero(x))
+        u = A_np.astype(np.float64) @ x
+        var = np.linalg.norm(u) if fid % 2 else np.sum(np.abs(u))
+        f = var if fid <= 4 else (var * var - par * np.count_nonzero(x) if fid <= 6
+                                  else var - par * np.sum(np.abs(x)))
+        assert abs(f - got["objective"]) <= 1e-9 * max(abs(f), 1.0)
+
+
+def test_fixed_work_and_graph(spca, problem):
+    _, _, A, X0 = problem
+    X0s = X0[:50].contiguous()
+    a = spca.am_solve(A, 1, 20.0, X0s, tol=-1.0, maxit=10, slots=16, check_every=4)
+    assert np.all(a["iters_per_start"] == 10)
+    assert np.all(a["status_per_start"] == spca.MAXIT)
+    assert a["iters_x_starts"] == 500
+    g = spca.am_solve(A, 1, 20.0, X0s, tol=-1.0, maxit=10, slots=16, check_every=4,
+                      flags=spca.FLAG_GRAPH)
+    assert np.array_equal(a["f_per_start"], g["f_per_start"])
+    assert np.array_equal(a["x"], g["x"]) and a["best_start"] == g["best_start"]
+    for fid in (3, 6):
+        e = spca.am_solve(A, fid, 7.0 if fid == 3 else 0.5, X0, tol=1e-7, maxit=100,
+                          slots=24)
+        h = spca.am_solve(A, fid, 7.0 if fid == 3 else 0.5, X0, tol=1e-7, maxit=100,
+                          slots=24, flags=spca.FLAG_GRAPH)
+        assert np.array_equal(e["f_per_start"], h["f_per_start"])
+        assert np.array_equal(e["iters_per_start"], h["iters_per_start"])
+
+
+def test_replacement_rejects_unsupported(spca, problem):
+    _, _, A, X0 = problem
+    with pytest.raises(spca.SpcaError):
+        spca.am_solve(A, 1, 20.0, X0, precision="bf16", polish_maxit=10, slots=16)
