@@ -166,6 +166,7 @@ typedef struct {
  * product's result depends on its K split, so tuned solves are
  * reproducible given the table (see spca_tune_table_export).              */
 #define SPCA_FLAG_AUTOTUNE 8
+#define SPCA_FLAG_NO_UNION 16    /* never use the union-of-supports product  */
 
 typedef struct {
   double* x;           /* host, p doubles (see spca_am_solve), or NULL      */
@@ -179,13 +180,15 @@ typedef struct {
   int32_t* status_per_start;
   int32_t* nnz_per_start;
   float* X_final;      /* optional device r x p: final iterates (FP32)      */
-  /* optional host array of 9 doubles: HIP-event times of the launches of
+  /* optional host array of 10 doubles: HIP-event times of the launches of
    * this solve, [0] total ms and [1] count of the V = A^T Y products,
    * [2] ms and [3] count of the x-updates, [4] ms and [5] count of the
    * dense U = A X products (including launches that found another product
    * selected and returned at once); [6], [7], [8] the iterations whose A x
-   * used the dense product, the per-start lists, and the product over the
-   * union of the supports.  NULL disables the events.                     */
+   * used the dense product, the per-start lists (both list kernels), and
+   * the product over the union of the supports; [9] of the list
+   * iterations, those that used the row-block list kernel.  NULL disables
+   * the events.                                                            */
   double* kernel_times;
 } spca_outputs;
 

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(PKG, "libspca.so")
 SPCA_OK, SPCA_EINVAL, SPCA_ENOMEM, SPCA_EHIP = 0, -1, -2, -3
 CONVERGED, MAXIT, DEGENERATE, ZERO = 0, 1, 2, 3
 PREC_FP32, PREC_BF16_POLISH = 0, 1
-FLAG_GRAPH, FLAG_CHECK_FINITE, FLAG_DENSE_ONLY, FLAG_AUTOTUNE = 1, 2, 4, 8
+FLAG_GRAPH, FLAG_CHECK_FINITE, FLAG_DENSE_ONLY, FLAG_AUTOTUNE, FLAG_NO_UNION = 1, 2, 4, 8, 16
 
 EXPORTED = ("spca_am_solve", "spca_am_solve_ex", "spca_ctx_create",
             "spca_ctx_destroy", "spca_workspace_bytes", "spca_last_error",
@@ -286,7 +286,7 @@ def am_solve(A, formulation, s_or_gamma, X0=None, tol=1e-8, maxit=200, *,
     status = np.zeros(total, dtype=np.int32)
     nnz = np.zeros(total, dtype=np.int32)
     Xf = torch.empty((r, p), dtype=torch.float32, device=A.device) if return_X else None
-    kt = np.zeros(9) if kernel_times else None
+    kt = np.zeros(10) if kernel_times else None
     prob = Problem(A.data_ptr(), n, p, lda, int(formulation), float(s_or_gamma))
     opts = SolveOpts(X0.data_ptr() if X0 is not None else None, r, float(tol), int(maxit),
                      int(precision), int(polish_maxit), int(check_every), int(flags),
@@ -309,7 +309,8 @@ def am_solve(A, formulation, s_or_gamma, X0=None, tol=1e-8, maxit=200, *,
                 "aty_ms": kt[0], "aty_launches": int(kt[1]), "x_update_ms": kt[2],
                 "x_update_launches": int(kt[3]), "ax_dense_ms": kt[4],
                 "ax_dense_launches": int(kt[5]), "iters_dense": int(kt[6]),
-                "iters_list": int(kt[7]), "iters_union": int(kt[8])}}
+                "iters_list": int(kt[7]), "iters_union": int(kt[8]),
+                "iters_list_rows": int(kt[9])}}
 
 
 def am_solve_simple(A, formulation, s_or_gamma, X0=None, tol=1e-8, maxit=200):

@@ -256,6 +256,7 @@ constexpr Shape kShapes[] = {
     {128, 64, 3, 0.85},   // 2x2 waves of 64x32
     {64, 128, 3, 0.85},   // 2x2 waves of 32x64
     {32, 128, 3, 0.70},   // 1x4 waves of 32x32
+    {64, 256, 2, 0.85},   // 1x4 waves of 64x64
 };
 constexpr int kNumShapes = (int)(sizeof(kShapes) / sizeof(kShapes[0]));
 
@@ -296,8 +297,11 @@ void dispatch(int shape, hipStream_t st, const T* P, int64_t ldp,
     case 4:
       launch<T, 64, 128, 2, 2>(st, P, ldp, Q, ldq, C, ldc, M, N, K, splits, split_stride, gate, gate_run, kdev);
       break;
-    default:
+    case 5:
       launch<T, 32, 128, 1, 4>(st, P, ldp, Q, ldq, C, ldc, M, N, K, splits, split_stride, gate, gate_run, kdev);
+      break;
+    default:
+      launch<T, 64, 256, 1, 4>(st, P, ldp, Q, ldq, C, ldc, M, N, K, splits, split_stride, gate, gate_run, kdev);
       break;
   }
 }

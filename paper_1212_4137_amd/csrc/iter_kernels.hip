@@ -192,13 +192,17 @@ __global__ void init_state_kernel(StartState s, int64_t r) {
 // One block: count running starts and their nonzeros, gather the union of
 // their supports, pick the product for the next A x.
 //
-// Cost model of the three ways to form U = X A^T (r x n), in microseconds on
+// Cost model of the ways to form U = X A^T (r x n), in microseconds on
 // MI355X: the dense MFMA product runs at about 100 TFLOP/s over all p
-// columns; the union product at about 80 TFLOP/s over the u union columns
+// columns (but reads all of A however few the starts); the union product at about 80 TFLOP/s over the u union columns
 // plus its gathers (about 2 TB/s) and a fixed 6 us; the list product reads
-// a column of A per list entry from cache at about 12 TB/s.
+// a column of A per list entry, at about 12 TB/s while the distinct columns
+// it touches (the last measured union, else all list entries) stay within
+// the 256 MB Infinity Cache (192 MB taken as usable) and at about 3 TB/s
+// beyond that.
 // The union is only gathered when the last x-update marked columns: while
-// the union product wins, every iteration, otherwise every 16th (a probe).
+// the union product wins, every iteration, otherwise on the first two
+// planner calls and every 16th (a probe).
 __global__ __launch_bounds__(1024) void plan_kernel(
     StartState s, int64_t r, int64_t n, int64_t p, int list_cap,
     int dense_only, int dense_splits, int64_t ucap,
@@ -237,13 +241,30 @@ __global__ __launch_bounds__(1024) void plan_kernel(
     plan->total_nnz = v[1];
     plan->max_nnz = mx;
     plan->union_size = u < 0 ? 0 : u;
+    if (u >= 0) plan->last_union = u;
     const double rd = (double)r, nd = (double)n;
-    const double dense_us = 2.0 * rd * nd * (double)p / 1.0e8;
-    const double union_us = u >= 0 && u <= ucap
+    // the dense product: MFMA time (starts padded to a 32-row tile) or one
+    // read of A at about 4 TB/s, whichever is longer, plus launch costs
+    const double mfma_us = 2.0 * (rd > 32.0 ? rd : 32.0) * nd * (double)p / 1.0e8;
+    const double read_us = nd * (double)p * 4.0 / 4.0e6;
+    const double dense_us = (mfma_us > read_us ? mfma_us : read_us) + 5.0;
+    const double union_us = u >= 1 && u <= ucap
                                 ? 2.0 * rd * nd * u / 0.8e8 + 6.0 +
                                       (rd + nd) * u * 8.0 / 2.0e6
                                 : 1e300;
-    const double list_us = mx <= list_cap ? (double)v[1] * nd * 4.0 / 12.0e6 + 3.0 : 1e300;
+    const double cols = plan->last_union > 0 ? (double)plan->last_union
+                                             : (double)(v[1] < p ? v[1] : p);
+    const double list_bw = cols * nd * 4.0 <= 192.0e6 ? 12.0e6 : 3.0e6;
+    // the one-workgroup-per-start kernel needs about 512 workgroups to reach
+    // that rate; the row-block kernel has r * ceil(n / 1024) of them and
+    // pays the separate y-update
+    const double wg1 = (double)v[0], wgr = (double)v[0] * ceil(nd / 1024.0);
+    const double list_us =
+        mx <= list_cap ? (double)v[1] * nd * 4.0 / (list_bw * (wg1 < 512.0 ? wg1 / 512.0 : 1.0)) + 3.0
+                       : 1e300;
+    const double rows_us =
+        mx <= list_cap ? (double)v[1] * nd * 4.0 / (list_bw * (wgr < 512.0 ? wgr / 512.0 : 1.0)) + 8.0
+                       : 1e300;
     int mode = kAxDense;
     double best = dense_us;
     if (!dense_only) {
@@ -255,6 +276,10 @@ __global__ __launch_bounds__(1024) void plan_kernel(
         best = list_us;
         mode = kAxList;
       }
+      if (rows_us < best) {
+        best = rows_us;
+        mode = kAxListRows;
+      }
     }
     plan->mode = mode;
     plan->ax_splits = mode == kAxDense ? dense_splits : 1;
@@ -262,7 +287,8 @@ __global__ __launch_bounds__(1024) void plan_kernel(
     plan->epoch = epoch + 1;
     const int32_t it = plan->iter + 1;
     plan->iter = it;
-    plan->mark = (colmark != nullptr && !dense_only && (mode == kAxUnion || it % 16 == 0)) ? 1 : 0;
+    plan->mark = (colmark != nullptr && !dense_only &&
+                  (mode == kAxUnion || it % 16 == 0 || it <= 2)) ? 1 : 0;
   }
 }
 
@@ -272,11 +298,13 @@ __global__ void init_plan_kernel(Plan* plan, int dense_splits) {
   plan->total_nnz = 0;
   plan->max_nnz = 0;
   plan->union_size = 0;
+  plan->last_union = 0;
   plan->epoch = 1;
   plan->ax_splits = dense_splits;
   plan->mark = 1;
   plan->iter = 0;
   plan->mode_count[0] = plan->mode_count[1] = plan->mode_count[2] = 0;
+  plan->mode_count[3] = 0;
 }
 
 // Union gathers: the blocks copy the union columns of the rows of X, then
@@ -519,7 +547,84 @@ void launch_sparse(hipStream_t st, const TA* A, int64_t lda, int64_t n,
     hipLaunchKernelGGL((sparse_ax_y_kernel<L1VAR, 2, TA>), g, b, 0, st, A, lda, n, li, lv, ldl, Y, ldu, s, plan, Yb, ldyb);
 }
 
+// Row-block list product: workgroup (c, j) forms rows [1024 c, 1024 c + 1024)
+// of u_j = sum_t A[:, idx_t] val_t, each thread four consecutive rows with
+// 16-byte loads, in list order, in FP64.
+constexpr int kRowsBlock = 4 * kSpThreads;
+
+template <typename TA>
+__global__ __launch_bounds__(kSpThreads) void sparse_ax_rows_kernel(
+    const TA* __restrict__ A, int64_t lda, int64_t n,
+    const int32_t* __restrict__ list_idx, const float* __restrict__ list_val,
+    int64_t ldl, float* __restrict__ U, int64_t ldu, StartState s,
+    const Plan* plan) {
+  __shared__ int32_t sidx[kSpStage];
+  __shared__ float sval[kSpStage];
+  if (plan->mode != kAxListRows) return;
+  const int64_t j = blockIdx.y;
+  if (s.status[j] != kRunning) return;
+  const int32_t cnt = s.nnz[j];
+  const int64_t row = (int64_t)blockIdx.x * kRowsBlock + 4 * threadIdx.x;
+  const bool full = row + 3 < n;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int32_t t0 = 0; t0 < cnt; t0 += kSpStage) {
+    const int32_t m = cnt - t0 < kSpStage ? cnt - t0 : kSpStage;
+    __syncthreads();
+    if ((int)threadIdx.x < m) {
+      sidx[threadIdx.x] = list_idx[j * ldl + t0 + threadIdx.x];
+      sval[threadIdx.x] = list_val[j * ldl + t0 + threadIdx.x];
+    }
+    __syncthreads();
+    if (row < n) {
+      for (int32_t t = 0; t < m; ++t) {
+        const TA* c = A + (int64_t)sidx[t] * lda;
+        const double w = (double)sval[t];
+        if (full) {
+          const floatx4_t a = load4(c, row);
+          acc[0] += (double)a.x * w;
+          acc[1] += (double)a.y * w;
+          acc[2] += (double)a.z * w;
+          acc[3] += (double)a.w * w;
+        } else {
+          for (int e = 0; e < 4; ++e)
+            if (row + e < n) acc[e] += (double)load1(c, row + e) * w;
+        }
+      }
+    }
+  }
+  float* u = U + j * ldu;
+  if (full) {
+    const floatx4_t o = {(float)acc[0], (float)acc[1], (float)acc[2], (float)acc[3]};
+    *reinterpret_cast<floatx4_t*>(u + row) = o;
+  } else {
+    for (int e = 0; e < 4; ++e)
+      if (row + e < n) u[row + e] = (float)acc[e];
+  }
+}
+
+template <typename TA>
+void launch_rows(hipStream_t st, const TA* A, int64_t lda, int64_t n,
+                 const int32_t* li, const float* lv, int64_t ldl, float* U,
+                 int64_t ldu, int64_t r, StartState s, const Plan* plan) {
+  const dim3 g((unsigned)ceil_div(n, (int64_t)kRowsBlock), (unsigned)r);
+  hipLaunchKernelGGL(sparse_ax_rows_kernel<TA>, g, dim3(kSpThreads), 0, st, A, lda, n,
+                     li, lv, ldl, U, ldu, s, plan);
+}
+
 }  // namespace
+
+void sparse_ax_rows(hipStream_t st, const float* A, int64_t lda, int64_t n,
+                    const int32_t* list_idx, const float* list_val, int64_t ldl,
+                    float* U, int64_t ldu, int64_t r, StartState s, const Plan* plan) {
+  launch_rows<float>(st, A, lda, n, list_idx, list_val, ldl, U, ldu, r, s, plan);
+}
+
+void sparse_ax_rows_bf16(hipStream_t st, const uint16_t* Ab, int64_t ldab, int64_t n,
+                         const int32_t* list_idx, const float* list_val, int64_t ldl,
+                         float* U, int64_t ldu, int64_t r, StartState s,
+                         const Plan* plan) {
+  launch_rows<uint16_t>(st, Ab, ldab, n, list_idx, list_val, ldl, U, ldu, r, s, plan);
+}
 
 void transpose_f32(hipStream_t st, const float* A, int64_t lda, float* At,
                    int64_t ldat, int64_t n, int64_t p) {

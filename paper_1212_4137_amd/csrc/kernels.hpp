@@ -32,7 +32,10 @@ struct StartState {
 //   kAxList   per-start sums over each start's (index, value) list,
 //   kAxUnion  MFMA GEMM over the union of the running starts' supports,
 //             with X and A gathered onto those columns.
-enum AxMode { kAxDense = 0, kAxList = 1, kAxUnion = 2 };
+// kAxList: one workgroup per start, y-update fused; kAxListRows: the same
+// product cut into row blocks (many workgroups per start, for few starts),
+// followed by the separate y-update
+enum AxMode { kAxDense = 0, kAxList = 1, kAxUnion = 2, kAxListRows = 3 };
 
 struct Plan {
   int32_t mode;         // AxMode of the next A x
@@ -44,7 +47,8 @@ struct Plan {
   int32_t ax_splits;    // K partials the y-update sums (dense mode)
   int32_t mark;         // the next x-update marks its columns
   int32_t iter;         // planner calls so far
-  int32_t mode_count[3];  // iterations run in each mode (statistics)
+  int32_t mode_count[4];  // iterations run in each mode (statistics)
+  int32_t last_union;   // most recent measured union size (0: none yet)
 };
 
 // Tile shape (index into the compiled shapes) and K split of one product.
@@ -169,6 +173,17 @@ void sparse_ax_y_update(hipStream_t st, int fid, const float* A, int64_t lda,
                         int64_t n, const int32_t* list_idx,
                         const float* list_val, int64_t ldl, float* Y,
                         int64_t ldu, int64_t r, StartState s, const Plan* plan);
+// U (slot 0) = A X from the support lists in row blocks of 1024, FP64
+// accumulation; runs only in mode kAxListRows (the y-update follows).
+// Needs lda % 4 == 0 and a 16-byte aligned A.
+void sparse_ax_rows(hipStream_t st, const float* A, int64_t lda, int64_t n,
+                    const int32_t* list_idx, const float* list_val, int64_t ldl,
+                    float* U, int64_t ldu, int64_t r, StartState s, const Plan* plan);
+void sparse_ax_rows_bf16(hipStream_t st, const uint16_t* Ab, int64_t ldab, int64_t n,
+                         const int32_t* list_idx, const float* list_val, int64_t ldl,
+                         float* U, int64_t ldu, int64_t r, StartState s,
+                         const Plan* plan);
+
 // The same with a BF16 column-major A (ldab % 4 == 0); Y also as BF16.
 void sparse_ax_y_update_bf16(hipStream_t st, int fid, const uint16_t* Ab,
                              int64_t ldab, int64_t n, const int32_t* list_idx,

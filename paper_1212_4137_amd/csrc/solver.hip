@@ -268,7 +268,7 @@ using namespace spca;
 template <typename F>
 static int autotune_product(hipStream_t st, int64_t M, int64_t N, int64_t K,
                             int split_cap, int max_splits, int eb, F launch) {
-  static const int kBM[] = {128, 128, 128, 128, 64, 32};
+  static const int kBM[] = {128, 128, 128, 128, 64, 32, 64};
   hipEvent_t e0, e1;
   SPCA_HIP_TRY(hipEventCreate(&e0));
   hipError_t ce = hipEventCreate(&e1);
@@ -606,11 +606,14 @@ int spca_am_solve_ex(spca_ctx* ctx, void* stream, const spca_problem* prob,
   SPCA_HIP_TRY(hipMemsetAsync(colmark, 0, sizeof(int32_t) * p, st));
   compact_rows(st, X, L.ldx, r, p, li, lv, L.ldx, s.nnz, s.status, colmark, plan);
   const int dense_only = (opts->flags & SPCA_FLAG_DENSE_ONLY) ? 1 : 0;
+  // the union product is offered only when allowed and while the union
+  // fits its buffers (at most ucap columns)
+  const int64_t ucap_eff = (opts->flags & SPCA_FLAG_NO_UNION) ? 0 : L.ucap;
   const int list_cap = list_cap_of(p);
   // the union product is offered only while the union fits its buffers
   // (at most ucap columns)
   auto plan_iter = [&]() {
-    plan_next(st, s, r, n, p, list_cap, dense_only, L.plan_ax.splits, L.ucap,
+    plan_next(st, s, r, n, p, list_cap, dense_only, L.plan_ax.splits, ucap_eff,
               colmark, ulist, plan);
   };
   plan_iter();
@@ -641,6 +644,10 @@ int spca_am_solve_ex(spca_ctx* ctx, void* stream, const spca_problem* prob,
       gemm_nt_f32(q, Xc, ldc_u, Qc, ldc_u, U, L.ldu, r, n, L.ucap, &plan->mode,
                   kAxUnion, L.plan_union, 0, &plan->union_size);
     }
+    if (bf16)
+      sparse_ax_rows_bf16(q, Ab, L.ldab, n, li, lv, L.ldx, U, L.ldu, r, s, plan);
+    else
+      sparse_ax_rows(q, A, ldA, n, li, lv, L.ldx, U, L.ldu, r, s, plan);
     y_update(q, fid, U, r * L.ldu, Y, L.ldu, r, n, s, plan, bf16 ? Yb : nullptr,
              L.ldyb);
     if (bf16)
@@ -664,7 +671,7 @@ int spca_am_solve_ex(spca_ctx* ctx, void* stream, const spca_problem* prob,
     if (otf)
       otf_step(q, fid, sg, A, ldA, n, p, X, L.ldx, opts->X0, li, lv, L.ldx, s, r,
                partial, fj, evj, xnorm, o, 0);
-    plan_next(q, s, r, n, p, list_cap, dense_only, L.plan_ax.splits, L.ucap,
+    plan_next(q, s, r, n, p, list_cap, dense_only, L.plan_ax.splits, ucap_eff,
               colmark, ulist, plan);
     if (bf16) rows_to_bf16(q, X, L.ldx, r, p, Xb, L.ldxb, plan);
     SPCA_LAUNCH_CHECK("AM iteration");
@@ -793,6 +800,8 @@ int spca_am_solve_ex(spca_ctx* ctx, void* stream, const spca_problem* prob,
     kt[6] = hplan.mode_count[kAxDense];
     kt[7] = hplan.mode_count[kAxList];
     kt[8] = hplan.mode_count[kAxUnion];
+    kt[7] += hplan.mode_count[kAxListRows];
+    kt[9] = hplan.mode_count[kAxListRows];
   }
   double total_iters = 0.0;
   for (int64_t j = 0; j < l; ++j) total_iters += it_all[j];

@@ -191,3 +191,23 @@ def test_budget_is_enforced(spca):
         spca.am_solve(A, 1, 5, X0, ctx=ctx)
     assert e.value.code == -2
     ctx.close()
+
+
+@pytest.mark.parametrize("fid", [1, 2, 3, 4])
+def test_row_block_list_product(spca, fid):
+    # few starts on tall columns, union product off: the planner picks the
+    # row-block list kernel (many workgroups per start); results keep parity
+    # with the oracle and agree with the dense product
+    sp = workloads.spiked_matrix(71, 8200, 1500, thetas=(200.0, 120.0), spike_nnz=20)
+    X0n = workloads.random_unit_starts(72, 12, 1500)
+    A, X0 = to_device_colmajor(sp.A), to_device_rows(X0n)
+    par = _param(fid, sp.A, 20)
+    got = spca.am_solve(A, fid, par, X0, tol=1e-8, maxit=200, kernel_times=True,
+                        flags=spca.FLAG_NO_UNION)
+    assert got["kernel_times"]["iters_list_rows"] > 0, got["kernel_times"]
+    assert got["kernel_times"]["iters_union"] == 0
+    ref = oracle.am_multi(sp.A.astype(np.float64), fid, par, X0n.astype(np.float64),
+                          1e-8, 200, nthreads=6)
+    compare_solve(got, ref, f"row-block list F{fid}")
+    dense = spca.am_solve(A, fid, par, X0, tol=1e-8, maxit=200, flags=spca.FLAG_DENSE_ONLY)
+    assert rel_err(got["objective"], dense["objective"]) <= 1e-5
