@@ -222,6 +222,11 @@ int spca_gemm_nt_f32(void* stream, const float* P, int64_t ldp, const float* Q,
 int spca_gemm_nt_bf16(void* stream, const uint16_t* P, int64_t ldp,
                       const uint16_t* Q, int64_t ldq, float* C, int64_t ldc,
                       int64_t M, int64_t N, int64_t K);
+/* The BF16 product with a given tile shape and K split, as
+ * spca_gemm_nt_f32_shape (C holds `splits` partial products).             */
+int spca_gemm_nt_bf16_shape(void* stream, const uint16_t* P, int64_t ldp,
+                            const uint16_t* Q, int64_t ldq, float* C, int64_t ldc,
+                            int64_t M, int64_t N, int64_t K, int shape, int splits);
 
 /* Tuning and testing variant of spca_gemm_nt_f32 with a forced tile shape
  * (0 .. 5: BMxBN of 128x128, 128x160, 128x96, 128x64, 64x128, 32x128) and

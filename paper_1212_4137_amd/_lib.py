@@ -28,7 +28,7 @@ EXPORTED = ("spca_am_solve", "spca_am_solve_ex", "spca_ctx_create",
             "spca_ctx_set_workspace", "spca_request_footprint", "spca_server_create",
             "spca_server_submit", "spca_server_poll", "spca_server_stats",
             "spca_server_destroy", "spca_tune_table_export", "spca_tune_table_import",
-            "spca_tune_table_clear")
+            "spca_tune_table_clear", "spca_gemm_nt_bf16_shape")
 
 
 class SpcaError(RuntimeError):
@@ -135,6 +135,9 @@ def load():
         lib.spca_gemm_nt_f32_shape.argtypes = [P, P, i64, P, i64, P, i64, i64, i64, i64,
                                                ctypes.c_int, ctypes.c_int]
         lib.spca_gemm_nt_f32_shape.restype = ctypes.c_int
+        lib.spca_gemm_nt_bf16_shape.argtypes = [P, P, i64, P, i64, P, i64, i64, i64, i64,
+                                                ctypes.c_int, ctypes.c_int]
+        lib.spca_gemm_nt_bf16_shape.restype = ctypes.c_int
         lib.spca_gemm_nt_f32_plan.argtypes = [i64, i64, i64, ctypes.c_int,
                                               ctypes.POINTER(ctypes.c_int),
                                               ctypes.POINTER(ctypes.c_int)]
@@ -399,10 +402,21 @@ def gemm_nt_bf16(P, Q, stream=None):
 
 def gemm_nt_shape(P, Q, shape, splits=1, stream=None):
     """Partial products of P Q^T with a forced tile shape and K split
-    (``spca_gemm_nt_f32_shape``); returns a (splits, M, N) tensor whose sum
-    over the first axis is the product."""
+    (``spca_gemm_nt_f32_shape``, or ``spca_gemm_nt_bf16_shape`` for
+    torch.bfloat16 operands); returns a (splits, M, N) tensor whose sum over
+    the first axis is the product."""
     import torch
 
+    if P.dtype == torch.bfloat16:
+        _require_gpu_tensor(Q, "Q", torch.bfloat16)
+        M, K = P.shape
+        N, _ = Q.shape
+        C = torch.empty((splits, M, N), dtype=torch.float32, device=P.device)
+        _check(load().spca_gemm_nt_bf16_shape(
+            _stream_ptr(stream), ctypes.c_void_p(P.data_ptr()), P.stride(0),
+            ctypes.c_void_p(Q.data_ptr()), Q.stride(0), ctypes.c_void_p(C.data_ptr()), N,
+            M, N, K, int(shape), int(splits)))
+        return C
     _require_gpu_tensor(P, "P", torch.float32)
     _require_gpu_tensor(Q, "Q", torch.float32)
     M, K = P.shape

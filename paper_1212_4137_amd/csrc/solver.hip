@@ -918,6 +918,25 @@ int spca_gemm_nt_f32_shape(void* stream, const float* P, int64_t ldp,
   return SPCA_OK;
 }
 
+int spca_gemm_nt_bf16_shape(void* stream, const uint16_t* P, int64_t ldp,
+                            const uint16_t* Q, int64_t ldq, float* C, int64_t ldc,
+                            int64_t M, int64_t N, int64_t K, int shape, int splits) {
+  SPCA_REQUIRE(P && Q && C, "P, Q and C must not be NULL");
+  SPCA_REQUIRE(M >= 0 && N >= 0 && K >= 0, "sizes must be >= 0");
+  SPCA_REQUIRE(M <= INT32_MAX && N <= INT32_MAX && K <= INT32_MAX,
+               "sizes must fit in int32");
+  SPCA_REQUIRE(ldp >= K && ldq >= K && ldc >= N, "leading dimensions too small");
+  SPCA_REQUIRE(ldp % 8 == 0 && ldq % 8 == 0, "ldp and ldq must be multiples of 8");
+  SPCA_REQUIRE((uintptr_t)P % 16 == 0 && (uintptr_t)Q % 16 == 0,
+               "P and Q must be 16-byte aligned");
+  SPCA_REQUIRE(shape >= 0 && shape < gemm_num_shapes(), "shape index out of range");
+  SPCA_REQUIRE(splits >= 1 && splits <= 64, "splits must be in 1..64");
+  gemm_nt_bf16((hipStream_t)stream, P, ldp, Q, ldq, C, ldc, M, N, K, nullptr, 0,
+               GemmPlan{shape, splits}, M * ldc);
+  SPCA_LAUNCH_CHECK("gemm_nt_bf16");
+  return SPCA_OK;
+}
+
 int spca_gemm_nt_bf16(void* stream, const uint16_t* P, int64_t ldp,
                       const uint16_t* Q, int64_t ldq, float* C, int64_t ldc,
                       int64_t M, int64_t N, int64_t K) {
