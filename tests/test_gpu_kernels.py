@@ -143,13 +143,16 @@ def test_x_update_gamma_boundaries(spca):
     assert np.all(nnz == 0)
 
 
-@pytest.mark.parametrize("s", [1.0, 1.7, 12.0, 99.5, 5000.0])
-def test_x_update_lambda_s_regimes(spca, s):
-    rng = np.random.default_rng(int(s * 10))
-    V_h = (rng.standard_normal((5, 2049)) * 10).astype(np.float32)
+@pytest.mark.parametrize("p", [2049, 20000])
+@pytest.mark.parametrize("s", [1.0, 1.7, 12.0, 99.5, 5000.0, 3000.0])
+def test_x_update_lambda_s_regimes(spca, s, p):
+    # p = 20000: the chunked kernels (candidates, and the interval search
+    # when the root lies below the candidates: s = 3000 needs M > 2048)
+    rng = np.random.default_rng(int(s * 10) + p)
+    V_h = (rng.standard_normal((5, p)) * 10).astype(np.float32)
     V_h[4, 100:] = 0.0
     X, phi, nnz = _check_xupdate(spca, 3, V_h, s, exact_support=False)
-    if s >= 5000:  # inactive constraint: x = v / ||v||
+    if s >= 5000 and p < 5000:  # inactive constraint: x = v / ||v||
         Vn = V_h.astype(np.float64)
         np.testing.assert_allclose(X, Vn / np.linalg.norm(Vn, axis=1, keepdims=True),
                                    atol=2e-7)
