@@ -65,7 +65,7 @@ def traffic_aty():
             "algorithmic_bytes": None, "source": TRAFFIC_ATY["profile"]}
 
 
-def cpu_baseline(A_np, X0_np, params, maxit_sample=25):
+def cpu_baseline(A_np, X0_np, params, maxit_sample=100):
     """FP64 oracle on a bounded sample of the same workload: every
     formulation, the first 2 x threads starts, maxit_sample iterations each
     (stop test disabled).  Returns iterations x starts per second."""

@@ -5,6 +5,7 @@ import ctypes
 import os
 import re
 import subprocess
+import sys
 
 import pytest
 
@@ -111,3 +112,35 @@ def test_tuning_table_round_trip_and_plan_lookup():
     assert m.tune_table_export() == text  # a rejected import changes nothing
     m.tune_table_clear()
     assert m.gemm_plan(1024, 10000, 1000, 1) == model
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    """Without the built HIP library the binding raises instead of falling
+    back to anything else (there is no CPU path in the product)."""
+    code = (
+        "import paper_1212_4137_amd._lib as L\n"
+        f"L.LIB_PATH = {str(tmp_path / 'absent.so')!r}\n"
+        "L._lib = None\n"
+        "try:\n"
+        "    L.load()\n"
+        "except ImportError as e:\n"
+        "    print('raised', e)\n"
+        "else:\n"
+        "    print('loaded')\n")
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True,
+                         cwd=os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                         timeout=120)
+    assert out.stdout.startswith("raised"), (out.stdout, out.stderr)
+
+
+def test_package_does_not_import_the_oracle():
+    """The product package and the oracle share no code: nothing under
+    paper_1212_4137_amd/ imports oracle/ (and the reverse)."""
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    for sub, other in (("paper_1212_4137_amd", "oracle"), ("oracle", "paper_1212_4137_amd")):
+        for dirpath, _, files in os.walk(os.path.join(root, sub)):
+            for f in files:
+                if f.endswith((".py", ".hip", ".hpp", ".h", ".c", ".cpp")):
+                    text = open(os.path.join(dirpath, f), errors="replace").read()
+                    assert not re.search(rf"^\s*(import|from)\s+{other}\b", text, re.M), f
+                    assert f'#include "{other}' not in text and f"../{other}/" not in text, f
