@@ -62,6 +62,9 @@ def _load():
     lib.orc_am_multi.argtypes = [P, i64, i64, i64, ctypes.c_int, d, P, i32, d,
                                  i32, ctypes.c_int, P, P, P, P, P, P]
     lib.orc_am_multi.restype = i32
+    lib.orc_am_multi_warm.argtypes = [P, i64, i64, i64, ctypes.c_int, d, i64, i32, P, i32,
+                                      d, i32, ctypes.c_int, P, P, P, P, P, P]
+    lib.orc_am_multi_warm.restype = i32
     lib.orc_max_norm_column.argtypes = [P, i64, i64, i64]
     lib.orc_max_norm_column.restype = i64
     _lib = lib
@@ -187,6 +190,35 @@ def am_multi(A, fid, s_or_gamma, X0, tol, maxit, nthreads=1, want_x=True):
                                 _ptr(phi), _ptr(iters), _ptr(status))
     return {"best": int(best), "X": X, "f": f, "ev": ev, "phi": phi,
             "iters": iters, "status": status}
+
+
+def am_multi_warm(A, fid, s_or_gamma, X0, tol, maxit, warm_iters, target_s=0,
+                  nthreads=1):
+    """Multi-start AM with the sparsity-targeted warm-up of Section 4.1:
+    the parameter (lambda for the L1 constraint, gamma for the penalties,
+    targeting target_s nonzeros) follows v for warm_iters x-updates and is
+    frozen afterwards.  The best start has the largest explained variance.
+    Returns the best start, per-start f, EV, final parameter, iterations,
+    status and final x (r x p)."""
+    A64, lda = _colmajor(A)
+    n, p = A64.shape
+    X0 = np.ascontiguousarray(np.asarray(X0, dtype=np.float64))
+    if X0.ndim == 1:
+        X0 = X0[None, :]
+    r = X0.shape[0]
+    assert X0.shape[1] == p
+    X = np.zeros((r, p))
+    f = np.zeros(r)
+    ev = np.zeros(r)
+    par = np.zeros(r)
+    iters = np.zeros(r, dtype=np.int32)
+    status = np.zeros(r, dtype=np.int32)
+    best = _load().orc_am_multi_warm(_ptr(A64), n, p, lda, int(fid), float(s_or_gamma),
+                                     int(target_s), int(warm_iters), _ptr(X0), r, float(tol),
+                                     int(maxit), int(nthreads), _ptr(X), _ptr(f), _ptr(ev),
+                                     _ptr(par), _ptr(iters), _ptr(status))
+    return {"best": int(best), "X": X, "f": f, "ev": ev, "param": par, "iters": iters,
+            "status": status}
 
 
 def max_norm_column(A):

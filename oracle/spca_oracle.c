@@ -381,6 +381,161 @@ int32_t orc_am_multi(const double* A, int64_t n, int64_t p, int64_t lda,
   return best;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Sparsity-targeted warm-up (Section 4.1)                                  */
+/* ------------------------------------------------------------------------ */
+
+static int cmp_double_desc(const void* pa, const void* pb) {
+  double a = *(const double*)pa, b = *(const double*)pb;
+  return (a < b) - (a > b);
+}
+
+/* the (s+1)-th largest of |v_i| (or of v_i^2 when squared), 0 if s >= p */
+static double target_threshold(const double* v, int64_t p, int64_t s, int squared) {
+  if (s >= p) return 0.0;
+  double* c = (double*)malloc(sizeof(double) * (size_t)p);
+  for (int64_t i = 0; i < p; ++i) c[i] = squared ? v[i] * v[i] : fabs(v[i]);
+  qsort(c, (size_t)p, sizeof(double), cmp_double_desc);
+  double t = c[s];
+  free(c);
+  return t;
+}
+
+int orc_am_single_warm(const double* A, int64_t n, int64_t p, int64_t lda,
+                       int fid, double s_or_gamma, int64_t target_s,
+                       int32_t warm_iters, const double* x0, double tol,
+                       int32_t maxit, double* x_out, int32_t* iters, double* f,
+                       double* ev, double* param_out) {
+  double* x = (double*)malloc(sizeof(double) * (size_t)p);
+  double* w = (double*)malloc(sizeof(double) * (size_t)p);
+  double* v = (double*)malloc(sizeof(double) * (size_t)p);
+  double* u = (double*)malloc(sizeof(double) * (size_t)n);
+  memcpy(x, x0, sizeof(double) * (size_t)p);
+  const int lambda_kind = fid == 3 || fid == 4;
+  /* the parameter in force: lambda (fid 3, 4) or gamma (fid 5..8) */
+  double param = lambda_kind ? 0.0 : s_or_gamma;
+
+  int status = ORC_MAXIT;
+  double phi_prev = 0.0;
+  int32_t k = 0;
+  while (k < maxit) {
+    matvec(A, n, p, lda, x, u);
+    double unorm = norm2(u, n);
+    if (unorm == 0.0) {
+      status = ORC_DEGENERATE;
+      break;
+    }
+    for (int64_t i = 0; i < n; ++i)
+      u[i] = is_l1_variance(fid) ? sgn(u[i]) : u[i] / unorm;
+    matvec_t(A, n, p, lda, u, v);
+    ++k;
+    const int warming = k <= warm_iters;
+    double phi;
+    if (lambda_kind) {
+      if (warming || warm_iters == 0) param = orc_lambda_s(v, p, s_or_gamma);
+      phi = param * sqrt(s_or_gamma) + orc_V_gamma(v, p, param, w);
+    } else if (fid <= 2) {
+      phi = orc_x_operator(fid, v, p, s_or_gamma, w);
+    } else {
+      const int l0pen = fid == 5 || fid == 6;
+      if (warming) param = target_threshold(v, p, target_s, l0pen);
+      phi = l0pen ? orc_U_gamma(v, p, param, w) : orc_V_gamma(v, p, param, w);
+    }
+    double wnorm = norm2(w, p);
+    if (wnorm == 0.0) {
+      status = ORC_ZERO;
+      break;
+    }
+    for (int64_t j = 0; j < p; ++j) x[j] = w[j] / wnorm;
+    if (k >= 2 && k >= warm_iters + 1 && tol >= 0.0 && phi <= (1.0 + tol) * phi_prev) {
+      status = ORC_CONVERGED;
+      break;
+    }
+    phi_prev = phi;
+  }
+  double evv = 0.0, fv = 0.0;
+  if (status == ORC_DEGENERATE || status == ORC_ZERO) {
+    for (int64_t j = 0; j < p; ++j) x[j] = 0.0;
+  } else {
+    fv = orc_objective(fid, A, n, p, lda, x, lambda_kind || fid <= 2 ? s_or_gamma : param,
+                       &evv);
+  }
+  if (x_out) memcpy(x_out, x, sizeof(double) * (size_t)p);
+  if (iters) *iters = k;
+  if (f) *f = fv;
+  if (ev) *ev = evv;
+  if (param_out) *param_out = param;
+  free(x);
+  free(w);
+  free(v);
+  free(u);
+  return status;
+}
+
+typedef struct {
+  const double* A;
+  int64_t n, p, lda;
+  int fid;
+  double s_or_gamma;
+  int64_t target_s;
+  int32_t warm_iters;
+  const double* X0;
+  int32_t r;
+  double tol;
+  int32_t maxit;
+  int nthreads, tid;
+  double *X_out, *f_out, *ev_out, *param_out, *ev_all;
+  int32_t *iters_out, *status_out;
+} warm_job_t;
+
+static void* warm_worker(void* arg) {
+  warm_job_t* jb = (warm_job_t*)arg;
+  for (int32_t j = jb->tid; j < jb->r; j += jb->nthreads) {
+    int32_t it = 0;
+    double fv = 0.0, evv = 0.0, par = 0.0;
+    double* xo = jb->X_out ? jb->X_out + (int64_t)j * jb->p : NULL;
+    int st = orc_am_single_warm(jb->A, jb->n, jb->p, jb->lda, jb->fid, jb->s_or_gamma,
+                                jb->target_s, jb->warm_iters, jb->X0 + (int64_t)j * jb->p,
+                                jb->tol, jb->maxit, xo, &it, &fv, &evv, &par);
+    jb->ev_all[j] = evv;
+    if (jb->f_out) jb->f_out[j] = fv;
+    if (jb->ev_out) jb->ev_out[j] = evv;
+    if (jb->param_out) jb->param_out[j] = par;
+    if (jb->iters_out) jb->iters_out[j] = it;
+    if (jb->status_out) jb->status_out[j] = st;
+  }
+  return NULL;
+}
+
+int32_t orc_am_multi_warm(const double* A, int64_t n, int64_t p, int64_t lda,
+                          int fid, double s_or_gamma, int64_t target_s,
+                          int32_t warm_iters, const double* X0, int32_t r,
+                          double tol, int32_t maxit, int nthreads, double* X_out,
+                          double* f_out, double* ev_out, double* param_out,
+                          int32_t* iters_out, int32_t* status_out) {
+  if (nthreads < 1) nthreads = 1;
+  if (nthreads > r) nthreads = r;
+  double* ev_all = (double*)malloc(sizeof(double) * (size_t)r);
+  warm_job_t* jobs = (warm_job_t*)malloc(sizeof(warm_job_t) * (size_t)nthreads);
+  pthread_t* th = (pthread_t*)malloc(sizeof(pthread_t) * (size_t)nthreads);
+  for (int t = 0; t < nthreads; ++t) {
+    warm_job_t jb = {A, n, p, lda, fid, s_or_gamma, target_s, warm_iters, X0, r, tol,
+                     maxit, nthreads, t, X_out, f_out, ev_out, param_out, ev_all,
+                     iters_out, status_out};
+    jobs[t] = jb;
+  }
+  for (int t = 1; t < nthreads; ++t) pthread_create(&th[t], NULL, warm_worker, &jobs[t]);
+  warm_worker(&jobs[0]);
+  for (int t = 1; t < nthreads; ++t) pthread_join(th[t], NULL);
+  int32_t best = 0;
+  for (int32_t j = 1; j < r; ++j)
+    if (ev_all[j] > ev_all[best]) best = j;
+  free(ev_all);
+  free(jobs);
+  free(th);
+  return best;
+}
+
 int64_t orc_max_norm_column(const double* A, int64_t n, int64_t p,
                             int64_t lda) {
   int64_t best = 0;

@@ -71,6 +71,39 @@ int32_t orc_am_multi(const double* A, int64_t n, int64_t p, int64_t lda,
                      double* f_out, double* ev_out, double* phi_out,
                      int32_t* iters_out, int32_t* status_out);
 
+/* Algorithm 2 with the sparsity-targeted warm-up used in the experiments of
+ * Section 4.1 (explained-variance hunt): during the first warm_iters
+ * x-updates the parameter follows the current v, afterwards it is frozen at
+ * its last value.
+ *   L1 constraint (fid 3, 4): lambda = lambda_s(v) while warming up, then
+ *     x = V_lambda(v) / ||.|| with the frozen lambda; phi = lambda sqrt(s)
+ *     + ||V_lambda(v)|| throughout.  s_or_gamma is s.
+ *   Penalties (fid 5..8): gamma = the (target_s + 1)-th largest v_i^2 (L0
+ *     penalty, U_gamma) or |v_i| (L1 penalty, V_gamma) while warming up
+ *     (0 when target_s >= p), so that exactly target_s entries pass the
+ *     strict threshold (ties aside); then frozen.  s_or_gamma is unused
+ *     when warm_iters > 0.
+ * The ratio stop test applies once the parameter is frozen (from x-update
+ * warm_iters + 1 on, and never before the second).  warm_iters = 0 is the
+ * plain algorithm.  *param_out receives the final lambda or gamma, which
+ * also enters f(x) for the penalties.  Returns the status.                 */
+int orc_am_single_warm(const double* A, int64_t n, int64_t p, int64_t lda,
+                       int fid, double s_or_gamma, int64_t target_s,
+                       int32_t warm_iters, const double* x0, double tol,
+                       int32_t maxit, double* x_out, int32_t* iters, double* f,
+                       double* ev, double* param_out);
+
+/* Multi-start driver of orc_am_single_warm.  The best start is the one with
+ * the largest explained variance (ties to the lowest index): with the
+ * warm-up every start ends with its own gamma, so f is not comparable
+ * across starts.  Returns the index of the best start.                    */
+int32_t orc_am_multi_warm(const double* A, int64_t n, int64_t p, int64_t lda,
+                          int fid, double s_or_gamma, int64_t target_s,
+                          int32_t warm_iters, const double* X0, int32_t r,
+                          double tol, int32_t maxit, int nthreads, double* X_out,
+                          double* f_out, double* ev_out, double* param_out,
+                          int32_t* iters_out, int32_t* status_out);
+
 /* argmax_i ||a_i||_2 over the columns of A, ties to the lowest index.     */
 int64_t orc_max_norm_column(const double* A, int64_t n, int64_t p,
                             int64_t lda);
