@@ -149,6 +149,17 @@ typedef struct {
    * The workspace grows by about 40 bytes per start beyond
    * spca_workspace_bytes(n, p, r, ...) plus 4p bytes.                    */
   int32_t total_starts;
+  /* Sparsity-targeted warm-up (the experiments of Section 4.1): during the
+   * first warmup_iters x-updates the parameter follows v and is then frozen
+   * per start.  L1 constraint (formulations 3, 4): lambda = lambda_s(v),
+   * then fixed.  Penalties (5..8): gamma = the (target_nnz + 1)-th largest
+   * v_i^2 (L0 penalty) or |v_i| (L1 penalty), so that target_nnz entries
+   * pass the strict threshold (ties aside), then fixed; s_or_gamma is
+   * unused.  The stop test applies once the parameter is frozen; with
+   * per-start gamma the best start is the one with the largest explained
+   * variance.  0 disables it.  FP32 only, not with total_starts > r.      */
+  int32_t warmup_iters;
+  int32_t target_nnz;   /* penalties under warm-up: 1..p                    */
 } spca_solve_opts;
 
 /* SPCA_FLAG_GRAPH: capture check_every iterations once per solve into a HIP
@@ -190,6 +201,9 @@ typedef struct {
    * iterations, those that used the row-block list kernel.  NULL disables
    * the events.                                                            */
   double* kernel_times;
+  /* optional host array (per start): the final lambda (formulations 3, 4)
+   * or gamma (5..8) of each start under the warm-up; untouched otherwise */
+  double* param_per_start;
 } spca_outputs;
 
 /* Full solve on a caller-chosen context and HIP stream (hipStream_t passed

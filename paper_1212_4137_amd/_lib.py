@@ -56,7 +56,8 @@ class SolveOpts(ctypes.Structure):
     _fields_ = [("X0", ctypes.c_void_p), ("r", ctypes.c_int32), ("tol", ctypes.c_double),
                 ("maxit", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("polish_maxit", ctypes.c_int32), ("check_every", ctypes.c_int32),
-                ("flags", ctypes.c_int32), ("total_starts", ctypes.c_int32)]
+                ("flags", ctypes.c_int32), ("total_starts", ctypes.c_int32),
+                ("warmup_iters", ctypes.c_int32), ("target_nnz", ctypes.c_int32)]
 
 
 class Outputs(ctypes.Structure):
@@ -65,7 +66,8 @@ class Outputs(ctypes.Structure):
                 ("f_per_start", ctypes.c_void_p), ("ev_per_start", ctypes.c_void_p),
                 ("phi_per_start", ctypes.c_void_p), ("iters_per_start", ctypes.c_void_p),
                 ("status_per_start", ctypes.c_void_p), ("nnz_per_start", ctypes.c_void_p),
-                ("X_final", ctypes.c_void_p), ("kernel_times", ctypes.c_void_p)]
+                ("X_final", ctypes.c_void_p), ("kernel_times", ctypes.c_void_p),
+                ("param_per_start", ctypes.c_void_p)]
 
 
 class Request(ctypes.Structure):
@@ -248,11 +250,13 @@ def colmajor_view(A):
 
 def am_solve(A, formulation, s_or_gamma, X0=None, tol=1e-8, maxit=200, *,
              precision=PREC_FP32, polish_maxit=0, check_every=8, flags=0,
-             ctx=None, stream=None, return_X=False, kernel_times=False, slots=None):
+             ctx=None, stream=None, return_X=False, kernel_times=False, slots=None,
+             warmup_iters=0, target_nnz=0):
     """Batched AM solve (``spca_am_solve_ex``).
 
     slots: run the rows of X0 through this many slots with on-the-fly
         replacement (``total_starts`` = rows of X0); None runs them all at once.
+    warmup_iters, target_nnz: the sparsity-targeted warm-up of lambda / gamma.
 
     A : torch.float32 GPU tensor (n, p), column-major (strides (1, lda)).
     precision: PREC_FP32 / PREC_BF16_POLISH, or "fp32" / "bf16".
@@ -293,10 +297,11 @@ def am_solve(A, formulation, s_or_gamma, X0=None, tol=1e-8, maxit=200, *,
     prob = Problem(A.data_ptr(), n, p, lda, int(formulation), float(s_or_gamma))
     opts = SolveOpts(X0.data_ptr() if X0 is not None else None, r, float(tol), int(maxit),
                      int(precision), int(polish_maxit), int(check_every), int(flags),
-                     int(total if total > r else 0))
+                     int(total if total > r else 0), int(warmup_iters), int(target_nnz))
+    par = np.zeros(total)
     out = Outputs(_np_ptr(x), _np_ptr(sup), ctypes.pointer(res), _np_ptr(f), _np_ptr(ev),
                   _np_ptr(phi), _np_ptr(iters), _np_ptr(status), _np_ptr(nnz),
-                  Xf.data_ptr() if Xf is not None else None, _np_ptr(kt))
+                  Xf.data_ptr() if Xf is not None else None, _np_ptr(kt), _np_ptr(par))
     _check(load().spca_am_solve_ex(ctx.handle, _stream_ptr(stream), ctypes.byref(prob),
                                    ctypes.byref(opts), ctypes.byref(out)))
     return {"x": x, "support": sup[: res.nnz].copy(), "objective": res.objective,
@@ -307,7 +312,7 @@ def am_solve(A, formulation, s_or_gamma, X0=None, tol=1e-8, maxit=200, *,
             "polish_iters": res.polish_iters,
             "f_per_start": f, "ev_per_start": ev, "phi_per_start": phi,
             "iters_per_start": iters, "status_per_start": status,
-            "nnz_per_start": nnz, "X_final": Xf,
+            "nnz_per_start": nnz, "X_final": Xf, "param_per_start": par,
             "kernel_times": None if kt is None else {
                 "aty_ms": kt[0], "aty_launches": int(kt[1]), "x_update_ms": kt[2],
                 "x_update_launches": int(kt[3]), "ax_dense_ms": kt[4],

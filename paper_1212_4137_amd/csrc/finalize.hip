@@ -86,7 +86,8 @@ __global__ __launch_bounds__(kFT) void final_matvec_kernel(
 __global__ void objective_kernel(int fid, double gamma, StartState s,
                                  int64_t r, const double* __restrict__ partial,
                                  int nchunks, const double* __restrict__ xnorm,
-                                 double* f, double* ev, const int32_t* only) {
+                                 double* f, double* ev, const int32_t* only,
+                                 const double* __restrict__ gam) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= r) return;
   if (only != nullptr && only[j] == 0) return;
@@ -104,6 +105,7 @@ __global__ void objective_kernel(int fid, double gamma, StartState s,
   }
   const bool l1var = fid % 2 == 0;
   const double var = l1var ? l1 : sqrt(sq);
+  if (gam != nullptr) gamma = gam[j];
   ev[j] = l1var ? l1 : sq;
   double fv;
   if (fid <= 4)
@@ -176,7 +178,7 @@ void evaluate_rows(hipStream_t st, int fid, double s_or_gamma, const float* A,
                    int64_t lda, int64_t n, const int32_t* list_idx,
                    const float* list_val, int64_t ldl, StartState s, int64_t r,
                    double* partial, double* f, double* ev, double* xnorm,
-                   const int32_t* only) {
+                   const int32_t* only, const double* gam) {
   const int nchunks = (int)ceil_div(n, kFT);
   hipLaunchKernelGGL(x_norms_kernel, dim3((unsigned)r), dim3(256), 0, st,
                      list_val, ldl, s, r, xnorm, only);
@@ -185,17 +187,18 @@ void evaluate_rows(hipStream_t st, int fid, double s_or_gamma, const float* A,
                      xnorm, partial, nchunks, only);
   hipLaunchKernelGGL(objective_kernel, dim3((unsigned)ceil_div(r, 256)),
                      dim3(256), 0, st, fid, s_or_gamma, s, r, partial, nchunks,
-                     xnorm, f, ev, only);
+                     xnorm, f, ev, only, gam);
 }
 
 void finalize(hipStream_t st, int fid, double s_or_gamma, const float* A,
               int64_t lda, int64_t n, int64_t p, const int32_t* list_idx,
               const float* list_val, int64_t ldl, StartState s, int64_t r,
               double* partial, double* f, double* ev, double* xnorm,
-              int32_t* best, double* x_out, int32_t* support_out) {
+              int32_t* best, double* x_out, int32_t* support_out,
+              const double* gam, bool by_ev) {
   evaluate_rows(st, fid, s_or_gamma, A, lda, n, list_idx, list_val, ldl, s, r,
-                partial, f, ev, xnorm, nullptr);
-  hipLaunchKernelGGL(best_kernel, dim3(1), dim3(1024), 0, st, f, s, r, p,
+                partial, f, ev, xnorm, nullptr, gam);
+  hipLaunchKernelGGL(best_kernel, dim3(1), dim3(1024), 0, st, by_ev ? ev : f, s, r, p,
                      list_idx, list_val, ldl, xnorm, best, x_out, support_out);
 }
 

@@ -51,6 +51,16 @@ struct Plan {
   int32_t last_union;   // most recent measured union size (0: none yet)
 };
 
+// Sparsity-targeted warm-up (Section 4.1): during x-updates 1..K the
+// parameter follows v (lambda_s(v) for the L1 constraint; for the
+// penalties gamma = the (target+1)-th largest v_i^2 or |v_i|, so that target
+// entries pass), afterwards it is frozen at gam[j].  K = 0: off.
+struct Warm {
+  int32_t K = 0;
+  int32_t target = 0;
+  double* gam = nullptr;  // r: the parameter of each start
+};
+
 // Tile shape (index into the compiled shapes) and K split of one product.
 struct GemmPlan {
   int shape;
@@ -204,7 +214,7 @@ void x_update(hipStream_t st, int fid, double s_or_gamma, const float* V,
               int64_t ldv, int64_t r, int64_t p, float* X, int64_t ldx,
               int32_t* list_idx, float* list_val, int64_t ldl, int list_cap,
               StartState s, double tol, int32_t maxit, int32_t* colmark,
-              const Plan* plan, void* wide = nullptr);
+              const Plan* plan, void* wide = nullptr, Warm wm = Warm{});
 
 constexpr int64_t kWideMinP = 12288;
 // scratch of the chunked x-update (0 when it does not apply: lambda_s, or
@@ -217,22 +227,25 @@ bool x_update_wide(hipStream_t st, int fid, double s_or_gamma, const float* V,
                    int64_t ldv, int64_t r, int64_t p, float* X, int64_t ldx,
                    int32_t* list_idx, float* list_val, int64_t ldl, int list_cap,
                    StartState s, double tol, int32_t maxit, int32_t* colmark,
-                   const Plan* plan, void* scratch);
+                   const Plan* plan, void* scratch, Warm wm);
 
 // FP64 finalisation: per start, x64 = x / ||x||_2 from the lists, f(x64)
 // of Table 1 and the explained variance; then the best start.
+// gam: per-start gamma of the penalties (warm-up), or null for s_or_gamma;
+// by_ev: pick the best start by explained variance instead of f
 void finalize(hipStream_t st, int fid, double s_or_gamma, const float* A,
               int64_t lda, int64_t n, int64_t p, const int32_t* list_idx,
               const float* list_val, int64_t ldl, StartState s, int64_t r,
               double* partial, double* f, double* ev, double* xnorm,
-              int32_t* best, double* x_out, int32_t* support_out);
+              int32_t* best, double* x_out, int32_t* support_out,
+              const double* gam = nullptr, bool by_ev = false);
 // The FP64 objective and explained variance of the rows with only[j] != 0
 // (the first three steps of finalize); other rows are left untouched.
 void evaluate_rows(hipStream_t st, int fid, double s_or_gamma, const float* A,
                    int64_t lda, int64_t n, const int32_t* list_idx,
                    const float* list_val, int64_t ldl, StartState s, int64_t r,
                    double* partial, double* f, double* ev, double* xnorm,
-                   const int32_t* only);
+                   const int32_t* only, const double* gam = nullptr);
 
 // On-the-fly replacement of finished starts (Section 4.3): state of the
 // slots and of the total_starts starts that flow through them.

@@ -53,7 +53,7 @@ struct Layout {
   size_t off_At, off_Ac, off_X, off_U, off_Y, off_V, off_li, off_lv;
   size_t off_phi, off_phip, off_nnz, off_it, off_st, off_plan, off_part,
       off_f, off_ev, off_xn, off_best, off_xout, off_sup, off_colsq, off_bad;
-  size_t off_mark, off_ulist, off_Xc, off_Qc, off_wide;
+  size_t off_mark, off_ulist, off_Xc, off_Qc, off_wide, off_gam;
   size_t wide_bytes;
   int64_t ucap;  // largest support union the union product can hold
   GemmPlan plan_union;
@@ -122,6 +122,7 @@ Layout make_layout(int64_t n, int64_t p, int64_t r, bool copy_a, bool bf16) {
   L.off_xn = carve(&c, sizeof(double) * 2 * r);
   L.off_best = carve(&c, sizeof(int32_t) * 2);
   L.off_xout = carve(&c, sizeof(double) * p);
+  L.off_gam = carve(&c, sizeof(double) * r);
   L.off_sup = carve(&c, sizeof(int32_t) * p);
   L.off_colsq = carve(&c, sizeof(double) * p);
   L.off_bad = carve(&c, sizeof(int32_t));
@@ -482,6 +483,15 @@ int spca_am_solve_ex(spca_ctx* ctx, void* stream, const spca_problem* prob,
   SPCA_REQUIRE(opts->total_starts >= 0, "total_starts must be >= 0");
   const int64_t l = opts->total_starts > r ? opts->total_starts : r;
   const bool otf = l > r;
+  SPCA_REQUIRE(opts->warmup_iters >= 0, "warmup_iters must be >= 0");
+  const bool warm = opts->warmup_iters > 0;
+  if (warm) {
+    SPCA_REQUIRE(fid >= 3, "the warm-up applies to formulations 3..8");
+    SPCA_REQUIRE(!bf16 && !otf, "the warm-up runs in FP32 without total_starts > r");
+    if (fid >= 5)
+      SPCA_REQUIRE(opts->target_nnz >= 1 && opts->target_nnz <= p,
+                   "target_nnz must be in 1..p for the penalty warm-up");
+  }
   if (otf) {
     SPCA_REQUIRE(!bf16, "on-the-fly replacement runs in FP32 only");
     SPCA_REQUIRE(opts->X0 != nullptr, "on-the-fly replacement needs X0 (total_starts rows)");
@@ -530,6 +540,13 @@ int spca_am_solve_ex(spca_ctx* ctx, void* stream, const spca_problem* prob,
   void* wide = L.wide_bytes ? (void*)(base + L.off_wide) : nullptr;
   Otf o{};
   if (otf) o = carve_otf(base + otf_off, r, p, l);
+  double* gam = (double*)(base + L.off_gam);
+  Warm wm;
+  if (warm) {
+    wm.K = opts->warmup_iters;
+    wm.target = fid >= 5 ? opts->target_nnz : 0;
+    wm.gam = gam;
+  }
 
   // a0: stage A (aligned column-major copy only when needed) and its
   // row-major twin used by the dense A x.
@@ -666,7 +683,7 @@ int spca_am_solve_ex(spca_ctx* ctx, void* stream, const spca_problem* prob,
     if (tm) SPCA_HIP_TRY(ctx->t_aty.mark(q));
     if (tm) SPCA_HIP_TRY(ctx->t_xup.mark(q));
     x_update(q, fid, sg, V, L.ldx, r, p, X, L.ldx, li, lv, L.ldx, list_cap, s,
-             opts->tol, maxit, colmark, plan, wide);
+             opts->tol, maxit, colmark, plan, wide, wm);
     if (tm) SPCA_HIP_TRY(ctx->t_xup.mark(q));
     if (otf)
       otf_step(q, fid, sg, A, ldA, n, p, X, L.ldx, opts->X0, li, lv, L.ldx, s, r,
@@ -750,8 +767,11 @@ int spca_am_solve_ex(spca_ctx* ctx, void* stream, const spca_problem* prob,
     otf_output(st, o, p, best, xout, sup);
   } else {
     compact_rows(st, X, L.ldx, r, p, li, lv, L.ldx, s.nnz, nullptr, nullptr, nullptr);
+    // under the penalty warm-up every start has its own gamma: f uses it,
+    // and the best start is the one with the largest explained variance
+    const bool per_start_gamma = warm && fid >= 5;
     finalize(st, fid, sg, A, ldA, n, p, li, lv, L.ldx, s, r, partial, fj, evj,
-             xnorm, best, xout, sup);
+             xnorm, best, xout, sup, per_start_gamma ? gam : nullptr, per_start_gamma);
   }
   SPCA_LAUNCH_CHECK("finalize");
 
@@ -782,6 +802,9 @@ int spca_am_solve_ex(spca_ctx* ctx, void* stream, const spca_problem* prob,
                                 hipMemcpyDeviceToHost, st));
   if (out->support && nnzb > 0)
     SPCA_HIP_TRY(hipMemcpyAsync(out->support, sup, sizeof(int32_t) * nnzb,
+                                hipMemcpyDeviceToHost, st));
+  if (out->param_per_start && warm)
+    SPCA_HIP_TRY(hipMemcpyAsync(out->param_per_start, gam, sizeof(double) * r,
                                 hipMemcpyDeviceToHost, st));
   if (out->X_final)
     SPCA_HIP_TRY(hipMemcpy2DAsync(out->X_final, sizeof(float) * p, X,

@@ -646,12 +646,14 @@ __device__ void radix_select(float (&v)[NPT], uint32_t need, RSmem& sm,
 
 // Register budget: the top-s kernel keeps its keys live across the radix
 // passes and is left at 2 waves per SIMD; the others fit 4.
-template <int KIND, int NPT>
-__global__ __launch_bounds__(kRT, KIND == kTopS ? 2 : 4) void x_update_reg_kernel(
+// WARM: the sparsity-targeted warm-up (Section 4.1) of the parameter.
+template <int KIND, int NPT, bool WARM>
+__global__ __launch_bounds__(kRT, (KIND == kTopS || WARM) ? 2 : 4) void x_update_reg_kernel(
     const float* __restrict__ V, int64_t ldv, int p, double param,
     float* __restrict__ X, int64_t ldx, int32_t* __restrict__ list_idx,
     float* __restrict__ list_val, int64_t ldl, int list_cap, StartState s,
-    double tol, int maxit, int32_t* __restrict__ colmark, const Plan* plan) {
+    double tol, int maxit, int32_t* __restrict__ colmark, const Plan* plan,
+    Warm wm) {
   static_assert(NPT % 4 == 0, "NPT must be a multiple of 4");
   __shared__ RSmem sm;
   const int64_t j = blockIdx.x;
@@ -680,6 +682,8 @@ __global__ __launch_bounds__(kRT, KIND == kTopS ? 2 : 4) void x_update_reg_kerne
   uint32_t thr_key = 0;
   int64_t cut = -1;
   double lam = 0.0;
+  const int itc = full ? s.iters[j] + 1 : 1;  // this x-update's number
+  const bool warming = WARM && itc <= wm.K;
   if (KIND == kTopS) {
     const uint32_t s_int = (uint32_t)((int64_t)param < (int64_t)p ? (int64_t)param : (int64_t)p);
     uint32_t above;
@@ -707,6 +711,8 @@ __global__ __launch_bounds__(kRT, KIND == kTopS ? 2 : 4) void x_update_reg_kerne
     }
     __syncthreads();
     cut = sm.cut;
+  } else if (KIND == kLambdaS && WARM && !warming) {
+    lam = wm.gam[j];  // frozen after the warm-up
   } else if (KIND == kLambdaS) {
     const double s_par = param;
     const double rs = sqrt(s_par);
@@ -904,6 +910,19 @@ __global__ __launch_bounds__(kRT, KIND == kTopS ? 2 : 4) void x_update_reg_kerne
       l = l > th ? th : l;
       lam = l;
     }
+  } else if (WARM && warming) {
+    // gamma for target nonzeros: the (target + 1)-th largest |v_i| (or its
+    // square for U_gamma), which the strict threshold then excludes
+    if ((int64_t)wm.target >= (int64_t)p) {
+      lam = 0.0;
+    } else {
+      uint32_t tk, above;
+      radix_select<NPT>(v, (uint32_t)wm.target + 1u, sm, &tk, &above);
+      const double t = (double)__uint_as_float(tk);
+      lam = KIND == kHardGamma ? t * t : t;
+    }
+  } else if (WARM) {
+    lam = wm.gam[j];
   } else {
     lam = param;
   }
@@ -982,6 +1001,7 @@ __global__ __launch_bounds__(kRT, KIND == kTopS ? 2 : 4) void x_update_reg_kerne
   }
 
   if (tid == 0) {
+    if (WARM && warming && KIND != kTopS) wm.gam[j] = lam;
     if (!full) {
       s.phi[j] = phi;
       s.nnz[j] = zero ? 0 : total;
@@ -994,7 +1014,8 @@ __global__ __launch_bounds__(kRT, KIND == kTopS ? 2 : 4) void x_update_reg_kerne
       s.nnz[j] = zero ? 0 : total;
       if (zero)
         s.status[j] = SPCA_ZERO;
-      else if (it >= 2 && tol >= 0.0 && phi <= (1.0 + tol) * prev)
+      else if (it >= 2 && tol >= 0.0 && (!WARM || it >= wm.K + 1) &&
+               phi <= (1.0 + tol) * prev)
         s.status[j] = SPCA_CONVERGED;
       else if (it >= maxit)
         s.status[j] = SPCA_MAXIT;
@@ -1006,33 +1027,38 @@ template <int KIND, int NPT>
 void launch_reg(hipStream_t st, double param, const float* V, int64_t ldv,
                 int64_t r, int64_t p, float* X, int64_t ldx, int32_t* li,
                 float* lv, int64_t ldl, int list_cap, StartState s, double tol,
-                int maxit, int32_t* colmark, const Plan* plan) {
-  hipLaunchKernelGGL((x_update_reg_kernel<KIND, NPT>), dim3((unsigned)r),
-                     dim3(kRT), 0, st, V, ldv, (int)p, param, X, ldx, li, lv,
-                     ldl, list_cap, s, tol, maxit, colmark, plan);
+                int maxit, int32_t* colmark, const Plan* plan, Warm wm) {
+  if (KIND != kTopS && wm.K > 0)
+    hipLaunchKernelGGL((x_update_reg_kernel<KIND, NPT, true>), dim3((unsigned)r),
+                       dim3(kRT), 0, st, V, ldv, (int)p, param, X, ldx, li, lv,
+                       ldl, list_cap, s, tol, maxit, colmark, plan, wm);
+  else
+    hipLaunchKernelGGL((x_update_reg_kernel<KIND, NPT, false>), dim3((unsigned)r),
+                       dim3(kRT), 0, st, V, ldv, (int)p, param, X, ldx, li, lv,
+                       ldl, list_cap, s, tol, maxit, colmark, plan, wm);
 }
 
 template <int KIND>
 void launch_kind(hipStream_t st, double param, const float* V, int64_t ldv,
                  int64_t r, int64_t p, float* X, int64_t ldx, int32_t* li,
                  float* lv, int64_t ldl, int list_cap, StartState s, double tol,
-                 int maxit, int32_t* colmark, const Plan* plan) {
+                 int maxit, int32_t* colmark, const Plan* plan, Warm wm) {
   const bool aligned = ldv % 4 == 0 && ldx % 4 == 0 &&
                        (uintptr_t)V % 16 == 0 && (uintptr_t)X % 16 == 0;
   const int64_t per = ceil_div(p, kRT);
   if (aligned && per <= 48) {
     if (per <= 8)
-      launch_reg<KIND, 8>(st, param, V, ldv, r, p, X, ldx, li, lv, ldl, list_cap, s, tol, maxit, colmark, plan);
+      launch_reg<KIND, 8>(st, param, V, ldv, r, p, X, ldx, li, lv, ldl, list_cap, s, tol, maxit, colmark, plan, wm);
     else if (per <= 16)
-      launch_reg<KIND, 16>(st, param, V, ldv, r, p, X, ldx, li, lv, ldl, list_cap, s, tol, maxit, colmark, plan);
+      launch_reg<KIND, 16>(st, param, V, ldv, r, p, X, ldx, li, lv, ldl, list_cap, s, tol, maxit, colmark, plan, wm);
     else if (per <= 24)
-      launch_reg<KIND, 24>(st, param, V, ldv, r, p, X, ldx, li, lv, ldl, list_cap, s, tol, maxit, colmark, plan);
+      launch_reg<KIND, 24>(st, param, V, ldv, r, p, X, ldx, li, lv, ldl, list_cap, s, tol, maxit, colmark, plan, wm);
     else if (per <= 32)
-      launch_reg<KIND, 32>(st, param, V, ldv, r, p, X, ldx, li, lv, ldl, list_cap, s, tol, maxit, colmark, plan);
+      launch_reg<KIND, 32>(st, param, V, ldv, r, p, X, ldx, li, lv, ldl, list_cap, s, tol, maxit, colmark, plan, wm);
     else if (per <= 40)
-      launch_reg<KIND, 40>(st, param, V, ldv, r, p, X, ldx, li, lv, ldl, list_cap, s, tol, maxit, colmark, plan);
+      launch_reg<KIND, 40>(st, param, V, ldv, r, p, X, ldx, li, lv, ldl, list_cap, s, tol, maxit, colmark, plan, wm);
     else
-      launch_reg<KIND, 48>(st, param, V, ldv, r, p, X, ldx, li, lv, ldl, list_cap, s, tol, maxit, colmark, plan);
+      launch_reg<KIND, 48>(st, param, V, ldv, r, p, X, ldx, li, lv, ldl, list_cap, s, tol, maxit, colmark, plan, wm);
     return;
   }
   if (p <= kStageMax) {
@@ -1053,27 +1079,27 @@ void x_update(hipStream_t st, int fid, double s_or_gamma, const float* V,
               int64_t ldv, int64_t r, int64_t p, float* X, int64_t ldx,
               int32_t* list_idx, float* list_val, int64_t ldl, int list_cap,
               StartState s, double tol, int32_t maxit, int32_t* colmark,
-              const Plan* plan, void* wide) {
+              const Plan* plan, void* wide, Warm wm) {
   if (wide != nullptr &&
       x_update_wide(st, fid, s_or_gamma, V, ldv, r, p, X, ldx, list_idx, list_val,
-                    ldl, list_cap, s, tol, maxit, colmark, plan, wide))
+                    ldl, list_cap, s, tol, maxit, colmark, plan, wide, wm))
     return;
   switch (xkind_of(fid)) {
     case kTopS:
       launch_kind<kTopS>(st, s_or_gamma, V, ldv, r, p, X, ldx, list_idx,
-                         list_val, ldl, list_cap, s, tol, maxit, colmark, plan);
+                         list_val, ldl, list_cap, s, tol, maxit, colmark, plan, wm);
       break;
     case kLambdaS:
       launch_kind<kLambdaS>(st, s_or_gamma, V, ldv, r, p, X, ldx, list_idx,
-                            list_val, ldl, list_cap, s, tol, maxit, colmark, plan);
+                            list_val, ldl, list_cap, s, tol, maxit, colmark, plan, wm);
       break;
     case kHardGamma:
       launch_kind<kHardGamma>(st, s_or_gamma, V, ldv, r, p, X, ldx, list_idx,
-                              list_val, ldl, list_cap, s, tol, maxit, colmark, plan);
+                              list_val, ldl, list_cap, s, tol, maxit, colmark, plan, wm);
       break;
     case kSoftGamma:
       launch_kind<kSoftGamma>(st, s_or_gamma, V, ldv, r, p, X, ldx, list_idx,
-                              list_val, ldl, list_cap, s, tol, maxit, colmark, plan);
+                              list_val, ldl, list_cap, s, tol, maxit, colmark, plan, wm);
       break;
   }
 }

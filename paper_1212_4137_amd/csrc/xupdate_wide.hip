@@ -69,6 +69,9 @@ struct Wide {
   uint32_t* lmax;   // r x nch (largest key per chunk)
   float* cand;      // r x kMaxCandW
   int nch;
+  int32_t warm_K;   // sparsity-targeted warm-up (0: off)
+  int32_t warm_target;
+  double* gam;      // r: parameter of each start under the warm-up
 };
 
 Wide carve_wide(void* base, int64_t r, int64_t p) {
@@ -89,6 +92,9 @@ Wide carve_wide(void* base, int64_t r, int64_t p) {
   w.lpart = (double*)take(sizeof(double) * 4 * r * w.nch);
   w.lmax = (uint32_t*)take(sizeof(uint32_t) * r * w.nch);
   w.cand = (float*)take(sizeof(float) * kMaxCandW * r);
+  w.warm_K = 0;
+  w.warm_target = 0;
+  w.gam = nullptr;
   return w;
 }
 
@@ -255,8 +261,8 @@ struct Keep {
         int tot;
         rank = before + block_exclusive_scan(eq, scan, &tot);
       }
-    } else if (KIND == kLambdaS) {
-      lam = w.rows[j].lam;
+    } else if (KIND == kLambdaS || w.warm_K > 0) {
+      lam = w.rows[j].lam;  // per row: lambda_s, or gamma under the warm-up
     } else {
       lam = param;
     }
@@ -304,7 +310,7 @@ __global__ __launch_bounds__(kWT) void wide_partial_kernel(
     if (keep(v[k], base + k < p, &wv)) {
       ++cnt;
       acc[0] += wv * wv;
-      if (KIND == kHardGamma) acc[1] += wv * wv - param;
+      if (KIND == kHardGamma) acc[1] += wv * wv - keep.lam;
     }
   }
   block_sum_n<double, 2>(acc, dred);
@@ -354,6 +360,7 @@ __global__ __launch_bounds__(64) void wide_row_kernel(
     s.nnz[j] = zero ? 0 : total;
   } else {
     const int it = s.iters[j] + 1;
+    if (KIND != kTopS && w.warm_K > 0 && it <= w.warm_K) w.gam[j] = R->lam;
     const double prev = s.phi[j];
     s.iters[j] = it;
     s.phi_prev[j] = prev;
@@ -361,7 +368,8 @@ __global__ __launch_bounds__(64) void wide_row_kernel(
     s.nnz[j] = zero ? 0 : total;
     if (zero)
       s.status[j] = SPCA_ZERO;
-    else if (it >= 2 && tol >= 0.0 && phi <= (1.0 + tol) * prev)
+    else if (it >= 2 && tol >= 0.0 && (w.warm_K == 0 || it >= w.warm_K + 1) &&
+             phi <= (1.0 + tol) * prev)
       s.status[j] = SPCA_CONVERGED;
     else if (it >= maxit)
       s.status[j] = SPCA_MAXIT;
@@ -486,6 +494,11 @@ __global__ __launch_bounds__(64) void lam_row_kernel(int64_t r, StartState s, Wi
   const int64_t j = (int64_t)blockIdx.x * 64 + threadIdx.x;
   if (j >= r || !row_live(s, j)) return;
   WRow* R = w.rows + j;
+  if (w.warm_K > 0 && s.status != nullptr && s.iters[j] + 1 > w.warm_K) {
+    R->lmode = 3;  // frozen after the warm-up
+    R->lam = w.gam[j];
+    return;
+  }
   double a[4] = {0.0, 0.0, 0.0, 0.0};
   int64_t nc = 0;
   uint32_t mk = 0u;
@@ -571,7 +584,7 @@ __global__ __launch_bounds__(kWT) void lam_solve_kernel(
   if (!row_live(s, j)) return;
   WRow* R = w.rows + j;
   int mode = R->lmode;
-  if (mode == 0) return;
+  if (mode == 0 || mode == 3) return;
   const int tid = threadIdx.x;
   const double rs = sqrt(s_par);
   if (mode == 1) {
@@ -729,6 +742,25 @@ __global__ __launch_bounds__(kWT) void lam_solve_kernel(
   }
 }
 
+// warm-up of the penalties: gamma of the row from the (target + 1)-th largest
+// key found by the digit passes, or the frozen value
+template <int KIND>
+__global__ __launch_bounds__(64) void gam_row_kernel(int64_t r, int p, StartState s,
+                                                     Wide w) {
+  const int64_t j = (int64_t)blockIdx.x * 64 + threadIdx.x;
+  if (j >= r || !row_live(s, j)) return;
+  WRow* R = w.rows + j;
+  const bool warming = s.status == nullptr || s.iters[j] + 1 <= w.warm_K;
+  if (!warming) {
+    R->lam = w.gam[j];
+  } else if ((int64_t)w.warm_target >= (int64_t)p) {
+    R->lam = 0.0;
+  } else {
+    const double t = (double)__uint_as_float(R->prefix);
+    R->lam = KIND == kHardGamma ? t * t : t;
+  }
+}
+
 template <int KIND>
 void launch_wide_kind(hipStream_t st, double param, const float* V,
                       int64_t ldv, int64_t r, int64_t p, float* X, int64_t ldx,
@@ -737,9 +769,11 @@ void launch_wide_kind(hipStream_t st, double param, const float* V,
                       const Plan* plan, const Wide& w) {
   const dim3 g2((unsigned)w.nch, (unsigned)r);
   const int ip = (int)p;
-  if (KIND == kTopS || KIND == kLambdaS) {
+  const bool warm_gamma = (KIND == kHardGamma || KIND == kSoftGamma) && w.warm_K > 0;
+  if (KIND == kTopS || KIND == kLambdaS || warm_gamma) {
     const int lm = KIND == kLambdaS ? 1 : 0;
-    const int32_t need = lm ? 0 : (int32_t)((int64_t)param < p ? (int64_t)param : p);
+    const int64_t want = warm_gamma ? (int64_t)w.warm_target + 1 : (int64_t)param;
+    const int32_t need = lm ? 0 : (int32_t)(want < p ? want : p);
     const dim3 g1((unsigned)r);
     hipLaunchKernelGGL(wide_hist_kernel<0>, g2, dim3(kWT), 0, st, V, ldv, ip, s, w);
     hipLaunchKernelGGL(wide_decide_kernel<0>, g1, dim3(kWT), 0, st, s, w, need, lm, param, ip);
@@ -750,6 +784,9 @@ void launch_wide_kind(hipStream_t st, double param, const float* V,
   }
   if (KIND == kTopS)
     hipLaunchKernelGGL(wide_eqcount_kernel, g2, dim3(kWT), 0, st, V, ldv, ip, s, w);
+  if (warm_gamma)
+    hipLaunchKernelGGL(gam_row_kernel<KIND>, dim3((unsigned)ceil_div(r, 64)), dim3(64), 0,
+                       st, r, ip, s, w);
   if (KIND == kLambdaS) {
     hipLaunchKernelGGL(lam_stats_kernel, g2, dim3(kWT), 0, st, V, ldv, ip, s, w);
     hipLaunchKernelGGL(lam_row_kernel, dim3((unsigned)ceil_div(r, 64)), dim3(64), 0, st,
@@ -788,12 +825,15 @@ bool x_update_wide(hipStream_t st, int fid, double s_or_gamma, const float* V,
                    int64_t ldv, int64_t r, int64_t p, float* X, int64_t ldx,
                    int32_t* list_idx, float* list_val, int64_t ldl, int list_cap,
                    StartState s, double tol, int32_t maxit, int32_t* colmark,
-                   const Plan* plan, void* scratch) {
+                   const Plan* plan, void* scratch, Warm wm) {
   const bool aligned = ldv % 4 == 0 && ldx % 4 == 0 && (uintptr_t)V % 16 == 0 &&
                        (uintptr_t)X % 16 == 0;
   if (scratch == nullptr || !aligned || x_update_wide_bytes(fid, r, p) == 0)
     return false;
-  const Wide w = carve_wide(scratch, r, p);
+  Wide w = carve_wide(scratch, r, p);
+  w.warm_K = wm.K;
+  w.warm_target = wm.target;
+  w.gam = wm.gam;
   switch (xkind_of(fid)) {
     case kTopS:
       launch_wide_kind<kTopS>(st, s_or_gamma, V, ldv, r, p, X, ldx, list_idx, list_val,
