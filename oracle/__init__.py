@@ -65,6 +65,8 @@ def _load():
     lib.orc_am_multi_warm.argtypes = [P, i64, i64, i64, ctypes.c_int, d, i64, i32, P, i32,
                                       d, i32, ctypes.c_int, P, P, P, P, P, P]
     lib.orc_am_multi_warm.restype = i32
+    lib.orc_deflate.argtypes = [P, i64, i64, i64, P, P, i64]
+    lib.orc_deflate.restype = None
     lib.orc_max_norm_column.argtypes = [P, i64, i64, i64]
     lib.orc_max_norm_column.restype = i64
     _lib = lib
@@ -219,6 +221,34 @@ def am_multi_warm(A, fid, s_or_gamma, X0, tol, maxit, warm_iters, target_s=0,
                                      _ptr(par), _ptr(iters), _ptr(status))
     return {"best": int(best), "X": X, "f": f, "ev": ev, "param": par, "iters": iters,
             "status": status}
+
+
+def deflate(A, x):
+    """A (I - x x^T) for a unit loading x (projection deflation)."""
+    A64, lda = _colmajor(A)
+    n, p = A64.shape
+    x = np.ascontiguousarray(np.asarray(x, dtype=np.float64))
+    out = np.zeros((p, n)).T  # column-major n x p
+    _load().orc_deflate(_ptr(A64), n, p, lda, _ptr(x), _ptr(out), n)
+    return out
+
+
+def am_components(A, fid, s_or_gamma, X0, ncomp, tol, maxit, nthreads=1):
+    """Several sparse loadings: component t is the multi-start AM solution
+    on A deflated by the loadings found before it (projection deflation),
+    from the same starts.  Returns per component the best start, f and
+    explained variance on its deflated matrix, and the loading."""
+    At = np.asfortranarray(np.asarray(A, dtype=np.float64))
+    comps = []
+    for _ in range(ncomp):
+        res = am_multi(At, fid, s_or_gamma, X0, tol, maxit, nthreads=nthreads)
+        b = res["best"]
+        x = res["X"][b].copy()
+        comps.append({"best": b, "f": res["f"][b], "ev": res["ev"][b], "x": x,
+                      "f_all": res["f"]})
+        if np.any(x):
+            At = deflate(At, x)
+    return comps
 
 
 def max_norm_column(A):

@@ -536,6 +536,15 @@ int32_t orc_am_multi_warm(const double* A, int64_t n, int64_t p, int64_t lda,
   return best;
 }
 
+void orc_deflate(const double* A, int64_t n, int64_t p, int64_t lda,
+                 const double* x, double* out, int64_t ldo) {
+  double* u = (double*)malloc(sizeof(double) * (size_t)n);
+  matvec(A, n, p, lda, x, u);
+  for (int64_t j = 0; j < p; ++j)
+    for (int64_t i = 0; i < n; ++i) out[j * ldo + i] = A[j * lda + i] - u[i] * x[j];
+  free(u);
+}
+
 int64_t orc_max_norm_column(const double* A, int64_t n, int64_t p,
                             int64_t lda) {
   int64_t best = 0;

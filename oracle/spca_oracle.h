@@ -104,6 +104,14 @@ int32_t orc_am_multi_warm(const double* A, int64_t n, int64_t p, int64_t lda,
                           double* f_out, double* ev_out, double* param_out,
                           int32_t* iters_out, int32_t* status_out);
 
+/* Deflation for further components (the paper obtains them by replacing A
+ * with a deflated matrix; the scheme is the projection deflation of the
+ * data matrix): out = A (I - x x^T) = A - (A x) x^T, FP64, out n x p with
+ * leading dimension ldo >= n.  Applied once per found loading x (unit
+ * norm), in the order the loadings were found.                            */
+void orc_deflate(const double* A, int64_t n, int64_t p, int64_t lda,
+                 const double* x, double* out, int64_t ldo);
+
 /* argmax_i ||a_i||_2 over the columns of A, ties to the lowest index.     */
 int64_t orc_max_norm_column(const double* A, int64_t n, int64_t p,
                             int64_t lda);
