@@ -160,6 +160,14 @@ typedef struct {
    * variance.  0 disables it.  FP32 only, not with total_starts > r.      */
   int32_t warmup_iters;
   int32_t target_nnz;   /* penalties under warm-up: 1..p                    */
+  /* Deflation for a further component: the solve works on
+   * A (I - x_1 x_1^T) ... (I - x_k x_k^T) for the deflate_k loadings in
+   * deflate_X (device, deflate_k x p, FP64, unit norm, in the order they
+   * were found), applied implicitly.  0..16 loadings; FP32 only, not with
+   * total_starts > r.  f and the explained variance are those of the
+   * deflated matrix.                                                       */
+  const double* deflate_X;
+  int32_t deflate_k;
 } spca_solve_opts;
 
 /* SPCA_FLAG_GRAPH: capture check_every iterations once per solve into a HIP
@@ -205,6 +213,17 @@ typedef struct {
    * or gamma (5..8) of each start under the warm-up; untouched otherwise */
   double* param_per_start;
 } spca_outputs;
+
+/* Several components, one after another: component c is the solve of
+ * (prob, opts) on A deflated by the loadings of components 0..c-1 (the
+ * paper's deflation, read as projection deflation of the data matrix), from
+ * the same starts.  X_out: host ncomp x p FP64 (the loadings); res: host
+ * ncomp results.  opts->deflate_X / deflate_k must be unset (NULL / 0);
+ * 1 <= ncomp <= 16.  Allocates and frees a small device buffer for the
+ * loadings and synchronizes the stream.                                   */
+int spca_am_components(spca_ctx* ctx, void* stream, const spca_problem* prob,
+                       const spca_solve_opts* opts, int32_t ncomp, double* X_out,
+                       spca_result* res);
 
 /* Full solve on a caller-chosen context and HIP stream (hipStream_t passed
  * as void*; NULL = null stream).  Same semantics as spca_am_solve.

@@ -28,7 +28,7 @@ EXPORTED = ("spca_am_solve", "spca_am_solve_ex", "spca_ctx_create",
             "spca_ctx_set_workspace", "spca_request_footprint", "spca_server_create",
             "spca_server_submit", "spca_server_poll", "spca_server_stats",
             "spca_server_destroy", "spca_tune_table_export", "spca_tune_table_import",
-            "spca_tune_table_clear", "spca_gemm_nt_bf16_shape")
+            "spca_tune_table_clear", "spca_gemm_nt_bf16_shape", "spca_am_components")
 
 
 class SpcaError(RuntimeError):
@@ -57,7 +57,8 @@ class SolveOpts(ctypes.Structure):
                 ("maxit", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("polish_maxit", ctypes.c_int32), ("check_every", ctypes.c_int32),
                 ("flags", ctypes.c_int32), ("total_starts", ctypes.c_int32),
-                ("warmup_iters", ctypes.c_int32), ("target_nnz", ctypes.c_int32)]
+                ("warmup_iters", ctypes.c_int32), ("target_nnz", ctypes.c_int32),
+                ("deflate_X", ctypes.c_void_p), ("deflate_k", ctypes.c_int32)]
 
 
 class Outputs(ctypes.Structure):
@@ -153,6 +154,10 @@ def load():
         lib.spca_tune_table_import.restype = ctypes.c_int
         lib.spca_tune_table_clear.argtypes = []
         lib.spca_tune_table_clear.restype = ctypes.c_int
+        lib.spca_am_components.argtypes = [P, P, ctypes.POINTER(Problem),
+                                           ctypes.POINTER(SolveOpts), i32, P,
+                                           ctypes.POINTER(Result)]
+        lib.spca_am_components.restype = ctypes.c_int
         lib.spca_ctx_set_workspace.argtypes = [P, P, ctypes.c_size_t]
         lib.spca_ctx_set_workspace.restype = ctypes.c_int
         lib.spca_request_footprint.argtypes = [ctypes.POINTER(Request)]
@@ -584,3 +589,37 @@ def tune_table_import(text):
 
 def tune_table_clear():
     _check(load().spca_tune_table_clear())
+
+
+def am_components(A, formulation, s_or_gamma, X0, ncomp, tol=1e-8, maxit=200, *,
+                  check_every=8, flags=0, ctx=None, stream=None, warmup_iters=0,
+                  target_nnz=0):
+    """Several components (``spca_am_components``): component c solves the
+    problem on A deflated by the loadings of components 0..c-1, from the
+    same starts.  Returns a list of dicts (objective, explained variance,
+    best start, nnz, iterations, status, x, support)."""
+    import torch
+
+    _require_gpu_tensor(A, "A", torch.float32)
+    n, p, lda = colmajor_view(A)
+    _require_gpu_tensor(X0, "X0", torch.float32)
+    if X0.dim() != 2 or X0.shape[1] != p or not X0.is_contiguous():
+        raise ValueError("X0 must be a contiguous (r, p) tensor")
+    r = X0.shape[0]
+    ctx = ctx or default_context(A.device.index or 0)
+    X = np.zeros((ncomp, p), dtype=np.float64)
+    res = (Result * ncomp)()
+    prob = Problem(A.data_ptr(), n, p, lda, int(formulation), float(s_or_gamma))
+    opts = SolveOpts(X0.data_ptr(), r, float(tol), int(maxit), PREC_FP32, 0,
+                     int(check_every), int(flags), 0, int(warmup_iters), int(target_nnz),
+                     None, 0)
+    _check(load().spca_am_components(ctx.handle, _stream_ptr(stream), ctypes.byref(prob),
+                                     ctypes.byref(opts), int(ncomp), _np_ptr(X), res))
+    out = []
+    for c in range(ncomp):
+        x = X[c]
+        out.append({"objective": res[c].objective, "explained_variance": res[c].explained_var,
+                    "best_start": res[c].best_start, "nnz": res[c].nnz,
+                    "iters": res[c].iters, "status": res[c].status, "x": x.copy(),
+                    "support": np.flatnonzero(x)})
+    return out

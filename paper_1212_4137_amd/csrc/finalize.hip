@@ -41,7 +41,7 @@ __global__ __launch_bounds__(kFT) void final_matvec_kernel(
     const float* __restrict__ A, int64_t lda, int64_t n,
     const int32_t* __restrict__ list_idx, const float* __restrict__ list_val,
     int64_t ldl, StartState s, const double* __restrict__ xnorm,
-    double* partial, int nchunks, const int32_t* only) {
+    double* partial, int nchunks, const int32_t* only, Defl defl) {
   __shared__ int32_t sidx[kFStage];
   __shared__ double sval[kFStage];
   __shared__ double red[2 * 5];
@@ -75,6 +75,10 @@ __global__ __launch_bounds__(kFT) void final_matvec_kernel(
         u += (double)A[i + (int64_t)sidx[t] * lda] * sval[t];
     }
   }
+  // deflated problem: A_k x = A x - sum_l alpha_l A x_l
+  if (defl.k > 0 && i < n)
+    for (int l = 0; l < defl.k; ++l)
+      u -= defl.alpha[j * kMaxDefl + l] * defl.scores[i * kMaxDefl + l];
   double acc[2] = {u * u, fabs(u)};
   block_sum_n<double, 2>(acc, red);
   if (threadIdx.x == 0) {
@@ -178,13 +182,13 @@ void evaluate_rows(hipStream_t st, int fid, double s_or_gamma, const float* A,
                    int64_t lda, int64_t n, const int32_t* list_idx,
                    const float* list_val, int64_t ldl, StartState s, int64_t r,
                    double* partial, double* f, double* ev, double* xnorm,
-                   const int32_t* only, const double* gam) {
+                   const int32_t* only, const double* gam, Defl defl) {
   const int nchunks = (int)ceil_div(n, kFT);
   hipLaunchKernelGGL(x_norms_kernel, dim3((unsigned)r), dim3(256), 0, st,
                      list_val, ldl, s, r, xnorm, only);
   hipLaunchKernelGGL(final_matvec_kernel, dim3((unsigned)r, (unsigned)nchunks),
                      dim3(kFT), 0, st, A, lda, n, list_idx, list_val, ldl, s,
-                     xnorm, partial, nchunks, only);
+                     xnorm, partial, nchunks, only, defl);
   hipLaunchKernelGGL(objective_kernel, dim3((unsigned)ceil_div(r, 256)),
                      dim3(256), 0, st, fid, s_or_gamma, s, r, partial, nchunks,
                      xnorm, f, ev, only, gam);
@@ -195,9 +199,9 @@ void finalize(hipStream_t st, int fid, double s_or_gamma, const float* A,
               const float* list_val, int64_t ldl, StartState s, int64_t r,
               double* partial, double* f, double* ev, double* xnorm,
               int32_t* best, double* x_out, int32_t* support_out,
-              const double* gam, bool by_ev) {
+              const double* gam, bool by_ev, Defl defl) {
   evaluate_rows(st, fid, s_or_gamma, A, lda, n, list_idx, list_val, ldl, s, r,
-                partial, f, ev, xnorm, nullptr, gam);
+                partial, f, ev, xnorm, nullptr, gam, defl);
   hipLaunchKernelGGL(best_kernel, dim3(1), dim3(1024), 0, st, by_ev ? ev : f, s, r, p,
                      list_idx, list_val, ldl, xnorm, best, x_out, support_out);
 }

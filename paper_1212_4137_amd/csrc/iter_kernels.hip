@@ -207,7 +207,7 @@ __global__ __launch_bounds__(1024) void plan_kernel(
     StartState s, int64_t r, int64_t n, int64_t p, int list_cap,
     int dense_only, int dense_splits, int64_t ucap,
     const int32_t* __restrict__ colmark, int32_t* __restrict__ ulist,
-    Plan* plan) {
+    Plan* plan, int no_fused) {
   __shared__ int64_t red[2 * 17];
   __shared__ int32_t mred[17];
   __shared__ int scan[20];
@@ -260,8 +260,9 @@ __global__ __launch_bounds__(1024) void plan_kernel(
     // pays the separate y-update
     const double wg1 = (double)v[0], wgr = (double)v[0] * ceil(nd / 1024.0);
     const double list_us =
-        mx <= list_cap ? (double)v[1] * nd * 4.0 / (list_bw * (wg1 < 512.0 ? wg1 / 512.0 : 1.0)) + 3.0
-                       : 1e300;
+        mx <= list_cap && !no_fused
+            ? (double)v[1] * nd * 4.0 / (list_bw * (wg1 < 512.0 ? wg1 / 512.0 : 1.0)) + 3.0
+            : 1e300;
     const double rows_us =
         mx <= list_cap ? (double)v[1] * nd * 4.0 / (list_bw * (wgr < 512.0 ? wgr / 512.0 : 1.0)) + 8.0
                        : 1e300;
@@ -673,10 +674,10 @@ void init_state(hipStream_t st, StartState s, int64_t r) {
 
 void plan_next(hipStream_t st, StartState s, int64_t r, int64_t n, int64_t p,
                int list_cap, int dense_only, int dense_splits, int64_t ucap,
-               const int32_t* colmark, int32_t* ulist, Plan* plan) {
+               const int32_t* colmark, int32_t* ulist, Plan* plan, int no_fused) {
   hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(1024), 0, st, s, r, n, p,
                      list_cap, dense_only, dense_splits, ucap, colmark, ulist,
-                     plan);
+                     plan, no_fused);
 }
 
 void init_plan(hipStream_t st, Plan* plan, int dense_splits) {

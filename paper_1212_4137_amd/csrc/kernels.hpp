@@ -61,6 +61,33 @@ struct Warm {
   double* gam = nullptr;  // r: the parameter of each start
 };
 
+// Deflation by k previously found loadings (projection deflation of the
+// data matrix), applied implicitly: see deflate.hip.
+constexpr int kMaxDefl = 16;
+struct Defl {
+  int k = 0;
+  int32_t* idx = nullptr;   // k x p: support of each loading
+  double* val = nullptr;    // k x p: its values
+  int32_t* cnt = nullptr;   // k: support sizes
+  double* gram = nullptr;   // kMaxDefl x kMaxDefl: x_i^T x_l
+  double* scores = nullptr; // n x kMaxDefl: A x_i (FP64)
+  double* alpha = nullptr;  // r x kMaxDefl: coefficients of the final evaluation
+};
+size_t deflate_bytes(int64_t n, int64_t p, int64_t r, int k);
+Defl carve_deflate(void* base, int64_t n, int64_t p, int64_t r, int k);
+// lists, Gram matrix and FP64 scores of the loadings Xd (device k x p FP64)
+void deflate_setup(hipStream_t st, const double* Xd, const float* A, int64_t lda,
+                   int64_t n, int64_t p, Defl d);
+// u -= sum alpha_i A x_i (first partial of U; not in the fused list mode)
+void deflate_u(hipStream_t st, const float* X, int64_t ldx, int64_t p, float* U,
+               int64_t ldu, int64_t n, int64_t r, StartState s, const Plan* plan, Defl d);
+// v -= sum beta_i x_i
+void deflate_v(hipStream_t st, float* V, int64_t ldv, int64_t p, int64_t r, StartState s,
+               Defl d);
+// alpha of each start's unit iterate, for the final evaluation
+void deflate_final_alpha(hipStream_t st, const float* X, int64_t ldx, int64_t p,
+                         int64_t r, Defl d);
+
 // Tile shape (index into the compiled shapes) and K split of one product.
 struct GemmPlan {
   int shape;
@@ -156,7 +183,7 @@ void init_state(hipStream_t st, StartState s, int64_t r);
 // start to have at most list_cap nonzeros (only those keep lists).
 void plan_next(hipStream_t st, StartState s, int64_t r, int64_t n, int64_t p,
                int list_cap, int dense_only, int dense_splits, int64_t ucap,
-               const int32_t* colmark, int32_t* ulist, Plan* plan);
+               const int32_t* colmark, int32_t* ulist, Plan* plan, int no_fused = 0);
 
 // Resets the plan (epoch 1, dense mode, zero statistics).
 void init_plan(hipStream_t st, Plan* plan, int dense_splits);
@@ -238,14 +265,15 @@ void finalize(hipStream_t st, int fid, double s_or_gamma, const float* A,
               const float* list_val, int64_t ldl, StartState s, int64_t r,
               double* partial, double* f, double* ev, double* xnorm,
               int32_t* best, double* x_out, int32_t* support_out,
-              const double* gam = nullptr, bool by_ev = false);
+              const double* gam = nullptr, bool by_ev = false, Defl defl = Defl{});
 // The FP64 objective and explained variance of the rows with only[j] != 0
 // (the first three steps of finalize); other rows are left untouched.
 void evaluate_rows(hipStream_t st, int fid, double s_or_gamma, const float* A,
                    int64_t lda, int64_t n, const int32_t* list_idx,
                    const float* list_val, int64_t ldl, StartState s, int64_t r,
                    double* partial, double* f, double* ev, double* xnorm,
-                   const int32_t* only, const double* gam = nullptr);
+                   const int32_t* only, const double* gam = nullptr,
+                   Defl defl = Defl{});
 
 // On-the-fly replacement of finished starts (Section 4.3): state of the
 // slots and of the total_starts starts that flow through them.

@@ -492,6 +492,13 @@ int spca_am_solve_ex(spca_ctx* ctx, void* stream, const spca_problem* prob,
       SPCA_REQUIRE(opts->target_nnz >= 1 && opts->target_nnz <= p,
                    "target_nnz must be in 1..p for the penalty warm-up");
   }
+  SPCA_REQUIRE(opts->deflate_k >= 0 && opts->deflate_k <= kMaxDefl,
+               "deflate_k must be in 0..16");
+  const int dk = opts->deflate_k;
+  if (dk > 0) {
+    SPCA_REQUIRE(opts->deflate_X != nullptr, "deflate_X must be set when deflate_k > 0");
+    SPCA_REQUIRE(!bf16 && !otf, "deflation runs in FP32 without total_starts > r");
+  }
   if (otf) {
     SPCA_REQUIRE(!bf16, "on-the-fly replacement runs in FP32 only");
     SPCA_REQUIRE(opts->X0 != nullptr, "on-the-fly replacement needs X0 (total_starts rows)");
@@ -505,7 +512,8 @@ int spca_am_solve_ex(spca_ctx* ctx, void* stream, const spca_problem* prob,
   const bool copy_a = (lda % 4) != 0 || ((uintptr_t)prob->A % 16) != 0;
   Layout L = make_layout(n, p, r, copy_a, bf16);
   const size_t otf_off = (size_t)round_up((int64_t)solve_bytes(L, n, p, r), 256);
-  rc = ensure_workspace(ctx, st, otf ? otf_off + otf_bytes(r, p, l) : solve_bytes(L, n, p, r));
+  rc = ensure_workspace(ctx, st, otf ? otf_off + otf_bytes(r, p, l)
+                                : otf_off + deflate_bytes(n, p, r, dk));
   if (rc != SPCA_OK) return rc;
   char* base = (char*)ctx->ws;
   float* At = (float*)(base + L.off_At);
@@ -540,6 +548,8 @@ int spca_am_solve_ex(spca_ctx* ctx, void* stream, const spca_problem* prob,
   void* wide = L.wide_bytes ? (void*)(base + L.off_wide) : nullptr;
   Otf o{};
   if (otf) o = carve_otf(base + otf_off, r, p, l);
+  Defl defl{};
+  if (dk > 0) defl = carve_deflate(base + otf_off, n, p, r, dk);
   double* gam = (double*)(base + L.off_gam);
   Warm wm;
   if (warm) {
@@ -574,6 +584,10 @@ int spca_am_solve_ex(spca_ctx* ctx, void* stream, const spca_problem* prob,
     transpose_f32(st, A, ldA, At, L.ldat, n, p);
   }
   SPCA_LAUNCH_CHECK("layout copies of A");
+  if (dk > 0) {
+    deflate_setup(st, opts->deflate_X, A, ldA, n, p, defl);
+    SPCA_LAUNCH_CHECK("deflation setup");
+  }
 
   // starting points
   if (opts->X0 != nullptr) {
@@ -631,7 +645,7 @@ int spca_am_solve_ex(spca_ctx* ctx, void* stream, const spca_problem* prob,
   // (at most ucap columns)
   auto plan_iter = [&]() {
     plan_next(st, s, r, n, p, list_cap, dense_only, L.plan_ax.splits, ucap_eff,
-              colmark, ulist, plan);
+              colmark, ulist, plan, dk > 0 ? 1 : 0);
   };
   plan_iter();
   if (bf16) rows_to_bf16(st, X, L.ldx, r, p, Xb, L.ldxb, plan);
@@ -665,6 +679,7 @@ int spca_am_solve_ex(spca_ctx* ctx, void* stream, const spca_problem* prob,
       sparse_ax_rows_bf16(q, Ab, L.ldab, n, li, lv, L.ldx, U, L.ldu, r, s, plan);
     else
       sparse_ax_rows(q, A, ldA, n, li, lv, L.ldx, U, L.ldu, r, s, plan);
+    if (dk > 0) deflate_u(q, X, L.ldx, p, U, L.ldu, n, r, s, plan, defl);
     y_update(q, fid, U, r * L.ldu, Y, L.ldu, r, n, s, plan, bf16 ? Yb : nullptr,
              L.ldyb);
     if (bf16)
@@ -681,6 +696,7 @@ int spca_am_solve_ex(spca_ctx* ctx, void* stream, const spca_problem* prob,
       gemm_nt_f32(q, Y, L.ldu, A, ldA, V, L.ldx, r, p, n, nullptr, 0,
                   L.plan_aty, 0);
     if (tm) SPCA_HIP_TRY(ctx->t_aty.mark(q));
+    if (dk > 0) deflate_v(q, V, L.ldx, p, r, s, defl);
     if (tm) SPCA_HIP_TRY(ctx->t_xup.mark(q));
     x_update(q, fid, sg, V, L.ldx, r, p, X, L.ldx, li, lv, L.ldx, list_cap, s,
              opts->tol, maxit, colmark, plan, wide, wm);
@@ -689,7 +705,7 @@ int spca_am_solve_ex(spca_ctx* ctx, void* stream, const spca_problem* prob,
       otf_step(q, fid, sg, A, ldA, n, p, X, L.ldx, opts->X0, li, lv, L.ldx, s, r,
                partial, fj, evj, xnorm, o, 0);
     plan_next(q, s, r, n, p, list_cap, dense_only, L.plan_ax.splits, ucap_eff,
-              colmark, ulist, plan);
+              colmark, ulist, plan, dk > 0 ? 1 : 0);
     if (bf16) rows_to_bf16(q, X, L.ldx, r, p, Xb, L.ldxb, plan);
     SPCA_LAUNCH_CHECK("AM iteration");
     return SPCA_OK;
@@ -770,8 +786,10 @@ int spca_am_solve_ex(spca_ctx* ctx, void* stream, const spca_problem* prob,
     // under the penalty warm-up every start has its own gamma: f uses it,
     // and the best start is the one with the largest explained variance
     const bool per_start_gamma = warm && fid >= 5;
+    if (dk > 0) deflate_final_alpha(st, X, L.ldx, p, r, defl);
     finalize(st, fid, sg, A, ldA, n, p, li, lv, L.ldx, s, r, partial, fj, evj,
-             xnorm, best, xout, sup, per_start_gamma ? gam : nullptr, per_start_gamma);
+             xnorm, best, xout, sup, per_start_gamma ? gam : nullptr, per_start_gamma,
+             defl);
   }
   SPCA_LAUNCH_CHECK("finalize");
 
@@ -868,6 +886,52 @@ int spca_am_solve_ex(spca_ctx* ctx, void* stream, const spca_problem* prob,
     if (out->nnz_per_start) out->nnz_per_start[j] = nnz_all[j];
   }
   return SPCA_OK;
+}
+
+int spca_am_components(spca_ctx* ctx, void* stream, const spca_problem* prob,
+                       const spca_solve_opts* opts, int32_t ncomp, double* X_out,
+                       spca_result* res) {
+  SPCA_REQUIRE(ctx && prob && opts && X_out && res,
+               "ctx, prob, opts, X_out and res must not be NULL");
+  SPCA_REQUIRE(ncomp >= 1 && ncomp <= kMaxDefl, "ncomp must be in 1..16");
+  SPCA_REQUIRE(opts->deflate_X == nullptr && opts->deflate_k == 0,
+               "deflate_X / deflate_k are set by the component loop");
+  SPCA_REQUIRE(prob->p >= 1, "p must be >= 1");
+  const int64_t p = prob->p;
+  hipStream_t st = (hipStream_t)stream;
+  double* Xd = nullptr;
+  {
+    DeviceGuard g(ctx->device);
+    SPCA_HIP_TRY(hipMalloc(&Xd, sizeof(double) * (size_t)ncomp * p));
+  }
+  std::vector<int32_t> sup(p);
+  int rc = SPCA_OK;
+  for (int32_t c = 0; c < ncomp && rc == SPCA_OK; ++c) {
+    spca_solve_opts o = *opts;
+    o.deflate_X = c > 0 ? Xd : nullptr;
+    o.deflate_k = c;
+    spca_outputs out{};
+    out.x = X_out + (int64_t)c * p;
+    out.support = sup.data();
+    out.res = &res[c];
+    rc = spca_am_solve_ex(ctx, stream, prob, &o, &out);
+    if (rc == SPCA_OK && c + 1 < ncomp) {
+      DeviceGuard g(ctx->device);
+      hipError_t e = hipMemcpyAsync(Xd + (int64_t)c * p, X_out + (int64_t)c * p,
+                                    sizeof(double) * p, hipMemcpyHostToDevice, st);
+      if (e == hipSuccess) e = hipStreamSynchronize(st);
+      if (e != hipSuccess) {
+        set_error(std::string("component loadings: ") + hipGetErrorString(e));
+        rc = SPCA_EHIP;
+      }
+    }
+  }
+  {
+    DeviceGuard g(ctx->device);
+    (void)hipStreamSynchronize(st);
+    (void)hipFree(Xd);
+  }
+  return rc;
 }
 
 static std::mutex g_default_mu;
