@@ -507,7 +507,96 @@ def bench_otf(args, spca, torch):
     }
 
 
-WORKLOADS = {"spiked-all8": bench_all8, "otf": bench_otf, "large": bench_large, "precision": bench_precision,
+def bench_hunt(args, spca, torch):
+    """Section 4.1, explained-variance hunt, on a faces-shaped stand-in: a
+    400 x 10304 Gaussian matrix with rows normalised and columns centred;
+    1000 random starts, maxit 200, tol 1e-6; for s = 1, 2, 4, ..., 4096 all
+    8 formulations, the constraints with parameter s and the penalties with
+    the sparsity-targeted warm-up (10 iterations) to s nonzeros, the L1
+    constraint with lambda frozen after 10 iterations.  A step is the whole
+    sweep; reported: solves/s, iterations x starts/s and the best explained
+    variance per formulation and s."""
+    rng = np.random.default_rng(workloads.SEED_BASE + 7)
+    n, p, l = 400, 10304, 1000
+    A_np = rng.standard_normal((n, p))
+    A_np /= np.linalg.norm(A_np, axis=1, keepdims=True)
+    A_np -= A_np.mean(axis=0, keepdims=True)
+    A = torch.from_numpy(np.ascontiguousarray(A_np.astype(np.float32).T)).cuda().t()
+    X0 = torch.from_numpy(workloads.random_unit_starts(workloads.SEED_BASE + 8, l, p)).cuda()
+    ctx = spca.Context(0)
+    stream = torch.cuda.current_stream()
+    svals = [2 ** k for k in range(13)]
+    best = {}
+
+    def step(timing):
+        work = 0.0
+        for fid in range(1, 9):
+            for sv in svals:
+                if fid <= 2:
+                    res = spca.am_solve(A, fid, float(sv), X0, tol=1e-6, maxit=200, ctx=ctx,
+                                        stream=stream, flags=args.flags)
+                elif fid <= 4:
+                    res = spca.am_solve(A, fid, float(sv), X0, tol=1e-6, maxit=200, ctx=ctx,
+                                        stream=stream, flags=args.flags, warmup_iters=10)
+                else:
+                    res = spca.am_solve(A, fid, 0.0, X0, tol=1e-6, maxit=200, ctx=ctx,
+                                        stream=stream, flags=args.flags, warmup_iters=10,
+                                        target_nnz=sv)
+                work += res["iters_x_starts"]
+                best[f"F{fid}/s={sv}"] = (round(res["explained_variance"], 6), int(res["nnz"]))
+        return {"work": work, "kt": {}}
+
+    dt, outs = _timed_steps(step, args.steps, args.warmup)
+    solves = 8 * len(svals)
+    return {
+        "metric": "solves/s (explained-variance hunt sweep)",
+        "value": solves * args.steps / dt, "unit": "solves/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (faces-shaped stand-in: Gaussian rows normalised, columns centred)",
+        "config": {"workload": "hunt-400x10304-l1000-s1to4096", "n": n, "p": p,
+                   "starting_points": l, "s": svals, "formulations": list(range(1, 9)),
+                   "warmup_iters": 10, "tol": 1e-6, "maxit": 200},
+        "iter_x_starts_per_s": sum(o["work"] for o in outs) / dt,
+        "best_explained_variance_and_nnz": best,
+    }
+
+
+def bench_components(args, spca, torch):
+    """The first 5 sparse components (deflation) on the spiked 1000 x 10000
+    model, F1 with s = 50, 1024 starts, tol 1e-6, maxit 200."""
+    cfg = workloads.SPIKED_ALL8
+    n, p, r = cfg["n"], cfg["p"], cfg["r"]
+    sp = workloads.spiked_matrix(cfg["seed"], n, p, cfg["thetas"], cfg["spike_nnz"])
+    A = torch.from_numpy(np.ascontiguousarray(sp.A.T)).cuda().t()
+    X0 = torch.from_numpy(workloads.random_unit_starts(cfg["seed"] + 1000, r, p)).cuda()
+    ctx = spca.Context(0)
+    out = {}
+
+    def step(timing):
+        comps = spca.am_components(A, 1, float(cfg["s"]), X0, 5, tol=1e-6, maxit=200,
+                                   ctx=ctx, flags=args.flags)
+        out["comps"] = comps
+        return {"work": 5, "kt": {}}
+
+    dt, outs = _timed_steps(step, args.steps, args.warmup)
+    comps = out["comps"]
+    planted = [set(s_.tolist()) for s_ in sp.supports]
+    return {
+        "metric": "components/s (deflation)", "value": 5 * args.steps / dt,
+        "unit": "components/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": dt / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "spiked-1000x10000-F1-s50-r1024-5components", "n": n, "p": p,
+                   "starts": r, "components": 5, "tol": 1e-6, "maxit": 200},
+        "components": [{"objective": c["objective"], "nnz": int(c["nnz"]),
+                        "overlap_with_planted": [len(set(c["support"].tolist()) & s_)
+                                                 for s_ in planted]} for c in comps],
+    }
+
+
+WORKLOADS = {"spiked-all8": bench_all8, "otf": bench_otf, "hunt": bench_hunt,
+             "components": bench_components, "large": bench_large, "precision": bench_precision,
              "serve": bench_serve}
 
 
