@@ -65,6 +65,9 @@ def _load():
     lib.orc_am_multi_warm.argtypes = [P, i64, i64, i64, ctypes.c_int, d, i64, i32, P, i32,
                                       d, i32, ctypes.c_int, P, P, P, P, P, P]
     lib.orc_am_multi_warm.restype = i32
+    lib.orc_am_multi_csc.argtypes = [P, P, P, i64, i64, ctypes.c_int, d, P, i32, d, i32,
+                                     ctypes.c_int, P, P, P, P, P]
+    lib.orc_am_multi_csc.restype = i32
     lib.orc_deflate.argtypes = [P, i64, i64, i64, P, P, i64]
     lib.orc_deflate.restype = None
     lib.orc_max_norm_column.argtypes = [P, i64, i64, i64]
@@ -221,6 +224,30 @@ def am_multi_warm(A, fid, s_or_gamma, X0, tol, maxit, warm_iters, target_s=0,
                                      _ptr(par), _ptr(iters), _ptr(status))
     return {"best": int(best), "X": X, "f": f, "ev": ev, "param": par, "iters": iters,
             "status": status}
+
+
+def am_multi_csc(col_ptr, row_idx, val, n, p, fid, s_or_gamma, X0, tol, maxit,
+                 nthreads=1):
+    """Multi-start AM on a sparse A in compressed sparse columns (int64
+    col_ptr of length p + 1, int32 row indices, values as FP64)."""
+    cp = np.ascontiguousarray(col_ptr, dtype=np.int64)
+    ri = np.ascontiguousarray(row_idx, dtype=np.int32)
+    vv = np.ascontiguousarray(val, dtype=np.float64)
+    assert cp.shape == (p + 1,) and ri.shape == vv.shape == (cp[-1],)
+    X0 = np.ascontiguousarray(np.asarray(X0, dtype=np.float64))
+    if X0.ndim == 1:
+        X0 = X0[None, :]
+    r = X0.shape[0]
+    X = np.zeros((r, p))
+    f = np.zeros(r)
+    ev = np.zeros(r)
+    iters = np.zeros(r, dtype=np.int32)
+    status = np.zeros(r, dtype=np.int32)
+    best = _load().orc_am_multi_csc(_ptr(cp), _ptr(ri), _ptr(vv), int(n), int(p), int(fid),
+                                    float(s_or_gamma), _ptr(X0), r, float(tol), int(maxit),
+                                    int(nthreads), _ptr(X), _ptr(f), _ptr(ev), _ptr(iters),
+                                    _ptr(status))
+    return {"best": int(best), "X": X, "f": f, "ev": ev, "iters": iters, "status": status}
 
 
 def deflate(A, x):

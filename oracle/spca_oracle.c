@@ -536,6 +536,155 @@ int32_t orc_am_multi_warm(const double* A, int64_t n, int64_t p, int64_t lda,
   return best;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Sparse A in compressed sparse columns                                    */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+  const int64_t* cp;
+  const int32_t* ri;
+  const double* v;
+  int64_t n, p;
+} csc_t;
+
+/* u = A x over the stored entries, column by column */
+static void csc_matvec(const csc_t* M, const double* x, double* u) {
+  for (int64_t i = 0; i < M->n; ++i) u[i] = 0.0;
+  for (int64_t j = 0; j < M->p; ++j) {
+    const double xj = x[j];
+    for (int64_t k = M->cp[j]; k < M->cp[j + 1]; ++k) u[M->ri[k]] += M->v[k] * xj;
+  }
+}
+
+/* v = A^T y */
+static void csc_matvec_t(const csc_t* M, const double* y, double* v) {
+  for (int64_t j = 0; j < M->p; ++j) {
+    double acc = 0.0;
+    for (int64_t k = M->cp[j]; k < M->cp[j + 1]; ++k) acc += M->v[k] * y[M->ri[k]];
+    v[j] = acc;
+  }
+}
+
+static int csc_am_single(const csc_t* M, int fid, double s_or_gamma, const double* x0,
+                         double tol, int32_t maxit, double* x_out, int32_t* iters,
+                         double* f, double* ev) {
+  const int64_t n = M->n, p = M->p;
+  double* x = (double*)malloc(sizeof(double) * (size_t)p);
+  double* w = (double*)malloc(sizeof(double) * (size_t)p);
+  double* v = (double*)malloc(sizeof(double) * (size_t)p);
+  double* u = (double*)malloc(sizeof(double) * (size_t)n);
+  memcpy(x, x0, sizeof(double) * (size_t)p);
+  int status = ORC_MAXIT;
+  double phi_prev = 0.0;
+  int32_t k = 0;
+  while (k < maxit) {
+    csc_matvec(M, x, u);
+    double unorm = norm2(u, n);
+    if (unorm == 0.0) {
+      status = ORC_DEGENERATE;
+      break;
+    }
+    for (int64_t i = 0; i < n; ++i)
+      u[i] = is_l1_variance(fid) ? sgn(u[i]) : u[i] / unorm;
+    csc_matvec_t(M, u, v);
+    double phi = orc_x_operator(fid, v, p, s_or_gamma, w);
+    ++k;
+    double wnorm = norm2(w, p);
+    if (wnorm == 0.0) {
+      status = ORC_ZERO;
+      break;
+    }
+    for (int64_t j = 0; j < p; ++j) x[j] = w[j] / wnorm;
+    if (k >= 2 && tol >= 0.0 && phi <= (1.0 + tol) * phi_prev) {
+      status = ORC_CONVERGED;
+      break;
+    }
+    phi_prev = phi;
+  }
+  double fv = 0.0, evv = 0.0;
+  if (status == ORC_DEGENERATE || status == ORC_ZERO) {
+    for (int64_t j = 0; j < p; ++j) x[j] = 0.0;
+  } else {
+    csc_matvec(M, x, u);
+    double var = is_l1_variance(fid) ? norm1(u, n) : norm2(u, n);
+    evv = is_l1_variance(fid) ? var : var * var;
+    if (fid <= 4)
+      fv = var;
+    else if (fid <= 6)
+      fv = var * var - s_or_gamma * norm0(x, p);
+    else
+      fv = var - s_or_gamma * norm1(x, p);
+  }
+  if (x_out) memcpy(x_out, x, sizeof(double) * (size_t)p);
+  if (iters) *iters = k;
+  if (f) *f = fv;
+  if (ev) *ev = evv;
+  free(x);
+  free(w);
+  free(v);
+  free(u);
+  return status;
+}
+
+typedef struct {
+  const csc_t* M;
+  int fid;
+  double s_or_gamma;
+  const double* X0;
+  int32_t r;
+  double tol;
+  int32_t maxit;
+  int nthreads, tid;
+  double *X_out, *f_out, *ev_out, *f_all;
+  int32_t *iters_out, *status_out;
+} csc_job_t;
+
+static void* csc_worker(void* arg) {
+  csc_job_t* jb = (csc_job_t*)arg;
+  const int64_t p = jb->M->p;
+  for (int32_t j = jb->tid; j < jb->r; j += jb->nthreads) {
+    int32_t it = 0;
+    double fv = 0.0, evv = 0.0;
+    int st = csc_am_single(jb->M, jb->fid, jb->s_or_gamma, jb->X0 + (int64_t)j * p, jb->tol,
+                           jb->maxit, jb->X_out ? jb->X_out + (int64_t)j * p : NULL, &it,
+                           &fv, &evv);
+    jb->f_all[j] = fv;
+    if (jb->f_out) jb->f_out[j] = fv;
+    if (jb->ev_out) jb->ev_out[j] = evv;
+    if (jb->iters_out) jb->iters_out[j] = it;
+    if (jb->status_out) jb->status_out[j] = st;
+  }
+  return NULL;
+}
+
+int32_t orc_am_multi_csc(const int64_t* col_ptr, const int32_t* row_idx,
+                         const double* val, int64_t n, int64_t p, int fid,
+                         double s_or_gamma, const double* X0, int32_t r, double tol,
+                         int32_t maxit, int nthreads, double* X_out, double* f_out,
+                         double* ev_out, int32_t* iters_out, int32_t* status_out) {
+  csc_t M = {col_ptr, row_idx, val, n, p};
+  if (nthreads < 1) nthreads = 1;
+  if (nthreads > r) nthreads = r;
+  double* f_all = (double*)malloc(sizeof(double) * (size_t)r);
+  csc_job_t* jobs = (csc_job_t*)malloc(sizeof(csc_job_t) * (size_t)nthreads);
+  pthread_t* th = (pthread_t*)malloc(sizeof(pthread_t) * (size_t)nthreads);
+  for (int t = 0; t < nthreads; ++t) {
+    csc_job_t jb = {&M, fid, s_or_gamma, X0, r, tol, maxit, nthreads, t, X_out, f_out,
+                    ev_out, f_all, iters_out, status_out};
+    jobs[t] = jb;
+  }
+  for (int t = 1; t < nthreads; ++t) pthread_create(&th[t], NULL, csc_worker, &jobs[t]);
+  csc_worker(&jobs[0]);
+  for (int t = 1; t < nthreads; ++t) pthread_join(th[t], NULL);
+  int32_t best = 0;
+  for (int32_t j = 1; j < r; ++j)
+    if (f_all[j] > f_all[best]) best = j;
+  free(f_all);
+  free(jobs);
+  free(th);
+  return best;
+}
+
 void orc_deflate(const double* A, int64_t n, int64_t p, int64_t lda,
                  const double* x, double* out, int64_t ldo) {
   double* u = (double*)malloc(sizeof(double) * (size_t)n);

@@ -112,6 +112,16 @@ int32_t orc_am_multi_warm(const double* A, int64_t n, int64_t p, int64_t lda,
 void orc_deflate(const double* A, int64_t n, int64_t p, int64_t lda,
                  const double* x, double* out, int64_t ldo);
 
+/* The same multi-start AM on a sparse A held in compressed sparse columns
+ * (col_ptr: p + 1 offsets, row_idx / val: the nonzeros of each column),
+ * FP64 values.  The products touch only the stored entries; otherwise it is
+ * orc_am_multi step for step.  Returns the best start.                    */
+int32_t orc_am_multi_csc(const int64_t* col_ptr, const int32_t* row_idx,
+                         const double* val, int64_t n, int64_t p, int fid,
+                         double s_or_gamma, const double* X0, int32_t r, double tol,
+                         int32_t maxit, int nthreads, double* X_out, double* f_out,
+                         double* ev_out, int32_t* iters_out, int32_t* status_out);
+
 /* argmax_i ||a_i||_2 over the columns of A, ties to the lowest index.     */
 int64_t orc_max_norm_column(const double* A, int64_t n, int64_t p,
                             int64_t lda);
