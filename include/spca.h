@@ -225,6 +225,28 @@ int spca_am_components(spca_ctx* ctx, void* stream, const spca_problem* prob,
                        const spca_solve_opts* opts, int32_t ncomp, double* X_out,
                        spca_result* res);
 
+/* Sparse A (the paper's text corpora are word-count matrices): the same
+ * batched solve with A held as compressed sparse columns and, for the
+ * product with a dense iterate, compressed sparse rows of the same matrix.
+ * All arrays are device memory owned by the caller: col_ptr (p + 1 int64),
+ * row_idx / col_val (nnz, rows ascending within a column), row_ptr (n + 1
+ * int64), col_idx / row_val (nnz).  Options as spca_am_solve_ex, with
+ * X0 required, FP32 only, and neither total_starts > r nor deflation.    */
+typedef struct {
+  int64_t n, p;
+  const int64_t* col_ptr;
+  const int32_t* row_idx;
+  const float* col_val;
+  const int64_t* row_ptr;
+  const int32_t* col_idx;
+  const float* row_val;
+  int32_t formulation;
+  double s_or_gamma;
+} spca_sparse_problem;
+
+int spca_am_solve_sparse(spca_ctx* ctx, void* stream, const spca_sparse_problem* prob,
+                         const spca_solve_opts* opts, spca_outputs* out);
+
 /* Full solve on a caller-chosen context and HIP stream (hipStream_t passed
  * as void*; NULL = null stream).  Same semantics as spca_am_solve.
  * Additional errors: SPCA_ENOMEM when the workspace exceeds the budget;

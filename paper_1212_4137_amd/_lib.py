@@ -28,7 +28,8 @@ EXPORTED = ("spca_am_solve", "spca_am_solve_ex", "spca_ctx_create",
             "spca_ctx_set_workspace", "spca_request_footprint", "spca_server_create",
             "spca_server_submit", "spca_server_poll", "spca_server_stats",
             "spca_server_destroy", "spca_tune_table_export", "spca_tune_table_import",
-            "spca_tune_table_clear", "spca_gemm_nt_bf16_shape", "spca_am_components")
+            "spca_tune_table_clear", "spca_gemm_nt_bf16_shape", "spca_am_components",
+            "spca_am_solve_sparse")
 
 
 class SpcaError(RuntimeError):
@@ -69,6 +70,14 @@ class Outputs(ctypes.Structure):
                 ("status_per_start", ctypes.c_void_p), ("nnz_per_start", ctypes.c_void_p),
                 ("X_final", ctypes.c_void_p), ("kernel_times", ctypes.c_void_p),
                 ("param_per_start", ctypes.c_void_p)]
+
+
+class SparseProblem(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("p", ctypes.c_int64), ("col_ptr", ctypes.c_void_p),
+                ("row_idx", ctypes.c_void_p), ("col_val", ctypes.c_void_p),
+                ("row_ptr", ctypes.c_void_p), ("col_idx", ctypes.c_void_p),
+                ("row_val", ctypes.c_void_p), ("formulation", ctypes.c_int32),
+                ("s_or_gamma", ctypes.c_double)]
 
 
 class Request(ctypes.Structure):
@@ -154,6 +163,10 @@ def load():
         lib.spca_tune_table_import.restype = ctypes.c_int
         lib.spca_tune_table_clear.argtypes = []
         lib.spca_tune_table_clear.restype = ctypes.c_int
+        lib.spca_am_solve_sparse.argtypes = [P, P, ctypes.POINTER(SparseProblem),
+                                             ctypes.POINTER(SolveOpts),
+                                             ctypes.POINTER(Outputs)]
+        lib.spca_am_solve_sparse.restype = ctypes.c_int
         lib.spca_am_components.argtypes = [P, P, ctypes.POINTER(Problem),
                                            ctypes.POINTER(SolveOpts), i32, P,
                                            ctypes.POINTER(Result)]
@@ -623,3 +636,56 @@ def am_components(A, formulation, s_or_gamma, X0, ncomp, tol=1e-8, maxit=200, *,
                     "iters": res[c].iters, "status": res[c].status, "x": x.copy(),
                     "support": np.flatnonzero(x)})
     return out
+
+
+def sparse_to_device(mat, device="cuda:0"):
+    """Device copies of a sparse matrix's two layouts (an object with n, p,
+    col_ptr, row_idx, col_val, row_ptr, col_idx, row_val host arrays)."""
+    import torch
+
+    dev = {"n": int(mat.n), "p": int(mat.p)}
+    for name, dt in (("col_ptr", np.int64), ("row_idx", np.int32), ("col_val", np.float32),
+                     ("row_ptr", np.int64), ("col_idx", np.int32), ("row_val", np.float32)):
+        dev[name] = torch.from_numpy(np.ascontiguousarray(getattr(mat, name), dtype=dt)).to(device)
+    return dev
+
+
+def am_solve_sparse(D, formulation, s_or_gamma, X0, tol=1e-8, maxit=200, *, check_every=8,
+                    flags=0, ctx=None, stream=None, warmup_iters=0, target_nnz=0,
+                    return_X=False):
+    """Batched AM solve on a sparse A (``spca_am_solve_sparse``); D from
+    sparse_to_device, X0 a contiguous (r, p) float32 GPU tensor."""
+    import torch
+
+    n, p = D["n"], D["p"]
+    _require_gpu_tensor(X0, "X0", torch.float32)
+    if X0.dim() != 2 or X0.shape[1] != p or not X0.is_contiguous():
+        raise ValueError("X0 must be a contiguous (r, p) tensor")
+    r = X0.shape[0]
+    ctx = ctx or default_context(X0.device.index or 0)
+    x = np.zeros(p, dtype=np.float64)
+    sup = np.zeros(p, dtype=np.int32)
+    res = Result()
+    f, ev, phi = np.zeros(r), np.zeros(r), np.zeros(r)
+    iters = np.zeros(r, dtype=np.int32)
+    status = np.zeros(r, dtype=np.int32)
+    nnz = np.zeros(r, dtype=np.int32)
+    par = np.zeros(r)
+    Xf = torch.empty((r, p), dtype=torch.float32, device=X0.device) if return_X else None
+    prob = SparseProblem(n, p, D["col_ptr"].data_ptr(), D["row_idx"].data_ptr(),
+                         D["col_val"].data_ptr(), D["row_ptr"].data_ptr(),
+                         D["col_idx"].data_ptr(), D["row_val"].data_ptr(), int(formulation),
+                         float(s_or_gamma))
+    opts = SolveOpts(X0.data_ptr(), r, float(tol), int(maxit), PREC_FP32, 0, int(check_every),
+                     int(flags), 0, int(warmup_iters), int(target_nnz), None, 0)
+    out = Outputs(_np_ptr(x), _np_ptr(sup), ctypes.pointer(res), _np_ptr(f), _np_ptr(ev),
+                  _np_ptr(phi), _np_ptr(iters), _np_ptr(status), _np_ptr(nnz),
+                  Xf.data_ptr() if Xf is not None else None, None, _np_ptr(par))
+    _check(load().spca_am_solve_sparse(ctx.handle, _stream_ptr(stream), ctypes.byref(prob),
+                                       ctypes.byref(opts), ctypes.byref(out)))
+    return {"x": x, "support": sup[: res.nnz].copy(), "objective": res.objective,
+            "explained_variance": res.explained_var, "best_start": res.best_start,
+            "nnz": res.nnz, "iters": res.iters, "status": res.status,
+            "iters_x_starts": res.iters_x_starts, "f_per_start": f, "ev_per_start": ev,
+            "iters_per_start": iters, "status_per_start": status, "nnz_per_start": nnz,
+            "param_per_start": par, "X_final": Xf}

@@ -194,6 +194,24 @@ void evaluate_rows(hipStream_t st, int fid, double s_or_gamma, const float* A,
                      xnorm, f, ev, only, gam);
 }
 
+void x_norms(hipStream_t st, const float* list_val, int64_t ldl, StartState s, int64_t r,
+             double* xnorm) {
+  hipLaunchKernelGGL(x_norms_kernel, dim3((unsigned)r), dim3(256), 0, st, list_val, ldl, s,
+                     r, xnorm, nullptr);
+}
+
+void objective_and_best(hipStream_t st, int fid, double s_or_gamma, StartState s,
+                        int64_t r, int64_t p, const double* partial, int nchunks,
+                        const int32_t* list_idx, const float* list_val, int64_t ldl,
+                        const double* xnorm, double* f, double* ev, int32_t* best,
+                        double* x_out, int32_t* support_out, const double* gam,
+                        bool by_ev) {
+  hipLaunchKernelGGL(objective_kernel, dim3((unsigned)ceil_div(r, 256)), dim3(256), 0, st,
+                     fid, s_or_gamma, s, r, partial, nchunks, xnorm, f, ev, nullptr, gam);
+  hipLaunchKernelGGL(best_kernel, dim3(1), dim3(1024), 0, st, by_ev ? ev : f, s, r, p,
+                     list_idx, list_val, ldl, xnorm, best, x_out, support_out);
+}
+
 void finalize(hipStream_t st, int fid, double s_or_gamma, const float* A,
               int64_t lda, int64_t n, int64_t p, const int32_t* list_idx,
               const float* list_val, int64_t ldl, StartState s, int64_t r,

@@ -275,6 +275,44 @@ void evaluate_rows(hipStream_t st, int fid, double s_or_gamma, const float* A,
                    const int32_t* only, const double* gam = nullptr,
                    Defl defl = Defl{});
 
+// The two ends of finalize, for products formed elsewhere (sparse A):
+// ||x||_2 of each start's list; then f, the explained variance and the best
+// start from per-start partial sums (sum u_i^2, sum |u_i|) of u = A x64.
+void x_norms(hipStream_t st, const float* list_val, int64_t ldl, StartState s, int64_t r,
+             double* xnorm);
+void objective_and_best(hipStream_t st, int fid, double s_or_gamma, StartState s,
+                        int64_t r, int64_t p, const double* partial, int nchunks,
+                        const int32_t* list_idx, const float* list_val, int64_t ldl,
+                        const double* xnorm, double* f, double* ev, int32_t* best,
+                        double* x_out, int32_t* support_out, const double* gam,
+                        bool by_ev);
+
+// Sparse A (compressed sparse columns, with its row-compressed twin).
+struct SparseA {
+  int64_t n, p;
+  const int64_t* col_ptr;
+  const int32_t* row_idx;
+  const float* col_val;
+  const int64_t* row_ptr;
+  const int32_t* col_idx;
+  const float* row_val;
+};
+// U (r x n) = A X for dense X from the rows (XT: X transposed, p x ldxt);
+// runs in mode kAxDense
+void sparse_ax_dense(hipStream_t st, SparseA a, const float* XT, int64_t ldxt, int64_t r,
+                     float* U, int64_t ldu, const Plan* plan);
+// U row j = sum over the start's support columns; runs in mode kAxListRows
+void sparse_ax_list(hipStream_t st, SparseA a, const int32_t* list_idx,
+                    const float* list_val, int64_t ldl, float* U, int64_t ldu, int64_t r,
+                    StartState s, const Plan* plan);
+// V (r x p) = A^T Y from the columns (YT: Y transposed, n x ldyt)
+void sparse_aty(hipStream_t st, SparseA a, const float* YT, int64_t ldyt, int64_t r,
+                float* V, int64_t ldv);
+// per-start partial sums of the FP64 u = A x / ||x|| for objective_and_best
+void sparse_final(hipStream_t st, SparseA a, const int32_t* list_idx,
+                  const float* list_val, int64_t ldl, StartState s, int64_t r,
+                  const double* xnorm, double* u64, double* partial);
+
 // On-the-fly replacement of finished starts (Section 4.3): state of the
 // slots and of the total_starts starts that flow through them.
 struct Otf {

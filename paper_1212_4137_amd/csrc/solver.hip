@@ -888,6 +888,238 @@ int spca_am_solve_ex(spca_ctx* ctx, void* stream, const spca_problem* prob,
   return SPCA_OK;
 }
 
+int spca_am_solve_sparse(spca_ctx* ctx, void* stream, const spca_sparse_problem* prob,
+                         const spca_solve_opts* opts, spca_outputs* out) {
+  SPCA_REQUIRE(ctx && prob && opts && out && out->res,
+               "ctx, prob, opts, out and out->res must not be NULL");
+  const int64_t n = prob->n, p = prob->p, r = opts->r;
+  const int fid = prob->formulation;
+  const double sg = prob->s_or_gamma;
+  int rc = check_problem(n, p, n, fid, sg, r, opts->tol, opts->maxit);
+  if (rc != SPCA_OK) return rc;
+  SPCA_REQUIRE(prob->col_ptr && prob->row_idx && prob->col_val && prob->row_ptr &&
+                   prob->col_idx && prob->row_val,
+               "every array of the sparse matrix must be set");
+  SPCA_REQUIRE(opts->X0 != nullptr, "the sparse solve needs X0");
+  SPCA_REQUIRE(opts->precision == SPCA_PREC_FP32, "the sparse solve runs in FP32");
+  SPCA_REQUIRE(opts->total_starts <= r && opts->deflate_k == 0,
+               "the sparse solve takes neither total_starts > r nor deflation");
+  SPCA_REQUIRE(opts->check_every >= 1, "check_every must be >= 1");
+  SPCA_REQUIRE(opts->warmup_iters >= 0, "warmup_iters must be >= 0");
+  const bool warm = opts->warmup_iters > 0;
+  if (warm) {
+    SPCA_REQUIRE(fid >= 3, "the warm-up applies to formulations 3..8");
+    if (fid >= 5)
+      SPCA_REQUIRE(opts->target_nnz >= 1 && opts->target_nnz <= p,
+                   "target_nnz must be in 1..p for the penalty warm-up");
+  }
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  DeviceGuard g(ctx->device);
+  hipStream_t st = (hipStream_t)stream;
+
+  // workspace: the iterates of the dense path plus the transposed operands
+  // and an FP64 row per start for the final evaluation
+  const int64_t ldx = round_up(p, 4), ldu = round_up(n, 4), ldt = round_up(r, 4);
+  size_t c = 0;
+  const size_t o_X = carve(&c, sizeof(float) * r * ldx);
+  const size_t o_XT = carve(&c, sizeof(float) * p * ldt);
+  const size_t o_U = carve(&c, sizeof(float) * r * ldu);
+  const size_t o_Y = carve(&c, sizeof(float) * r * ldu);
+  const size_t o_YT = carve(&c, sizeof(float) * n * ldt);
+  const size_t o_V = carve(&c, sizeof(float) * r * ldx);
+  const size_t o_li = carve(&c, sizeof(int32_t) * r * ldx);
+  const size_t o_lv = carve(&c, sizeof(float) * r * ldx);
+  const size_t o_phi = carve(&c, sizeof(double) * r);
+  const size_t o_phip = carve(&c, sizeof(double) * r);
+  const size_t o_nnz = carve(&c, sizeof(int32_t) * r);
+  const size_t o_it = carve(&c, sizeof(int32_t) * r);
+  const size_t o_st = carve(&c, sizeof(int32_t) * r);
+  const size_t o_plan = carve(&c, sizeof(Plan));
+  const size_t o_part = carve(&c, sizeof(double) * 2 * r);
+  const size_t o_f = carve(&c, sizeof(double) * r);
+  const size_t o_ev = carve(&c, sizeof(double) * r);
+  const size_t o_xn = carve(&c, sizeof(double) * 2 * r);
+  const size_t o_best = carve(&c, sizeof(int32_t) * 2);
+  const size_t o_xout = carve(&c, sizeof(double) * p);
+  const size_t o_sup = carve(&c, sizeof(int32_t) * p);
+  const size_t o_mark = carve(&c, sizeof(int32_t) * p);
+  const size_t o_ul = carve(&c, sizeof(int32_t) * p);
+  const size_t o_u64 = carve(&c, sizeof(double) * r * n);
+  const size_t o_gam = carve(&c, sizeof(double) * r);
+  const size_t wide_bytes = x_update_wide_bytes(1, r, p);
+  const size_t o_wide = carve(&c, wide_bytes);
+  rc = ensure_workspace(ctx, st, c);
+  if (rc != SPCA_OK) return rc;
+  char* base = (char*)ctx->ws;
+  float* X = (float*)(base + o_X);
+  float* XT = (float*)(base + o_XT);
+  float* U = (float*)(base + o_U);
+  float* Y = (float*)(base + o_Y);
+  float* YT = (float*)(base + o_YT);
+  float* V = (float*)(base + o_V);
+  int32_t* li = (int32_t*)(base + o_li);
+  float* lv = (float*)(base + o_lv);
+  StartState s{(double*)(base + o_phi), (double*)(base + o_phip), (int32_t*)(base + o_nnz),
+               (int32_t*)(base + o_it), (int32_t*)(base + o_st)};
+  Plan* plan = (Plan*)(base + o_plan);
+  double* partial = (double*)(base + o_part);
+  double* fj = (double*)(base + o_f);
+  double* evj = (double*)(base + o_ev);
+  double* xnorm = (double*)(base + o_xn);
+  int32_t* best = (int32_t*)(base + o_best);
+  double* xout = (double*)(base + o_xout);
+  int32_t* sup = (int32_t*)(base + o_sup);
+  int32_t* colmark = (int32_t*)(base + o_mark);
+  int32_t* ulist = (int32_t*)(base + o_ul);
+  double* u64 = (double*)(base + o_u64);
+  double* gam = (double*)(base + o_gam);
+  void* wide = wide_bytes ? (void*)(base + o_wide) : nullptr;
+  Warm wm;
+  if (warm) {
+    wm.K = opts->warmup_iters;
+    wm.target = fid >= 5 ? opts->target_nnz : 0;
+    wm.gam = gam;
+  }
+  const SparseA a{n, p, prob->col_ptr, prob->row_idx, prob->col_val,
+                  prob->row_ptr, prob->col_idx, prob->row_val};
+
+  SPCA_HIP_TRY(hipMemcpy2DAsync(X, sizeof(float) * ldx, opts->X0, sizeof(float) * p,
+                                sizeof(float) * p, r, hipMemcpyDeviceToDevice, st));
+  init_state(st, s, r);
+  init_plan(st, plan, 1);
+  if (wide) SPCA_HIP_TRY(x_update_wide_reset(st, wide, r));
+  SPCA_HIP_TRY(hipMemsetAsync(colmark, 0, sizeof(int32_t) * p, st));
+  compact_rows(st, X, ldx, r, p, li, lv, ldx, s.nnz, s.status, colmark, plan);
+  const int list_cap = list_cap_of(p);
+  // the planner of the dense path, without the union product and with the
+  // list product always followed by the separate y-update: its mode picks
+  // the row gather (dense) or the support-column scatter (lists)
+  plan_next(st, s, r, n, p, list_cap, 0, 1, 0, colmark, ulist, plan, 1);
+  SPCA_LAUNCH_CHECK("sparse staging");
+  const int32_t maxit = opts->maxit;
+  auto iteration = [&](hipStream_t q) -> int {
+    transpose_f32(q, X, ldx, XT, ldt, p, r);
+    sparse_ax_dense(q, a, XT, ldt, r, U, ldu, plan);
+    sparse_ax_list(q, a, li, lv, ldx, U, ldu, r, s, plan);
+    y_update(q, fid, U, r * ldu, Y, ldu, r, n, s, plan, nullptr, 0);
+    transpose_f32(q, Y, ldu, YT, ldt, n, r);
+    sparse_aty(q, a, YT, ldt, r, V, ldx);
+    x_update(q, fid, sg, V, ldx, r, p, X, ldx, li, lv, ldx, list_cap, s, opts->tol, maxit,
+             colmark, plan, wide, wm);
+    plan_next(q, s, r, n, p, list_cap, 0, 1, 0, colmark, ulist, plan, 1);
+    SPCA_LAUNCH_CHECK("sparse AM iteration");
+    return SPCA_OK;
+  };
+  auto none_active = [&](bool* done) -> int {
+    SPCA_HIP_TRY(hipMemcpyAsync(ctx->host_poll, &plan->active, sizeof(int32_t),
+                                hipMemcpyDeviceToHost, st));
+    SPCA_HIP_TRY(hipStreamSynchronize(st));
+    *done = ctx->host_poll[0] == 0;
+    return SPCA_OK;
+  };
+  const int32_t every = opts->check_every;
+  int32_t it = 0;
+  bool done = false;
+  if ((opts->flags & SPCA_FLAG_GRAPH) && maxit >= every) {
+    rc = ensure_capture_stream(ctx);
+    if (rc != SPCA_OK) return rc;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    SPCA_HIP_TRY(hipStreamBeginCapture(ctx->capture, hipStreamCaptureModeThreadLocal));
+    int body_rc = SPCA_OK;
+    for (int32_t k = 0; k < every && body_rc == SPCA_OK; ++k) body_rc = iteration(ctx->capture);
+    hipError_t end_rc = hipStreamEndCapture(ctx->capture, &graph);
+    if (body_rc != SPCA_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return body_rc;
+    }
+    SPCA_HIP_TRY(end_rc);
+    hipError_t inst_rc = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    SPCA_HIP_TRY(inst_rc);
+    int loop_rc = SPCA_OK;
+    while (!done && it + every <= maxit) {
+      hipError_t e = hipGraphLaunch(exec, st);
+      if (e != hipSuccess) {
+        set_error(std::string("hipGraphLaunch: ") + hipGetErrorString(e));
+        loop_rc = SPCA_EHIP;
+        break;
+      }
+      it += every;
+      if (it < maxit) {
+        loop_rc = none_active(&done);
+        if (loop_rc != SPCA_OK) break;
+      }
+    }
+    (void)hipGraphExecDestroy(exec);
+    if (loop_rc != SPCA_OK) return loop_rc;
+  }
+  for (; !done && it < maxit; ++it) {
+    rc = iteration(st);
+    if (rc != SPCA_OK) return rc;
+    if ((it + 1) % every == 0 && it + 1 < maxit) {
+      rc = none_active(&done);
+      if (rc != SPCA_OK) return rc;
+    }
+  }
+
+  // FP64 evaluation on the sparse matrix
+  compact_rows(st, X, ldx, r, p, li, lv, ldx, s.nnz, nullptr, nullptr, nullptr);
+  x_norms(st, lv, ldx, s, r, xnorm);
+  sparse_final(st, a, li, lv, ldx, s, r, xnorm, u64, partial);
+  const bool per_start_gamma = warm && fid >= 5;
+  objective_and_best(st, fid, sg, s, r, p, partial, 1, li, lv, ldx, xnorm, fj, evj, best,
+                     xout, sup, per_start_gamma ? gam : nullptr, per_start_gamma);
+  SPCA_LAUNCH_CHECK("sparse finalize");
+
+  int32_t hb[2];
+  SPCA_HIP_TRY(hipMemcpyAsync(hb, best, sizeof(hb), hipMemcpyDeviceToHost, st));
+  std::vector<double> f_all(r), ev_all(r), phi_all(r);
+  std::vector<int32_t> it_all(r), st_all(r), nnz_all(r);
+  SPCA_HIP_TRY(hipMemcpyAsync(f_all.data(), fj, sizeof(double) * r, hipMemcpyDeviceToHost, st));
+  SPCA_HIP_TRY(hipMemcpyAsync(ev_all.data(), evj, sizeof(double) * r, hipMemcpyDeviceToHost, st));
+  SPCA_HIP_TRY(hipMemcpyAsync(phi_all.data(), s.phi, sizeof(double) * r, hipMemcpyDeviceToHost, st));
+  SPCA_HIP_TRY(hipMemcpyAsync(it_all.data(), s.iters, sizeof(int32_t) * r, hipMemcpyDeviceToHost, st));
+  SPCA_HIP_TRY(hipMemcpyAsync(st_all.data(), s.status, sizeof(int32_t) * r, hipMemcpyDeviceToHost, st));
+  SPCA_HIP_TRY(hipMemcpyAsync(nnz_all.data(), s.nnz, sizeof(int32_t) * r, hipMemcpyDeviceToHost, st));
+  SPCA_HIP_TRY(hipStreamSynchronize(st));
+  const int32_t jb = hb[0], nnzb = hb[1];
+  if (out->x)
+    SPCA_HIP_TRY(hipMemcpyAsync(out->x, xout, sizeof(double) * p, hipMemcpyDeviceToHost, st));
+  if (out->support && nnzb > 0)
+    SPCA_HIP_TRY(hipMemcpyAsync(out->support, sup, sizeof(int32_t) * nnzb,
+                                hipMemcpyDeviceToHost, st));
+  if (out->param_per_start && warm)
+    SPCA_HIP_TRY(hipMemcpyAsync(out->param_per_start, gam, sizeof(double) * r,
+                                hipMemcpyDeviceToHost, st));
+  if (out->X_final)
+    SPCA_HIP_TRY(hipMemcpy2DAsync(out->X_final, sizeof(float) * p, X, sizeof(float) * ldx,
+                                  sizeof(float) * p, r, hipMemcpyDeviceToDevice, st));
+  SPCA_HIP_TRY(hipStreamSynchronize(st));
+  double total_iters = 0.0;
+  for (int64_t j = 0; j < r; ++j) total_iters += it_all[j];
+  spca_result* res = out->res;
+  res->objective = f_all[jb];
+  res->objective_pre_polish = f_all[jb];
+  res->polish_iters = 0;
+  res->explained_var = ev_all[jb];
+  res->phi = phi_all[jb];
+  res->iters_x_starts = total_iters;
+  res->best_start = jb;
+  res->nnz = nnzb;
+  res->iters = it_all[jb];
+  res->status = st_all[jb];
+  for (int64_t j = 0; j < r; ++j) {
+    if (out->f_per_start) out->f_per_start[j] = f_all[j];
+    if (out->ev_per_start) out->ev_per_start[j] = ev_all[j];
+    if (out->phi_per_start) out->phi_per_start[j] = phi_all[j];
+    if (out->iters_per_start) out->iters_per_start[j] = it_all[j];
+    if (out->status_per_start) out->status_per_start[j] = st_all[j];
+    if (out->nnz_per_start) out->nnz_per_start[j] = nnz_all[j];
+  }
+  return SPCA_OK;
+}
+
 int spca_am_components(spca_ctx* ctx, void* stream, const spca_problem* prob,
                        const spca_solve_opts* opts, int32_t ncomp, double* X_out,
                        spca_result* res) {
