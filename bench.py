@@ -595,7 +595,48 @@ def bench_components(args, spca, torch):
     }
 
 
+def bench_sparse(args, spca, torch):
+    """Sparse A shaped like the paper's NYTimes bag of words (300000 documents
+    x 102660 words, about 70M nonzero counts, Zipf word frequencies,
+    generated on the host from a seed), F1 with s = 5 from 20 random starts,
+    maxit 20, tol 1e-6 (the paper's setting for that corpus).  A step is one
+    solve."""
+    from workloads import sparse as sparse_w
+
+    mat = sparse_w.bag_of_words(workloads.SEED_BASE + 9, 300000, 102660, 103_000_000)
+    D = spca.sparse_to_device(mat)
+    r = args.starts or 20
+    X0 = torch.from_numpy(workloads.random_unit_starts(workloads.SEED_BASE + 10, r,
+                                                       mat.p)).cuda()
+    ctx = spca.Context(0)
+    last = {}
+    flags = args.flags | {"auto": 0, "on": spca.FLAG_SPARSE_PANELS,
+                          "off": spca.FLAG_SPARSE_NO_PANELS}[args.panels]
+
+    def step(timing):
+        res = spca.am_solve_sparse(D, 1, 5.0, X0, tol=1e-6, maxit=20, ctx=ctx, flags=flags)
+        last.update(res)
+        return {"work": res["iters_x_starts"], "kt": {}}
+
+    dt, outs = _timed_steps(step, args.steps, args.warmup)
+    counts = np.diff(mat.col_ptr)
+    return {
+        "metric": "solves/s (sparse A)", "value": args.steps / dt, "unit": "solves/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": dt / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (Zipf bag-of-words stand-in for the NYTimes corpus)",
+        "config": {"workload": "bagofwords-300000x102660-F1-s5", "n": mat.n, "p": mat.p,
+                   "nnz": mat.nnz, "largest_column": int(counts.max()), "starts": r,
+                   "tol": 1e-6, "maxit": 20},
+        "iter_x_starts_per_s": sum(o["work"] for o in outs) / dt,
+        "result": {"objective": last["objective"], "support": last["support"].tolist(),
+                   "iters": int(last["iters"])},
+    }
+
+
 WORKLOADS = {"spiked-all8": bench_all8, "otf": bench_otf, "hunt": bench_hunt,
+             "sparse": bench_sparse,
              "components": bench_components, "large": bench_large, "precision": bench_precision,
              "serve": bench_serve}
 
@@ -612,6 +653,9 @@ def main():
                     help="formulations in a step of spiked-all8 (default: all 8)")
     ap.add_argument("--maxit", type=int, default=0, help="iterations per solve (large)")
     ap.add_argument("--slots", type=int, default=64, help="otf: slots")
+    ap.add_argument("--starts", type=int, default=0, help="sparse: starting points")
+    ap.add_argument("--panels", default="auto", choices=("auto", "on", "off"),
+                    help="sparse: row panels of the columns for A^T Y")
     ap.add_argument("--requests", type=int, default=200, help="serve: requests")
     ap.add_argument("--loads", default="0.5,1,2",
                     help="serve: offered loads as multiples of the baseline saturation rate")

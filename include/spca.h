@@ -186,6 +186,14 @@ typedef struct {
  * reproducible given the table (see spca_tune_table_export).              */
 #define SPCA_FLAG_AUTOTUNE 8
 #define SPCA_FLAG_NO_UNION 16    /* never use the union-of-supports product  */
+/* Sparse solve only: A^T Y reads a copy of the columns split into row
+ * panels (one panel's rows per XCD at a time, so that the gathered rows of
+ * Y stay in that XCD's L2), built at the start of each solve.  By default
+ * the solve uses panels when Y is larger than one L2 and A has at least
+ * 2^20 nonzeros; these flags force them on or off.  Results differ from
+ * the unpanelled product only in the order of the sums.                   */
+#define SPCA_FLAG_SPARSE_PANELS 32
+#define SPCA_FLAG_SPARSE_NO_PANELS 64
 
 typedef struct {
   double* x;           /* host, p doubles (see spca_am_solve), or NULL      */
@@ -228,10 +236,18 @@ int spca_am_components(spca_ctx* ctx, void* stream, const spca_problem* prob,
 /* Sparse A (the paper's text corpora are word-count matrices): the same
  * batched solve with A held as compressed sparse columns and, for the
  * product with a dense iterate, compressed sparse rows of the same matrix.
- * All arrays are device memory owned by the caller: col_ptr (p + 1 int64),
- * row_idx / col_val (nnz, rows ascending within a column), row_ptr (n + 1
- * int64), col_idx / row_val (nnz).  Options as spca_am_solve_ex, with
- * X0 required, FP32 only, and neither total_starts > r nor deflation.    */
+ * All arrays are device memory owned by the caller, 16-byte aligned:
+ * col_ptr (p + 1 int64), row_idx / col_val (nnz, rows strictly ascending
+ * within a column), row_ptr (n + 1 int64), col_idx / row_val (nnz).  Both
+ * pointer arrays start at 0 and end at the same nnz.  Options as
+ * spca_am_solve_ex, with X0 required, FP32 only, and neither
+ * total_starts > r nor deflation.  The solve first checks the arrays on
+ * the device (pointer arrays non-decreasing, every index in range, rows of
+ * a column strictly ascending; SPCA_EINVAL otherwise, before any product
+ * runs), synchronizing the stream; it synchronizes again when it builds row
+ * panels (see SPCA_FLAG_SPARSE_PANELS).  The workspace holds, besides the
+ * iterates, the transposed operands and, with panels, a copy of the
+ * columns (8 bytes per nonzero).                                          */
 typedef struct {
   int64_t n, p;
   const int64_t* col_ptr;

@@ -20,6 +20,7 @@ SPCA_OK, SPCA_EINVAL, SPCA_ENOMEM, SPCA_EHIP = 0, -1, -2, -3
 CONVERGED, MAXIT, DEGENERATE, ZERO = 0, 1, 2, 3
 PREC_FP32, PREC_BF16_POLISH = 0, 1
 FLAG_GRAPH, FLAG_CHECK_FINITE, FLAG_DENSE_ONLY, FLAG_AUTOTUNE, FLAG_NO_UNION = 1, 2, 4, 8, 16
+FLAG_SPARSE_PANELS, FLAG_SPARSE_NO_PANELS = 32, 64
 
 EXPORTED = ("spca_am_solve", "spca_am_solve_ex", "spca_ctx_create",
             "spca_ctx_destroy", "spca_workspace_bytes", "spca_last_error",

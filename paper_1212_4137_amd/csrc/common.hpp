@@ -124,33 +124,33 @@ __device__ __forceinline__ T block_max(T v, T* scratch) {
   return v;
 }
 
-// Exclusive prefix sum of one int per thread in thread order; returns the
+// Exclusive prefix sum of one value per thread in thread order; returns the
 // thread's offset and writes the block total to *total.  scratch holds
-// blockDim/64 + 1 ints.
-__device__ __forceinline__ int block_exclusive_scan(int v, int* scratch,
-                                                    int* total) {
+// blockDim/64 + 1 values.
+template <typename T>
+__device__ __forceinline__ T block_exclusive_scan(T v, T* scratch, T* total) {
   const int lane = threadIdx.x % kWave;
   const int wave = threadIdx.x / kWave;
   const int nwaves = blockDim.x / kWave;
-  int incl = v;
+  T incl = v;
 #pragma unroll
   for (int off = 1; off < kWave; off <<= 1) {
-    int o = __shfl_up(incl, off, kWave);
+    T o = __shfl_up(incl, off, kWave);
     if (lane >= off) incl += o;
   }
   if (lane == kWave - 1) scratch[wave] = incl;
   __syncthreads();
   if (threadIdx.x == 0) {
-    int run = 0;
+    T run = 0;
     for (int w = 0; w < nwaves; ++w) {
-      int t = scratch[w];
+      T t = scratch[w];
       scratch[w] = run;
       run += t;
     }
     scratch[nwaves] = run;
   }
   __syncthreads();
-  int res = scratch[wave] + incl - v;
+  T res = scratch[wave] + incl - v;
   *total = scratch[nwaves];
   __syncthreads();
   return res;

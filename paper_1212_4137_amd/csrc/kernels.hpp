@@ -287,31 +287,74 @@ void objective_and_best(hipStream_t st, int fid, double s_or_gamma, StartState s
                         double* x_out, int32_t* support_out, const double* gam,
                         bool by_ev);
 
-// Sparse A (compressed sparse columns, with its row-compressed twin).
+// Sparse A (compressed sparse columns, with its row-compressed twin), plus
+// the chunk tables of the balanced products (first nonempty column / row of
+// every chunk of consecutive nonzeros; sparse_chunks(nnz) entries each).
 struct SparseA {
-  int64_t n, p;
+  int64_t n, p, nnz;
   const int64_t* col_ptr;
   const int32_t* row_idx;
   const float* col_val;
   const int64_t* row_ptr;
   const int32_t* col_idx;
   const float* row_val;
+  int32_t* col_first;
+  int32_t* row_first;
+  // row panels of the columns for A^T Y (npan = 0: none): panel P holds rows
+  // [P prow, (P + 1) prow); "major" P p + c is column c restricted to panel
+  // P, stored at pptr[P p + c] .. pptr[P p + c + 1] of pidx / pval
+  int32_t npan = 0;
+  int64_t prow = 0;
+  int64_t maxg = 0;         // chunk groups of the largest panel (set by the solve)
+  int64_t* pptr = nullptr;  // npan p + 1
+  int32_t* pidx = nullptr;
+  float* pval = nullptr;
+  int32_t* pfirst = nullptr;  // chunk table of the panel layout
+  int64_t* ptmp = nullptr;    // sparse_panel_tmp(npan, p) int64 of scratch
 };
-// U (r x n) = A X for dense X from the rows (XT: X transposed, p x ldxt);
-// runs in mode kAxDense
-void sparse_ax_dense(hipStream_t st, SparseA a, const float* XT, int64_t ldxt, int64_t r,
-                     float* U, int64_t ldu, const Plan* plan);
+int64_t sparse_chunks(int64_t nnz);
+// panels for A^T Y: 0 (none) or a multiple of the XCD count, from the size of
+// a panel's slice of YT; force: 1 on, -1 off, 0 by size
+int32_t sparse_panels(int64_t n, int64_t p, int64_t nnz, int64_t ldt, int force);
+int64_t sparse_panel_tmp(int32_t npan, int64_t p);
+// builds the panel layout from the (validated) columns
+void sparse_build_panels(hipStream_t st, SparseA& a);
+// chunk groups of the largest panel, from the panel starts pptr[P p]
+int64_t sparse_panel_groups(const int64_t* starts, int32_t npan);
+// leading dimension of the transposed operands and products for r starts
+int64_t sparse_ld(int64_t r);
+// partial pairs per start of sparse_final
+int64_t sparse_final_parts(int64_t n);
+// checks (bits or-ed into *bad: 1 a pointer array decreases, 2 an index out
+// of range, 4 row indices of a column not strictly increasing) and builds
+// the chunk tables; reads only inside the arrays as sized by nnz
+void sparse_prepare(hipStream_t st, const SparseA& a, int32_t* bad);
+// U (r x n) = A X for dense X from the rows (XT: X transposed, p x ldxt;
+// UT: n x ldxt; carry: 2 * sparse_chunks(nnz) x ldxt); runs in mode
+// kAxDense, for the running starts
+void sparse_ax_dense(hipStream_t st, const SparseA& a, const float* XT, int64_t ldxt,
+                     int64_t r, float* UT, float* carry, float* U, int64_t ldu,
+                     StartState s, const Plan* plan);
+// y-update of the running starts from start-major U straight into YT (n x
+// ldt); partial: r * sparse_y_parts(n) doubles
+int64_t sparse_y_parts(int64_t n);
+void sparse_y_update(hipStream_t st, int fid, const float* U, int64_t ldu, int64_t n,
+                     int64_t r, StartState s, double* partial, float* YT, int64_t ldt);
 // U row j = sum over the start's support columns; runs in mode kAxListRows
-void sparse_ax_list(hipStream_t st, SparseA a, const int32_t* list_idx,
+void sparse_ax_list(hipStream_t st, const SparseA& a, const int32_t* list_idx,
                     const float* list_val, int64_t ldl, float* U, int64_t ldu, int64_t r,
                     StartState s, const Plan* plan);
-// V (r x p) = A^T Y from the columns (YT: Y transposed, n x ldyt)
-void sparse_aty(hipStream_t st, SparseA a, const float* YT, int64_t ldyt, int64_t r,
-                float* V, int64_t ldv);
-// per-start partial sums of the FP64 u = A x / ||x|| for objective_and_best
-void sparse_final(hipStream_t st, SparseA a, const int32_t* list_idx,
+// V (r x p) = A^T Y from the columns, or from their row panels when
+// a.npan > 0 (YT: Y transposed, n x ldyt; VT: max(npan, 1) p x ldyt; carry
+// as above), for the running starts
+void sparse_aty(hipStream_t st, const SparseA& a, const float* YT, int64_t ldyt, int64_t r,
+                float* VT, float* carry, float* V, int64_t ldv, StartState s,
+                const Plan* plan);
+// per-start partial pairs (sparse_final_parts(n) each) of the FP64
+// u = A x / ||x|| for objective_and_best
+void sparse_final(hipStream_t st, const SparseA& a, const int32_t* list_idx,
                   const float* list_val, int64_t ldl, StartState s, int64_t r,
-                  const double* xnorm, double* u64, double* partial);
+                  const double* xnorm, double* partial);
 
 // On-the-fly replacement of finished starts (Section 4.3): state of the
 // slots and of the total_starts starts that flow through them.

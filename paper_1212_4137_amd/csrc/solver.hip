@@ -900,6 +900,10 @@ int spca_am_solve_sparse(spca_ctx* ctx, void* stream, const spca_sparse_problem*
   SPCA_REQUIRE(prob->col_ptr && prob->row_idx && prob->col_val && prob->row_ptr &&
                    prob->col_idx && prob->row_val,
                "every array of the sparse matrix must be set");
+  SPCA_REQUIRE(((uintptr_t)prob->row_idx | (uintptr_t)prob->col_val | (uintptr_t)prob->col_idx |
+                (uintptr_t)prob->row_val | (uintptr_t)prob->col_ptr |
+                (uintptr_t)prob->row_ptr) % 16 == 0,
+               "the arrays of the sparse matrix must be 16-byte aligned");
   SPCA_REQUIRE(opts->X0 != nullptr, "the sparse solve needs X0");
   SPCA_REQUIRE(opts->precision == SPCA_PREC_FP32, "the sparse solve runs in FP32");
   SPCA_REQUIRE(opts->total_starts <= r && opts->deflate_k == 0,
@@ -917,16 +921,45 @@ int spca_am_solve_sparse(spca_ctx* ctx, void* stream, const spca_sparse_problem*
   DeviceGuard g(ctx->device);
   hipStream_t st = (hipStream_t)stream;
 
-  // workspace: the iterates of the dense path plus the transposed operands
-  // and an FP64 row per start for the final evaluation
-  const int64_t ldx = round_up(p, 4), ldu = round_up(n, 4), ldt = round_up(r, 4);
+  // nnz from the two pointer arrays (their first entries must be 0 and
+  // their last ones equal)
+  int64_t ends[4];
+  SPCA_HIP_TRY(hipMemcpyAsync(&ends[0], prob->col_ptr, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  SPCA_HIP_TRY(hipMemcpyAsync(&ends[1], prob->col_ptr + p, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  SPCA_HIP_TRY(hipMemcpyAsync(&ends[2], prob->row_ptr, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  SPCA_HIP_TRY(hipMemcpyAsync(&ends[3], prob->row_ptr + n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  SPCA_HIP_TRY(hipStreamSynchronize(st));
+  SPCA_REQUIRE(ends[0] == 0 && ends[2] == 0 && ends[1] == ends[3] && ends[1] >= 0,
+               "col_ptr and row_ptr must start at 0 and end at the same nnz");
+  const int64_t nnz = ends[1];
+
+  // workspace: the iterates of the dense path, the transposed operands and
+  // products, the chunk tables and partials of the balanced products, and
+  // the partials of the final evaluation
+  const int64_t ldx = round_up(p, 4), ldu = round_up(n, 4), ldt = sparse_ld(r);
+  const int64_t nch = sparse_chunks(nnz), nfin = sparse_final_parts(n);
+  const int force = (opts->flags & SPCA_FLAG_SPARSE_PANELS)      ? 1
+                    : (opts->flags & SPCA_FLAG_SPARSE_NO_PANELS) ? -1
+                                                                 : 0;
+  const int32_t npan = sparse_panels(n, p, nnz, ldt, force);
   size_t c = 0;
   const size_t o_X = carve(&c, sizeof(float) * r * ldx);
   const size_t o_XT = carve(&c, sizeof(float) * p * ldt);
   const size_t o_U = carve(&c, sizeof(float) * r * ldu);
-  const size_t o_Y = carve(&c, sizeof(float) * r * ldu);
+  const size_t o_UT = carve(&c, sizeof(float) * n * ldt);
+  const size_t o_ypart = carve(&c, sizeof(double) * r * sparse_y_parts(n));
   const size_t o_YT = carve(&c, sizeof(float) * n * ldt);
   const size_t o_V = carve(&c, sizeof(float) * r * ldx);
+  const size_t o_VT = carve(&c, sizeof(float) * (npan > 0 ? npan : 1) * p * ldt);
+  const size_t o_pptr = carve(&c, sizeof(int64_t) * (npan * p + 1));
+  const size_t o_pidx = carve(&c, npan > 0 ? sizeof(int32_t) * nnz : 0);
+  const size_t o_pval = carve(&c, npan > 0 ? sizeof(float) * nnz : 0);
+  const size_t o_pfirst = carve(&c, npan > 0 ? sizeof(int32_t) * nch : 0);
+  const size_t o_ptmp = carve(&c, npan > 0 ? sizeof(int64_t) * sparse_panel_tmp(npan, p) : 0);
+  const size_t o_carry = carve(&c, sizeof(float) * 2 * nch * ldt);
+  const size_t o_cf = carve(&c, sizeof(int32_t) * nch);
+  const size_t o_rf = carve(&c, sizeof(int32_t) * nch);
+  const size_t o_bad = carve(&c, sizeof(int32_t));
   const size_t o_li = carve(&c, sizeof(int32_t) * r * ldx);
   const size_t o_lv = carve(&c, sizeof(float) * r * ldx);
   const size_t o_phi = carve(&c, sizeof(double) * r);
@@ -935,7 +968,7 @@ int spca_am_solve_sparse(spca_ctx* ctx, void* stream, const spca_sparse_problem*
   const size_t o_it = carve(&c, sizeof(int32_t) * r);
   const size_t o_st = carve(&c, sizeof(int32_t) * r);
   const size_t o_plan = carve(&c, sizeof(Plan));
-  const size_t o_part = carve(&c, sizeof(double) * 2 * r);
+  const size_t o_part = carve(&c, sizeof(double) * 2 * r * nfin);
   const size_t o_f = carve(&c, sizeof(double) * r);
   const size_t o_ev = carve(&c, sizeof(double) * r);
   const size_t o_xn = carve(&c, sizeof(double) * 2 * r);
@@ -944,7 +977,6 @@ int spca_am_solve_sparse(spca_ctx* ctx, void* stream, const spca_sparse_problem*
   const size_t o_sup = carve(&c, sizeof(int32_t) * p);
   const size_t o_mark = carve(&c, sizeof(int32_t) * p);
   const size_t o_ul = carve(&c, sizeof(int32_t) * p);
-  const size_t o_u64 = carve(&c, sizeof(double) * r * n);
   const size_t o_gam = carve(&c, sizeof(double) * r);
   const size_t wide_bytes = x_update_wide_bytes(1, r, p);
   const size_t o_wide = carve(&c, wide_bytes);
@@ -954,9 +986,13 @@ int spca_am_solve_sparse(spca_ctx* ctx, void* stream, const spca_sparse_problem*
   float* X = (float*)(base + o_X);
   float* XT = (float*)(base + o_XT);
   float* U = (float*)(base + o_U);
-  float* Y = (float*)(base + o_Y);
+  float* UT = (float*)(base + o_UT);
+  double* ypart = (double*)(base + o_ypart);
   float* YT = (float*)(base + o_YT);
   float* V = (float*)(base + o_V);
+  float* VT = (float*)(base + o_VT);
+  float* carry = (float*)(base + o_carry);
+  int32_t* bad = (int32_t*)(base + o_bad);
   int32_t* li = (int32_t*)(base + o_li);
   float* lv = (float*)(base + o_lv);
   StartState s{(double*)(base + o_phi), (double*)(base + o_phip), (int32_t*)(base + o_nnz),
@@ -971,7 +1007,6 @@ int spca_am_solve_sparse(spca_ctx* ctx, void* stream, const spca_sparse_problem*
   int32_t* sup = (int32_t*)(base + o_sup);
   int32_t* colmark = (int32_t*)(base + o_mark);
   int32_t* ulist = (int32_t*)(base + o_ul);
-  double* u64 = (double*)(base + o_u64);
   double* gam = (double*)(base + o_gam);
   void* wide = wide_bytes ? (void*)(base + o_wide) : nullptr;
   Warm wm;
@@ -980,8 +1015,36 @@ int spca_am_solve_sparse(spca_ctx* ctx, void* stream, const spca_sparse_problem*
     wm.target = fid >= 5 ? opts->target_nnz : 0;
     wm.gam = gam;
   }
-  const SparseA a{n, p, prob->col_ptr, prob->row_idx, prob->col_val,
-                  prob->row_ptr, prob->col_idx, prob->row_val};
+  SparseA a{n, p, nnz, prob->col_ptr, prob->row_idx, prob->col_val, prob->row_ptr,
+            prob->col_idx, prob->row_val, (int32_t*)(base + o_cf), (int32_t*)(base + o_rf)};
+
+  // validation and chunk tables (every later kernel relies on them)
+  SPCA_HIP_TRY(hipMemsetAsync(bad, 0, sizeof(int32_t), st));
+  sparse_prepare(st, a, bad);
+  SPCA_LAUNCH_CHECK("sparse validation");
+  int32_t hbad = 0;
+  SPCA_HIP_TRY(hipMemcpyAsync(&hbad, bad, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  SPCA_HIP_TRY(hipStreamSynchronize(st));
+  SPCA_REQUIRE(!(hbad & 1), "col_ptr or row_ptr decreases");
+  SPCA_REQUIRE(!(hbad & 2), "a row or column index is out of range");
+  SPCA_REQUIRE(!(hbad & 4), "the row indices of a column must be strictly increasing");
+  if (npan > 0) {
+    a.npan = npan;
+    a.prow = ceil_div(n, (int64_t)npan);
+    a.pptr = (int64_t*)(base + o_pptr);
+    a.pidx = (int32_t*)(base + o_pidx);
+    a.pval = (float*)(base + o_pval);
+    a.pfirst = (int32_t*)(base + o_pfirst);
+    a.ptmp = (int64_t*)(base + o_ptmp);
+    sparse_build_panels(st, a);
+    SPCA_LAUNCH_CHECK("sparse row panels");
+    std::vector<int64_t> starts(npan + 1);
+    for (int32_t P = 0; P <= npan; ++P)
+      SPCA_HIP_TRY(hipMemcpyAsync(&starts[P], a.pptr + P * p, sizeof(int64_t),
+                                  hipMemcpyDeviceToHost, st));
+    SPCA_HIP_TRY(hipStreamSynchronize(st));
+    a.maxg = sparse_panel_groups(starts.data(), npan);
+  }
 
   SPCA_HIP_TRY(hipMemcpy2DAsync(X, sizeof(float) * ldx, opts->X0, sizeof(float) * p,
                                 sizeof(float) * p, r, hipMemcpyDeviceToDevice, st));
@@ -999,11 +1062,10 @@ int spca_am_solve_sparse(spca_ctx* ctx, void* stream, const spca_sparse_problem*
   const int32_t maxit = opts->maxit;
   auto iteration = [&](hipStream_t q) -> int {
     transpose_f32(q, X, ldx, XT, ldt, p, r);
-    sparse_ax_dense(q, a, XT, ldt, r, U, ldu, plan);
+    sparse_ax_dense(q, a, XT, ldt, r, UT, carry, U, ldu, s, plan);
     sparse_ax_list(q, a, li, lv, ldx, U, ldu, r, s, plan);
-    y_update(q, fid, U, r * ldu, Y, ldu, r, n, s, plan, nullptr, 0);
-    transpose_f32(q, Y, ldu, YT, ldt, n, r);
-    sparse_aty(q, a, YT, ldt, r, V, ldx);
+    sparse_y_update(q, fid, U, ldu, n, r, s, ypart, YT, ldt);
+    sparse_aty(q, a, YT, ldt, r, VT, carry, V, ldx, s, plan);
     x_update(q, fid, sg, V, ldx, r, p, X, ldx, li, lv, ldx, list_cap, s, opts->tol, maxit,
              colmark, plan, wide, wm);
     plan_next(q, s, r, n, p, list_cap, 0, 1, 0, colmark, ulist, plan, 1);
@@ -1066,9 +1128,9 @@ int spca_am_solve_sparse(spca_ctx* ctx, void* stream, const spca_sparse_problem*
   // FP64 evaluation on the sparse matrix
   compact_rows(st, X, ldx, r, p, li, lv, ldx, s.nnz, nullptr, nullptr, nullptr);
   x_norms(st, lv, ldx, s, r, xnorm);
-  sparse_final(st, a, li, lv, ldx, s, r, xnorm, u64, partial);
+  sparse_final(st, a, li, lv, ldx, s, r, xnorm, partial);
   const bool per_start_gamma = warm && fid >= 5;
-  objective_and_best(st, fid, sg, s, r, p, partial, 1, li, lv, ldx, xnorm, fj, evj, best,
+  objective_and_best(st, fid, sg, s, r, p, partial, (int)nfin, li, lv, ldx, xnorm, fj, evj, best,
                      xout, sup, per_start_gamma ? gam : nullptr, per_start_gamma);
   SPCA_LAUNCH_CHECK("sparse finalize");
 

@@ -77,3 +77,114 @@ def test_sparse_warmup_and_checks(spca):
     assert ok.mean() >= 0.9
     with pytest.raises(spca.SpcaError):
         spca.am_solve_sparse(D, 1, 5000.0, to_device_rows(X0n))
+
+
+def _from_columns(n, cols):
+    """SparseMatrix from per-column (rows, values), rows ascending."""
+    p = len(cols)
+    col_ptr = np.zeros(p + 1, dtype=np.int64)
+    col_ptr[1:] = np.cumsum([len(rw) for rw, _ in cols])
+    row_idx = np.concatenate([rw for rw, _ in cols]).astype(np.int32)
+    col_val = np.concatenate([v for _, v in cols]).astype(np.float32)
+    col = np.repeat(np.arange(p), np.diff(col_ptr))
+    order = np.lexsort((col, row_idx))
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(np.bincount(row_idx, minlength=n), out=row_ptr[1:])
+    return sparse.SparseMatrix(n, p, col_ptr, row_idx, col_val, row_ptr,
+                               col[order].astype(np.int32), col_val[order])
+
+
+def _chunk_boundary_matrix():
+    """Columns laid out so that nonzero chunks of 2048 end exactly at column
+    ends followed by empty columns, one column spans several chunks, and the
+    first and last columns and rows are empty."""
+    rng = np.random.default_rng(0x5BA5E)
+    n = 5000
+
+    def col(k, lo=5, hi=4990):
+        rows = np.sort(rng.choice(np.arange(lo, hi), size=k, replace=False))
+        return rows, rng.integers(1, 6, size=k).astype(np.float32)
+
+    empty = (np.zeros(0, np.int64), np.zeros(0, np.float32))
+    cols = [empty, col(2048), empty, empty, col(2148), col(1948), empty, col(4980, 5, 4985)]
+    cols += [col(int(k)) for k in rng.integers(1, 41, size=300)]
+    cols += [empty, empty, empty]
+    mat = _from_columns(n, cols)
+    assert mat.col_ptr[2] == 2048 and mat.col_ptr[6] == 3 * 2048
+    return mat
+
+
+@pytest.mark.parametrize("r", [4, 12, 20, 33, 40, 70])
+@pytest.mark.parametrize("panels", [False, True])
+def test_sparse_chunk_boundaries(spca, r, panels):
+    """Every start-block width of the balanced products (4 .. 32 starts per
+    block; two or three blocks above 32) over chunk-aligned column ends,
+    empty columns and rows, and a column crossing several chunks; with and
+    without the row-panel copy of the columns."""
+    print(f"sparse chunk boundaries r={r} panels={panels}", flush=True)
+    mat = _chunk_boundary_matrix()
+    X0n = workloads.random_unit_starts(48 + r, r, mat.p)
+    D = spca.sparse_to_device(mat)
+    flags = spca.FLAG_SPARSE_PANELS if panels else spca.FLAG_SPARSE_NO_PANELS
+    for fid, par in ((1, 10.0), (6, workloads.s_or_gamma_for(6, mat.dense(), 10, "scaled"))):
+        got = spca.am_solve_sparse(D, fid, par, to_device_rows(X0n), tol=1e-8, maxit=200,
+                                   flags=flags)
+        ref = oracle.am_multi_csc(mat.col_ptr, mat.row_idx, mat.col_val.astype(np.float64),
+                                  mat.n, mat.p, fid, par, X0n.astype(np.float64), 1e-8, 200,
+                                  nthreads=8)
+        compare_solve(got, ref, f"sparse boundaries F{fid} r={r} panels={panels}")
+
+
+def test_sparse_heavy_column(spca):
+    """Zipf words steep enough that the top column holds most documents and
+    crosses many nonzero chunks; parity with the oracle and with the dense
+    GPU path."""
+    mat = sparse.bag_of_words(47, 30000, 400, 600000, zipf=1.3)
+    assert np.diff(mat.col_ptr).max() > 8 * 2048
+    X0n = workloads.random_unit_starts(49, 20, mat.p)
+    D = spca.sparse_to_device(mat)
+    ref = oracle.am_multi_csc(mat.col_ptr, mat.row_idx, mat.col_val.astype(np.float64), mat.n,
+                              mat.p, 1, 5.0, X0n.astype(np.float64), 1e-8, 300, nthreads=8)
+    dense = spca.am_solve(to_device_colmajor(mat.dense().astype(np.float32)), 1, 5.0,
+                          to_device_rows(X0n), tol=1e-8, maxit=300)
+    for flags in (spca.FLAG_SPARSE_NO_PANELS, spca.FLAG_SPARSE_PANELS,
+                  spca.FLAG_SPARSE_PANELS | spca.FLAG_GRAPH):
+        got = spca.am_solve_sparse(D, 1, 5.0, to_device_rows(X0n), tol=1e-8, maxit=300,
+                                   flags=flags, return_X=True)
+        compare_solve(got, ref, f"sparse heavy column flags={flags}")
+        assert rel_err(got["objective"], dense["objective"]) <= 1e-5
+        if flags & spca.FLAG_GRAPH:
+            assert torch.equal(got["X_final"], eager["X_final"])
+        eager = got
+
+
+def test_sparse_rejects_malformed(spca):
+    """Malformed arrays (sized consistently with their pointer arrays) are
+    rejected by the solve's checks before any product runs."""
+    mat = _chunk_boundary_matrix()
+    X0 = to_device_rows(workloads.random_unit_starts(50, 4, mat.p))
+    base = spca.sparse_to_device(mat)
+    spca.am_solve_sparse(base, 1, 10.0, X0, maxit=5)
+
+    def bad(**repl):
+        D = dict(base)
+        for k, v in repl.items():
+            D[k] = torch.from_numpy(v).cuda()
+        with pytest.raises(spca.SpcaError):
+            spca.am_solve_sparse(D, 1, 10.0, X0, maxit=5)
+
+    ri = mat.row_idx.copy()
+    ri[3000] = mat.n
+    bad(row_idx=ri)
+    ci = mat.col_idx.copy()
+    ci[10] = -1
+    bad(col_idx=ci)
+    ri = mat.row_idx.copy()
+    ri[[100, 101]] = ri[[101, 100]]
+    bad(row_idx=ri)
+    cp = mat.col_ptr.copy()
+    cp[[5, 6]] = cp[[6, 5]]
+    bad(col_ptr=cp)
+    rp = mat.row_ptr.copy()
+    rp[-1] -= 1
+    bad(row_ptr=rp)
