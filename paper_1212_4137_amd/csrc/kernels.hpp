@@ -305,22 +305,27 @@ struct SparseA {
   // P, stored at pptr[P p + c] .. pptr[P p + c + 1] of pidx / pval
   int32_t npan = 0;
   int64_t prow = 0;
-  int64_t maxg = 0;         // chunk groups of the largest panel (set by the solve)
   int64_t* pptr = nullptr;  // npan p + 1
   int32_t* pidx = nullptr;
   float* pval = nullptr;
   int32_t* pfirst = nullptr;  // chunk table of the panel layout
   int64_t* ptmp = nullptr;    // sparse_panel_tmp(npan, p) int64 of scratch
+  // majors crossing a chunk boundary (sparse_chunks(nnz) entries each): rows
+  // of the row layout, columns (or panel majors) of the column layout
+  int32_t* row_split = nullptr;
+  int32_t* col_split = nullptr;
+  int64_t nrow_split = 0, ncol_split = 0;
 };
 int64_t sparse_chunks(int64_t nnz);
-// panels for A^T Y: 0 (none) or a multiple of the XCD count, from the size of
-// a panel's slice of YT; force: 1 on, -1 off, 0 by size
+// panels for A^T Y: 0 (none) or the count that keeps each panel's slice of
+// YT within the gather window; force: 1 on, -1 off, 0 by size
 int32_t sparse_panels(int64_t n, int64_t p, int64_t nnz, int64_t ldt, int force);
 int64_t sparse_panel_tmp(int32_t npan, int64_t p);
 // builds the panel layout from the (validated) columns
 void sparse_build_panels(hipStream_t st, SparseA& a);
-// chunk groups of the largest panel, from the panel starts pptr[P p]
-int64_t sparse_panel_groups(const int64_t* starts, int32_t npan);
+// lists the majors crossing chunk boundaries of both layouts (after the
+// panels, if any); counts[0] (rows) and counts[1] (columns) must be zero
+void sparse_split_lists(hipStream_t st, const SparseA& a, int32_t* counts);
 // leading dimension of the transposed operands and products for r starts
 int64_t sparse_ld(int64_t r);
 // partial pairs per start of sparse_final

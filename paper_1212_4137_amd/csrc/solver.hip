@@ -959,7 +959,9 @@ int spca_am_solve_sparse(spca_ctx* ctx, void* stream, const spca_sparse_problem*
   const size_t o_carry = carve(&c, sizeof(float) * 2 * nch * ldt);
   const size_t o_cf = carve(&c, sizeof(int32_t) * nch);
   const size_t o_rf = carve(&c, sizeof(int32_t) * nch);
-  const size_t o_bad = carve(&c, sizeof(int32_t));
+  const size_t o_cs = carve(&c, sizeof(int32_t) * nch);
+  const size_t o_rs = carve(&c, sizeof(int32_t) * nch);
+  const size_t o_bad = carve(&c, sizeof(int32_t) * 4);
   const size_t o_li = carve(&c, sizeof(int32_t) * r * ldx);
   const size_t o_lv = carve(&c, sizeof(float) * r * ldx);
   const size_t o_phi = carve(&c, sizeof(double) * r);
@@ -1038,13 +1040,21 @@ int spca_am_solve_sparse(spca_ctx* ctx, void* stream, const spca_sparse_problem*
     a.ptmp = (int64_t*)(base + o_ptmp);
     sparse_build_panels(st, a);
     SPCA_LAUNCH_CHECK("sparse row panels");
-    std::vector<int64_t> starts(npan + 1);
-    for (int32_t P = 0; P <= npan; ++P)
-      SPCA_HIP_TRY(hipMemcpyAsync(&starts[P], a.pptr + P * p, sizeof(int64_t),
-                                  hipMemcpyDeviceToHost, st));
-    SPCA_HIP_TRY(hipStreamSynchronize(st));
-    a.maxg = sparse_panel_groups(starts.data(), npan);
   }
+  // majors crossing chunk boundaries; products leave the rows of empty
+  // majors alone, so the transposed products start at zero
+  a.row_split = (int32_t*)(base + o_rs);
+  a.col_split = (int32_t*)(base + o_cs);
+  SPCA_HIP_TRY(hipMemsetAsync(bad + 1, 0, 2 * sizeof(int32_t), st));
+  sparse_split_lists(st, a, bad + 1);
+  SPCA_LAUNCH_CHECK("sparse split lists");
+  SPCA_HIP_TRY(hipMemsetAsync(UT, 0, sizeof(float) * n * ldt, st));
+  SPCA_HIP_TRY(hipMemsetAsync(VT, 0, sizeof(float) * (npan > 0 ? npan : 1) * p * ldt, st));
+  int32_t nsplit[2];
+  SPCA_HIP_TRY(hipMemcpyAsync(nsplit, bad + 1, sizeof(nsplit), hipMemcpyDeviceToHost, st));
+  SPCA_HIP_TRY(hipStreamSynchronize(st));
+  a.nrow_split = nsplit[0];
+  a.ncol_split = nsplit[1];
 
   SPCA_HIP_TRY(hipMemcpy2DAsync(X, sizeof(float) * ldx, opts->X0, sizeof(float) * p,
                                 sizeof(float) * p, r, hipMemcpyDeviceToDevice, st));

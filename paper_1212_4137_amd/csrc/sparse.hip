@@ -37,8 +37,13 @@ constexpr int kWPB = 4;       // waves per workgroup
 constexpr int kTT = 64;       // tile of the transposed-to-start-major copy
 constexpr int kRB = 8192;     // rows per block, FP32 list product (32 KB LDS)
 constexpr int kRB64 = 4096;   // rows per block, FP64 evaluation (32 KB LDS)
-constexpr int kXcd = 8;       // XCDs; workgroup i of a launch runs on XCD i % 8
-constexpr int64_t kPanelBytes = 3 << 20;  // a panel's slice of YT, within one L2
+// gathers of rows spread over more than about 16 MB run several times slower
+// than within it (address translation reach, measured on MI355X); a panel's
+// slice of YT stays well inside that window
+#ifndef SPCA_PANEL_BYTES
+#define SPCA_PANEL_BYTES (8 << 20)
+#endif
+constexpr int64_t kPanelBytes = SPCA_PANEL_BYTES;
 constexpr int kScanB = 4096;  // elements per block of the panel offset scan
 
 // --------------------------------------------------------------------------
@@ -100,8 +105,8 @@ __global__ __launch_bounds__(256) void sp_check_sorted_kernel(
 }
 
 // --------------------------------------------------------------------------
-// row panels of the columns (for A^T Y): every XCD gathers from its own
-// slice of YT, which stays in its L2
+// row panels of the columns (for A^T Y): the chunks run in panel order, so
+// at any time the gathers fall into one or two panels' slices of YT
 // --------------------------------------------------------------------------
 
 // first position in [lo, hi) whose index is >= target (hi if none)
@@ -178,22 +183,29 @@ __global__ __launch_bounds__(1024) void sp_scan_out_kernel(const int64_t* __rest
   if (blockIdx.x == 0 && threadIdx.x == 0) pptr[len] = bsum[nb];
 }
 
-// copies every (panel, column) segment into the panel layout; one wave per
-// segment
+// copies the columns into the panel layout, one wave per chunk of kW
+// destination positions (walking the panel majors of the chunk from its
+// first one)
 __global__ __launch_bounds__(256) void sp_pan_copy_kernel(
-    const int64_t* __restrict__ src, const int64_t* __restrict__ cnt,
-    const int64_t* __restrict__ pptr, int64_t len, const int32_t* __restrict__ row_idx,
+    const int64_t* __restrict__ src, const int64_t* __restrict__ pptr, int64_t len,
+    int64_t nnz, const int32_t* __restrict__ pfirst, const int32_t* __restrict__ row_idx,
     const float* __restrict__ col_val, int32_t* __restrict__ pidx,
     float* __restrict__ pval) {
   const int lane = threadIdx.x % kWave;
-  for (int64_t M = (int64_t)blockIdx.x * kWPB +
-                   __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-       M < len; M += (int64_t)gridDim.x * kWPB) {
-    const int64_t s0 = src[M], d0 = pptr[M], k = cnt[M];
-    for (int64_t t = lane; t < k; t += kWave) {
-      pidx[d0 + t] = row_idx[s0 + t];
-      pval[d0 + t] = col_val[s0 + t];
+  const int64_t w =
+      (int64_t)blockIdx.x * kWPB + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int64_t lo = w * kW;
+  if (lo >= nnz) return;
+  const int64_t hi = lo + kW < nnz ? lo + kW : nnz;
+  int64_t M = pfirst[w];
+  for (int64_t k = lo; k < hi && M < len; ++M) {
+    const int64_t e = pptr[M + 1] < hi ? pptr[M + 1] : hi;
+    const int64_t off = src[M] - pptr[M];  // source position - destination position
+    for (int64_t t = k + lane; t < e; t += kWave) {
+      pidx[t] = row_idx[t + off];
+      pval[t] = col_val[t + off];
     }
+    k = e > k ? e : k;
   }
 }
 
@@ -216,9 +228,10 @@ enum SegGate { kGateNone = 0, kGateDense = 1, kGateActive = 2 };
 // touches one cache line per row; every lane keeps the running sums of its
 // four starts for the current major.  The indices and values reach the wave
 // kSS at a time through LDS: the next stage is loaded with coalesced 16-byte
-// loads while the current one is worked off, kU rows per lane at a time,
-// independent of where majors begin and end; where a major ends, the sums of
-// the 64 / L nonzero slots are combined by a fixed xor butterfly and written.
+// loads while the current one is worked off in steps of kU 64 / L nonzeros
+// (each of the 64 / L lane slots takes kU consecutive ones), independent of
+// where majors begin and end; where a major ends, the sums of the slots are
+// combined by a fixed xor butterfly and written.
 // OFF32: every byte offset into BT fits in 32 bits.
 constexpr int kU = 8;      // row loads per lane and step
 constexpr int kSS = 512;   // nonzeros per stage
@@ -229,10 +242,10 @@ __global__ __launch_bounds__(256) void sp_seg_kernel(
     const float* __restrict__ val, int64_t m, int64_t nnz,
     const int32_t* __restrict__ first, const float* __restrict__ BT, int64_t ldb, int64_t r,
     float* __restrict__ OT, int64_t ldo, float* __restrict__ carry, const Plan* plan,
-    int gate, int64_t pan_p, int64_t maxg) {
+    int gate) {
   constexpr int NPI = kWave / L;      // nonzeros per load instruction
   constexpr int NS = kU * NPI;        // nonzeros per step
-  static_assert(kSS % NS == 0, "a stage holds whole steps");
+  static_assert(kSS % NS == 0 && kU % 4 == 0, "a stage holds whole steps");
   __shared__ int32_t sidx[kWPB][2][kSS];
   __shared__ float sval[kWPB][2][kSS];
   if ((gate & kGateDense) && plan->mode != kAxDense) return;
@@ -243,20 +256,7 @@ __global__ __launch_bounds__(256) void sp_seg_kernel(
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int slot = lane / L, quad = lane % L;
   const int64_t j0 = (int64_t)blockIdx.y * 4 * L + 4 * quad;  // this lane's first start
-  int64_t w;
-  if (maxg == 0) {
-    w = (int64_t)blockIdx.x * kWPB + wv;
-  } else {
-    // panels: the workgroups of XCD x take the chunks of panels x, x + 8, ..
-    // (in that order); a chunk belongs to the panel holding its first
-    // nonzero.  m / pan_p panels of pan_p majors each.
-    const int64_t x = blockIdx.x % kXcd, l = blockIdx.x / kXcd;
-    const int64_t P = x + kXcd * (l / maxg);
-    if (P >= m / pan_p) return;
-    const int64_t w0 = ceil_div(ptr[P * pan_p], kW), w1 = ceil_div(ptr[(P + 1) * pan_p], kW);
-    w = w0 + (l % maxg) * kWPB + wv;
-    if (w >= w1) return;
-  }
+  const int64_t w = (int64_t)blockIdx.x * kWPB + wv;
   const int64_t lo = w * kW;
   if (lo >= nnz) return;
   const int64_t hi = lo + kW < nnz ? lo + kW : nnz;
@@ -325,13 +325,27 @@ __global__ __launch_bounds__(256) void sp_seg_kernel(
   for (int64_t sb = lo; sb < hi && open; sb += kSS, buf ^= 1) {
     const int64_t send = sb + kSS < hi ? sb + kSS : hi;
     for (int64_t tb = sb; tb < send && open; tb += NS) {
-      const int base = (int)(tb - sb) + slot;
+      // slot s takes positions tb + s kU .. tb + s kU + kU - 1 (wide LDS reads)
+      const int base = (int)(tb - sb) + slot * kU;
       float v[kU];
       float4 b[kU];
+      int32_t ii[kU];
+#pragma unroll
+      for (int u = 0; u < kU; u += 4) {
+        const int4 q4 = *reinterpret_cast<const int4*>(&sidx[wv][buf][base + u]);
+        const float4 f4 = *reinterpret_cast<const float4*>(&sval[wv][buf][base + u]);
+        ii[u] = q4.x;
+        ii[u + 1] = q4.y;
+        ii[u + 2] = q4.z;
+        ii[u + 3] = q4.w;
+        v[u] = f4.x;
+        v[u + 1] = f4.y;
+        v[u + 2] = f4.z;
+        v[u + 3] = f4.w;
+      }
 #pragma unroll
       for (int u = 0; u < kU; ++u) {
-        const int32_t i = sidx[wv][buf][base + u * NPI];
-        v[u] = sval[wv][buf][base + u * NPI];
+        const int32_t i = ii[u];
         if (OFF32)
           b[u] = *reinterpret_cast<const float4*>(
               reinterpret_cast<const char*>(BT) +
@@ -346,7 +360,7 @@ __global__ __launch_bounds__(256) void sp_seg_kernel(
         const int rhi = (int)((ce < bend ? ce : bend) - tb);
 #pragma unroll
         for (int u = 0; u < kU; ++u) {
-          const int rel = u * NPI + slot;
+          const int rel = slot * kU + u;
           if (rel >= rlo && rel < rhi) {
             acc.x = fmaf(v[u], b[u].x, acc.x);
             acc.y = fmaf(v[u], b[u].y, acc.y);
@@ -379,25 +393,23 @@ __global__ __launch_bounds__(256) void sp_seg_kernel(
   if (open) flush(acc, c, cb, ce);  // crosses into the next chunk
 }
 
-// majors crossing chunk boundaries: sum of their chunk partials in chunk
-// order; empty majors: zero.  One wave per major.
+// majors crossing chunk boundaries (listed once per solve): sum of their
+// chunk partials in chunk order.  One wave per listed major.
 __global__ __launch_bounds__(256) void sp_fix_kernel(const int64_t* __restrict__ ptr,
-                                                     int64_t m, const float* __restrict__ carry,
+                                                     const int32_t* __restrict__ split,
+                                                     int64_t nsplit,
+                                                     const float* __restrict__ carry,
                                                      int64_t r, float* __restrict__ OT,
                                                      int64_t ldo, const Plan* plan, int gate) {
   if ((gate & kGateDense) && plan->mode != kAxDense) return;
   if ((gate & kGateActive) && plan->active == 0) return;
-  const int64_t c =
+  const int64_t k =
       (int64_t)blockIdx.x * kWPB + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-  if (c >= m) return;
+  if (k >= nsplit) return;
   const int lane = threadIdx.x % kWave;
+  const int64_t c = split[k];
   const int64_t cb = ptr[c], ce = ptr[c + 1];
-  if (cb == ce) {
-    for (int64_t j = lane; j < r; j += kWave) OT[c * ldo + j] = 0.f;
-    return;
-  }
   const int64_t w0 = cb / kW, w1 = (ce - 1) / kW;
-  if (w0 == w1) return;
   const int64_t s0 = cb == w0 * kW ? 0 : 1;
   for (int64_t j = lane; j < r; j += kWave) {
     float acc = carry[(w0 * 2 + s0) * ldo + j];
@@ -405,6 +417,16 @@ __global__ __launch_bounds__(256) void sp_fix_kernel(const int64_t* __restrict__
     for (int64_t w = w0 + 1; w <= w1; ++w) acc += carry[w * 2 * ldo + j];
     OT[c * ldo + j] = acc;
   }
+}
+
+// the nonempty majors crossing a chunk boundary, in any order
+__global__ __launch_bounds__(256) void sp_split_list_kernel(const int64_t* __restrict__ ptr,
+                                                            int64_t m, int32_t* split,
+                                                            int32_t* count) {
+  const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (c >= m) return;
+  const int64_t cb = ptr[c], ce = ptr[c + 1];
+  if (cb < ce && cb / kW != (ce - 1) / kW) split[atomicAdd(count, 1)] = (int32_t)c;
 }
 
 // O[j][c] = sum over the npan panels of OT[P m + c][j] (in panel order),
@@ -623,53 +645,52 @@ __global__ __launch_bounds__(256) void sp_final_kernel(
 int seg_lanes(int64_t r) { return r <= 8 ? 2 : r <= 16 ? 4 : r <= 32 ? 8 : 16; }
 int64_t seg_blocks(int64_t r) { return ceil_div(r, (int64_t)4 * seg_lanes(r)); }
 
-// grid.x: chunk groups, or with panels XCDs x panel rounds x groups per panel
 template <int L>
 void launch_seg(hipStream_t st, const int64_t* ptr, const int32_t* idx, const float* val,
                 int64_t m, int64_t nnz, const int32_t* first, const float* BT, int64_t ldb,
                 int64_t minor, int64_t r, float* OT, int64_t ldo, float* carry,
-                const Plan* plan, int gate, int64_t pan_p, int64_t maxg) {
+                const Plan* plan, int gate) {
   const int64_t nchunks = ceil_div(nnz, kW);
   if (nchunks == 0) return;
-  const int64_t gx = maxg == 0 ? ceil_div(nchunks, (int64_t)kWPB)
-                               : (int64_t)kXcd * ceil_div(m / pan_p, (int64_t)kXcd) * maxg;
-  const dim3 g((unsigned)gx, (unsigned)seg_blocks(r));
+  const dim3 g((unsigned)ceil_div(nchunks, (int64_t)kWPB), (unsigned)seg_blocks(r));
   // BT (minor rows of ldb floats) within 4 GiB: 32-bit address arithmetic
   if (minor * ldb * (int64_t)sizeof(float) <= (int64_t)UINT32_MAX)
     hipLaunchKernelGGL((sp_seg_kernel<L, true>), g, dim3(256), 0, st, ptr, idx, val, m, nnz,
-                       first, BT, ldb, r, OT, ldo, carry, plan, gate, pan_p, maxg);
+                       first, BT, ldb, r, OT, ldo, carry, plan, gate);
   else
     hipLaunchKernelGGL((sp_seg_kernel<L, false>), g, dim3(256), 0, st, ptr, idx, val, m, nnz,
-                       first, BT, ldb, r, OT, ldo, carry, plan, gate, pan_p, maxg);
+                       first, BT, ldb, r, OT, ldo, carry, plan, gate);
 }
 
 // O (r x mo, start-major, ld) = the product of A's compressed layout (ptr,
-// idx, val; m = npan mo majors) with BT, through OT (m x ldo) and carry
+// idx, val; m = npan mo majors) with BT, through OT (m x ldo; the rows of
+// empty majors hold zeros) and carry; split: the majors crossing chunks
 void seg_product(hipStream_t st, const int64_t* ptr, const int32_t* idx, const float* val,
-                 int64_t m, int64_t nnz, const int32_t* first, const float* BT, int64_t ldb,
-                 int64_t minor, int64_t r, float* OT, int64_t ldo, float* carry, float* O, int64_t ld,
-                 const Plan* plan, int gate, int32_t npan, int64_t maxg) {
+                 int64_t m, int64_t nnz, const int32_t* first, const int32_t* split,
+                 int64_t nsplit, const float* BT, int64_t ldb, int64_t minor, int64_t r,
+                 float* OT, int64_t ldo, float* carry, float* O, int64_t ld, const Plan* plan,
+                 int gate, int32_t npan) {
   const int64_t mo = npan > 0 ? m / npan : m;
-  const int64_t mg = npan > 0 ? maxg : 0;
   switch (seg_lanes(r)) {
     case 2:
-      launch_seg<2>(st, ptr, idx, val, m, nnz, first, BT, ldb, minor, r, OT, ldo, carry, plan, gate,
-                    mo, mg);
+      launch_seg<2>(st, ptr, idx, val, m, nnz, first, BT, ldb, minor, r, OT, ldo, carry, plan,
+                    gate);
       break;
     case 4:
-      launch_seg<4>(st, ptr, idx, val, m, nnz, first, BT, ldb, minor, r, OT, ldo, carry, plan, gate,
-                    mo, mg);
+      launch_seg<4>(st, ptr, idx, val, m, nnz, first, BT, ldb, minor, r, OT, ldo, carry, plan,
+                    gate);
       break;
     case 8:
-      launch_seg<8>(st, ptr, idx, val, m, nnz, first, BT, ldb, minor, r, OT, ldo, carry, plan, gate,
-                    mo, mg);
+      launch_seg<8>(st, ptr, idx, val, m, nnz, first, BT, ldb, minor, r, OT, ldo, carry, plan,
+                    gate);
       break;
     default:
-      launch_seg<16>(st, ptr, idx, val, m, nnz, first, BT, ldb, minor, r, OT, ldo, carry, plan, gate,
-                     mo, mg);
+      launch_seg<16>(st, ptr, idx, val, m, nnz, first, BT, ldb, minor, r, OT, ldo, carry, plan,
+                     gate);
   }
-  hipLaunchKernelGGL(sp_fix_kernel, dim3((unsigned)ceil_div(m, (int64_t)kWPB)), dim3(256), 0,
-                     st, ptr, m, carry, r, OT, ldo, plan, gate);
+  if (nsplit > 0)
+    hipLaunchKernelGGL(sp_fix_kernel, dim3((unsigned)ceil_div(nsplit, (int64_t)kWPB)),
+                       dim3(256), 0, st, ptr, split, nsplit, carry, r, OT, ldo, plan, gate);
   const dim3 g((unsigned)ceil_div(mo, (int64_t)kTT), (unsigned)ceil_div(r, (int64_t)kTT));
   hipLaunchKernelGGL(sp_to_starts_kernel, g, dim3(256), 0, st, OT, ldo, mo, r,
                      npan > 0 ? npan : 1, O, ld, plan, gate);
@@ -684,12 +705,11 @@ int64_t sparse_ld(int64_t r) { return seg_blocks(r) * 4 * seg_lanes(r); }
 
 int32_t sparse_panels(int64_t n, int64_t p, int64_t nnz, int64_t ldt, int force) {
   (void)p;
-  const int64_t slice = ceil_div(n, (int64_t)kXcd) * ldt * (int64_t)sizeof(float);
-  if (force < 0 || n < kXcd || nnz == 0) return 0;
-  if (force == 0 && (n * ldt * (int64_t)sizeof(float) <= kPanelBytes || nnz < (1 << 20)))
-    return 0;
-  const int64_t rounds = ceil_div(slice, kPanelBytes);
-  return (int32_t)(kXcd * (rounds < 8 ? rounds : 8));
+  const int64_t bytes = n * ldt * (int64_t)sizeof(float);
+  if (force < 0 || n < 2 || nnz == 0) return 0;
+  if (force == 0 && (bytes <= 2 * kPanelBytes || nnz < (1 << 20))) return 0;
+  const int64_t np = std::max<int64_t>(2, ceil_div(bytes, kPanelBytes));
+  return (int32_t)std::min<int64_t>(np, std::min<int64_t>(n, 64));
 }
 
 int64_t sparse_panel_tmp(int32_t npan, int64_t p) {
@@ -697,13 +717,14 @@ int64_t sparse_panel_tmp(int32_t npan, int64_t p) {
   return 2 * len + ceil_div(len, (int64_t)kScanB) + 1;
 }
 
-int64_t sparse_panel_groups(const int64_t* starts, int32_t npan) {
-  int64_t g = 0;
-  for (int32_t P = 0; P < npan; ++P) {
-    const int64_t c = ceil_div(starts[P + 1], kW) - ceil_div(starts[P], kW);
-    g = std::max(g, ceil_div(c, (int64_t)kWPB));
-  }
-  return std::max<int64_t>(g, 1);
+void sparse_split_lists(hipStream_t st, const SparseA& a, int32_t* counts) {
+  if (a.nnz == 0) return;
+  hipLaunchKernelGGL(sp_split_list_kernel, dim3((unsigned)ceil_div(a.n, (int64_t)256)),
+                     dim3(256), 0, st, a.row_ptr, a.n, a.row_split, counts);
+  const int64_t mc = a.npan > 0 ? a.npan * a.p : a.p;
+  hipLaunchKernelGGL(sp_split_list_kernel, dim3((unsigned)ceil_div(mc, (int64_t)256)),
+                     dim3(256), 0, st, a.npan > 0 ? a.pptr : a.col_ptr, mc, a.col_split,
+                     counts + 1);
 }
 
 void sparse_build_panels(hipStream_t st, SparseA& a) {
@@ -718,14 +739,15 @@ void sparse_build_panels(hipStream_t st, SparseA& a) {
   hipLaunchKernelGGL(sp_scan_top_kernel, dim3(1), dim3(64), 0, st, bsum, nb);
   hipLaunchKernelGGL(sp_scan_out_kernel, dim3((unsigned)nb), dim3(1024), 0, st, cnt, len,
                      bsum, nb, a.pptr);
-  const unsigned gc = (unsigned)std::min<int64_t>(ceil_div(len, (int64_t)kWPB), 65536);
-  hipLaunchKernelGGL(sp_pan_copy_kernel, dim3(gc), dim3(256), 0, st, src, cnt, a.pptr, len,
-                     a.row_idx, a.col_val, a.pidx, a.pval);
   const int64_t nch = sparse_chunks(a.nnz);
   (void)hipMemsetAsync(a.pfirst, 0, sizeof(int32_t) * nch, st);
   hipLaunchKernelGGL(sp_first_kernel, dim3((unsigned)ceil_div(len, (int64_t)256)), dim3(256),
                      0, st, a.pptr, len, nch, a.pfirst);
+  hipLaunchKernelGGL(sp_pan_copy_kernel, dim3((unsigned)ceil_div(nch, (int64_t)kWPB)),
+                     dim3(256), 0, st, src, a.pptr, len, a.nnz, a.pfirst, a.row_idx,
+                     a.col_val, a.pidx, a.pval);
 }
+
 int64_t sparse_final_parts(int64_t n) { return ceil_div(n, (int64_t)kRB64); }
 
 void sparse_prepare(hipStream_t st, const SparseA& a, int32_t* bad) {
@@ -755,21 +777,21 @@ void sparse_prepare(hipStream_t st, const SparseA& a, int32_t* bad) {
 void sparse_ax_dense(hipStream_t st, const SparseA& a, const float* XT, int64_t ldxt,
                      int64_t r, float* UT, float* carry, float* U, int64_t ldu,
                      StartState s, const Plan* plan) {
-  seg_product(st, a.row_ptr, a.col_idx, a.row_val, a.n, a.nnz, a.row_first, XT, ldxt, a.p, r,
-              UT,
-              ldxt, carry, U, ldu, plan, kGateDense | kGateActive, 0, 0);
+  seg_product(st, a.row_ptr, a.col_idx, a.row_val, a.n, a.nnz, a.row_first, a.row_split,
+              a.nrow_split, XT, ldxt, a.p, r, UT, ldxt, carry, U, ldu, plan,
+              kGateDense | kGateActive, 0);
 }
 
 void sparse_aty(hipStream_t st, const SparseA& a, const float* YT, int64_t ldyt, int64_t r,
                 float* VT, float* carry, float* V, int64_t ldv, StartState s,
                 const Plan* plan) {
   if (a.npan > 0)
-    seg_product(st, a.pptr, a.pidx, a.pval, a.npan * a.p, a.nnz, a.pfirst, YT, ldyt, a.n, r,
-                VT,
-                ldyt, carry, V, ldv, plan, kGateActive, a.npan, a.maxg);
+    seg_product(st, a.pptr, a.pidx, a.pval, a.npan * a.p, a.nnz, a.pfirst, a.col_split,
+                a.ncol_split, YT, ldyt, a.n, r, VT, ldyt, carry, V, ldv, plan, kGateActive,
+                a.npan);
   else
-    seg_product(st, a.col_ptr, a.row_idx, a.col_val, a.p, a.nnz, a.col_first, YT, ldyt, a.n,
-                r, VT, ldyt, carry, V, ldv, plan, kGateActive, 0, 0);
+    seg_product(st, a.col_ptr, a.row_idx, a.col_val, a.p, a.nnz, a.col_first, a.col_split,
+                a.ncol_split, YT, ldyt, a.n, r, VT, ldyt, carry, V, ldv, plan, kGateActive, 0);
 }
 
 int64_t sparse_y_parts(int64_t n) { return ceil_div(n, (int64_t)kYB); }
