@@ -151,6 +151,30 @@ __global__ __launch_bounds__(1024) void argmax_start_kernel(
 // Lists of nonzeros of the rows of X, in index order
 // ---------------------------------------------------------------------------
 
+// 16 consecutive entries of a row from position i0 (zeros past len); one
+// 16-byte load per four entries when the whole run is inside and aligned
+template <typename T>
+__device__ __forceinline__ void load16(const T* __restrict__ a, int64_t i0, int64_t len,
+                                       T (&v)[16]) {
+  static_assert(sizeof(T) == 4, "4-byte entries");
+  if (i0 + 16 <= len && ((uintptr_t)(a + i0) & 15) == 0) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int4 w = *reinterpret_cast<const int4*>(a + i0 + 4 * q);
+      v[4 * q] = __builtin_bit_cast(T, w.x);
+      v[4 * q + 1] = __builtin_bit_cast(T, w.y);
+      v[4 * q + 2] = __builtin_bit_cast(T, w.z);
+      v[4 * q + 3] = __builtin_bit_cast(T, w.w);
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < 16; ++k) v[k] = i0 + k < len ? a[i0 + k] : T(0);
+  }
+}
+
+// One block per start: the (index, value) list of the row's nonzeros in
+// index order.  The row is read in passes of 16 consecutive entries per
+// thread (coalesced), one block scan per pass.
 __global__ __launch_bounds__(1024) void compact_rows_kernel(
     const float* __restrict__ X, int64_t ldx, int64_t p, int32_t* list_idx,
     float* list_val, int64_t ldl, int32_t* nnz, const int32_t* status,
@@ -161,23 +185,28 @@ __global__ __launch_bounds__(1024) void compact_rows_kernel(
   if (only != nullptr && only[j] == 0) return;
   const int32_t epoch = colmark != nullptr ? plan->epoch : 0;
   const float* x = X + j * ldx;
-  const int64_t chunk = ceil_div(p, blockDim.x);
-  const int64_t b = threadIdx.x * chunk;
-  const int64_t e = b + chunk < p ? b + chunk : p;
-  int cnt = 0;
-  for (int64_t i = b; i < e; ++i) cnt += x[i] != 0.f;
-  int total;
-  int off = block_exclusive_scan(cnt, scan, &total);
-  for (int64_t i = b; i < e; ++i) {
-    float v = x[i];
-    if (v != 0.f) {
-      list_idx[j * ldl + off] = (int32_t)i;
-      list_val[j * ldl + off] = v;
-      ++off;
-      if (colmark != nullptr) colmark[i] = epoch;
+  int run = 0;
+  for (int64_t base = 0; base < p; base += 16 * (int64_t)blockDim.x) {
+    const int64_t i0 = base + 16 * (int64_t)threadIdx.x;
+    float v[16];
+    load16(x, i0, p, v);
+    int cnt = 0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) cnt += v[k] != 0.f;
+    int total;
+    int off = run + block_exclusive_scan(cnt, scan, &total);
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      if (v[k] != 0.f) {
+        list_idx[j * ldl + off] = (int32_t)(i0 + k);
+        list_val[j * ldl + off] = v[k];
+        ++off;
+        if (colmark != nullptr) colmark[i0 + k] = epoch;
+      }
     }
+    run += total;
   }
-  if (threadIdx.x == 0) nnz[j] = total;
+  if (threadIdx.x == 0) nnz[j] = run;
 }
 
 __global__ void init_state_kernel(StartState s, int64_t r) {
@@ -227,14 +256,22 @@ __global__ __launch_bounds__(1024) void plan_kernel(
   const bool marked = colmark != nullptr && plan->mark != 0;
   int u = -1;
   if (marked) {
-    const int64_t chunk = ceil_div(p, blockDim.x);
-    const int64_t b = threadIdx.x * chunk < p ? threadIdx.x * chunk : p;
-    const int64_t e = b + chunk < p ? b + chunk : p;
-    int cnt = 0;
-    for (int64_t i = b; i < e; ++i) cnt += colmark[i] == epoch;
-    int off = block_exclusive_scan(cnt, scan, &u);
-    for (int64_t i = b; i < e; ++i)
-      if (colmark[i] == epoch) ulist[off++] = (int32_t)i;
+    // passes of 16 consecutive columns per thread (coalesced)
+    u = 0;
+    for (int64_t base = 0; base < p; base += 16 * (int64_t)blockDim.x) {
+      const int64_t i0 = base + 16 * (int64_t)threadIdx.x;
+      int32_t m[16];
+      load16(colmark, i0, p, m);
+      int cnt = 0;
+#pragma unroll
+      for (int k = 0; k < 16; ++k) cnt += i0 + k < p && m[k] == epoch;
+      int total;
+      int off = u + block_exclusive_scan(cnt, scan, &total);
+#pragma unroll
+      for (int k = 0; k < 16; ++k)
+        if (i0 + k < p && m[k] == epoch) ulist[off++] = (int32_t)(i0 + k);
+      u += total;
+    }
   }
   if (threadIdx.x == 0) {
     plan->active = (int32_t)v[0];
