@@ -636,6 +636,12 @@ def bench_sparse(args, spca, torch):
                              "objective": res["objective"],
                              "explained_variance": res["explained_variance"],
                              "nnz": int(len(res["support"])), "iters": int(res["iters"])}
+    # A^T Y per launch with every start running (stop test off, 8 iterations),
+    # HIP events on the solve's stream
+    kt = spca.am_solve_sparse(D, 1, 5.0, X0, tol=-1.0, maxit=8, ctx=ctx, flags=flags,
+                              kernel_times=True)["kernel_times"]
+    aty_ms = kt["aty_ms"] / kt["aty_launches"]
+    aty_bytes = mat.nnz * 8 + (mat.n + mat.p) * r * 4
     return {
         "metric": "solves/s (sparse A)", "value": args.steps / dt, "unit": "solves/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -649,6 +655,14 @@ def bench_sparse(args, spca, torch):
         "result": {"objective": last["objective"], "support": last["support"].tolist(),
                    "iters": int(last["iters"])},
         "all_formulations": per_fid,
+        "roofline": {"kernel": "sp_seg_kernel (V = A^T Y, columns)", "bound": "hbm",
+                     "achieved": aty_bytes / (aty_ms * 1e-3) / 1e9, "peak": 8000.0,
+                     "unit": "GB/s", "frac": aty_bytes / (aty_ms * 1e-3) / 8e12,
+                     "traffic": None, "avg_launch_ms": aty_ms,
+                     "launches": kt["aty_launches"],
+                     "algorithmic_bytes": aty_bytes,
+                     "note": "8 B per nonzero (row index, value) + Y + V; the kernel is "
+                             "bound by random row reads of Y, not HBM"},
     }
 
 

@@ -653,7 +653,7 @@ def sparse_to_device(mat, device="cuda:0"):
 
 def am_solve_sparse(D, formulation, s_or_gamma, X0, tol=1e-8, maxit=200, *, check_every=8,
                     flags=0, ctx=None, stream=None, warmup_iters=0, target_nnz=0,
-                    return_X=False):
+                    return_X=False, kernel_times=False):
     """Batched AM solve on a sparse A (``spca_am_solve_sparse``); D from
     sparse_to_device, X0 a contiguous (r, p) float32 GPU tensor."""
     import torch
@@ -679,9 +679,11 @@ def am_solve_sparse(D, formulation, s_or_gamma, X0, tol=1e-8, maxit=200, *, chec
                          float(s_or_gamma))
     opts = SolveOpts(X0.data_ptr(), r, float(tol), int(maxit), PREC_FP32, 0, int(check_every),
                      int(flags), 0, int(warmup_iters), int(target_nnz), None, 0)
+    kt = np.zeros(10) if kernel_times else None
     out = Outputs(_np_ptr(x), _np_ptr(sup), ctypes.pointer(res), _np_ptr(f), _np_ptr(ev),
                   _np_ptr(phi), _np_ptr(iters), _np_ptr(status), _np_ptr(nnz),
-                  Xf.data_ptr() if Xf is not None else None, None, _np_ptr(par))
+                  Xf.data_ptr() if Xf is not None else None,
+                  _np_ptr(kt) if kt is not None else None, _np_ptr(par))
     _check(load().spca_am_solve_sparse(ctx.handle, _stream_ptr(stream), ctypes.byref(prob),
                                        ctypes.byref(opts), ctypes.byref(out)))
     return {"x": x, "support": sup[: res.nnz].copy(), "objective": res.objective,
@@ -689,4 +691,9 @@ def am_solve_sparse(D, formulation, s_or_gamma, X0, tol=1e-8, maxit=200, *, chec
             "nnz": res.nnz, "iters": res.iters, "status": res.status,
             "iters_x_starts": res.iters_x_starts, "f_per_start": f, "ev_per_start": ev,
             "iters_per_start": iters, "status_per_start": status, "nnz_per_start": nnz,
-            "param_per_start": par, "X_final": Xf}
+            "param_per_start": par, "X_final": Xf,
+            "kernel_times": None if kt is None else {
+                "aty_ms": kt[0], "aty_launches": int(kt[1]), "x_update_ms": kt[2],
+                "x_update_launches": int(kt[3]), "ax_dense_ms": kt[4],
+                "ax_dense_launches": int(kt[5]), "iters_dense": int(kt[6]),
+                "iters_list": int(kt[7] - kt[9]), "iters_list_rows": int(kt[9])}}

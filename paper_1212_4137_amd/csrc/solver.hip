@@ -1070,14 +1070,24 @@ int spca_am_solve_sparse(spca_ctx* ctx, void* stream, const spca_sparse_problem*
   plan_next(st, s, r, n, p, list_cap, 0, 1, 0, colmark, ulist, plan, 1);
   SPCA_LAUNCH_CHECK("sparse staging");
   const int32_t maxit = opts->maxit;
-  auto iteration = [&](hipStream_t q) -> int {
+  const bool timed = out->kernel_times != nullptr;
+  ctx->t_aty.reset();
+  ctx->t_xup.reset();
+  ctx->t_ax.reset();
+  auto iteration = [&](hipStream_t q, bool tm) -> int {
     transpose_f32(q, X, ldx, XT, ldt, p, r);
+    if (tm) SPCA_HIP_TRY(ctx->t_ax.mark(q));
     sparse_ax_dense(q, a, XT, ldt, r, UT, carry, U, ldu, s, plan);
+    if (tm) SPCA_HIP_TRY(ctx->t_ax.mark(q));
     sparse_ax_list(q, a, li, lv, ldx, U, ldu, r, s, plan);
     sparse_y_update(q, fid, U, ldu, n, r, s, ypart, YT, ldt);
+    if (tm) SPCA_HIP_TRY(ctx->t_aty.mark(q));
     sparse_aty(q, a, YT, ldt, r, VT, carry, V, ldx, s, plan);
+    if (tm) SPCA_HIP_TRY(ctx->t_aty.mark(q));
+    if (tm) SPCA_HIP_TRY(ctx->t_xup.mark(q));
     x_update(q, fid, sg, V, ldx, r, p, X, ldx, li, lv, ldx, list_cap, s, opts->tol, maxit,
              colmark, plan, wide, wm);
+    if (tm) SPCA_HIP_TRY(ctx->t_xup.mark(q));
     plan_next(q, s, r, n, p, list_cap, 0, 1, 0, colmark, ulist, plan, 1);
     SPCA_LAUNCH_CHECK("sparse AM iteration");
     return SPCA_OK;
@@ -1092,14 +1102,15 @@ int spca_am_solve_sparse(spca_ctx* ctx, void* stream, const spca_sparse_problem*
   const int32_t every = opts->check_every;
   int32_t it = 0;
   bool done = false;
-  if ((opts->flags & SPCA_FLAG_GRAPH) && maxit >= every) {
+  if ((opts->flags & SPCA_FLAG_GRAPH) && maxit >= every && !timed) {
     rc = ensure_capture_stream(ctx);
     if (rc != SPCA_OK) return rc;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     SPCA_HIP_TRY(hipStreamBeginCapture(ctx->capture, hipStreamCaptureModeThreadLocal));
     int body_rc = SPCA_OK;
-    for (int32_t k = 0; k < every && body_rc == SPCA_OK; ++k) body_rc = iteration(ctx->capture);
+    for (int32_t k = 0; k < every && body_rc == SPCA_OK; ++k)
+      body_rc = iteration(ctx->capture, false);
     hipError_t end_rc = hipStreamEndCapture(ctx->capture, &graph);
     if (body_rc != SPCA_OK) {
       if (graph) (void)hipGraphDestroy(graph);
@@ -1127,7 +1138,7 @@ int spca_am_solve_sparse(spca_ctx* ctx, void* stream, const spca_sparse_problem*
     if (loop_rc != SPCA_OK) return loop_rc;
   }
   for (; !done && it < maxit; ++it) {
-    rc = iteration(st);
+    rc = iteration(st, timed);
     if (rc != SPCA_OK) return rc;
     if ((it + 1) % every == 0 && it + 1 < maxit) {
       rc = none_active(&done);
@@ -1154,7 +1165,24 @@ int spca_am_solve_sparse(spca_ctx* ctx, void* stream, const spca_sparse_problem*
   SPCA_HIP_TRY(hipMemcpyAsync(it_all.data(), s.iters, sizeof(int32_t) * r, hipMemcpyDeviceToHost, st));
   SPCA_HIP_TRY(hipMemcpyAsync(st_all.data(), s.status, sizeof(int32_t) * r, hipMemcpyDeviceToHost, st));
   SPCA_HIP_TRY(hipMemcpyAsync(nnz_all.data(), s.nnz, sizeof(int32_t) * r, hipMemcpyDeviceToHost, st));
+  Plan hplan;
+  SPCA_HIP_TRY(hipMemcpyAsync(&hplan, plan, sizeof(Plan), hipMemcpyDeviceToHost, st));
   SPCA_HIP_TRY(hipStreamSynchronize(st));
+  if (timed) {
+    // as in spca_am_solve_ex; [4] covers the row-gather A x (launches of list
+    // iterations return at once)
+    double* kt = out->kernel_times;
+    SPCA_HIP_TRY(ctx->t_aty.total_ms(&kt[0]));
+    kt[1] = (double)(ctx->t_aty.used / 2);
+    SPCA_HIP_TRY(ctx->t_xup.total_ms(&kt[2]));
+    kt[3] = (double)(ctx->t_xup.used / 2);
+    SPCA_HIP_TRY(ctx->t_ax.total_ms(&kt[4]));
+    kt[5] = (double)(ctx->t_ax.used / 2);
+    kt[6] = hplan.mode_count[kAxDense];
+    kt[7] = hplan.mode_count[kAxList] + hplan.mode_count[kAxListRows];
+    kt[8] = hplan.mode_count[kAxUnion];
+    kt[9] = hplan.mode_count[kAxListRows];
+  }
   const int32_t jb = hb[0], nnzb = hb[1];
   if (out->x)
     SPCA_HIP_TRY(hipMemcpyAsync(out->x, xout, sizeof(double) * p, hipMemcpyDeviceToHost, st));
