@@ -300,7 +300,8 @@ int spca_gemm_nt_bf16_shape(void* stream, const uint16_t* P, int64_t ldp,
                             int64_t M, int64_t N, int64_t K, int shape, int splits);
 
 /* Tuning and testing variant of spca_gemm_nt_f32 with a forced tile shape
- * (0 .. 5: BMxBN of 128x128, 128x160, 128x96, 128x64, 64x128, 32x128) and
+ * (0 .. 8: BMxBN of 128x128, 128x160, 128x96, 128x64, 64x128, 32x128,
+ * 64x256, 256x128, 256x256) and
  * K split count (1 .. 64).  With splits > 1, C must hold splits x M rows:
  * split s writes its partial product (K slabs s*ceil(K/32/splits) onward)
  * at C + s * M * ldc, and the product is the sum of the partials.       */

@@ -244,19 +244,24 @@ __global__ __launch_bounds__(WM* WN* kWave) void gemm_nt_kernel(
 
 // Compiled tile shapes.  occ = workgroups a CU holds at once (LDS and
 // registers); eff = relative MFMA efficiency of the shape measured on
-// MI355X (larger per-wave tiles reuse each LDS read for more MFMAs).
+// MI355X (larger per-wave tiles reuse each LDS read for more MFMAs); eff16
+// the same for BF16 operands, where a tile's operand bytes per MFMA (global
+// and LDS) limit it long before the matrix cores do, so the largest tiles
+// win (measured on 256 x 50000 x 5000 and 256 x 5000 x 50000).
 struct Shape {
   int bm, bn, occ;
-  double eff;
+  double eff, eff16;
 };
 constexpr Shape kShapes[] = {
-    {128, 128, 2, 1.00},  // 2x2 waves of 64x64
-    {128, 160, 2, 1.00},  // 4x1 waves of 32x160
-    {128, 96, 2, 0.92},   // 4x1 waves of 32x96
-    {128, 64, 3, 0.85},   // 2x2 waves of 64x32
-    {64, 128, 3, 0.85},   // 2x2 waves of 32x64
-    {32, 128, 3, 0.70},   // 1x4 waves of 32x32
-    {64, 256, 2, 0.85},   // 1x4 waves of 64x64
+    {128, 128, 2, 1.00, 0.73},  // 2x2 waves of 64x64
+    {128, 160, 2, 1.00, 0.80},  // 4x1 waves of 32x160
+    {128, 96, 2, 0.92, 0.73},   // 4x1 waves of 32x96
+    {128, 64, 3, 0.85, 0.64},   // 2x2 waves of 64x32
+    {64, 128, 3, 0.85, 0.65},   // 2x2 waves of 32x64
+    {32, 128, 3, 0.70, 0.48},   // 1x4 waves of 32x32
+    {64, 256, 2, 0.85, 0.57},   // 1x4 waves of 64x64
+    {256, 128, 1, 0.90, 0.85},  // 2x2 waves of 128x64
+    {256, 256, 1, 0.90, 1.25},  // 2x2 waves of 128x128
 };
 constexpr int kNumShapes = (int)(sizeof(kShapes) / sizeof(kShapes[0]));
 
@@ -300,8 +305,14 @@ void dispatch(int shape, hipStream_t st, const T* P, int64_t ldp,
     case 5:
       launch<T, 32, 128, 1, 4>(st, P, ldp, Q, ldq, C, ldc, M, N, K, splits, split_stride, gate, gate_run, kdev);
       break;
-    default:
+    case 6:
       launch<T, 64, 256, 1, 4>(st, P, ldp, Q, ldq, C, ldc, M, N, K, splits, split_stride, gate, gate_run, kdev);
+      break;
+    case 7:
+      launch<T, 256, 128, 2, 2>(st, P, ldp, Q, ldq, C, ldc, M, N, K, splits, split_stride, gate, gate_run, kdev);
+      break;
+    default:
+      launch<T, 256, 256, 2, 2>(st, P, ldp, Q, ldq, C, ldc, M, N, K, splits, split_stride, gate, gate_run, kdev);
       break;
   }
 }
@@ -419,8 +430,9 @@ GemmPlan model_plan_gemm_nt(int64_t M, int64_t N, int64_t K, int max_splits,
   double best_cost = 1e300;
   const int64_t slab_k = 128 / elem_bytes;
   const int64_t kslabs = ceil_div(K, slab_k);
-  // MACs per cycle per CU: FP32 MFMA 128; BF16 operands are limited by LDS
-  // reads well below their MFMA rate, taken as 4x FP32
+  // MACs per cycle per CU: FP32 MFMA 128; BF16 operands are limited by
+  // operand traffic well below their MFMA rate, taken as 4x FP32 times the
+  // shape's BF16 efficiency
   const double macs = elem_bytes == 4 ? 128.0 : 512.0;
   for (int s = 0; s < kNumShapes; ++s) {
     const Shape& sh = kShapes[s];
@@ -431,7 +443,8 @@ GemmPlan model_plan_gemm_nt(int64_t M, int64_t N, int64_t K, int max_splits,
       if (splits > 1 && per < 8) break;  // too little K per split
       const int64_t wgs = tiles * splits;
       const int64_t slots = 256LL * sh.occ;
-      const double w = (double)sh.bm * sh.bn * (double)(per * slab_k) / (macs * sh.eff);
+      const double eff = elem_bytes == 4 ? sh.eff : sh.eff16;
+      const double w = (double)sh.bm * sh.bn * (double)(per * slab_k) / (macs * eff);
       const int64_t full = wgs / slots;
       const int64_t rest = wgs % slots;
       double cost = (double)full * w * (sh.occ > 1.5 ? sh.occ : 1.5);

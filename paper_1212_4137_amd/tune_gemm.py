@@ -13,7 +13,8 @@ import argparse
 import json
 import sys
 
-SHAPES = ["128x128", "128x160", "128x96", "128x64", "64x128", "32x128", "64x256"]
+SHAPES = ["128x128", "128x160", "128x96", "128x64", "64x128", "32x128", "64x256", "256x128",
+          "256x256"]
 
 
 def time_launch(fn, reps, warmup=3):

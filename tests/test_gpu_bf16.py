@@ -51,6 +51,26 @@ def test_gemm_bf16_matches_fp64(spca, M, N, K):
     assert np.all(np.abs(C.cpu().numpy().astype(np.float64) - ref) <= bound)
 
 
+@pytest.mark.parametrize("shape", range(9))
+@pytest.mark.parametrize("M,N,K,splits", [(130, 333, 1001, 1), (300, 290, 4100, 4)])
+def test_gemm_bf16_every_shape_and_split(spca, shape, M, N, K, splits):
+    print(f"bf16 gemm shape={shape} M={M} N={N} K={K} splits={splits}", flush=True)
+    rng = np.random.default_rng(shape * 13 + M + 3 * N + 7 * K + splits)
+    ldk = (K + 7) // 8 * 8
+    P = torch.zeros((M, ldk), dtype=torch.bfloat16)
+    Q = torch.zeros((N, ldk), dtype=torch.bfloat16)
+    P[:, :K] = torch.from_numpy(rng.standard_normal((M, K)).astype(np.float32)).to(torch.bfloat16)
+    Q[:, :K] = torch.from_numpy(rng.standard_normal((N, K)).astype(np.float32)).to(torch.bfloat16)
+    P64 = P[:, :K].float().numpy().astype(np.float64)
+    Q64 = Q[:, :K].float().numpy().astype(np.float64)
+    parts = spca.gemm_nt_shape(P.cuda()[:, :K], Q.cuda()[:, :K], shape, splits)
+    torch.cuda.synchronize()
+    C = parts.cpu().numpy().astype(np.float64).sum(axis=0)
+    ref = P64 @ Q64.T
+    bound = (np.abs(P64) @ np.abs(Q64).T) * ((K + splits) * 2.0 ** -24) * 1.01 + 1e-30
+    assert np.all(np.abs(C - ref) <= bound)
+
+
 def test_host_bf16_rounding_matches_torch():
     x = np.random.default_rng(0).standard_normal(10000).astype(np.float32)
     ref = torch.from_numpy(x).to(torch.bfloat16).float().numpy().astype(np.float64)
