@@ -418,8 +418,15 @@ int max_feasible_splits(int64_t K, int max_splits, int elem_bytes) {
 GemmPlan plan_gemm_nt(int64_t M, int64_t N, int64_t K, int max_splits,
                       int elem_bytes) {
   {
+    // a tuning-table entry covers a size bucket: its split count is capped
+    // at what this K allows, which is what callers size split buffers for
     GemmPlan t;
-    if (tuned_plan(M, N, K, max_splits, elem_bytes, &t)) return t;
+    if (tuned_plan(M, N, K, max_splits, elem_bytes, &t)) {
+      const int cap = max_feasible_splits(K, max_splits, elem_bytes);
+      if (t.splits > cap) t.splits = cap;
+      if (t.splits < 1) t.splits = 1;
+      return t;
+    }
   }
   return model_plan_gemm_nt(M, N, K, max_splits, elem_bytes);
 }
@@ -463,6 +470,9 @@ GemmPlan model_plan_gemm_nt(int64_t M, int64_t N, int64_t K, int max_splits,
 }
 
 int gemm_num_shapes() { return kNumShapes; }
+int gemm_shape_bm(int shape) {
+  return shape >= 0 && shape < kNumShapes ? kShapes[shape].bm : 0;
+}
 
 void gemm_nt_f32(hipStream_t st, const float* P, int64_t ldp, const float* Q,
                  int64_t ldq, float* C, int64_t ldc, int64_t M, int64_t N,

@@ -2,6 +2,8 @@
 // the layout copies of A, the start x0 = e_{i*}, the per-start state, the
 // choice between the dense and the list-based product A x, and the y-update
 // y = sgn(u) or u / ||u||_2 (Table 3, rows S1 and S2).
+#include <algorithm>
+
 #include "../../include/spca.h"
 #include "common.hpp"
 #include "kernels.hpp"
@@ -12,6 +14,34 @@ namespace {
 // ---------------------------------------------------------------------------
 // Layout copies
 // ---------------------------------------------------------------------------
+
+// K-split partials summed in split order, four entries per thread and step
+// (stride and count multiples of 4 take the 16-byte path)
+__global__ __launch_bounds__(256) void sum_splits_kernel(float* __restrict__ V, int64_t stride,
+                                                         int splits, int64_t count) {
+  const bool vec = stride % 4 == 0 && count % 4 == 0 && ((uintptr_t)V & 15) == 0;
+  for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; 4 * q < count;
+       q += (int64_t)gridDim.x * 256) {
+    const int64_t i = 4 * q;
+    if (vec) {
+      float4 a = *reinterpret_cast<const float4*>(V + i);
+      for (int sp = 1; sp < splits; ++sp) {
+        const float4 b = *reinterpret_cast<const float4*>(V + sp * stride + i);
+        a.x += b.x;
+        a.y += b.y;
+        a.z += b.z;
+        a.w += b.w;
+      }
+      *reinterpret_cast<float4*>(V + i) = a;
+    } else {
+      for (int e = 0; e < 4 && i + e < count; ++e) {
+        float a = V[i + e];
+        for (int sp = 1; sp < splits; ++sp) a += V[sp * stride + i + e];
+        V[i + e] = a;
+      }
+    }
+  }
+}
 
 constexpr int kTT = 64;  // transpose tile
 
@@ -729,6 +759,13 @@ void union_gather(hipStream_t st, const float* X, int64_t ldx, int64_t r,
   hipLaunchKernelGGL(union_gather_kernel, dim3(blocks),
                      dim3(256), 0, st, X, ldx, r, A, lda, n, ulist, plan, Xc,
                      ldxc, Qc, ldqc);
+}
+
+void sum_splits(hipStream_t st, float* V, int64_t stride, int splits, int64_t count) {
+  if (splits <= 1 || count <= 0) return;
+  const int64_t n4 = ceil_div(count, (int64_t)4);
+  const unsigned g = (unsigned)std::min<int64_t>(ceil_div(n4, (int64_t)256), 8192);
+  hipLaunchKernelGGL(sum_splits_kernel, dim3(g), dim3(256), 0, st, V, stride, splits, count);
 }
 
 void y_update(hipStream_t st, int fid, const float* U, int64_t split_stride,

@@ -102,6 +102,8 @@ GemmPlan plan_gemm_nt(int64_t M, int64_t N, int64_t K, int max_splits,
 GemmPlan model_plan_gemm_nt(int64_t M, int64_t N, int64_t K, int max_splits,
                             int elem_bytes = 4);
 int gemm_num_shapes();
+// rows of the output tile of a shape (0 for an unknown shape)
+int gemm_shape_bm(int shape);
 // largest power-of-two split count (<= max_splits) that leaves every split
 // at least 8 K slabs
 int max_feasible_splits(int64_t K, int max_splits, int elem_bytes);
@@ -197,6 +199,10 @@ void union_gather(hipStream_t st, const float* X, int64_t ldx, int64_t r,
 
 // y-update of Algorithm 2 from a dense U (r x n), given as plan->ax_splits
 // partial products split_stride floats apart that are summed in order:
+// V[i] = V[i] + V[stride + i] + ... + V[(splits - 1) stride + i] for i < count
+// (the K-split partials of a product, summed in split order, in place)
+void sum_splits(hipStream_t st, float* V, int64_t stride, int splits, int64_t count);
+
 // Y = sgn(U) (L1 variance) or U / ||U||_2 per row (L2 variance); a zero row
 // ends its start as DEGENERATE.  Skipped in list mode.
 // With Yb != nullptr the rows are also written as BF16 (ldyb).

@@ -49,7 +49,7 @@ struct Layout {
   int64_t ldab, ldatb, ldyb, ldxb;
   size_t off_Ab, off_Atb, off_Yb, off_Xb, off_Xp;
   GemmPlan plan_ax, plan_aty;
-  int ax_split_cap;
+  int ax_split_cap, aty_split_cap;
   size_t off_At, off_Ac, off_X, off_U, off_Y, off_V, off_li, off_lv;
   size_t off_phi, off_phip, off_nnz, off_it, off_st, off_plan, off_part,
       off_f, off_ev, off_xn, off_best, off_xout, off_sup, off_colsq, off_bad;
@@ -85,7 +85,7 @@ Layout make_layout(int64_t n, int64_t p, int64_t r, bool copy_a, bool bf16) {
   L.nchunks = (int)ceil_div(n, 256);
   const int eb = bf16 ? 2 : 4;
   L.plan_ax = plan_gemm_nt(r, n, p, kMaxSplits, eb);   // U^T = X^T A^T, K = p
-  L.plan_aty = plan_gemm_nt(r, p, n, 1, eb);           // V^T = Y^T A,   K = n
+  L.plan_aty = plan_gemm_nt(r, p, n, kMaxSplits, eb);  // V^T = Y^T A,   K = n
   // union product (FP32 only): K = u <= ucap columns, gathered A is
   // n x ucap (<= 256 MB)
   L.ucap = bf16 ? 0 : p;
@@ -107,7 +107,10 @@ Layout make_layout(int64_t n, int64_t p, int64_t r, bool copy_a, bool bf16) {
   if (L.ax_split_cap < L.plan_ax.splits) L.ax_split_cap = L.plan_ax.splits;
   L.off_U = carve(&c, sizeof(float) * (size_t)L.ax_split_cap * r * L.ldu);
   L.off_Y = carve(&c, sizeof(float) * (size_t)r * L.ldu);
-  L.off_V = carve(&c, sizeof(float) * (size_t)r * L.ldx);
+  // V and the partials of a K-split A^T Y (summed into V before the x-update)
+  L.aty_split_cap = max_feasible_splits(n, kMaxSplits, eb);
+  if (L.aty_split_cap < L.plan_aty.splits) L.aty_split_cap = L.plan_aty.splits;
+  L.off_V = carve(&c, sizeof(float) * (size_t)L.aty_split_cap * r * L.ldx);
   L.off_li = carve(&c, sizeof(int32_t) * (size_t)r * L.ldx);
   L.off_lv = carve(&c, sizeof(float) * (size_t)r * L.ldx);
   L.off_phi = carve(&c, sizeof(double) * r);
@@ -269,7 +272,6 @@ using namespace spca;
 template <typename F>
 static int autotune_product(hipStream_t st, int64_t M, int64_t N, int64_t K,
                             int split_cap, int max_splits, int eb, F launch) {
-  static const int kBM[] = {128, 128, 128, 128, 64, 32, 64};
   hipEvent_t e0, e1;
   SPCA_HIP_TRY(hipEventCreate(&e0));
   hipError_t ce = hipEventCreate(&e1);
@@ -282,7 +284,8 @@ static int autotune_product(hipStream_t st, int64_t M, int64_t N, int64_t K,
   hipError_t err = hipSuccess;
   const int cap = max_feasible_splits(K, split_cap, eb);
   for (int shape = 0; shape < gemm_num_shapes() && err == hipSuccess; ++shape) {
-    if (kBM[shape] > 32 && M <= kBM[shape] / 2) continue;
+    const int bm = gemm_shape_bm(shape);
+    if (bm > 32 && M <= bm / 2) continue;
     for (int splits = 1; splits <= cap && err == hipSuccess; splits *= 2) {
       const GemmPlan g{shape, splits};
       launch(g);
@@ -617,18 +620,19 @@ int spca_am_solve_ex(spca_ctx* ctx, void* stream, const spca_problem* prob,
       rc = autotune_product(st, r, n, p, L.ax_split_cap, kMaxSplits, eb, run_ax);
       if (rc != SPCA_OK) return rc;
     }
-    if (!tuned_plan(r, p, n, 1, eb, &tmp)) {
+    if (!tuned_plan(r, p, n, kMaxSplits, eb, &tmp)) {
       auto run_aty = [&](GemmPlan g) {
         if (bf16)
-          gemm_nt_bf16(st, Yb, L.ldyb, Ab, L.ldab, V, L.ldx, r, p, n, nullptr, 0, g, 0);
+          gemm_nt_bf16(st, Yb, L.ldyb, Ab, L.ldab, V, L.ldx, r, p, n, nullptr, 0, g,
+                       r * L.ldx);
         else
-          gemm_nt_f32(st, Y, L.ldu, A, ldA, V, L.ldx, r, p, n, nullptr, 0, g, 0);
+          gemm_nt_f32(st, Y, L.ldu, A, ldA, V, L.ldx, r, p, n, nullptr, 0, g, r * L.ldx);
       };
-      rc = autotune_product(st, r, p, n, 1, 1, eb, run_aty);
+      rc = autotune_product(st, r, p, n, L.aty_split_cap, kMaxSplits, eb, run_aty);
       if (rc != SPCA_OK) return rc;
     }
     L.plan_ax = plan_gemm_nt(r, n, p, kMaxSplits, eb);
-    L.plan_aty = plan_gemm_nt(r, p, n, 1, eb);
+    L.plan_aty = plan_gemm_nt(r, p, n, kMaxSplits, eb);
   }
   init_state(st, s, r);
   if (otf) otf_init(st, o, r);
@@ -691,10 +695,11 @@ int spca_am_solve_ex(spca_ctx* ctx, void* stream, const spca_problem* prob,
     if (tm) SPCA_HIP_TRY(ctx->t_aty.mark(q));
     if (bf16)
       gemm_nt_bf16(q, Yb, L.ldyb, Ab, L.ldab, V, L.ldx, r, p, n, nullptr, 0,
-                   L.plan_aty, 0);
+                   L.plan_aty, r * L.ldx);
     else
       gemm_nt_f32(q, Y, L.ldu, A, ldA, V, L.ldx, r, p, n, nullptr, 0,
-                  L.plan_aty, 0);
+                  L.plan_aty, r * L.ldx);
+    sum_splits(q, V, r * L.ldx, L.plan_aty.splits, r * L.ldx);
     if (tm) SPCA_HIP_TRY(ctx->t_aty.mark(q));
     if (dk > 0) deflate_v(q, V, L.ldx, p, r, s, defl);
     if (tm) SPCA_HIP_TRY(ctx->t_xup.mark(q));

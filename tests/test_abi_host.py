@@ -110,6 +110,12 @@ def test_tuning_table_round_trip_and_plan_lookup():
         with pytest.raises(m.SpcaError):
             m.tune_table_import(bad)
     assert m.tune_table_export() == text  # a rejected import changes nothing
+    # an entry covers a K bucket (here 861..1218); its split count is capped
+    # at what the exact K allows (at least 8 slabs of 32 per split), since
+    # the solve sizes its split buffers for that
+    m.tune_table_import("4 16 20 27 20 0 4\n")
+    assert m.gemm_plan(1024, 10000, 1200, 16) == (0, 4)  # 38 slabs
+    assert m.gemm_plan(1024, 10000, 870, 16) == (0, 2)   # 28 slabs
     m.tune_table_clear()
     assert m.gemm_plan(1024, 10000, 1000, 1) == model
 

@@ -211,3 +211,32 @@ def test_row_block_list_product(spca, fid):
     compare_solve(got, ref, f"row-block list F{fid}")
     dense = spca.am_solve(A, fid, par, X0, tol=1e-8, maxit=200, flags=spca.FLAG_DENSE_ONLY)
     assert rel_err(got["objective"], dense["objective"]) <= 1e-5
+
+
+@pytest.mark.parametrize("fid", [1, 6])
+def test_k_split_aty_product(spca, fid):
+    """Few starts and a long p: the planner splits the K = n loop of
+    V = A^T Y and the partials are summed before the x-update.  Parity with
+    the oracle, and with the same solve forced to one split through the
+    tuning table."""
+    n, p, r = 2000, 8000, 16
+    print(f"k-split A^T Y case fid={fid}", flush=True)
+    assert spca.gemm_plan(r, p, n, 16)[1] > 1
+    sp = workloads.spiked_matrix(workloads.SEED_BASE + 120 + fid, n, p,
+                                 thetas=(80.0, 60.0, 40.0), spike_nnz=40)
+    A_np = sp.A
+    par = _param(fid, A_np, 40)
+    X0 = workloads.random_unit_starts(workloads.SEED_BASE + 220 + fid, r, p)
+    A = to_device_colmajor(A_np)
+    got = spca.am_solve(A, fid, par, to_device_rows(X0), tol=1e-8, maxit=120)
+    ref = oracle.am_multi(A_np, fid, par, X0, 1e-8, 120, nthreads=8)
+    compare_solve(got, ref, f"k-split F{fid}")
+    shape = spca.gemm_plan(r, p, n, 16)[0]
+    # bucket(x) = round(2 log2 x): 16 -> 8, 8000 -> 26, 2000 -> 22
+    spca.tune_table_import(f"4 16 8 26 22 {shape} 1\n")
+    try:
+        assert spca.gemm_plan(r, p, n, 16) == (shape, 1)
+        one = spca.am_solve(A, fid, par, to_device_rows(X0), tol=1e-8, maxit=120)
+    finally:
+        spca.tune_table_clear()
+    assert rel_err(got["objective"], one["objective"]) <= 1e-5
