@@ -173,7 +173,7 @@ def bench_all8(args, spca, torch):
              "ax_dense_avg_ms": round(kt_all["ax_dense_ms"] / kt_all["ax_dense_launches"], 5),
              "mean_nnz_per_start": outs[-1]["nnz"],
              "ax_modes_dense_list_union": modes,
-             "gemm_plans": {"aty": spca.gemm_plan(r, p, n, 1),
+             "gemm_plans": {"aty": spca.gemm_plan(r, p, n, 16),
                             "ax_dense": spca.gemm_plan(r, n, p, 16)},
              "tuning_table": spca.tune_table_export()}
     rec = {
@@ -636,6 +636,17 @@ def bench_sparse(args, spca, torch):
                              "objective": res["objective"],
                              "explained_variance": res["explained_variance"],
                              "nnz": int(len(res["support"])), "iters": int(res["iters"])}
+    # the first five components by deflation (the paper lists several per
+    # corpus), F1, s = 5, the same starts
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    comps = spca.am_components_sparse(D, 1, 5.0, X0, 5, tol=1e-6, maxit=20, ctx=ctx,
+                                      flags=flags)
+    torch.cuda.synchronize()
+    comp_ms = (time.perf_counter() - t0) * 1e3
+    components = {"ms_for_5": comp_ms,
+                  "supports": [c["support"].tolist() for c in comps],
+                  "objectives": [c["objective"] for c in comps]}
     # A^T Y per launch with every start running (stop test off, 8 iterations),
     # HIP events on the solve's stream
     kt = spca.am_solve_sparse(D, 1, 5.0, X0, tol=-1.0, maxit=8, ctx=ctx, flags=flags,
@@ -655,6 +666,7 @@ def bench_sparse(args, spca, torch):
         "result": {"objective": last["objective"], "support": last["support"].tolist(),
                    "iters": int(last["iters"])},
         "all_formulations": per_fid,
+        "components": components,
         "roofline": {"kernel": "sp_seg_kernel (V = A^T Y, columns)", "bound": "hbm",
                      "achieved": aty_bytes / (aty_ms * 1e-3) / 1e9, "peak": 8000.0,
                      "unit": "GB/s", "frac": aty_bytes / (aty_ms * 1e-3) / 8e12,

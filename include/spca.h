@@ -240,8 +240,9 @@ int spca_am_components(spca_ctx* ctx, void* stream, const spca_problem* prob,
  * col_ptr (p + 1 int64), row_idx / col_val (nnz, rows strictly ascending
  * within a column), row_ptr (n + 1 int64), col_idx / row_val (nnz).  Both
  * pointer arrays start at 0 and end at the same nnz.  Options as
- * spca_am_solve_ex, with X0 required, FP32 only, and neither
- * total_starts > r nor deflation.  The solve first checks the arrays on
+ * spca_am_solve_ex, with X0 required, FP32 only and no total_starts > r;
+ * deflate_X / deflate_k as there (the scores A x_i are formed from the
+ * columns in FP64).  The solve first checks the arrays on
  * the device (pointer arrays non-decreasing, every index in range, rows of
  * a column strictly ascending; SPCA_EINVAL otherwise, before any product
  * runs), synchronizing the stream; it synchronizes again when it builds row
@@ -262,6 +263,13 @@ typedef struct {
 
 int spca_am_solve_sparse(spca_ctx* ctx, void* stream, const spca_sparse_problem* prob,
                          const spca_solve_opts* opts, spca_outputs* out);
+
+/* Further components on a sparse A: the component loop of
+ * spca_am_components over spca_am_solve_sparse (deflate_X / deflate_k
+ * unset in opts; 1 <= ncomp <= 16; same outputs and synchronization).     */
+int spca_am_components_sparse(spca_ctx* ctx, void* stream, const spca_sparse_problem* prob,
+                              const spca_solve_opts* opts, int32_t ncomp, double* X_out,
+                              spca_result* res);
 
 /* Full solve on a caller-chosen context and HIP stream (hipStream_t passed
  * as void*; NULL = null stream).  Same semantics as spca_am_solve.

@@ -30,7 +30,7 @@ EXPORTED = ("spca_am_solve", "spca_am_solve_ex", "spca_ctx_create",
             "spca_server_submit", "spca_server_poll", "spca_server_stats",
             "spca_server_destroy", "spca_tune_table_export", "spca_tune_table_import",
             "spca_tune_table_clear", "spca_gemm_nt_bf16_shape", "spca_am_components",
-            "spca_am_solve_sparse")
+            "spca_am_solve_sparse", "spca_am_components_sparse")
 
 
 class SpcaError(RuntimeError):
@@ -172,6 +172,10 @@ def load():
                                            ctypes.POINTER(SolveOpts), i32, P,
                                            ctypes.POINTER(Result)]
         lib.spca_am_components.restype = ctypes.c_int
+        lib.spca_am_components_sparse.argtypes = [P, P, ctypes.POINTER(SparseProblem),
+                                                  ctypes.POINTER(SolveOpts), i32, P,
+                                                  ctypes.POINTER(Result)]
+        lib.spca_am_components_sparse.restype = ctypes.c_int
         lib.spca_ctx_set_workspace.argtypes = [P, P, ctypes.c_size_t]
         lib.spca_ctx_set_workspace.restype = ctypes.c_int
         lib.spca_request_footprint.argtypes = [ctypes.POINTER(Request)]
@@ -629,6 +633,42 @@ def am_components(A, formulation, s_or_gamma, X0, ncomp, tol=1e-8, maxit=200, *,
                      None, 0)
     _check(load().spca_am_components(ctx.handle, _stream_ptr(stream), ctypes.byref(prob),
                                      ctypes.byref(opts), int(ncomp), _np_ptr(X), res))
+    out = []
+    for c in range(ncomp):
+        x = X[c]
+        out.append({"objective": res[c].objective, "explained_variance": res[c].explained_var,
+                    "best_start": res[c].best_start, "nnz": res[c].nnz,
+                    "iters": res[c].iters, "status": res[c].status, "x": x.copy(),
+                    "support": np.flatnonzero(x)})
+    return out
+
+
+def am_components_sparse(D, formulation, s_or_gamma, X0, ncomp, tol=1e-8, maxit=200, *,
+                         check_every=8, flags=0, ctx=None, stream=None, warmup_iters=0,
+                         target_nnz=0):
+    """Several components on a sparse A (``spca_am_components_sparse``); D
+    from sparse_to_device, X0 a contiguous (r, p) float32 GPU tensor.
+    Returns the same list of dicts as am_components."""
+    import torch
+
+    n, p = D["n"], D["p"]
+    _require_gpu_tensor(X0, "X0", torch.float32)
+    if X0.dim() != 2 or X0.shape[1] != p or not X0.is_contiguous():
+        raise ValueError("X0 must be a contiguous (r, p) tensor")
+    r = X0.shape[0]
+    ctx = ctx or default_context(X0.device.index or 0)
+    X = np.zeros((ncomp, p), dtype=np.float64)
+    res = (Result * ncomp)()
+    prob = SparseProblem(n, p, D["col_ptr"].data_ptr(), D["row_idx"].data_ptr(),
+                         D["col_val"].data_ptr(), D["row_ptr"].data_ptr(),
+                         D["col_idx"].data_ptr(), D["row_val"].data_ptr(), int(formulation),
+                         float(s_or_gamma))
+    opts = SolveOpts(X0.data_ptr(), r, float(tol), int(maxit), PREC_FP32, 0,
+                     int(check_every), int(flags), 0, int(warmup_iters), int(target_nnz),
+                     None, 0)
+    _check(load().spca_am_components_sparse(ctx.handle, _stream_ptr(stream),
+                                            ctypes.byref(prob), ctypes.byref(opts),
+                                            int(ncomp), _np_ptr(X), res))
     out = []
     for c in range(ncomp):
         x = X[c]

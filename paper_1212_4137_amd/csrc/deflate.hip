@@ -193,10 +193,14 @@ Defl carve_deflate(void* base, int64_t n, int64_t p, int64_t r, int k) {
   return d;
 }
 
-void deflate_setup(hipStream_t st, const double* Xd, const float* A, int64_t lda,
-                   int64_t n, int64_t p, Defl d) {
+void deflate_loadings(hipStream_t st, const double* Xd, int64_t p, Defl d) {
   hipLaunchKernelGGL(defl_compact_kernel, dim3((unsigned)d.k), dim3(1024), 0, st, Xd, p, d);
   hipLaunchKernelGGL(defl_gram_kernel, dim3((unsigned)d.k), dim3(kDT), 0, st, Xd, p, d);
+}
+
+void deflate_setup(hipStream_t st, const double* Xd, const float* A, int64_t lda,
+                   int64_t n, int64_t p, Defl d) {
+  deflate_loadings(st, Xd, p, d);
   hipLaunchKernelGGL(defl_scores_kernel, dim3((unsigned)d.k, (unsigned)ceil_div(n, kDT)),
                      dim3(kDT), 0, st, A, lda, n, p, d);
 }

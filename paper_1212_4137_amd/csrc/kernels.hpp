@@ -75,7 +75,9 @@ struct Defl {
 };
 size_t deflate_bytes(int64_t n, int64_t p, int64_t r, int k);
 Defl carve_deflate(void* base, int64_t n, int64_t p, int64_t r, int k);
-// lists, Gram matrix and FP64 scores of the loadings Xd (device k x p FP64)
+// lists and Gram matrix of the loadings Xd (device k x p FP64)
+void deflate_loadings(hipStream_t st, const double* Xd, int64_t p, Defl d);
+// the same plus the FP64 scores A x_i of a dense column-major A
 void deflate_setup(hipStream_t st, const double* Xd, const float* A, int64_t lda,
                    int64_t n, int64_t p, Defl d);
 // u -= sum alpha_i A x_i (first partial of U; not in the fused list mode)
@@ -362,10 +364,13 @@ void sparse_aty(hipStream_t st, const SparseA& a, const float* YT, int64_t ldyt,
                 float* VT, float* carry, float* V, int64_t ldv, StartState s,
                 const Plan* plan);
 // per-start partial pairs (sparse_final_parts(n) each) of the FP64
-// u = A x / ||x|| for objective_and_best
+// u = A x / ||x|| (minus sum alpha_i A x_i under deflation) for
+// objective_and_best
 void sparse_final(hipStream_t st, const SparseA& a, const int32_t* list_idx,
                   const float* list_val, int64_t ldl, StartState s, int64_t r,
-                  const double* xnorm, double* partial);
+                  const double* xnorm, double* partial, Defl defl);
+// FP64 scores A x_i of the deflation loadings (after deflate_loadings)
+void sparse_deflate_scores(hipStream_t st, const SparseA& a, Defl d);
 
 // On-the-fly replacement of finished starts (Section 4.3): state of the
 // slots and of the total_starts starts that flow through them.

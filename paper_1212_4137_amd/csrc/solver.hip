@@ -309,6 +309,55 @@ static int autotune_product(hipStream_t st, int64_t M, int64_t N, int64_t K,
   return SPCA_OK;
 }
 
+// Components one after another: component c is solved on A deflated by the
+// loadings 1 .. c - 1 (SOLVE: the dense or the sparse solve).
+template <typename Prob, typename Solve>
+static int components_loop(spca_ctx* ctx, void* stream, const Prob* prob,
+                           const spca_solve_opts* opts, int32_t ncomp, double* X_out,
+                           spca_result* res, Solve solve) {
+  SPCA_REQUIRE(ctx && prob && opts && X_out && res,
+               "ctx, prob, opts, X_out and res must not be NULL");
+  SPCA_REQUIRE(ncomp >= 1 && ncomp <= kMaxDefl, "ncomp must be in 1..16");
+  SPCA_REQUIRE(opts->deflate_X == nullptr && opts->deflate_k == 0,
+               "deflate_X / deflate_k are set by the component loop");
+  SPCA_REQUIRE(prob->p >= 1, "p must be >= 1");
+  const int64_t p = prob->p;
+  hipStream_t st = (hipStream_t)stream;
+  double* Xd = nullptr;
+  {
+    DeviceGuard g(ctx->device);
+    SPCA_HIP_TRY(hipMalloc(&Xd, sizeof(double) * (size_t)ncomp * p));
+  }
+  std::vector<int32_t> sup(p);
+  int rc = SPCA_OK;
+  for (int32_t c = 0; c < ncomp && rc == SPCA_OK; ++c) {
+    spca_solve_opts o = *opts;
+    o.deflate_X = c > 0 ? Xd : nullptr;
+    o.deflate_k = c;
+    spca_outputs out{};
+    out.x = X_out + (int64_t)c * p;
+    out.support = sup.data();
+    out.res = &res[c];
+    rc = solve(ctx, stream, prob, &o, &out);
+    if (rc == SPCA_OK && c + 1 < ncomp) {
+      DeviceGuard g(ctx->device);
+      hipError_t e = hipMemcpyAsync(Xd + (int64_t)c * p, X_out + (int64_t)c * p,
+                                    sizeof(double) * p, hipMemcpyHostToDevice, st);
+      if (e == hipSuccess) e = hipStreamSynchronize(st);
+      if (e != hipSuccess) {
+        set_error(std::string("component loadings: ") + hipGetErrorString(e));
+        rc = SPCA_EHIP;
+      }
+    }
+  }
+  {
+    DeviceGuard g(ctx->device);
+    (void)hipStreamSynchronize(st);
+    (void)hipFree(Xd);
+  }
+  return rc;
+}
+
 extern "C" {
 
 const char* spca_last_error(void) { return spca::last_error(); }
@@ -911,8 +960,12 @@ int spca_am_solve_sparse(spca_ctx* ctx, void* stream, const spca_sparse_problem*
                "the arrays of the sparse matrix must be 16-byte aligned");
   SPCA_REQUIRE(opts->X0 != nullptr, "the sparse solve needs X0");
   SPCA_REQUIRE(opts->precision == SPCA_PREC_FP32, "the sparse solve runs in FP32");
-  SPCA_REQUIRE(opts->total_starts <= r && opts->deflate_k == 0,
-               "the sparse solve takes neither total_starts > r nor deflation");
+  SPCA_REQUIRE(opts->total_starts <= r, "the sparse solve takes no total_starts > r");
+  SPCA_REQUIRE(opts->deflate_k >= 0 && opts->deflate_k <= kMaxDefl,
+               "deflate_k must be in 0..16");
+  const int dk = opts->deflate_k;
+  SPCA_REQUIRE(dk == 0 || opts->deflate_X != nullptr,
+               "deflate_X must be set when deflate_k > 0");
   SPCA_REQUIRE(opts->check_every >= 1, "check_every must be >= 1");
   SPCA_REQUIRE(opts->warmup_iters >= 0, "warmup_iters must be >= 0");
   const bool warm = opts->warmup_iters > 0;
@@ -987,6 +1040,7 @@ int spca_am_solve_sparse(spca_ctx* ctx, void* stream, const spca_sparse_problem*
   const size_t o_gam = carve(&c, sizeof(double) * r);
   const size_t wide_bytes = x_update_wide_bytes(1, r, p);
   const size_t o_wide = carve(&c, wide_bytes);
+  const size_t o_defl = carve(&c, deflate_bytes(n, p, r, dk));
   rc = ensure_workspace(ctx, st, c);
   if (rc != SPCA_OK) return rc;
   char* base = (char*)ctx->ws;
@@ -1016,6 +1070,8 @@ int spca_am_solve_sparse(spca_ctx* ctx, void* stream, const spca_sparse_problem*
   int32_t* ulist = (int32_t*)(base + o_ul);
   double* gam = (double*)(base + o_gam);
   void* wide = wide_bytes ? (void*)(base + o_wide) : nullptr;
+  Defl defl{};
+  if (dk > 0) defl = carve_deflate(base + o_defl, n, p, r, dk);
   Warm wm;
   if (warm) {
     wm.K = opts->warmup_iters;
@@ -1061,6 +1117,12 @@ int spca_am_solve_sparse(spca_ctx* ctx, void* stream, const spca_sparse_problem*
   a.nrow_split = nsplit[0];
   a.ncol_split = nsplit[1];
 
+  if (dk > 0) {
+    // deflation (further components): loadings, Gram matrix, FP64 scores
+    deflate_loadings(st, opts->deflate_X, p, defl);
+    sparse_deflate_scores(st, a, defl);
+    SPCA_LAUNCH_CHECK("sparse deflation setup");
+  }
   SPCA_HIP_TRY(hipMemcpy2DAsync(X, sizeof(float) * ldx, opts->X0, sizeof(float) * p,
                                 sizeof(float) * p, r, hipMemcpyDeviceToDevice, st));
   init_state(st, s, r);
@@ -1085,10 +1147,12 @@ int spca_am_solve_sparse(spca_ctx* ctx, void* stream, const spca_sparse_problem*
     sparse_ax_dense(q, a, XT, ldt, r, UT, carry, U, ldu, s, plan);
     if (tm) SPCA_HIP_TRY(ctx->t_ax.mark(q));
     sparse_ax_list(q, a, li, lv, ldx, U, ldu, r, s, plan);
+    if (dk > 0) deflate_u(q, X, ldx, p, U, ldu, n, r, s, plan, defl);
     sparse_y_update(q, fid, U, ldu, n, r, s, ypart, YT, ldt);
     if (tm) SPCA_HIP_TRY(ctx->t_aty.mark(q));
     sparse_aty(q, a, YT, ldt, r, VT, carry, V, ldx, s, plan);
     if (tm) SPCA_HIP_TRY(ctx->t_aty.mark(q));
+    if (dk > 0) deflate_v(q, V, ldx, p, r, s, defl);
     if (tm) SPCA_HIP_TRY(ctx->t_xup.mark(q));
     x_update(q, fid, sg, V, ldx, r, p, X, ldx, li, lv, ldx, list_cap, s, opts->tol, maxit,
              colmark, plan, wide, wm);
@@ -1154,7 +1218,8 @@ int spca_am_solve_sparse(spca_ctx* ctx, void* stream, const spca_sparse_problem*
   // FP64 evaluation on the sparse matrix
   compact_rows(st, X, ldx, r, p, li, lv, ldx, s.nnz, nullptr, nullptr, nullptr);
   x_norms(st, lv, ldx, s, r, xnorm);
-  sparse_final(st, a, li, lv, ldx, s, r, xnorm, partial);
+  if (dk > 0) deflate_final_alpha(st, X, ldx, p, r, defl);
+  sparse_final(st, a, li, lv, ldx, s, r, xnorm, partial, defl);
   const bool per_start_gamma = warm && fid >= 5;
   objective_and_best(st, fid, sg, s, r, p, partial, (int)nfin, li, lv, ldx, xnorm, fj, evj, best,
                      xout, sup, per_start_gamma ? gam : nullptr, per_start_gamma);
@@ -1225,50 +1290,16 @@ int spca_am_solve_sparse(spca_ctx* ctx, void* stream, const spca_sparse_problem*
   return SPCA_OK;
 }
 
+int spca_am_components_sparse(spca_ctx* ctx, void* stream, const spca_sparse_problem* prob,
+                              const spca_solve_opts* opts, int32_t ncomp, double* X_out,
+                              spca_result* res) {
+  return components_loop(ctx, stream, prob, opts, ncomp, X_out, res, spca_am_solve_sparse);
+}
+
 int spca_am_components(spca_ctx* ctx, void* stream, const spca_problem* prob,
                        const spca_solve_opts* opts, int32_t ncomp, double* X_out,
                        spca_result* res) {
-  SPCA_REQUIRE(ctx && prob && opts && X_out && res,
-               "ctx, prob, opts, X_out and res must not be NULL");
-  SPCA_REQUIRE(ncomp >= 1 && ncomp <= kMaxDefl, "ncomp must be in 1..16");
-  SPCA_REQUIRE(opts->deflate_X == nullptr && opts->deflate_k == 0,
-               "deflate_X / deflate_k are set by the component loop");
-  SPCA_REQUIRE(prob->p >= 1, "p must be >= 1");
-  const int64_t p = prob->p;
-  hipStream_t st = (hipStream_t)stream;
-  double* Xd = nullptr;
-  {
-    DeviceGuard g(ctx->device);
-    SPCA_HIP_TRY(hipMalloc(&Xd, sizeof(double) * (size_t)ncomp * p));
-  }
-  std::vector<int32_t> sup(p);
-  int rc = SPCA_OK;
-  for (int32_t c = 0; c < ncomp && rc == SPCA_OK; ++c) {
-    spca_solve_opts o = *opts;
-    o.deflate_X = c > 0 ? Xd : nullptr;
-    o.deflate_k = c;
-    spca_outputs out{};
-    out.x = X_out + (int64_t)c * p;
-    out.support = sup.data();
-    out.res = &res[c];
-    rc = spca_am_solve_ex(ctx, stream, prob, &o, &out);
-    if (rc == SPCA_OK && c + 1 < ncomp) {
-      DeviceGuard g(ctx->device);
-      hipError_t e = hipMemcpyAsync(Xd + (int64_t)c * p, X_out + (int64_t)c * p,
-                                    sizeof(double) * p, hipMemcpyHostToDevice, st);
-      if (e == hipSuccess) e = hipStreamSynchronize(st);
-      if (e != hipSuccess) {
-        set_error(std::string("component loadings: ") + hipGetErrorString(e));
-        rc = SPCA_EHIP;
-      }
-    }
-  }
-  {
-    DeviceGuard g(ctx->device);
-    (void)hipStreamSynchronize(st);
-    (void)hipFree(Xd);
-  }
-  return rc;
+  return components_loop(ctx, stream, prob, opts, ncomp, X_out, res, spca_am_solve_ex);
 }
 
 static std::mutex g_default_mu;

@@ -599,7 +599,7 @@ __global__ __launch_bounds__(256) void sp_final_kernel(
     const int64_t* __restrict__ col_ptr, const int32_t* __restrict__ row_idx,
     const float* __restrict__ val, int64_t n, const int32_t* __restrict__ list_idx,
     const float* __restrict__ list_val, int64_t ldl, StartState s,
-    const double* __restrict__ xnorm, double* __restrict__ partial) {
+    const double* __restrict__ xnorm, double* __restrict__ partial, Defl defl) {
   __shared__ double ub[kRB64];
   __shared__ int64_t bnd[2];
   __shared__ double red[2 * 5];
@@ -628,6 +628,11 @@ __global__ __launch_bounds__(256) void sp_final_kernel(
     }
     __syncthreads();
   }
+  // deflated problem: A_k x = A x - sum_l alpha_l A x_l
+  if (live && defl.k > 0)
+    for (int64_t i = threadIdx.x; b0 + i < b1; i += 256)
+      for (int l = 0; l < defl.k; ++l)
+        ub[i] -= defl.alpha[j * kMaxDefl + l] * defl.scores[(b0 + i) * kMaxDefl + l];
   double acc[2] = {0.0, 0.0};
   for (int64_t i = threadIdx.x; b0 + i < b1; i += 256) {
     acc[0] += ub[i] * ub[i];
@@ -644,6 +649,38 @@ __global__ __launch_bounds__(256) void sp_final_kernel(
 // above 64 starts
 int seg_lanes(int64_t r) { return r <= 8 ? 2 : r <= 16 ? 4 : r <= 32 ? 8 : 16; }
 int64_t seg_blocks(int64_t r) { return ceil_div(r, (int64_t)4 * seg_lanes(r)); }
+
+// FP64 scores of the deflation loadings: rows [b0, b1) of B[:, i] = A x_i
+// from the loading's (index, value) list, in LDS, column by column
+__global__ __launch_bounds__(256) void sp_scores_kernel(
+    const int64_t* __restrict__ col_ptr, const int32_t* __restrict__ row_idx,
+    const float* __restrict__ val, int64_t n, int64_t p, Defl d) {
+  __shared__ double ub[kRB64];
+  __shared__ int64_t bnd[2];
+  const int i = blockIdx.y;
+  const int64_t b0 = (int64_t)blockIdx.x * kRB64;
+  const int64_t b1 = b0 + kRB64 < n ? b0 + kRB64 : n;
+  const int wave = threadIdx.x / kWave;
+  for (int e = threadIdx.x; e < kRB64; e += 256) ub[e] = 0.0;
+  const int32_t cnt = d.cnt[i];
+  for (int32_t t = 0; t < cnt; ++t) {
+    const int32_t c = d.idx[i * p + t];
+    const double x = d.val[i * p + t];
+    const int64_t cb = col_ptr[c], ce = col_ptr[c + 1];
+    if (wave < 2) {
+      const int64_t pos = wave_lower_bound(row_idx, cb, ce, wave == 0 ? b0 : b1);
+      if (threadIdx.x % kWave == 0) bnd[wave] = pos;
+    }
+    __syncthreads();
+    const int64_t kb = bnd[0], ke = bnd[1];
+    for (int64_t k = kb + threadIdx.x; k < ke; k += 256) {
+      const int64_t row = row_idx[k];
+      if (row >= b0 && row < b1) ub[row - b0] += (double)val[k] * x;
+    }
+    __syncthreads();
+  }
+  for (int64_t e = threadIdx.x; b0 + e < b1; e += 256) d.scores[(b0 + e) * kMaxDefl + i] = ub[e];
+}
 
 template <int L>
 void launch_seg(hipStream_t st, const int64_t* ptr, const int32_t* idx, const float* val,
@@ -821,10 +858,17 @@ void sparse_ax_list(hipStream_t st, const SparseA& a, const int32_t* list_idx,
 
 void sparse_final(hipStream_t st, const SparseA& a, const int32_t* list_idx,
                   const float* list_val, int64_t ldl, StartState s, int64_t r,
-                  const double* xnorm, double* partial) {
+                  const double* xnorm, double* partial, Defl defl) {
   const dim3 g((unsigned)sparse_final_parts(a.n), (unsigned)r);
   hipLaunchKernelGGL(sp_final_kernel, g, dim3(256), 0, st, a.col_ptr, a.row_idx, a.col_val,
-                     a.n, list_idx, list_val, ldl, s, xnorm, partial);
+                     a.n, list_idx, list_val, ldl, s, xnorm, partial, defl);
+}
+
+void sparse_deflate_scores(hipStream_t st, const SparseA& a, Defl d) {
+  if (d.k <= 0 || a.n == 0) return;
+  const dim3 g((unsigned)sparse_final_parts(a.n), (unsigned)d.k);
+  hipLaunchKernelGGL(sp_scores_kernel, g, dim3(256), 0, st, a.col_ptr, a.row_idx, a.col_val,
+                     a.n, a.p, d);
 }
 
 }  // namespace spca

@@ -188,3 +188,29 @@ def test_sparse_rejects_malformed(spca):
     rp = mat.row_ptr.copy()
     rp[-1] -= 1
     bad(row_ptr=rp)
+
+
+@pytest.mark.parametrize("fid", [1, 3, 7])
+@pytest.mark.parametrize("panels", [False, True])
+def test_sparse_components_match_oracle(spca, fid, panels):
+    """Further components on a sparse A (implicit projection deflation, FP64
+    scores from the columns): per component the objective and the support
+    agree with the oracle, which deflates the dense copy explicitly, and
+    with the dense GPU component loop."""
+    print(f"sparse components fid={fid} panels={panels}", flush=True)
+    mat = sparse.bag_of_words(53, 900, 1600, 45000)
+    A = mat.dense()
+    X0n = workloads.random_unit_starts(54, 16, mat.p)
+    par = {1: 8.0, 3: 4.0}.get(fid) or workloads.s_or_gamma_for(fid, A, 8, "scaled")
+    flags = spca.FLAG_SPARSE_PANELS if panels else spca.FLAG_SPARSE_NO_PANELS
+    got = spca.am_components_sparse(spca.sparse_to_device(mat), fid, par, to_device_rows(X0n),
+                                    3, tol=1e-9, maxit=400, flags=flags)
+    ref = oracle.am_components(A, fid, par, X0n.astype(np.float64), 3, 1e-9, 400, nthreads=8)
+    dense = spca.am_components(to_device_colmajor(A.astype(np.float32)), fid, par,
+                               to_device_rows(X0n), 3, tol=1e-9, maxit=400)
+    for c in range(3):
+        print(c, got[c]["objective"], ref[c]["f"], len(got[c]["support"]), flush=True)
+        assert rel_err(got[c]["objective"], ref[c]["f"]) <= 1e-5, (fid, c)
+        assert np.array_equal(got[c]["support"], np.flatnonzero(ref[c]["x"])), (fid, c)
+        assert rel_err(got[c]["objective"], dense[c]["objective"]) <= 1e-5, (fid, c)
+        assert abs(np.linalg.norm(got[c]["x"]) - 1.0) < 1e-12
