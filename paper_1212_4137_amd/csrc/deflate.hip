@@ -100,7 +100,12 @@ __device__ __forceinline__ void alphas(const Defl& d, double (&a)[kMaxDefl]) {
 }
 
 // u_j (first partial of U) -= sum_i alpha_i B[:, i], for the running starts,
-// in the modes whose U goes through the separate y-update
+// in the modes whose U goes through the separate y-update.  Workgroup
+// (b, j) corrects rows [b kDR, (b + 1) kDR) of start j (alpha is formed
+// again by every block of the start: k dot products over the loadings'
+// supports).
+constexpr int64_t kDR = 4096;
+
 __global__ __launch_bounds__(kDT) void defl_u_kernel(const float* __restrict__ X,
                                                      int64_t ldx, int64_t p,
                                                      float* __restrict__ U, int64_t ldu,
@@ -108,13 +113,15 @@ __global__ __launch_bounds__(kDT) void defl_u_kernel(const float* __restrict__ X
                                                      const Plan* plan, Defl d) {
   __shared__ double red[kMaxDefl * (kDT / kWave + 1)];
   if (plan->mode == kAxList) return;
-  const int64_t j = blockIdx.x;
+  const int64_t j = blockIdx.y;
   if (s.status[j] != kRunning) return;
   double a[kMaxDefl];
   loading_dots(d, X + j * ldx, p, a, red);
   alphas(d, a);
   float* u = U + j * ldu;
-  for (int64_t row = threadIdx.x; row < n; row += kDT) {
+  const int64_t b0 = (int64_t)blockIdx.x * kDR;
+  const int64_t b1 = b0 + kDR < n ? b0 + kDR : n;
+  for (int64_t row = b0 + threadIdx.x; row < b1; row += kDT) {
     double c = 0.0;
     for (int l = 0; l < d.k; ++l) c += a[l] * d.scores[row * kMaxDefl + l];
     u[row] = (float)((double)u[row] - c);
@@ -207,8 +214,8 @@ void deflate_setup(hipStream_t st, const double* Xd, const float* A, int64_t lda
 
 void deflate_u(hipStream_t st, const float* X, int64_t ldx, int64_t p, float* U,
                int64_t ldu, int64_t n, int64_t r, StartState s, const Plan* plan, Defl d) {
-  hipLaunchKernelGGL(defl_u_kernel, dim3((unsigned)r), dim3(kDT), 0, st, X, ldx, p, U, ldu,
-                     n, s, plan, d);
+  hipLaunchKernelGGL(defl_u_kernel, dim3((unsigned)ceil_div(n, kDR), (unsigned)r), dim3(kDT),
+                     0, st, X, ldx, p, U, ldu, n, s, plan, d);
 }
 
 void deflate_v(hipStream_t st, float* V, int64_t ldv, int64_t p, int64_t r, StartState s,
