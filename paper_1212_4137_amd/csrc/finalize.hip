@@ -87,6 +87,121 @@ __global__ __launch_bounds__(kFT) void final_matvec_kernel(
   }
 }
 
+// The same partial sums for mostly dense iterates, as one FP64 product on the
+// matrix cores: U = A Xs with Xs[c][j] = x_j[c] / ||x_j|| (x_j the FP32
+// iterate, A exact in FP64).  Workgroup (t, g) owns rows [64 t, 64 t + 64)
+// and starts [64 g, 64 g + 64); its 2 x 2 waves own 32 x 32, four 16 x 16
+// blocks of v_mfma_f64_16x16x4f64 (operand lane l: A[l % 16][l / 16] and
+// B[l / 16][l % 16]; result element e of lane l: D[4 e + l / 16][l % 16]).
+// The columns advance 16 at a time through LDS, the next 16 already in
+// registers.  Partial pairs per (start, 64-row tile), summed in a fixed order.
+typedef double double4_t __attribute__((ext_vector_type(4)));
+constexpr int kGT = 64;  // rows and starts per workgroup tile
+constexpr int kGK = 16;  // columns per stage
+
+__global__ __launch_bounds__(256) void final_gemm64_kernel(
+    const float* __restrict__ A, int64_t lda, int64_t n, int64_t p,
+    const float* __restrict__ X, int64_t ldx, StartState s, int64_t r,
+    const double* __restrict__ xnorm, double* partial, int ntiles, Defl defl) {
+  __shared__ double sA[kGK][kGT];  // A[row][col] by column
+  __shared__ double sB[kGK][kGT];  // Xs[col][start] by column
+  __shared__ double scale[kGT];
+  __shared__ double red[2][4][kGT][2];
+  const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
+  const int wm = wave % 2, wn = wave / 2;
+  const int64_t i0 = (int64_t)blockIdx.x * kGT, j0 = (int64_t)blockIdx.y * kGT;
+  if (tid < kGT) {
+    const int64_t j = j0 + tid;
+    double sc = 0.0;
+    if (j < r) {
+      const double nrm = xnorm[j];
+      const bool live = s.status[j] != SPCA_DEGENERATE && s.status[j] != SPCA_ZERO;
+      if (live && nrm > 0.0) sc = 1.0 / nrm;
+    }
+    scale[tid] = sc;
+  }
+  // staging: A as (row tid % 64, columns 4 (tid / 64) .. + 3); X as
+  // (start tid / 4, columns 4 (tid % 4) .. + 3)
+  const int ar = tid % kGT, ac = 4 * (tid / kGT);
+  const int xj = tid / 4, xc = 4 * (tid % 4);
+  float pa[4], px[4];
+  auto fetch = [&](int64_t c0) {
+    const int64_t i = i0 + ar, j = j0 + xj;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int64_t ca = c0 + ac + e, cx = c0 + xc + e;
+      pa[e] = (i < n && ca < p) ? A[i + ca * lda] : 0.f;
+      px[e] = (j < r && cx < p) ? X[j * ldx + cx] : 0.f;
+    }
+  };
+  double4_t acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = {0.0, 0.0, 0.0, 0.0};
+  fetch(0);
+  __syncthreads();  // scale
+  for (int64_t c0 = 0; c0 < p; c0 += kGK) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      sA[ac + e][ar] = (double)pa[e];
+      sB[xc + e][xj] = (double)px[e] * scale[xj];
+    }
+    __syncthreads();
+    if (c0 + kGK < p) fetch(c0 + kGK);
+#pragma unroll
+    for (int k0 = 0; k0 < kGK; k0 += 4) {
+      const int k = k0 + lane / 16, q = lane % 16;
+      double fa[2], fb[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) fa[a] = sA[k][wm * 32 + a * 16 + q];
+#pragma unroll
+      for (int b = 0; b < 2; ++b) fb[b] = sB[k][wn * 32 + b * 16 + q];
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[a], fb[b], acc[a][b], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  // epilogue: lane holds rows wm 32 + a 16 + 4 e + lane / 16 of start
+  // wn 32 + b 16 + lane % 16
+#pragma unroll
+  for (int b = 0; b < 2; ++b) {
+    const int jl = wn * 32 + b * 16 + lane % 16;
+    const int64_t j = j0 + jl;
+    double sq = 0.0, ab = 0.0;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t i = i0 + wm * 32 + a * 16 + 4 * e + lane / 16;
+        if (i < n && j < r) {
+          double u = acc[a][b][e];
+          if (defl.k > 0)
+            for (int l = 0; l < defl.k; ++l)
+              u -= defl.alpha[j * kMaxDefl + l] * defl.scores[i * kMaxDefl + l];
+          sq += u * u;
+          ab += fabs(u);
+        }
+      }
+    red[wm][lane / 16][jl][0] = sq;
+    red[wm][lane / 16][jl][1] = ab;
+  }
+  __syncthreads();
+  if (tid < kGT && j0 + tid < r) {
+    double sq = 0.0, ab = 0.0;
+    for (int m = 0; m < 2; ++m)
+      for (int g = 0; g < 4; ++g) {
+        sq += red[m][g][tid][0];
+        ab += red[m][g][tid][1];
+      }
+    partial[((j0 + tid) * ntiles + blockIdx.x) * 2] = sq;
+    partial[((j0 + tid) * ntiles + blockIdx.x) * 2 + 1] = ab;
+  }
+}
+
 __global__ void objective_kernel(int fid, double gamma, StartState s,
                                  int64_t r, const double* __restrict__ partial,
                                  int nchunks, const double* __restrict__ xnorm,
@@ -217,9 +332,21 @@ void finalize(hipStream_t st, int fid, double s_or_gamma, const float* A,
               const float* list_val, int64_t ldl, StartState s, int64_t r,
               double* partial, double* f, double* ev, double* xnorm,
               int32_t* best, double* x_out, int32_t* support_out,
-              const double* gam, bool by_ev, Defl defl) {
-  evaluate_rows(st, fid, s_or_gamma, A, lda, n, list_idx, list_val, ldl, s, r,
-                partial, f, ev, xnorm, nullptr, gam, defl);
+              const double* gam, bool by_ev, Defl defl, const float* X_dense,
+              int64_t ldx) {
+  if (X_dense == nullptr) {
+    evaluate_rows(st, fid, s_or_gamma, A, lda, n, list_idx, list_val, ldl, s, r,
+                  partial, f, ev, xnorm, nullptr, gam, defl);
+  } else {
+    const int ntiles = (int)ceil_div(n, (int64_t)kGT);
+    hipLaunchKernelGGL(x_norms_kernel, dim3((unsigned)r), dim3(256), 0, st, list_val, ldl, s,
+                       r, xnorm, nullptr);
+    hipLaunchKernelGGL(final_gemm64_kernel,
+                       dim3((unsigned)ntiles, (unsigned)ceil_div(r, (int64_t)kGT)), dim3(256),
+                       0, st, A, lda, n, p, X_dense, ldx, s, r, xnorm, partial, ntiles, defl);
+    hipLaunchKernelGGL(objective_kernel, dim3((unsigned)ceil_div(r, 256)), dim3(256), 0, st,
+                       fid, s_or_gamma, s, r, partial, ntiles, xnorm, f, ev, nullptr, gam);
+  }
   hipLaunchKernelGGL(best_kernel, dim3(1), dim3(1024), 0, st, by_ev ? ev : f, s, r, p,
                      list_idx, list_val, ldl, xnorm, best, x_out, support_out);
 }

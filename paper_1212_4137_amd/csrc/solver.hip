@@ -82,7 +82,7 @@ Layout make_layout(int64_t n, int64_t p, int64_t r, bool copy_a, bool bf16) {
   L.ldatb = round_up(p, 8);
   L.ldyb = round_up(n, 8);
   L.ldxb = round_up(p, 8);
-  L.nchunks = (int)ceil_div(n, 256);
+  L.nchunks = (int)ceil_div(n, 64);  // partial pairs per start (64-row tiles at most)
   const int eb = bf16 ? 2 : 4;
   L.plan_ax = plan_gemm_nt(r, n, p, kMaxSplits, eb);   // U^T = X^T A^T, K = p
   L.plan_aty = plan_gemm_nt(r, p, n, kMaxSplits, eb);  // V^T = Y^T A,   K = n
@@ -841,9 +841,18 @@ int spca_am_solve_ex(spca_ctx* ctx, void* stream, const spca_problem* prob,
     // and the best start is the one with the largest explained variance
     const bool per_start_gamma = warm && fid >= 5;
     if (dk > 0) deflate_final_alpha(st, X, L.ldx, p, r, defl);
+    // mostly dense iterates (a quarter of all entries or more): one FP64
+    // product on the matrix cores instead of per-start sums over the lists
+    std::vector<int32_t> nnz_h(r);
+    SPCA_HIP_TRY(hipMemcpyAsync(nnz_h.data(), s.nnz, sizeof(int32_t) * r,
+                                hipMemcpyDeviceToHost, st));
+    SPCA_HIP_TRY(hipStreamSynchronize(st));
+    double tot_nnz = 0.0;
+    for (int64_t j = 0; j < r; ++j) tot_nnz += nnz_h[j];
+    const bool dense_eval = r >= 16 && tot_nnz * 4.0 >= (double)r * (double)p;
     finalize(st, fid, sg, A, ldA, n, p, li, lv, L.ldx, s, r, partial, fj, evj,
              xnorm, best, xout, sup, per_start_gamma ? gam : nullptr, per_start_gamma,
-             defl);
+             defl, dense_eval ? X : nullptr, L.ldx);
   }
   SPCA_LAUNCH_CHECK("finalize");
 
