@@ -155,7 +155,29 @@ __global__ __launch_bounds__(WM* WN* kWave) void gemm_nt_kernel(
   floatx4 pre_p[Cfg::kPVec];
   floatx4 pre_q[Cfg::kQVec];
 
+  // Small wave tiles (at most two MFMA blocks) load interior slabs of full
+  // tiles without per-row or per-K guards, and read the operands of the
+  // next 8-wide K chunk from LDS while the current chunk's MFMAs run (two
+  // register sets).  Larger wave tiles issue enough MFMAs per LDS read to
+  // cover its latency, and measured slower with either change.
+  constexpr bool kPrefetch = Cfg::kFM * Cfg::kFN <= 2;
+  const bool full_rows = mrows >= BM && nrows >= BN;
   auto fetch = [&](int k0) {
+    if (kPrefetch && full_rows && k0 + SK <= kend) {
+#pragma unroll
+      for (int v = 0; v < Cfg::kPVec; ++v) {
+        const int f = tid + v * Cfg::kThreads;
+        pre_p[v] = *reinterpret_cast<const floatx4*>(
+            Pblk + (int64_t)(f / kChunks) * ldp + k0 + (f % kChunks) * E);
+      }
+#pragma unroll
+      for (int v = 0; v < Cfg::kQVec; ++v) {
+        const int f = tid + v * Cfg::kThreads;
+        pre_q[v] = *reinterpret_cast<const floatx4*>(
+            Qblk + (int64_t)(f / kChunks) * ldq + k0 + (f % kChunks) * E);
+      }
+      return;
+    }
 #pragma unroll
     for (int v = 0; v < Cfg::kPVec; ++v) {
       int f = tid + v * Cfg::kThreads;
@@ -190,19 +212,30 @@ __global__ __launch_bounds__(WM* WN* kWave) void gemm_nt_kernel(
     const float* sp = lds + (ks & 1) * Cfg::kStage;
     const float* sq = sp + BM * kBK;
     if (ks + 1 < nslabs) fetch(kbeg + (ks + 1) * SK);
-#pragma unroll
-    for (int c8 = 0; c8 < kChunks; c8 += 2) {
+    floatx4 a[2][Cfg::kFM];
+    floatx4 bq[2][Cfg::kFN];
+    auto read_ops = [&](int buf, int c8) {
       const int chunk = c8 + lhalf;  // k offset 4 * chunk within the slab
-      floatx4 a[Cfg::kFM];
-      floatx4 bq[Cfg::kFN];
 #pragma unroll
       for (int i = 0; i < Cfg::kFM; ++i)
-        a[i] = *reinterpret_cast<const floatx4*>(
+        a[buf][i] = *reinterpret_cast<const floatx4*>(
             &sp[swz(wm * Cfg::kTM + i * 32 + lrow, chunk)]);
 #pragma unroll
       for (int j = 0; j < Cfg::kFN; ++j)
-        bq[j] = *reinterpret_cast<const floatx4*>(
+        bq[buf][j] = *reinterpret_cast<const floatx4*>(
             &sq[swz(wn * Cfg::kTN + j * 32 + lrow, chunk)]);
+    };
+    if (kPrefetch) read_ops(0, 0);
+#pragma unroll
+    for (int c8 = 0; c8 < kChunks; c8 += 2) {
+      const int cur = kPrefetch ? (c8 / 2) & 1 : 0;
+      if (!kPrefetch) {
+        read_ops(0, c8);
+      } else if (c8 + 2 < kChunks) {
+        read_ops(cur ^ 1, c8 + 2);
+        // keep the scheduler from sinking those reads below the MFMAs
+        __builtin_amdgcn_sched_barrier(0);
+      }
       if constexpr (E == 4) {
 #pragma unroll
         for (int e = 0; e < 4; ++e)
@@ -210,7 +243,7 @@ __global__ __launch_bounds__(WM* WN* kWave) void gemm_nt_kernel(
           for (int i = 0; i < Cfg::kFM; ++i)
 #pragma unroll
             for (int j = 0; j < Cfg::kFN; ++j)
-              acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i][e], bq[j][e],
+              acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[cur][i][e], bq[cur][j][e],
                                                                acc[i][j], 0, 0, 0);
       } else {
 #pragma unroll
@@ -218,7 +251,7 @@ __global__ __launch_bounds__(WM* WN* kWave) void gemm_nt_kernel(
 #pragma unroll
           for (int j = 0; j < Cfg::kFN; ++j)
             acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                __builtin_bit_cast(bf16x8, a[i]), __builtin_bit_cast(bf16x8, bq[j]),
+                __builtin_bit_cast(bf16x8, a[cur][i]), __builtin_bit_cast(bf16x8, bq[cur][j]),
                 acc[i][j], 0, 0, 0);
       }
     }
