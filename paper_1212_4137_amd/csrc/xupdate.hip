@@ -551,7 +551,64 @@ struct RSmem {
   int64_t cut;
   uint32_t sel[2];  // selected bin, count above it
   double seg[4];
+  uint64_t pscan[3 * (kRW + 1)];  // packed per-row counts (rank_rows)
 };
+
+// Index-order ranks over the striped row layout of the one-workgroup
+// x-update: thread t holds elements 4 (q kRT + t) + e, e < 4, for rows q <
+// R.  Given per-thread counts c[q] <= 4 of the elements that satisfy a
+// predicate, returns in base[q] the number of such elements at a lower
+// index than this thread's row-q group (earlier rows of the whole block,
+// then lower threads of the same row), and the block total.  Four 16-bit
+// fields per 64-bit word hold row counts up to 4 kRT without carries.
+template <int R>
+__device__ __forceinline__ int rank_rows(const int (&c)[R], int (&base)[R], uint64_t* scratch) {
+  constexpr int W = (R + 3) / 4;
+  const int lane = threadIdx.x % kWave;
+  const int wave = threadIdx.x / kWave;
+  uint64_t in[W], inc[W];
+#pragma unroll
+  for (int w = 0; w < W; ++w) in[w] = 0;
+#pragma unroll
+  for (int q = 0; q < R; ++q) in[q / 4] |= (uint64_t)c[q] << (16 * (q % 4));
+#pragma unroll
+  for (int w = 0; w < W; ++w) inc[w] = in[w];
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      const uint64_t o = __shfl_up(inc[w], off, kWave);
+      if (lane >= off) inc[w] += o;
+    }
+  }
+  if (lane == kWave - 1) {
+#pragma unroll
+    for (int w = 0; w < W; ++w) scratch[wave * W + w] = inc[w];
+  }
+  __syncthreads();
+  uint64_t before[W], tot[W];
+#pragma unroll
+  for (int w = 0; w < W; ++w) before[w] = tot[w] = 0;
+#pragma unroll
+  for (int u = 0; u < kRW; ++u) {
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      const uint64_t x = scratch[u * W + w];
+      if (u < wave) before[w] += x;
+      tot[w] += x;
+    }
+  }
+  __syncthreads();
+  int run = 0;
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    const int sh = 16 * (q % 4);
+    const int mine = (int)(((before[q / 4] + inc[q / 4] - in[q / 4]) >> sh) & 0xffffu);
+    base[q] = run + mine;
+    run += (int)((tot[q / 4] >> sh) & 0xffffu);
+  }
+  return run;
+}
 
 // Exclusive prefix sums of two doubles per thread in thread order (kRT).
 __device__ __forceinline__ void rscan2(double (&v)[2], double* scratch) {
@@ -661,12 +718,15 @@ __global__ __launch_bounds__(kRT, (KIND == kTopS || WARM) ? 2 : 4) void x_update
   if (full && s.status[j] != kRunning) return;
   const int tid = threadIdx.x;
   const int lane = tid % kWave;
-  const int base = tid * NPT;
+  // Striped rows: element 4 (q kRT + tid) + e is v[4 q + e], so that each
+  // 16-byte load and store instruction covers 1 KB of contiguous memory.
+  constexpr int R = NPT / 4;
+  auto gidx = [&](int k) { return 4 * ((k / 4) * kRT + tid) + k % 4; };
   const float* vg = V + j * ldv;
   float v[NPT];
 #pragma unroll
   for (int q = 0; q < NPT; q += 4) {
-    const int i = base + q;
+    const int i = gidx(q);
     if (i + 3 < p) {
       const floatx4 t = *reinterpret_cast<const floatx4*>(vg + i);
       v[q] = t.x;
@@ -690,22 +750,27 @@ __global__ __launch_bounds__(kRT, (KIND == kTopS || WARM) ? 2 : 4) void x_update
     radix_select<NPT>(v, s_int, sm, &thr_key, &above);
     // ties at thr_key: keep the first (s - #{key > thr_key}) in index order
     if (tid == 0) sm.cut = -1;
-    int eq = 0;
+    int eq[R], eq_base[R];
 #pragma unroll
-    for (int k = 0; k < NPT; ++k) {
-      reload(v[k]);
-      eq += key_of(v[k]) == thr_key && base + k < p;
+    for (int q = 0; q < R; ++q) {
+      eq[q] = 0;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        reload(v[4 * q + e]);
+        eq[q] += key_of(v[4 * q + e]) == thr_key && gidx(4 * q + e) < p;
+      }
     }
-    int eq_total;
-    const int eq_off = block_exclusive_scan(eq, sm.scan, &eq_total);
+    rank_rows<R>(eq, eq_base, sm.pscan);
     const int need = (int)s_int - (int)above;  // >= 1
-    if (eq_off < need && need <= eq_off + eq) {
-      int seen = eq_off;
 #pragma unroll
-      for (int k = 0; k < NPT; ++k) {
-        if (key_of(v[k]) == thr_key && base + k < p) {
+    for (int q = 0; q < R; ++q) {
+      int seen = eq_base[q];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int k = 4 * q + e;
+        if (key_of(v[k]) == thr_key && gidx(k) < p) {
           ++seen;
-          if (seen == need) sm.cut = base + k;
+          if (seen == need) sm.cut = gidx(k);
         }
       }
     }
@@ -942,20 +1007,25 @@ __global__ __launch_bounds__(kRT, (KIND == kTopS || WARM) ? 2 : 4) void x_update
     }
   };
 
-  int cnt = 0;
+  int cnt[R], off[R];
   double acc[2] = {0.0, 0.0};
 #pragma unroll
-  for (int k = 0; k < NPT; ++k) {
-    double w;
-    if (kept(base + k, v[k], &w)) {
-      ++cnt;
-      acc[0] += w * w;
-      if (KIND == kHardGamma) acc[1] += w * w - lam;
+  for (int q = 0; q < R; ++q) {
+    cnt[q] = 0;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int k = 4 * q + e;
+      double w;
+      reload(v[k]);
+      if (kept(gidx(k), v[k], &w)) {
+        ++cnt[q];
+        acc[0] += w * w;
+        if (KIND == kHardGamma) acc[1] += w * w - lam;
+      }
     }
   }
   block_sum_n<double, 2>(acc, sm.dred);
-  int total;
-  int off = block_exclusive_scan(cnt, sm.scan, &total);
+  const int total = rank_rows<R>(cnt, off, sm.pscan);
   const double nrm = sqrt(acc[0]);
   double phi;
   if (KIND == kHardGamma)
@@ -977,19 +1047,22 @@ __global__ __launch_bounds__(kRT, (KIND == kTopS || WARM) ? 2 : 4) void x_update
 #pragma unroll
   for (int q = 0; q < NPT; q += 4) {
     float xo[4];
+    int o = off[q / 4];
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       double w;
-      const bool kp = kept(base + q + e, v[q + e], &w) && !zero;
+      const int gi = gidx(q + e);
+      reload(v[q + e]);  // recompute w here rather than hold it since the count pass
+      const bool kp = kept(gi, v[q + e], &w) && !zero;
       xo[e] = kp ? (float)(w * inv) : 0.f;
       if (kp && li != nullptr) {
-        li[off] = base + q + e;
-        lv[off] = xo[e];
-        ++off;
+        li[o] = gi;
+        lv[o] = xo[e];
+        ++o;
       }
-      if (kp && marking) colmark[base + q + e] = epoch;
+      if (kp && marking) colmark[gi] = epoch;
     }
-    const int i = base + q;
+    const int i = gidx(q);
     if (i + 3 < p) {
       floatx4 t = {xo[0], xo[1], xo[2], xo[3]};
       *reinterpret_cast<floatx4*>(x + i) = t;

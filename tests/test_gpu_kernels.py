@@ -125,6 +125,24 @@ def test_x_update_T_s_ties_and_edges(spca):
     _check_xupdate(spca, 2, V_h, p)
 
 
+def test_x_update_T_s_ties_across_rows(spca):
+    """p = 5000: the one-workgroup kernel holds elements 1024 apart in one
+    thread, so ties at the s-th key that span several such groups, and a
+    cut through an all-equal row, must still keep the lowest indices."""
+    p = 5000
+    V_h = np.zeros((4, p), np.float32)
+    V_h[0, [4999, 7, 1027, 2100, 1030, 3071, 4096]] = [2.0, -2.0, 2.0, -2.0, 2.0, 2.0, -2.0]
+    V_h[0, 500] = 3.0
+    V_h[1, :] = 1.0
+    rng = np.random.default_rng(11)
+    V_h[2] = rng.integers(-3, 4, size=p).astype(np.float32)  # many ties
+    V_h[3] = (rng.standard_normal(p) * 3).astype(np.float32)
+    X, phi, nnz = _check_xupdate(spca, 1, V_h, 4)
+    assert np.flatnonzero(X[0]).tolist() == [7, 500, 1027, 1030]
+    X, _, _ = _check_xupdate(spca, 2, V_h, 1500)
+    assert np.flatnonzero(X[1]).tolist() == list(range(1500))
+
+
 def test_x_update_gamma_boundaries(spca):
     rng = np.random.default_rng(5)
     V_h = (rng.standard_normal((4, 513)) * 2).astype(np.float32)
