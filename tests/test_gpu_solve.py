@@ -213,6 +213,22 @@ def test_row_block_list_product(spca, fid):
     assert rel_err(got["objective"], dense["objective"]) <= 1e-5
 
 
+def test_row_block_list_product_many_starts(spca):
+    """More starts than the row-block kernel's capped grid height (256), so
+    each workgroup row serves several starts: per-start results agree with
+    the dense product on the same starts."""
+    sp = workloads.spiked_matrix(73, 8200, 1500, thetas=(200.0, 120.0), spike_nnz=20)
+    X0n = workloads.random_unit_starts(74, 300, 1500)
+    A, X0 = to_device_colmajor(sp.A), to_device_rows(X0n)
+    got = spca.am_solve(A, 1, 20.0, X0, tol=1e-8, maxit=100, kernel_times=True,
+                        flags=spca.FLAG_NO_UNION)
+    assert got["kernel_times"]["iters_list_rows"] > 0, got["kernel_times"]
+    dense = spca.am_solve(A, 1, 20.0, X0, tol=1e-8, maxit=100, flags=spca.FLAG_DENSE_ONLY)
+    assert rel_err(got["objective"], dense["objective"]) <= 1e-5
+    ok = [rel_err(a, b) <= 1e-5 for a, b in zip(got["f_per_start"], dense["f_per_start"])]
+    assert np.mean(ok) >= 0.98
+
+
 @pytest.mark.parametrize("fid", [1, 6])
 def test_k_split_aty_product(spca, fid):
     """Few starts and a long p: the planner splits the K = n loop of
