@@ -706,6 +706,8 @@ def main():
     ap.add_argument("--arena-gb", type=float, default=64.0, help="serve: HBM arena")
     ap.add_argument("--autotune", action="store_true",
                     help="time every tile shape and split first (spiked-all8, large)")
+    ap.add_argument("--no-union", action="store_true",
+                    help="keep the planner off the union-of-supports product")
     ap.add_argument("--graph", action="store_true",
                     help="replay the iterations from a captured HIP graph")
     args = ap.parse_args()
@@ -719,7 +721,7 @@ def main():
     import paper_1212_4137_amd as spca
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
-    args.flags = spca.FLAG_GRAPH if args.graph else 0
+    args.flags = (spca.FLAG_GRAPH if args.graph else 0) | (spca.FLAG_NO_UNION if args.no_union else 0)
     rec = WORKLOADS[args.workload](args, spca, torch)
     print(json.dumps(rec), flush=True)
 

@@ -723,7 +723,7 @@ int spca_am_solve_ex(spca_ctx* ctx, void* stream, const spca_problem* prob,
       gemm_nt_f32(q, X, L.ldx, At, L.ldat, U, L.ldu, r, n, p, &plan->mode,
                   kAxDense, L.plan_ax, r * L.ldu);
     if (tm) SPCA_HIP_TRY(ctx->t_ax.mark(q));
-    if (!bf16) {
+    if (!bf16 && ucap_eff > 0) {  // the planner can pick the union product
       union_gather(q, X, L.ldx, r, A, ldA, n, ulist, plan, Xc, ldc_u, Qc, ldc_u);
       gemm_nt_f32(q, Xc, ldc_u, Qc, ldc_u, U, L.ldu, r, n, L.ucap, &plan->mode,
                   kAxUnion, L.plan_union, 0, &plan->union_size);
