@@ -185,7 +185,10 @@ typedef struct {
  * product's result depends on its K split, so tuned solves are
  * reproducible given the table (see spca_tune_table_export).              */
 #define SPCA_FLAG_AUTOTUNE 8
-#define SPCA_FLAG_NO_UNION 16    /* never use the union-of-supports product  */
+/* SPCA_FLAG_NO_UNION: never use the union-of-supports product; its gather
+ * and product kernels are then not launched at all (each launch that a
+ * solve's planner gates off still costs a few microseconds).               */
+#define SPCA_FLAG_NO_UNION 16
 /* Sparse solve only: A^T Y reads a copy of the columns split into row
  * panels (one panel's rows per XCD at a time, so that the gathered rows of
  * Y stay in that XCD's L2), built at the start of each solve.  By default
