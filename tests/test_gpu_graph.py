@@ -66,3 +66,21 @@ def test_graph_with_maxit_below_block(spca, problem):
                       flags=spca.FLAG_GRAPH)
     _same(a, b)
     assert np.all(b["iters_per_start"] == 5)
+
+
+@pytest.mark.parametrize("fid", [1, 5])
+def test_graph_without_union_launches(spca, problem, fid):
+    """With the union product disabled its kernels are left out of the
+    launch sequence; the replayed graph still matches the eager solve, and
+    both match the solve with the union product available whenever the
+    planner picks no union product there."""
+    A_np, A, X0 = problem
+    par = workloads.s_or_gamma_for(fid, A_np, 20, "literal")
+    kw = dict(tol=-1.0, maxit=40, check_every=8, return_X=True)
+    eager = spca.am_solve(A, fid, par, X0, flags=spca.FLAG_NO_UNION, kernel_times=True, **kw)
+    g = spca.am_solve(A, fid, par, X0, flags=spca.FLAG_NO_UNION | spca.FLAG_GRAPH, **kw)
+    _same(eager, g)
+    assert eager["kernel_times"]["iters_union"] == 0
+    full = spca.am_solve(A, fid, par, X0, kernel_times=True, **kw)
+    if full["kernel_times"]["iters_union"] == 0:
+        _same(eager, full)
