@@ -143,6 +143,25 @@ def test_x_update_T_s_ties_across_rows(spca):
     assert np.flatnonzero(X[1]).tolist() == list(range(1500))
 
 
+@pytest.mark.parametrize("p", [12287, 12288])
+def test_x_update_widest_register_rows(spca, p):
+    """The widest rows the one-workgroup kernel holds in registers (48 per
+    thread, twelve row groups, three packed scan words): ties spread over
+    every group, a ragged tail, and all four operators."""
+    rng = np.random.default_rng(p)
+    V_h = (rng.standard_normal((6, p)) * 2).astype(np.float32)
+    V_h[0] = 0.0
+    V_h[0, np.arange(7, p, 1000)] = 2.0          # 13 ties, one per 1000
+    V_h[0, [3, p - 1]] = 5.0
+    V_h[1] = rng.integers(-2, 3, size=p).astype(np.float32)
+    X, _, _ = _check_xupdate(spca, 1, V_h, 6)
+    assert np.flatnonzero(X[0]).tolist() == [3, 7, 1007, 2007, 3007, p - 1]
+    _check_xupdate(spca, 2, V_h, 300)
+    _check_xupdate(spca, 3, V_h, 40.0, exact_support=False)
+    _check_xupdate(spca, 5, V_h, 4.0)
+    _check_xupdate(spca, 7, V_h, 1.5)
+
+
 def test_x_update_gamma_boundaries(spca):
     rng = np.random.default_rng(5)
     V_h = (rng.standard_normal((4, 513)) * 2).astype(np.float32)
