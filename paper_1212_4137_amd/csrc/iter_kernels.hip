@@ -331,8 +331,9 @@ __global__ __launch_bounds__(1024) void plan_kernel(
             ? (double)v[1] * nd * 4.0 / (list_bw * (wg1 < 512.0 ? wg1 / 512.0 : 1.0)) + 3.0
             : 1e300;
     const double rows_us =
-        mx <= list_cap ? (double)v[1] * nd * 4.0 / (list_bw * (wgr < 512.0 ? wgr / 512.0 : 1.0)) + 8.0
-                       : 1e300;
+        mx <= list_cap && rows_product_possible(n, no_fused)
+            ? (double)v[1] * nd * 4.0 / (list_bw * (wgr < 512.0 ? wgr / 512.0 : 1.0)) + 8.0
+            : 1e300;
     int mode = kAxDense;
     double best = dense_us;
     if (!dense_only) {
@@ -619,6 +620,7 @@ void launch_sparse(hipStream_t st, const TA* A, int64_t lda, int64_t n,
 // of u_j = sum_t A[:, idx_t] val_t, each thread four consecutive rows with
 // 16-byte loads, in list order, in FP64.
 constexpr int kRowsBlock = 4 * kSpThreads;
+static_assert(kRowsBlock == kRowsBlockN, "row-block height");
 
 template <typename TA>
 __global__ __launch_bounds__(kSpThreads) void sparse_ax_rows_kernel(

@@ -192,6 +192,15 @@ void plan_next(hipStream_t st, StartState s, int64_t r, int64_t n, int64_t p,
 // Resets the plan (epoch 1, dense mode, zero statistics).
 void init_plan(hipStream_t st, Plan* plan, int dense_splits);
 
+// Rows of A that one workgroup of the row-block list product covers.  With
+// n at most this, that product has one workgroup per start, as the fused
+// list product does, but costs more, so the planner only considers it when
+// the fused product is not allowed; solves then leave its launch out.
+constexpr int64_t kRowsBlockN = 1024;
+__host__ __device__ inline bool rows_product_possible(int64_t n, int no_fused) {
+  return no_fused != 0 || n > kRowsBlockN;
+}
+
 // For kAxUnion: Xc[j][c] = X[j][ulist[c]] (r x u) and Qc[i][c] =
 // A[i, ulist[c]] (n x u, row-major), u = plan->union_size.
 void union_gather(hipStream_t st, const float* X, int64_t ldx, int64_t r,

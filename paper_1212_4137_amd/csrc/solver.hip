@@ -728,10 +728,13 @@ int spca_am_solve_ex(spca_ctx* ctx, void* stream, const spca_problem* prob,
       gemm_nt_f32(q, Xc, ldc_u, Qc, ldc_u, U, L.ldu, r, n, L.ucap, &plan->mode,
                   kAxUnion, L.plan_union, 0, &plan->union_size);
     }
-    if (bf16)
+    if (!rows_product_possible(n, dk > 0 ? 1 : 0)) {
+      // the planner never picks the row-block product here
+    } else if (bf16) {
       sparse_ax_rows_bf16(q, Ab, L.ldab, n, li, lv, L.ldx, U, L.ldu, r, s, plan);
-    else
+    } else {
       sparse_ax_rows(q, A, ldA, n, li, lv, L.ldx, U, L.ldu, r, s, plan);
+    }
     if (dk > 0) deflate_u(q, X, L.ldx, p, U, L.ldu, n, r, s, plan, defl);
     y_update(q, fid, U, r * L.ldu, Y, L.ldu, r, n, s, plan, bf16 ? Yb : nullptr,
              L.ldyb);
