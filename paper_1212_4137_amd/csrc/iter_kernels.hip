@@ -266,7 +266,7 @@ __global__ __launch_bounds__(1024) void plan_kernel(
     StartState s, int64_t r, int64_t n, int64_t p, int list_cap,
     int dense_only, int dense_splits, int64_t ucap,
     const int32_t* __restrict__ colmark, int32_t* __restrict__ ulist,
-    Plan* plan, int no_fused) {
+    Plan* plan, int no_fused, int allow_union) {
   __shared__ int64_t red[2 * 17];
   __shared__ int32_t mred[17];
   __shared__ int scan[20];
@@ -337,7 +337,11 @@ __global__ __launch_bounds__(1024) void plan_kernel(
     int mode = kAxDense;
     double best = dense_us;
     if (!dense_only) {
-      if (union_us < best) {
+      // the best product without the union one: dense, list or row-block
+      double other = dense_us;
+      other = list_us < other ? list_us : other;
+      other = rows_us < other ? rows_us : other;
+      if (allow_union && union_us < best) {
         best = union_us;
         mode = kAxUnion;
       }
@@ -349,6 +353,12 @@ __global__ __launch_bounds__(1024) void plan_kernel(
         best = rows_us;
         mode = kAxListRows;
       }
+      // evidence for the host's decision to keep launching the union
+      // product (it reads this at its polls)
+      if (mode == kAxUnion)
+        plan->union_close = 1;
+      else if (u >= 0)
+        plan->union_close = union_us < 2.0 * other ? 1 : 0;
     }
     plan->mode = mode;
     plan->ax_splits = mode == kAxDense ? dense_splits : 1;
@@ -364,6 +374,7 @@ __global__ __launch_bounds__(1024) void plan_kernel(
 __global__ void init_plan_kernel(Plan* plan, int dense_splits) {
   plan->mode = kAxDense;
   plan->active = 0;
+  plan->union_close = 0;
   plan->total_nnz = 0;
   plan->max_nnz = 0;
   plan->union_size = 0;
@@ -743,10 +754,11 @@ void init_state(hipStream_t st, StartState s, int64_t r) {
 
 void plan_next(hipStream_t st, StartState s, int64_t r, int64_t n, int64_t p,
                int list_cap, int dense_only, int dense_splits, int64_t ucap,
-               const int32_t* colmark, int32_t* ulist, Plan* plan, int no_fused) {
+               const int32_t* colmark, int32_t* ulist, Plan* plan, int no_fused,
+               int allow_union) {
   hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(1024), 0, st, s, r, n, p,
                      list_cap, dense_only, dense_splits, ucap, colmark, ulist,
-                     plan, no_fused);
+                     plan, no_fused, allow_union);
 }
 
 void init_plan(hipStream_t st, Plan* plan, int dense_splits) {

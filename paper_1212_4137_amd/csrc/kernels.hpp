@@ -40,6 +40,8 @@ enum AxMode { kAxDense = 0, kAxList = 1, kAxUnion = 2, kAxListRows = 3 };
 struct Plan {
   int32_t mode;         // AxMode of the next A x
   int32_t active;       // starts still running
+  int32_t union_close;  // the union product was picked, or came within 2x of
+                        // the best product at the latest probe
   int64_t total_nnz;    // sum of nnz over running starts
   int32_t max_nnz;      // largest nnz over running starts
   int32_t union_size;   // columns used by the running starts (kAxUnion's K)
@@ -187,7 +189,8 @@ void init_state(hipStream_t st, StartState s, int64_t r);
 // start to have at most list_cap nonzeros (only those keep lists).
 void plan_next(hipStream_t st, StartState s, int64_t r, int64_t n, int64_t p,
                int list_cap, int dense_only, int dense_splits, int64_t ucap,
-               const int32_t* colmark, int32_t* ulist, Plan* plan, int no_fused = 0);
+               const int32_t* colmark, int32_t* ulist, Plan* plan, int no_fused = 0,
+               int allow_union = 1);
 
 // Resets the plan (epoch 1, dense mode, zero statistics).
 void init_plan(hipStream_t st, Plan* plan, int dense_splits);

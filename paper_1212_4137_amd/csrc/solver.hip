@@ -13,6 +13,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cstddef>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -694,11 +695,16 @@ int spca_am_solve_ex(spca_ctx* ctx, void* stream, const spca_problem* prob,
   // fits its buffers (at most ucap columns)
   const int64_t ucap_eff = (opts->flags & SPCA_FLAG_NO_UNION) ? 0 : L.ucap;
   const int list_cap = list_cap_of(p);
-  // the union product is offered only while the union fits its buffers
-  // (at most ucap columns)
+  // union_on: the union gather and product are launched and the planner may
+  // pick them.  At each poll the host keeps them while the planner reports
+  // the union product picked or within 2x of the best product at its latest
+  // probe, and drops them otherwise (never while the plan of the next
+  // iteration is the union product); the probes go on, so a union that
+  // becomes cheap brings them back at the next poll.
+  bool union_on = ucap_eff > 0;
   auto plan_iter = [&]() {
     plan_next(st, s, r, n, p, list_cap, dense_only, L.plan_ax.splits, ucap_eff,
-              colmark, ulist, plan, dk > 0 ? 1 : 0);
+              colmark, ulist, plan, dk > 0 ? 1 : 0, union_on ? 1 : 0);
   };
   plan_iter();
   if (bf16) rows_to_bf16(st, X, L.ldx, r, p, Xb, L.ldxb, plan);
@@ -723,7 +729,7 @@ int spca_am_solve_ex(spca_ctx* ctx, void* stream, const spca_problem* prob,
       gemm_nt_f32(q, X, L.ldx, At, L.ldat, U, L.ldu, r, n, p, &plan->mode,
                   kAxDense, L.plan_ax, r * L.ldu);
     if (tm) SPCA_HIP_TRY(ctx->t_ax.mark(q));
-    if (!bf16 && ucap_eff > 0) {  // the planner can pick the union product
+    if (!bf16 && union_on) {  // the planner can pick the union product
       union_gather(q, X, L.ldx, r, A, ldA, n, ulist, plan, Xc, ldc_u, Qc, ldc_u);
       gemm_nt_f32(q, Xc, ldc_u, Qc, ldc_u, U, L.ldu, r, n, L.ucap, &plan->mode,
                   kAxUnion, L.plan_union, 0, &plan->union_size);
@@ -762,18 +768,27 @@ int spca_am_solve_ex(spca_ctx* ctx, void* stream, const spca_problem* prob,
       otf_step(q, fid, sg, A, ldA, n, p, X, L.ldx, opts->X0, li, lv, L.ldx, s, r,
                partial, fj, evj, xnorm, o, 0);
     plan_next(q, s, r, n, p, list_cap, dense_only, L.plan_ax.splits, ucap_eff,
-              colmark, ulist, plan, dk > 0 ? 1 : 0);
+              colmark, ulist, plan, dk > 0 ? 1 : 0, union_on ? 1 : 0);
     if (bf16) rows_to_bf16(q, X, L.ldx, r, p, Xb, L.ldxb, plan);
     SPCA_LAUNCH_CHECK("AM iteration");
     return SPCA_OK;
   };
   // the host reads the number of active starts after every check_every
   // iterations and stops once none is left
+  // (and updates union_on from the plan's mode and union evidence)
   auto none_active = [&](bool* done) -> int {
-    SPCA_HIP_TRY(hipMemcpyAsync(ctx->host_poll, &plan->active, sizeof(int32_t),
+    static_assert(offsetof(Plan, active) == 4 && offsetof(Plan, union_close) == 8,
+                  "mode, active and union_close lead the plan");
+    SPCA_HIP_TRY(hipMemcpyAsync(ctx->host_poll, plan, 3 * sizeof(int32_t),
                                 hipMemcpyDeviceToHost, st));
     SPCA_HIP_TRY(hipStreamSynchronize(st));
-    *done = ctx->host_poll[0] == 0;
+    *done = ctx->host_poll[1] == 0;
+    if (ucap_eff > 0) {
+      if (union_on && ctx->host_poll[2] == 0 && ctx->host_poll[0] != kAxUnion)
+        union_on = false;
+      else if (!union_on && ctx->host_poll[2] != 0)
+        union_on = true;
+    }
     return SPCA_OK;
   };
   const int32_t every = opts->check_every;
@@ -790,23 +805,32 @@ int spca_am_solve_ex(spca_ctx* ctx, void* stream, const spca_problem* prob,
     // launches only.
     rc = ensure_capture_stream(ctx);
     if (rc != SPCA_OK) return rc;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    SPCA_HIP_TRY(hipStreamBeginCapture(ctx->capture, hipStreamCaptureModeThreadLocal));
-    int body_rc = SPCA_OK;
-    for (int32_t k = 0; k < every && body_rc == SPCA_OK; ++k)
-      body_rc = iteration(ctx->capture, false);
-    hipError_t end_rc = hipStreamEndCapture(ctx->capture, &graph);
-    if (body_rc != SPCA_OK) {
-      if (graph) (void)hipGraphDestroy(graph);
-      return body_rc;
-    }
-    SPCA_HIP_TRY(end_rc);
-    hipError_t inst_rc = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(graph);
-    SPCA_HIP_TRY(inst_rc);
+    // one graph per union_on state, captured when first needed
+    hipGraphExec_t execs[2] = {nullptr, nullptr};
+    auto capture = [&](hipGraphExec_t* exec) -> int {
+      hipGraph_t graph = nullptr;
+      SPCA_HIP_TRY(hipStreamBeginCapture(ctx->capture, hipStreamCaptureModeThreadLocal));
+      int body_rc = SPCA_OK;
+      for (int32_t k = 0; k < every && body_rc == SPCA_OK; ++k)
+        body_rc = iteration(ctx->capture, false);
+      hipError_t end_rc = hipStreamEndCapture(ctx->capture, &graph);
+      if (body_rc != SPCA_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return body_rc;
+      }
+      SPCA_HIP_TRY(end_rc);
+      hipError_t inst_rc = hipGraphInstantiate(exec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      SPCA_HIP_TRY(inst_rc);
+      return SPCA_OK;
+    };
     int loop_rc = SPCA_OK;
     while (!done && it + every <= loop_max) {
+      hipGraphExec_t& exec = execs[union_on ? 1 : 0];
+      if (exec == nullptr) {
+        loop_rc = capture(&exec);
+        if (loop_rc != SPCA_OK) break;
+      }
       hipError_t e = hipGraphLaunch(exec, st);
       if (e != hipSuccess) {
         set_error(std::string("hipGraphLaunch: ") + hipGetErrorString(e));
@@ -819,7 +843,8 @@ int spca_am_solve_ex(spca_ctx* ctx, void* stream, const spca_problem* prob,
         if (loop_rc != SPCA_OK) break;
       }
     }
-    (void)hipGraphExecDestroy(exec);
+    for (hipGraphExec_t e : execs)
+      if (e != nullptr) (void)hipGraphExecDestroy(e);
     if (loop_rc != SPCA_OK) return loop_rc;
   }
   for (; !done && it < loop_max; ++it) {

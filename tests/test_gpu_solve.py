@@ -256,3 +256,23 @@ def test_k_split_aty_product(spca, fid):
     finally:
         spca.tune_table_clear()
     assert rel_err(got["objective"], one["objective"]) <= 1e-5
+
+
+def test_union_product_used_and_agrees(spca):
+    """512 starts made of four distinct ones, so that their supports
+    overlap almost entirely: the planner moves A x to the union-of-supports
+    product (which the host keeps launching while it is picked); per-start
+    results agree with the dense product, and the graph replays the same
+    adaptive launch sequence bit for bit."""
+    sp = workloads.spiked_matrix(75, 2000, 4000, thetas=(300.0,), spike_nnz=20)
+    X0n = np.ascontiguousarray(np.repeat(workloads.random_unit_starts(76, 4, 4000), 128, axis=0))
+    A, X0 = to_device_colmajor(sp.A), to_device_rows(X0n)
+    kw = dict(tol=-1.0, maxit=64, return_X=True)
+    got = spca.am_solve(A, 1, 20.0, X0, kernel_times=True, **kw)
+    assert got["kernel_times"]["iters_union"] > 0, got["kernel_times"]
+    dense = spca.am_solve(A, 1, 20.0, X0, flags=spca.FLAG_DENSE_ONLY, **kw)
+    ok = [rel_err(a, b) <= 1e-5 for a, b in zip(got["f_per_start"], dense["f_per_start"])]
+    assert np.mean(ok) >= 0.98
+    g = spca.am_solve(A, 1, 20.0, X0, flags=spca.FLAG_GRAPH, **kw)
+    assert np.array_equal(g["f_per_start"], got["f_per_start"])
+    assert torch.equal(g["X_final"], got["X_final"])
