@@ -189,7 +189,8 @@ typedef struct {
  * and product kernels are then not launched at all (each launch that a
  * solve's planner gates off still costs a few microseconds).  Without it a
  * solve launches them while its planner picks the union product or finds it
- * within 2x of the best product at its latest probe, checked at each poll. */
+ * within 1.25x of the best product at its latest probe, checked at each
+ * poll.                                                                    */
 #define SPCA_FLAG_NO_UNION 16
 /* Sparse solve only: A^T Y reads a copy of the columns split into row
  * panels (one panel's rows per XCD at a time, so that the gathered rows of

@@ -358,7 +358,7 @@ __global__ __launch_bounds__(1024) void plan_kernel(
       if (mode == kAxUnion)
         plan->union_close = 1;
       else if (u >= 0)
-        plan->union_close = union_us < 2.0 * other ? 1 : 0;
+        plan->union_close = union_us < 1.25 * other ? 1 : 0;
     }
     plan->mode = mode;
     plan->ax_splits = mode == kAxDense ? dense_splits : 1;

@@ -40,7 +40,7 @@ enum AxMode { kAxDense = 0, kAxList = 1, kAxUnion = 2, kAxListRows = 3 };
 struct Plan {
   int32_t mode;         // AxMode of the next A x
   int32_t active;       // starts still running
-  int32_t union_close;  // the union product was picked, or came within 2x of
+  int32_t union_close;  // the union product was picked, or came within 1.25x of
                         // the best product at the latest probe
   int64_t total_nnz;    // sum of nnz over running starts
   int32_t max_nnz;      // largest nnz over running starts

@@ -697,7 +697,7 @@ int spca_am_solve_ex(spca_ctx* ctx, void* stream, const spca_problem* prob,
   const int list_cap = list_cap_of(p);
   // union_on: the union gather and product are launched and the planner may
   // pick them.  At each poll the host keeps them while the planner reports
-  // the union product picked or within 2x of the best product at its latest
+  // the union product picked or within 1.25x of the best product at its latest
   // probe, and drops them otherwise (never while the plan of the next
   // iteration is the union product); the probes go on, so a union that
   // becomes cheap brings them back at the next poll.
