@@ -276,3 +276,24 @@ def test_union_product_used_and_agrees(spca):
     g = spca.am_solve(A, 1, 20.0, X0, flags=spca.FLAG_GRAPH, **kw)
     assert np.array_equal(g["f_per_start"], got["f_per_start"])
     assert torch.equal(g["X_final"], got["X_final"])
+
+
+def test_union_product_returns_when_supports_converge(spca):
+    """Random starts on a moderate spike: their supports differ at first
+    (the list product serves, and the host stops launching the union
+    product) and converge later, when the probes bring the union product
+    back.  Per-start results agree with the dense product, and the graph
+    replays the same launch decisions bit for bit."""
+    sp = workloads.spiked_matrix(75, 2000, 4000, thetas=(600.0,), spike_nnz=20)
+    X0n = workloads.random_unit_starts(77, 512, 4000)
+    A, X0 = to_device_colmajor(sp.A), to_device_rows(X0n)
+    kw = dict(tol=-1.0, maxit=96, return_X=True)
+    got = spca.am_solve(A, 1, 20.0, X0, kernel_times=True, **kw)
+    kt = got["kernel_times"]
+    assert kt["iters_list"] > 8 and kt["iters_union"] > 0, kt
+    dense = spca.am_solve(A, 1, 20.0, X0, flags=spca.FLAG_DENSE_ONLY, **kw)
+    ok = [rel_err(a, b) <= 1e-5 for a, b in zip(got["f_per_start"], dense["f_per_start"])]
+    assert np.mean(ok) >= 0.98
+    g = spca.am_solve(A, 1, 20.0, X0, flags=spca.FLAG_GRAPH, **kw)
+    assert np.array_equal(g["f_per_start"], got["f_per_start"])
+    assert torch.equal(g["X_final"], got["X_final"])
