@@ -145,7 +145,8 @@ typedef struct {
    * together.  A value l > r makes X0 hold l starts that flow through r
    * slots: whenever a start stops, it is evaluated and the next start takes
    * its slot, until all l have run (each for at most maxit iterations).
-   * Per-start outputs then have l entries; FP32 only; X_final must be NULL.
+   * Per-start outputs then have l entries, and X_final (when set) holds l
+   * rows: the final iterate of each start, filed as it finishes; FP32 only.
    * The workspace grows by about 40 bytes per start beyond
    * spca_workspace_bytes(n, p, r, ...) plus 4p bytes.                    */
   int32_t total_starts;
@@ -212,7 +213,8 @@ typedef struct {
   int32_t* iters_per_start;
   int32_t* status_per_start;
   int32_t* nnz_per_start;
-  float* X_final;      /* optional device r x p: final iterates (FP32)      */
+  float* X_final;      /* optional device r x p (l x p with total_starts > r):
+                          final iterates (FP32)                             */
   /* optional host array of 10 doubles: HIP-event times of the launches of
    * this solve, [0] total ms and [1] count of the V = A^T Y products,
    * [2] ms and [3] count of the x-updates, [4] ms and [5] count of the

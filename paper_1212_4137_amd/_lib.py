@@ -302,8 +302,6 @@ def am_solve(A, formulation, s_or_gamma, X0=None, tol=1e-8, maxit=200, *,
         r = 1
     total = r
     if slots is not None and slots < r:
-        if return_X:
-            raise ValueError("return_X is not available with slots")
         r = int(slots)
     ctx = ctx or default_context(A.device.index or 0)
     x = np.zeros(p, dtype=np.float64)
@@ -315,7 +313,7 @@ def am_solve(A, formulation, s_or_gamma, X0=None, tol=1e-8, maxit=200, *,
     iters = np.zeros(total, dtype=np.int32)
     status = np.zeros(total, dtype=np.int32)
     nnz = np.zeros(total, dtype=np.int32)
-    Xf = torch.empty((r, p), dtype=torch.float32, device=A.device) if return_X else None
+    Xf = torch.empty((total, p), dtype=torch.float32, device=A.device) if return_X else None
     kt = np.zeros(10) if kernel_times else None
     prob = Problem(A.data_ptr(), n, p, lda, int(formulation), float(s_or_gamma))
     opts = SolveOpts(X0.data_ptr() if X0 is not None else None, r, float(tol), int(maxit),

@@ -404,6 +404,7 @@ struct Otf {
   int32_t* iters;       // total: per start iterations, status, nnz
   int32_t* status;
   int32_t* nnz;
+  float* x_all;         // total x p or null: each start's final iterate
   int64_t total;
 };
 // per iteration, after the x-update: mark finished slots, evaluate them,

@@ -65,6 +65,7 @@ __global__ void otf_commit_kernel(Otf o, StartState s, int64_t r,
     o.iters[id] = s.iters[j];
     o.status[id] = stj;
     o.nnz[id] = live ? s.nnz[j] : 0;
+    o.retiring[j] = id + 1;  // the copy kernel files the iterate under id
     if (f[j] > *o.best_f || (f[j] == *o.best_f && id < o.ctl[1])) {
       *o.best_f = f[j];
       o.ctl[1] = id;
@@ -81,7 +82,8 @@ __global__ void otf_commit_kernel(Otf o, StartState s, int64_t r,
   }
 }
 
-// per slot: keep the best start's iterate, then load the slot's next start
+// per slot: keep the best start's iterate (and, when asked, every finished
+// start's), then load the slot's next start
 __global__ __launch_bounds__(256) void otf_copy_kernel(
     Otf o, StartState s, float* __restrict__ X, int64_t ldx,
     const float* __restrict__ X0, int64_t p) {
@@ -89,6 +91,11 @@ __global__ __launch_bounds__(256) void otf_copy_kernel(
   float* x = X + j * ldx;
   if (o.ctl[2] == j)
     for (int64_t i = threadIdx.x; i < p; i += 256) o.best_x[i] = x[i];
+  const int32_t done_id = o.retiring[j] - 1;
+  if (o.x_all != nullptr && done_id >= 0) {
+    float* dst = o.x_all + (int64_t)done_id * p;
+    for (int64_t i = threadIdx.x; i < p; i += 256) dst[i] = x[i];
+  }
   __syncthreads();
   const int32_t id = o.refill[j];
   if (id < 0) return;

@@ -170,6 +170,7 @@ Otf carve_otf(char* base, int64_t r, int64_t p, int64_t l) {
   o.iters = q;
   o.status = q + l;
   o.nnz = q + 2 * l;
+  o.x_all = nullptr;
   o.total = l;
   return o;
 }
@@ -555,7 +556,6 @@ int spca_am_solve_ex(spca_ctx* ctx, void* stream, const spca_problem* prob,
   if (otf) {
     SPCA_REQUIRE(!bf16, "on-the-fly replacement runs in FP32 only");
     SPCA_REQUIRE(opts->X0 != nullptr, "on-the-fly replacement needs X0 (total_starts rows)");
-    SPCA_REQUIRE(out->X_final == nullptr, "X_final is not available with total_starts > r");
   }
 
   std::lock_guard<std::mutex> lock(ctx->mu);
@@ -600,7 +600,10 @@ int spca_am_solve_ex(spca_ctx* ctx, void* stream, const spca_problem* prob,
   uint16_t* Xb = (uint16_t*)(base + L.off_Xb);
   void* wide = L.wide_bytes ? (void*)(base + L.off_wide) : nullptr;
   Otf o{};
-  if (otf) o = carve_otf(base + otf_off, r, p, l);
+  if (otf) {
+    o = carve_otf(base + otf_off, r, p, l);
+    o.x_all = out->X_final;  // l x p, filed as each start finishes
+  }
   Defl defl{};
   if (dk > 0) defl = carve_deflate(base + otf_off, n, p, r, dk);
   double* gam = (double*)(base + L.off_gam);
@@ -915,7 +918,7 @@ int spca_am_solve_ex(spca_ctx* ctx, void* stream, const spca_problem* prob,
   if (out->param_per_start && warm)
     SPCA_HIP_TRY(hipMemcpyAsync(out->param_per_start, gam, sizeof(double) * r,
                                 hipMemcpyDeviceToHost, st));
-  if (out->X_final)
+  if (out->X_final && !otf)
     SPCA_HIP_TRY(hipMemcpy2DAsync(out->X_final, sizeof(float) * p, X,
                                   sizeof(float) * L.ldx, sizeof(float) * p, r,
                                   hipMemcpyDeviceToDevice, st));

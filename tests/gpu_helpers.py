@@ -1,8 +1,26 @@
 """Helpers shared by the GPU tests: device upload in the library's layout and
-the parity protocol used to compare a batched solve with the FP64 oracle."""
+the parity protocol used to compare a batched solve with the FP64 oracle.
+
+The protocol (several correct results, Section 4: trajectories from
+different starts, or from one start under different rounding, may split at
+a near-tie and end at different stationary points of Algorithm 2):
+
+1. the best-of-r objective agrees with the oracle's best-of-r on the same
+   starts within the tolerance;
+2. every start agrees with the oracle's run from the same start (objective
+   within the tolerance and the same status), or else its final iterate
+   passes the FP64 fixed-point certificate: one more FP64 step of
+   Algorithm 2 from it keeps its support (up to a near-tie, whose margin is
+   printed) and raises the objective by no more than the tolerance.  No
+   start is let through without one or the other;
+3. no start exceeds the oracle's best by more than the tolerance.
+"""
 import numpy as np
 
+import oracle
+
 REL_TOL_FP32 = 1e-5  # relative objective error allowed for the FP32 path
+NEAR_TIE = 1e-5      # relative margin below which a support decision is a tie
 
 
 def to_device_colmajor(A_np, device="cuda:0", lda=None):
@@ -27,52 +45,134 @@ def rel_err(a, b):
     return abs(a - b) / max(abs(b), 1e-300)
 
 
-def compare_solve(got, ref, label, rel_tol=REL_TOL_FP32, min_start_match=0.9):
-    """Parity of a batched GPU solve against the oracle on the same starts.
-
-    * the best objective agrees within rel_tol;
-    * per start, the objective agrees within rel_tol for at least
-      ``min_start_match`` of the starts (trajectories may split at near-ties
-      and end at different stationary points; no GPU start may exceed the
-      oracle's best by more than the tolerance);
-    * per-start status agrees for the matching starts.
-    Returns a dict of diagnostics.
-    """
-    f_ref = ref["f"]
-    f_got = got["f_per_start"]
-    best_ref = f_ref[ref["best"]]
-    err_best = rel_err(got["objective"], best_ref)
-    match = np.array([rel_err(a, b) <= rel_tol or abs(a - b) <= rel_tol * abs(best_ref)
-                      for a, b in zip(f_got, f_ref)])
-    info = {"label": label, "best_rel_err": err_best, "start_match": float(match.mean()),
-            "gpu_best": got["objective"], "oracle_best": best_ref}
-    print("parity", info, flush=True)
-    assert err_best <= rel_tol, info
-    assert match.mean() >= min_start_match, info
-    assert np.all(f_got <= best_ref + rel_tol * max(abs(best_ref), 1e-300)), info
-    st_ok = got["status_per_start"][match] == ref["status"][match]
-    assert st_ok.mean() >= 0.9, (info, got["status_per_start"], ref["status"])
-    return info
-
-
-def support_near_tie_margin(A, x_best, fid, s_or_gamma):
-    """Relative margin of the decision that fixed the oracle's best support:
-    for T_s the gap between the s-th and (s+1)-th |v_i|, for the thresholds
-    the smallest | |v_i| - lambda | relative to lambda (FP64)."""
-    A = np.asarray(A, np.float64)
-    u = A @ x_best
+def _image(A, fid, x):
+    """v = A^T y(x) in FP64 (the argument of the x-operator one step on)."""
+    u = A @ x
     if not np.any(u):
-        return np.inf
+        return None
     y = np.sign(u) if fid % 2 == 0 else u / np.linalg.norm(u)
-    v = np.abs(A.T @ y)
+    return A.T @ y
+
+
+def support_near_tie_margin(A, x, fid, s_or_gamma):
+    """Relative margin of the decision that fixes the support of the image of
+    x: for T_s the gap between the s-th and (s+1)-th |v_i| (relative to the
+    s-th), for U_gamma / V_gamma / V_lambda the smallest distance of v_i^2 or
+    |v_i| to the threshold, relative to the threshold (FP64)."""
+    A = np.asarray(A, np.float64)
+    v = _image(A, fid, np.asarray(x, np.float64))
+    if v is None:
+        return np.inf
+    v = np.abs(v)
     if fid <= 2:
         srt = np.sort(v)[::-1]
         s = int(s_or_gamma)
         if s >= v.size:
             return np.inf
         return (srt[s - 1] - srt[s]) / max(srt[s - 1], 1e-300)
+    if fid <= 4:
+        lam = oracle.lambda_s(v, s_or_gamma)
+        if lam <= 0:
+            return np.inf
+        return np.min(np.abs(v - lam)) / lam
+    if s_or_gamma <= 0:
+        return np.inf
     if fid in (5, 6):
-        return np.min(np.abs(v * v - s_or_gamma)) / max(s_or_gamma, 1e-300)
-    if fid in (7, 8):
-        return np.min(np.abs(v - s_or_gamma)) / max(s_or_gamma, 1e-300)
-    return np.inf
+        return np.min(np.abs(v * v - s_or_gamma)) / s_or_gamma
+    return np.min(np.abs(v - s_or_gamma)) / s_or_gamma
+
+
+def fixed_point_certificate(A, fid, s_or_gamma, x, f_reported, rel_tol=REL_TOL_FP32):
+    """FP64 certificate that x (a final iterate of the GPU path) is a
+    stationary point of Algorithm 2: one more FP64 step from x keeps its
+    support (or the decision is a near-tie) and raises f by at most rel_tol
+    relative; also f(x) in FP64 agrees with the reported objective.
+    Returns a dict with 'ok' and the figures."""
+    A = np.asarray(A, np.float64)
+    x = np.asarray(x, np.float64)
+    nx = np.linalg.norm(x)
+    if nx == 0:
+        return {"ok": False, "why": "zero iterate"}
+    x = x / nx
+    f0, _ = oracle.objective(fid, A, x, s_or_gamma)
+    step = oracle.am_single(A, fid, s_or_gamma, x, -1.0, 1)
+    f1 = step["f"]
+    scale = max(abs(f0), 1e-300)
+    gain = (f1 - f0) / scale
+    same = np.array_equal(np.flatnonzero(step["x"]), np.flatnonzero(x))
+    margin = support_near_tie_margin(A, x, fid, s_or_gamma)
+    consistent = abs(f0 - f_reported) <= 1e-6 * scale
+    ok = bool(gain <= rel_tol and (same or margin < NEAR_TIE) and consistent)
+    return {"ok": ok, "gain": gain, "same_support": bool(same), "margin": margin,
+            "f_x": f0, "f_reported": f_reported}
+
+
+def per_start_parity(got, ref, label, A=None, fid=None, s_or_gamma=None,
+                     rel_tol=REL_TOL_FP32, params=None, cert_fid=None):
+    """Step 2 of the protocol: every start agrees with the oracle's run from
+    the same start (objective within rel_tol, same status) or its final
+    iterate ``got['X_final'][j]`` passes the FP64 fixed-point certificate on
+    (A, fid, s_or_gamma).  Under the warm-up the map after the freeze is the
+    one to certify: ``params`` gives each start's frozen parameter and
+    ``cert_fid`` the formulation whose x-operator it parameterises (the
+    objective is then not compared, as the two formulations' f differ).
+    Returns (fraction of agreeing starts, number certified)."""
+    f_ref = np.asarray(ref["f"])
+    f_got = np.asarray(got["f_per_start"])
+    scale_best = max(abs(f_ref[ref["best"]]), 1e-300)
+    f_ok = np.array([abs(a - b) <= rel_tol * max(abs(b), 1e-300)
+                     or abs(a - b) <= rel_tol * scale_best for a, b in zip(f_got, f_ref)])
+    st_ok = np.asarray(got["status_per_start"]) == np.asarray(ref["status"])
+    both_zero = (f_got == 0) & (f_ref == 0)
+    agree = (f_ok & st_ok) | both_zero
+    X = got.get("X_final")
+    n_cert = 0
+    for j in np.flatnonzero(~agree):
+        assert X is not None and A is not None, (
+            f"{label}: start {j} differs from the oracle (gpu f {f_got[j]!r} status "
+            f"{got['status_per_start'][j]}, oracle f {f_ref[j]!r} status "
+            f"{ref['status'][j]}) and no final iterate was given to certify it")
+        xj = X[j].detach().cpu().numpy() if hasattr(X, "detach") else np.asarray(X[j])
+        par = s_or_gamma if params is None else float(params[j])
+        cf = cert_fid or fid
+        c = fixed_point_certificate(A, cf, par, xj, f_got[j], rel_tol)
+        if cf != fid:
+            c["ok"] = c["ok"] or (c.get("gain", np.inf) <= rel_tol and
+                                  (c["same_support"] or c["margin"] < NEAR_TIE))
+        n_cert += 1
+        print(f"{label}: start {j} gpu f {f_got[j]:.10g} oracle f {f_ref[j]:.10g} "
+              f"-> certificate {c}", flush=True)
+        assert c["ok"], (label, j, c)
+    return float(agree.mean()), n_cert
+
+
+def compare_solve(got, ref, label, A=None, fid=None, s_or_gamma=None,
+                  rel_tol=REL_TOL_FP32):
+    """Parity of a batched GPU solve against the oracle on the same starts
+    (the protocol in the module docstring).  ``A``, ``fid`` and
+    ``s_or_gamma`` (the problem, FP64 or FP32 host array) and
+    ``got['X_final']`` (the GPU's final iterates) are needed to certify a
+    start that differs.  Returns a dict of diagnostics."""
+    f_ref = np.asarray(ref["f"])
+    f_got = np.asarray(got["f_per_start"])
+    best_ref = f_ref[ref["best"]]
+    scale_best = max(abs(best_ref), 1e-300)
+    err_best = rel_err(got["objective"], best_ref)
+    match, n_cert = per_start_parity(got, ref, label, A, fid, s_or_gamma, rel_tol)
+    info = {"label": label, "best_rel_err": err_best, "start_match": match,
+            "certified": n_cert, "gpu_best": got["objective"], "oracle_best": best_ref}
+    print("parity", info, flush=True)
+    assert err_best <= rel_tol, info
+    assert np.all(f_got <= best_ref + rel_tol * scale_best), info
+    return info
+
+
+def subset(got, idx):
+    """The per-start outputs of a GPU solve restricted to the starts idx
+    (to compare a sample of starts with the oracle run on those starts)."""
+    idx = np.asarray(idx)
+    out = {k: np.asarray(got[k])[idx] for k in ("f_per_start", "status_per_start",
+                                                 "iters_per_start", "ev_per_start")}
+    out["X_final"] = got["X_final"][idx] if got.get("X_final") is not None else None
+    out["objective"] = float(np.max(out["f_per_start"]))
+    return out

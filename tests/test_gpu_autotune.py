@@ -47,7 +47,7 @@ def test_autotune_fills_table_and_is_reproducible(spca, prec):
             par = workloads.s_or_gamma_for(fid, sp.A, 20)
             ref = oracle.am_multi(sp.A.astype(np.float64), fid, par, X0n.astype(np.float64),
                                   1e-8, 200, nthreads=8)
-            compare_solve(res[fid], ref, f"autotuned F{fid}")
+            compare_solve(res[fid], ref, f"autotuned F{fid}", sp.A, fid, par)
     text = spca.tune_table_export()
     spca.tune_table_clear()
     spca.tune_table_import(text)

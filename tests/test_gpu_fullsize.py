@@ -1,5 +1,11 @@
 """Parity at the full sizes of the large workloads, on outputs the host can
-check one by one (the FP64 fixed-point certificate of the returned x):
+check one by one (the oracle from sampled starts, or the FP64 fixed-point
+certificate of the returned x):
+
+* 1000 x 10000 spiked model, all 8 formulations, 1024 starts in one solve,
+  literal gamma, maxit 200 and the stop test off: exactly the solve the
+  throughput benchmark times.  The oracle replays a sample of the starts
+  (and the GPU's best one) and each must agree or be certified;
 
 * 20000 x 200000 FP32 (16 GB, counter-generated in HBM), F1, s = 200, 64
   starts: f and the explained variance recomputed in FP64 from the support
@@ -10,11 +16,14 @@ check one by one (the FP64 fixed-point certificate of the returned x):
   full FP64 AM map applied to the returned x keeps its support and gains no
   more than the stop tolerance, f matches FP64, and the BF16-phase
   objective is within 1e-3 of the polished one."""
+import os
+
 import numpy as np
 import pytest
 
+import oracle
 import workloads
-from gpu_helpers import to_device_colmajor, to_device_rows
+from gpu_helpers import per_start_parity, rel_err, subset, to_device_colmajor, to_device_rows
 from workloads import counter
 
 pytestmark = pytest.mark.gpu
@@ -30,6 +39,44 @@ def spca():
 
     m.load()
     return m
+
+
+@pytest.fixture(scope="module")
+def headline():
+    cfg = workloads.SPIKED_ALL8
+    sp = workloads.spiked_matrix(cfg["seed"], cfg["n"], cfg["p"], cfg["thetas"],
+                                 cfg["spike_nnz"])
+    X0 = workloads.random_unit_starts(cfg["seed"] + 1000, cfg["r"], cfg["p"])
+    return cfg, sp.A, X0, to_device_colmajor(sp.A), to_device_rows(X0)
+
+
+@pytest.mark.parametrize("fid", range(1, 9))
+def test_headline_workload_sampled_starts(spca, headline, fid):
+    cfg, A_np, X0_np, A, X0 = headline
+    par = workloads.s_or_gamma_for(fid, A_np, cfg["s"])  # literal gamma
+    print(f"headline case fid={fid} par={par}", flush=True)
+    got = spca.am_solve(A, fid, par, X0, tol=-1.0, maxit=cfg["maxit"], return_X=True)
+    jb = got["best_start"]
+    idx = np.unique(np.r_[0:16, 100:1024:128, jb])
+    threads = max(1, min(len(os.sched_getaffinity(0)), 16))
+    ref = oracle.am_multi(A_np, fid, par, X0_np[idx], -1.0, cfg["maxit"],
+                          nthreads=threads)
+    assert np.all(ref["iters"][ref["status"] == 1] == cfg["maxit"])
+    sub = subset(got, idx)
+    match, n_cert = per_start_parity(sub, ref, f"headline F{fid}", A_np, fid, par)
+    print(f"headline F{fid}: {match:.3f} of {len(idx)} sampled starts agree, "
+          f"{n_cert} certified; best start {jb} f {got['objective']:.10g}", flush=True)
+    # the best of all 1024 starts is no worse than any sampled oracle start
+    assert got["objective"] >= np.max(ref["f"]) * (1 - 1e-5) - 1e-12
+    assert got["objective"] == np.max(got["f_per_start"])
+    # the returned vector: unit norm, its support, f and explained variance
+    # in FP64 (oracle evaluation of the same x)
+    x = got["x"]
+    assert abs(np.linalg.norm(x) - 1.0) < 1e-12
+    assert np.array_equal(got["support"], np.flatnonzero(x)) and got["nnz"] == len(got["support"])
+    f_chk, ev_chk = oracle.objective(fid, A_np, x, par)
+    assert rel_err(got["objective"], f_chk) <= 1e-9
+    assert rel_err(got["explained_variance"], ev_chk) <= 1e-9
 
 
 def test_large_instance_certificate(spca):

@@ -93,7 +93,9 @@ def _check_xupdate(spca, fid, V_h, par, exact_support=True):
     return X, phi, nnz
 
 
-@pytest.mark.parametrize("p", [37, 1500, 20000, 60001, 200000])
+# p = 10000 is the row length of the 1000 x 10000 throughput workload (rows
+# of 40 floats per thread in the one-workgroup kernel)
+@pytest.mark.parametrize("p", [37, 1500, 10000, 20000, 60001, 200000])
 @pytest.mark.parametrize("fid", [1, 3, 5, 7])
 def test_x_update_random(spca, fid, p):
     print(f"x_update case fid={fid} p={p}", flush=True)
@@ -125,11 +127,12 @@ def test_x_update_T_s_ties_and_edges(spca):
     _check_xupdate(spca, 2, V_h, p)
 
 
-def test_x_update_T_s_ties_across_rows(spca):
-    """p = 5000: the one-workgroup kernel holds elements 1024 apart in one
-    thread, so ties at the s-th key that span several such groups, and a
-    cut through an all-equal row, must still keep the lowest indices."""
-    p = 5000
+@pytest.mark.parametrize("p", [5000, 10000])
+def test_x_update_T_s_ties_across_rows(spca, p):
+    """p = 5000 and 10000: the one-workgroup kernel holds elements 1024
+    apart in one thread, so ties at the s-th key that span several such
+    groups, and a cut through an all-equal row, must still keep the lowest
+    indices."""
     V_h = np.zeros((4, p), np.float32)
     V_h[0, [4999, 7, 1027, 2100, 1030, 3071, 4096]] = [2.0, -2.0, 2.0, -2.0, 2.0, 2.0, -2.0]
     V_h[0, 500] = 3.0
@@ -141,6 +144,15 @@ def test_x_update_T_s_ties_across_rows(spca):
     assert np.flatnonzero(X[0]).tolist() == [7, 500, 1027, 1030]
     X, _, _ = _check_xupdate(spca, 2, V_h, 1500)
     assert np.flatnonzero(X[1]).tolist() == list(range(1500))
+    if p == 10000:
+        # ties in the last row groups and the ragged tail of the row
+        V_h[2] = 0.0
+        V_h[2, [9999, 8191, 8192, 9216, 10, 9500]] = [3.0, -3.0, 3.0, 3.0, -3.0, 3.0]
+        V_h[2, 9001] = 4.0
+        X, _, _ = _check_xupdate(spca, 1, V_h, 5)
+        assert np.flatnonzero(X[2]).tolist() == [10, 8191, 8192, 9001, 9216]
+        for fid, par in ((3, 30.0), (5, 4.0), (7, 1.5), (6, 9.0), (8, 2.0)):
+            _check_xupdate(spca, fid, V_h, par, exact_support=fid != 3)
 
 
 @pytest.mark.parametrize("p", [12287, 12288])
@@ -233,7 +245,7 @@ def test_solve_long_rows_match_oracle(spca, fid):
     X0 = workloads.random_unit_starts(42, 6, 20000)
     par = workloads.s_or_gamma_for(fid, sp.A, 30, "scaled" if fid in (6, 8) else "literal")
     got = spca.am_solve(to_device_colmajor(sp.A), fid, par, to_device_rows(X0),
-                        tol=1e-8, maxit=300)
+                        tol=1e-8, maxit=300, return_X=True)
     ref = oracle.am_multi(sp.A.astype(np.float64), fid, par, X0.astype(np.float64),
                           1e-8, 300, nthreads=6)
-    compare_solve(got, ref, f"long rows F{fid}")
+    compare_solve(got, ref, f"long rows F{fid}", sp.A, fid, par)

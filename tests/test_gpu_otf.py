@@ -36,11 +36,20 @@ def test_replacement_matches_oracle(spca, problem, fid):
     print(f"otf case fid={fid}", flush=True)
     A_np, X0_np, A, X0 = problem
     par = workloads.s_or_gamma_for(fid, A_np, 20, "scaled" if fid in (6, 8) else "literal")
-    got = spca.am_solve(A, fid, par, X0, tol=1e-8, maxit=300, slots=16)
-    assert len(got["f_per_start"]) == 96
+    got = spca.am_solve(A, fid, par, X0, tol=1e-8, maxit=300, slots=16, return_X=True)
+    assert len(got["f_per_start"]) == 96 and got["X_final"].shape[0] == 96
     ref = oracle.am_multi(A_np.astype(np.float64), fid, par, X0_np.astype(np.float64),
                           1e-8, 300, nthreads=8)
-    compare_solve(got, ref, f"otf F{fid}")
+    compare_solve(got, ref, f"otf F{fid}", A_np, fid, par)
+    # every start's filed iterate is the one its objective was taken on
+    Xf = got["X_final"].cpu().numpy().astype(np.float64)
+    for j in range(0, 96, 7):
+        xj = Xf[j]
+        if not xj.any():
+            assert got["f_per_start"][j] == 0.0
+            continue
+        fj, _ = oracle.objective(fid, A_np, xj / np.linalg.norm(xj), par)
+        assert abs(fj - got["f_per_start"][j]) <= 1e-9 * max(abs(fj), 1.0), j
     # the reported vector is the best start's, evaluated in FP64
     x = got["x"]
     j = got["best_start"]

@@ -9,8 +9,8 @@ import pytest
 
 import oracle
 import workloads
-from gpu_helpers import (compare_solve, rel_err, support_near_tie_margin,
-                         to_device_colmajor, to_device_rows)
+from gpu_helpers import (compare_solve, per_start_parity, rel_err, subset,
+                         support_near_tie_margin, to_device_colmajor, to_device_rows)
 
 pytestmark = pytest.mark.gpu
 
@@ -29,26 +29,32 @@ def spca():
     return m
 
 
-def _param(fid, A, s):
-    return workloads.s_or_gamma_for(fid, A, s, "scaled" if fid in (6, 8) else "literal")
+def _param(fid, A, s, gamma_mode=None):
+    mode = gamma_mode or ("scaled" if fid in (6, 8) else "literal")
+    return workloads.s_or_gamma_for(fid, A, s, mode)
 
 
 # n = 300 (2 tiles + 44), p = 1500 (11 tiles + 92): several tiles and ragged
 # tails in both products; r = 40 and 130 exercise the small-M and multi-M
-# GEMM paths.
-@pytest.mark.parametrize("fid", range(1, 9))
-@pytest.mark.parametrize("r", [40, 130])
-def test_all_formulations_match_oracle(spca, fid, r):
-    print(f"solve case fid={fid} r={r}", flush=True)
+# GEMM paths.  F6 / F8 run with both readings of gamma: the literal
+# 0.1 max ||a_i||_2 of the graded workloads (iterates mostly dense: the dense
+# A x and the FP64 MFMA evaluation) and the scale-consistent one (sparse).
+CASES = [(fid, r, None) for fid in range(1, 9) for r in (40, 130)]
+CASES += [(fid, r, "literal") for fid in (6, 8) for r in (40, 130)]
+
+
+@pytest.mark.parametrize("fid,r,gamma_mode", CASES)
+def test_all_formulations_match_oracle(spca, fid, r, gamma_mode):
+    print(f"solve case fid={fid} r={r} gamma={gamma_mode}", flush=True)
     sp = workloads.spiked_matrix(workloads.SEED_BASE + 100 + fid, 300, 1500,
                                  thetas=(45.0, 30.0, 20.0), spike_nnz=25)
     A_np = sp.A
-    par = _param(fid, A_np, 25)
+    par = _param(fid, A_np, 25, gamma_mode)
     X0 = workloads.random_unit_starts(workloads.SEED_BASE + 200 + fid, r, 1500)
     got = spca.am_solve(to_device_colmajor(A_np), fid, par, to_device_rows(X0),
-                        tol=1e-8, maxit=300)
+                        tol=1e-8, maxit=300, return_X=True)
     ref = oracle.am_multi(A_np, fid, par, X0, 1e-8, 300, nthreads=8)
-    compare_solve(got, ref, f"F{fid} r={r}")
+    compare_solve(got, ref, f"F{fid} r={r}", A_np, fid, par)
     xb = ref["X"][ref["best"]]
     sup_ref = np.flatnonzero(xb)
     margin = support_near_tie_margin(A_np, xb, fid, par)
@@ -146,9 +152,10 @@ def test_unaligned_leading_dimension_and_odd_sizes(spca):
         A = to_device_colmajor(A_np, lda=lda)
         for fid in (1, 4, 5, 8):
             par = {1: 5, 4: 5.0, 5: 2.0, 8: 3.0}[fid]
-            got = spca.am_solve(A, fid, par, to_device_rows(X0), tol=1e-10, maxit=500)
+            got = spca.am_solve(A, fid, par, to_device_rows(X0), tol=1e-10, maxit=500,
+                                return_X=True)
             ref = oracle.am_multi(A_np, fid, par, X0, 1e-10, 500)
-            compare_solve(got, ref, f"odd lda={lda} F{fid}", min_start_match=0.6)
+            compare_solve(got, ref, f"odd lda={lda} F{fid}", A_np, fid, par)
 
 
 def test_degenerate_and_zero_starts(spca):
@@ -203,12 +210,12 @@ def test_row_block_list_product(spca, fid):
     A, X0 = to_device_colmajor(sp.A), to_device_rows(X0n)
     par = _param(fid, sp.A, 20)
     got = spca.am_solve(A, fid, par, X0, tol=1e-8, maxit=200, kernel_times=True,
-                        flags=spca.FLAG_NO_UNION)
+                        flags=spca.FLAG_NO_UNION, return_X=True)
     assert got["kernel_times"]["iters_list_rows"] > 0, got["kernel_times"]
     assert got["kernel_times"]["iters_union"] == 0
     ref = oracle.am_multi(sp.A.astype(np.float64), fid, par, X0n.astype(np.float64),
                           1e-8, 200, nthreads=6)
-    compare_solve(got, ref, f"row-block list F{fid}")
+    compare_solve(got, ref, f"row-block list F{fid}", sp.A, fid, par)
     dense = spca.am_solve(A, fid, par, X0, tol=1e-8, maxit=200, flags=spca.FLAG_DENSE_ONLY)
     assert rel_err(got["objective"], dense["objective"]) <= 1e-5
 
@@ -244,9 +251,10 @@ def test_k_split_aty_product(spca, fid):
     par = _param(fid, A_np, 40)
     X0 = workloads.random_unit_starts(workloads.SEED_BASE + 220 + fid, r, p)
     A = to_device_colmajor(A_np)
-    got = spca.am_solve(A, fid, par, to_device_rows(X0), tol=1e-8, maxit=120)
+    got = spca.am_solve(A, fid, par, to_device_rows(X0), tol=1e-8, maxit=120,
+                        return_X=True)
     ref = oracle.am_multi(A_np, fid, par, X0, 1e-8, 120, nthreads=8)
-    compare_solve(got, ref, f"k-split F{fid}")
+    compare_solve(got, ref, f"k-split F{fid}", A_np, fid, par)
     shape = spca.gemm_plan(r, p, n, 16)[0]
     # bucket(x) = round(2 log2 x): 16 -> 8, 8000 -> 26, 2000 -> 22
     spca.tune_table_import(f"4 16 8 26 22 {shape} 1\n")
@@ -270,6 +278,11 @@ def test_union_product_used_and_agrees(spca):
     kw = dict(tol=-1.0, maxit=64, return_X=True)
     got = spca.am_solve(A, 1, 20.0, X0, kernel_times=True, **kw)
     assert got["kernel_times"]["iters_union"] > 0, got["kernel_times"]
+    # the oracle from the four distinct starts, per start and best of all
+    ref4 = oracle.am_multi(sp.A, 1, 20.0, X0n[::128], -1.0, 64, nthreads=4)
+    ref = {k: np.repeat(ref4[k], 128, axis=0) for k in ("f", "status", "iters")}
+    ref["best"] = ref4["best"] * 128
+    compare_solve(got, ref, "union product", sp.A, 1, 20.0)
     dense = spca.am_solve(A, 1, 20.0, X0, flags=spca.FLAG_DENSE_ONLY, **kw)
     ok = [rel_err(a, b) <= 1e-5 for a, b in zip(got["f_per_start"], dense["f_per_start"])]
     assert np.mean(ok) >= 0.98
@@ -291,6 +304,10 @@ def test_union_product_returns_when_supports_converge(spca):
     got = spca.am_solve(A, 1, 20.0, X0, kernel_times=True, **kw)
     kt = got["kernel_times"]
     assert kt["iters_list"] > 8 and kt["iters_union"] > 0, kt
+    # a sample of the starts against the oracle from the same starts
+    idx = np.r_[0:24, 100:512:64]
+    ref = oracle.am_multi(sp.A, 1, 20.0, X0n[idx], -1.0, 96, nthreads=8)
+    per_start_parity(subset(got, idx), ref, "union product (sample)", sp.A, 1, 20.0)
     dense = spca.am_solve(A, 1, 20.0, X0, flags=spca.FLAG_DENSE_ONLY, **kw)
     ok = [rel_err(a, b) <= 1e-5 for a, b in zip(got["f_per_start"], dense["f_per_start"])]
     assert np.mean(ok) >= 0.98

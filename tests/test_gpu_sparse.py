@@ -40,10 +40,11 @@ def test_sparse_matches_oracle(spca, fid):
     X0n = workloads.random_unit_starts(42, 32, mat.p)
     par = _param(fid, mat)
     D = spca.sparse_to_device(mat)
-    got = spca.am_solve_sparse(D, fid, par, to_device_rows(X0n), tol=1e-8, maxit=300)
+    got = spca.am_solve_sparse(D, fid, par, to_device_rows(X0n), tol=1e-8, maxit=300,
+                               return_X=True)
     ref = oracle.am_multi_csc(mat.col_ptr, mat.row_idx, mat.col_val.astype(np.float64), mat.n,
                               mat.p, fid, par, X0n.astype(np.float64), 1e-8, 300, nthreads=8)
-    compare_solve(got, ref, f"sparse F{fid}")
+    compare_solve(got, ref, f"sparse F{fid}", mat.dense(), fid, par)
     dense = spca.am_solve(to_device_colmajor(mat.dense().astype(np.float32)), fid, par,
                           to_device_rows(X0n), tol=1e-8, maxit=300)
     assert rel_err(got["objective"], dense["objective"]) <= 1e-5
@@ -59,7 +60,7 @@ def test_sparse_long_rows_and_graph(spca, fid):
     got = spca.am_solve_sparse(D, fid, par, X0, tol=1e-8, maxit=300, return_X=True)
     ref = oracle.am_multi_csc(mat.col_ptr, mat.row_idx, mat.col_val.astype(np.float64), mat.n,
                               mat.p, fid, par, X0n.astype(np.float64), 1e-8, 300, nthreads=6)
-    compare_solve(got, ref, f"sparse long rows F{fid}")
+    compare_solve(got, ref, f"sparse long rows F{fid}", mat.dense(), fid, par)
     g = spca.am_solve_sparse(D, fid, par, X0, tol=1e-8, maxit=300, return_X=True,
                              flags=spca.FLAG_GRAPH)
     assert g["objective"] == got["objective"] and torch.equal(g["X_final"], got["X_final"])
@@ -126,13 +127,15 @@ def test_sparse_chunk_boundaries(spca, r, panels):
     X0n = workloads.random_unit_starts(48 + r, r, mat.p)
     D = spca.sparse_to_device(mat)
     flags = spca.FLAG_SPARSE_PANELS if panels else spca.FLAG_SPARSE_NO_PANELS
-    for fid, par in ((1, 10.0), (6, workloads.s_or_gamma_for(6, mat.dense(), 10, "scaled"))):
+    dense = mat.dense()
+    for fid, par in ((1, 10.0), (6, workloads.s_or_gamma_for(6, dense, 10, "scaled"))):
         got = spca.am_solve_sparse(D, fid, par, to_device_rows(X0n), tol=1e-8, maxit=200,
-                                   flags=flags)
+                                   flags=flags, return_X=True)
         ref = oracle.am_multi_csc(mat.col_ptr, mat.row_idx, mat.col_val.astype(np.float64),
                                   mat.n, mat.p, fid, par, X0n.astype(np.float64), 1e-8, 200,
                                   nthreads=8)
-        compare_solve(got, ref, f"sparse boundaries F{fid} r={r} panels={panels}")
+        compare_solve(got, ref, f"sparse boundaries F{fid} r={r} panels={panels}", dense,
+                      fid, par)
 
 
 def test_sparse_heavy_column(spca):
@@ -143,15 +146,16 @@ def test_sparse_heavy_column(spca):
     assert np.diff(mat.col_ptr).max() > 8 * 2048
     X0n = workloads.random_unit_starts(49, 20, mat.p)
     D = spca.sparse_to_device(mat)
+    dense_np = mat.dense()
     ref = oracle.am_multi_csc(mat.col_ptr, mat.row_idx, mat.col_val.astype(np.float64), mat.n,
                               mat.p, 1, 5.0, X0n.astype(np.float64), 1e-8, 300, nthreads=8)
-    dense = spca.am_solve(to_device_colmajor(mat.dense().astype(np.float32)), 1, 5.0,
+    dense = spca.am_solve(to_device_colmajor(dense_np.astype(np.float32)), 1, 5.0,
                           to_device_rows(X0n), tol=1e-8, maxit=300)
     for flags in (spca.FLAG_SPARSE_NO_PANELS, spca.FLAG_SPARSE_PANELS,
                   spca.FLAG_SPARSE_PANELS | spca.FLAG_GRAPH):
         got = spca.am_solve_sparse(D, 1, 5.0, to_device_rows(X0n), tol=1e-8, maxit=300,
                                    flags=flags, return_X=True)
-        compare_solve(got, ref, f"sparse heavy column flags={flags}")
+        compare_solve(got, ref, f"sparse heavy column flags={flags}", dense_np, 1, 5.0)
         assert rel_err(got["objective"], dense["objective"]) <= 1e-5
         if flags & spca.FLAG_GRAPH:
             assert torch.equal(got["X_final"], eager["X_final"])

@@ -60,6 +60,9 @@ def test_robust_pca_reduction(fid):
     want = opt ** 2 if fid == 6 else opt
     assert best <= want * (1 + 1e-12)
     assert best == pytest.approx(want, rel=1e-9)
+    # the explained variance of L1 variance is ||Ax||_1 itself (not squared):
+    # at s = p / gamma = 0 it is the robust-PCA optimum for every formulation
+    assert res["ev"][res["best"]] == pytest.approx(opt, rel=1e-9)
 
 
 # -- brute force on tiny inputs -------------------------------------------------
@@ -133,6 +136,15 @@ def test_brute_force_L1_variance(fid):
     # F_X(y) equals the objective at the optimal x for that y
     assert np.all(res["f"] <= opt * (1 + 1e-9))
     assert res["f"][res["best"]] == pytest.approx(opt, rel=1e-7)
+    # explained variance at the optimum, from the maximising sign vector y*
+    # alone: there y* = sgn(A x*), so ||A x*||_1 = y*^T A x* = v*^T x* with
+    # v* = A^T y* and x* the normalised image of v* under the x-operator
+    ys = [np.array(y) for y in itertools.product((-1, 1), repeat=A.shape[0])]
+    vals = [_phi_l1_var(fid, A.T @ y, par) for y in ys]
+    v = A.T @ ys[int(np.argmax(vals))]
+    w, _ = oracle.x_operator(fid, v, par)
+    x_star = w / np.linalg.norm(w)
+    assert res["ev"][res["best"]] == pytest.approx(float(v @ x_star), rel=1e-6)
 
 
 @pytest.mark.parametrize("fid", (1, 3, 5, 7))

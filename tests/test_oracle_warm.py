@@ -82,8 +82,16 @@ def test_after_warmup_parameter_is_frozen(prob, fid, plain, par):
         np.testing.assert_allclose(warm["X"][j], rest["X"][0], rtol=0, atol=1e-13)
 
 
-def test_no_stop_before_freeze_and_best_by_explained_variance(prob):
+@pytest.mark.parametrize("fid", [7, 6, 8])
+def test_no_stop_before_freeze_and_best_by_explained_variance(prob, fid):
     A, X0 = prob
-    res = oracle.am_multi_warm(A, 7, 0.0, X0, 1e-3, 200, 6, 10)
+    res = oracle.am_multi_warm(A, fid, 0.0, X0, 1e-3, 200, 6, 10)
     assert np.all(res["iters"] >= 7)
     assert res["best"] == int(np.argmax(res["ev"]))
+    # each start's explained variance is that of its returned x: ||Ax||_2^2
+    # for L2 variance, ||Ax||_1 (the value y^T A x at y = sgn(Ax)) for L1
+    for j in range(len(X0)):
+        x = res["X"][j]
+        u = A @ x
+        want = float(np.sign(u) @ u) if fid % 2 == 0 else float(u @ u)
+        assert res["ev"][j] == pytest.approx(want, rel=1e-12)
