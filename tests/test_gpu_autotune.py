@@ -6,7 +6,7 @@ import pytest
 
 import oracle
 import workloads
-from gpu_helpers import compare_solve, to_device_colmajor, to_device_rows
+from gpu_helpers import compare_solve, gpu_stepper, to_device_colmajor, to_device_rows
 
 pytestmark = pytest.mark.gpu
 
@@ -47,7 +47,8 @@ def test_autotune_fills_table_and_is_reproducible(spca, prec):
             par = workloads.s_or_gamma_for(fid, sp.A, 20)
             ref = oracle.am_multi(sp.A.astype(np.float64), fid, par, X0n.astype(np.float64),
                                   1e-8, 200, nthreads=8)
-            compare_solve(res[fid], ref, f"autotuned F{fid}", sp.A, fid, par)
+            compare_solve(res[fid], ref, f"autotuned F{fid}", sp.A, fid, par, X0=X0n,
+                          stepper=gpu_stepper(spca.am_solve, A, fid, par, X0, tol=1e-8))
     text = spca.tune_table_export()
     spca.tune_table_clear()
     spca.tune_table_import(text)

@@ -23,7 +23,8 @@ import pytest
 
 import oracle
 import workloads
-from gpu_helpers import per_start_parity, rel_err, subset, to_device_colmajor, to_device_rows
+from gpu_helpers import (gpu_stepper, per_start_parity, rel_err, subset, to_device_colmajor,
+                         to_device_rows)
 from workloads import counter
 
 pytestmark = pytest.mark.gpu
@@ -63,7 +64,10 @@ def test_headline_workload_sampled_starts(spca, headline, fid):
                           nthreads=threads)
     assert np.all(ref["iters"][ref["status"] == 1] == cfg["maxit"])
     sub = subset(got, idx)
-    match, n_cert = per_start_parity(sub, ref, f"headline F{fid}", A_np, fid, par)
+    match, n_cert = per_start_parity(sub, ref, f"headline F{fid}", A_np, fid, par,
+                                     X0=X0_np[idx],
+                                     stepper=gpu_stepper(spca.am_solve, A, fid, par, X0,
+                                                         tol=-1.0, rows=idx))
     print(f"headline F{fid}: {match:.3f} of {len(idx)} sampled starts agree, "
           f"{n_cert} certified; best start {jb} f {got['objective']:.10g}", flush=True)
     # the best of all 1024 starts is no worse than any sampled oracle start

@@ -238,14 +238,15 @@ def test_solve_long_rows_match_oracle(spca, fid):
     # p = 20000 > 12288: the chunked x-update inside the solve (the L1
     # constraint keeps the one-workgroup kernel)
     import workloads
-    from gpu_helpers import compare_solve, to_device_colmajor, to_device_rows
+    from gpu_helpers import compare_solve, gpu_stepper, to_device_colmajor, to_device_rows
 
     print(f"long-row solve fid={fid}", flush=True)
     sp = workloads.spiked_matrix(41, 150, 20000, thetas=(80.0, 40.0), spike_nnz=30)
     X0 = workloads.random_unit_starts(42, 6, 20000)
     par = workloads.s_or_gamma_for(fid, sp.A, 30, "scaled" if fid in (6, 8) else "literal")
-    got = spca.am_solve(to_device_colmajor(sp.A), fid, par, to_device_rows(X0),
-                        tol=1e-8, maxit=300, return_X=True)
+    Ad, X0d = to_device_colmajor(sp.A), to_device_rows(X0)
+    got = spca.am_solve(Ad, fid, par, X0d, tol=1e-8, maxit=300, return_X=True)
     ref = oracle.am_multi(sp.A.astype(np.float64), fid, par, X0.astype(np.float64),
                           1e-8, 300, nthreads=6)
-    compare_solve(got, ref, f"long rows F{fid}", sp.A, fid, par)
+    compare_solve(got, ref, f"long rows F{fid}", sp.A, fid, par, X0=X0,
+                  stepper=gpu_stepper(spca.am_solve, Ad, fid, par, X0d, tol=1e-8))

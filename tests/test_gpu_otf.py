@@ -7,7 +7,7 @@ import pytest
 
 import oracle
 import workloads
-from gpu_helpers import compare_solve, to_device_colmajor, to_device_rows
+from gpu_helpers import compare_solve, gpu_stepper, to_device_colmajor, to_device_rows
 
 pytestmark = pytest.mark.gpu
 
@@ -40,7 +40,8 @@ def test_replacement_matches_oracle(spca, problem, fid):
     assert len(got["f_per_start"]) == 96 and got["X_final"].shape[0] == 96
     ref = oracle.am_multi(A_np.astype(np.float64), fid, par, X0_np.astype(np.float64),
                           1e-8, 300, nthreads=8)
-    compare_solve(got, ref, f"otf F{fid}", A_np, fid, par)
+    compare_solve(got, ref, f"otf F{fid}", A_np, fid, par, X0=X0_np,
+                  stepper=gpu_stepper(spca.am_solve, A, fid, par, X0, tol=1e-8, slots=16))
     # every start's filed iterate is the one its objective was taken on
     Xf = got["X_final"].cpu().numpy().astype(np.float64)
     for j in range(0, 96, 7):

@@ -9,7 +9,7 @@ import pytest
 
 import oracle
 import workloads
-from gpu_helpers import (compare_solve, per_start_parity, rel_err, subset,
+from gpu_helpers import (compare_solve, gpu_stepper, per_start_parity, rel_err, subset,
                          support_near_tie_margin, to_device_colmajor, to_device_rows)
 
 pytestmark = pytest.mark.gpu
@@ -51,10 +51,11 @@ def test_all_formulations_match_oracle(spca, fid, r, gamma_mode):
     A_np = sp.A
     par = _param(fid, A_np, 25, gamma_mode)
     X0 = workloads.random_unit_starts(workloads.SEED_BASE + 200 + fid, r, 1500)
-    got = spca.am_solve(to_device_colmajor(A_np), fid, par, to_device_rows(X0),
-                        tol=1e-8, maxit=300, return_X=True)
+    Ad, X0d = to_device_colmajor(A_np), to_device_rows(X0)
+    got = spca.am_solve(Ad, fid, par, X0d, tol=1e-8, maxit=300, return_X=True)
     ref = oracle.am_multi(A_np, fid, par, X0, 1e-8, 300, nthreads=8)
-    compare_solve(got, ref, f"F{fid} r={r}", A_np, fid, par)
+    compare_solve(got, ref, f"F{fid} r={r}", A_np, fid, par, X0=X0,
+                  stepper=gpu_stepper(spca.am_solve, Ad, fid, par, X0d, tol=1e-8))
     xb = ref["X"][ref["best"]]
     sup_ref = np.flatnonzero(xb)
     margin = support_near_tie_margin(A_np, xb, fid, par)
@@ -155,7 +156,9 @@ def test_unaligned_leading_dimension_and_odd_sizes(spca):
             got = spca.am_solve(A, fid, par, to_device_rows(X0), tol=1e-10, maxit=500,
                                 return_X=True)
             ref = oracle.am_multi(A_np, fid, par, X0, 1e-10, 500)
-            compare_solve(got, ref, f"odd lda={lda} F{fid}", A_np, fid, par)
+            compare_solve(got, ref, f"odd lda={lda} F{fid}", A_np, fid, par, X0=X0,
+                          stepper=gpu_stepper(spca.am_solve, A, fid, par, to_device_rows(X0),
+                                              tol=1e-10))
 
 
 def test_degenerate_and_zero_starts(spca):
@@ -215,7 +218,9 @@ def test_row_block_list_product(spca, fid):
     assert got["kernel_times"]["iters_union"] == 0
     ref = oracle.am_multi(sp.A.astype(np.float64), fid, par, X0n.astype(np.float64),
                           1e-8, 200, nthreads=6)
-    compare_solve(got, ref, f"row-block list F{fid}", sp.A, fid, par)
+    compare_solve(got, ref, f"row-block list F{fid}", sp.A, fid, par, X0=X0n,
+                  stepper=gpu_stepper(spca.am_solve, A, fid, par, X0, tol=1e-8,
+                                      flags=spca.FLAG_NO_UNION))
     dense = spca.am_solve(A, fid, par, X0, tol=1e-8, maxit=200, flags=spca.FLAG_DENSE_ONLY)
     assert rel_err(got["objective"], dense["objective"]) <= 1e-5
 
@@ -254,7 +259,9 @@ def test_k_split_aty_product(spca, fid):
     got = spca.am_solve(A, fid, par, to_device_rows(X0), tol=1e-8, maxit=120,
                         return_X=True)
     ref = oracle.am_multi(A_np, fid, par, X0, 1e-8, 120, nthreads=8)
-    compare_solve(got, ref, f"k-split F{fid}", A_np, fid, par)
+    compare_solve(got, ref, f"k-split F{fid}", A_np, fid, par, X0=X0,
+                  stepper=gpu_stepper(spca.am_solve, A, fid, par, to_device_rows(X0),
+                                      tol=1e-8))
     shape = spca.gemm_plan(r, p, n, 16)[0]
     # bucket(x) = round(2 log2 x): 16 -> 8, 8000 -> 26, 2000 -> 22
     spca.tune_table_import(f"4 16 8 26 22 {shape} 1\n")
@@ -282,7 +289,8 @@ def test_union_product_used_and_agrees(spca):
     ref4 = oracle.am_multi(sp.A, 1, 20.0, X0n[::128], -1.0, 64, nthreads=4)
     ref = {k: np.repeat(ref4[k], 128, axis=0) for k in ("f", "status", "iters")}
     ref["best"] = ref4["best"] * 128
-    compare_solve(got, ref, "union product", sp.A, 1, 20.0)
+    compare_solve(got, ref, "union product", sp.A, 1, 20.0, X0=X0n,
+                  stepper=gpu_stepper(spca.am_solve, A, 1, 20.0, X0, tol=-1.0))
     dense = spca.am_solve(A, 1, 20.0, X0, flags=spca.FLAG_DENSE_ONLY, **kw)
     ok = [rel_err(a, b) <= 1e-5 for a, b in zip(got["f_per_start"], dense["f_per_start"])]
     assert np.mean(ok) >= 0.98
@@ -307,7 +315,9 @@ def test_union_product_returns_when_supports_converge(spca):
     # a sample of the starts against the oracle from the same starts
     idx = np.r_[0:24, 100:512:64]
     ref = oracle.am_multi(sp.A, 1, 20.0, X0n[idx], -1.0, 96, nthreads=8)
-    per_start_parity(subset(got, idx), ref, "union product (sample)", sp.A, 1, 20.0)
+    per_start_parity(subset(got, idx), ref, "union product (sample)", sp.A, 1, 20.0,
+                     X0=X0n[idx], stepper=gpu_stepper(spca.am_solve, A, 1, 20.0, X0,
+                                                      tol=-1.0, rows=idx))
     dense = spca.am_solve(A, 1, 20.0, X0, flags=spca.FLAG_DENSE_ONLY, **kw)
     ok = [rel_err(a, b) <= 1e-5 for a, b in zip(got["f_per_start"], dense["f_per_start"])]
     assert np.mean(ok) >= 0.98

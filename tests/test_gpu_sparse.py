@@ -7,7 +7,7 @@ import pytest
 
 import oracle
 import workloads
-from gpu_helpers import compare_solve, rel_err, to_device_colmajor, to_device_rows
+from gpu_helpers import compare_solve, gpu_stepper, rel_err, to_device_colmajor, to_device_rows
 from workloads import sparse
 
 pytestmark = pytest.mark.gpu
@@ -40,11 +40,12 @@ def test_sparse_matches_oracle(spca, fid):
     X0n = workloads.random_unit_starts(42, 32, mat.p)
     par = _param(fid, mat)
     D = spca.sparse_to_device(mat)
-    got = spca.am_solve_sparse(D, fid, par, to_device_rows(X0n), tol=1e-8, maxit=300,
-                               return_X=True)
+    X0d = to_device_rows(X0n)
+    got = spca.am_solve_sparse(D, fid, par, X0d, tol=1e-8, maxit=300, return_X=True)
     ref = oracle.am_multi_csc(mat.col_ptr, mat.row_idx, mat.col_val.astype(np.float64), mat.n,
                               mat.p, fid, par, X0n.astype(np.float64), 1e-8, 300, nthreads=8)
-    compare_solve(got, ref, f"sparse F{fid}", mat.dense(), fid, par)
+    compare_solve(got, ref, f"sparse F{fid}", mat.dense(), fid, par, X0=X0n,
+                  stepper=gpu_stepper(spca.am_solve_sparse, D, fid, par, X0d, tol=1e-8))
     dense = spca.am_solve(to_device_colmajor(mat.dense().astype(np.float32)), fid, par,
                           to_device_rows(X0n), tol=1e-8, maxit=300)
     assert rel_err(got["objective"], dense["objective"]) <= 1e-5
@@ -60,7 +61,8 @@ def test_sparse_long_rows_and_graph(spca, fid):
     got = spca.am_solve_sparse(D, fid, par, X0, tol=1e-8, maxit=300, return_X=True)
     ref = oracle.am_multi_csc(mat.col_ptr, mat.row_idx, mat.col_val.astype(np.float64), mat.n,
                               mat.p, fid, par, X0n.astype(np.float64), 1e-8, 300, nthreads=6)
-    compare_solve(got, ref, f"sparse long rows F{fid}", mat.dense(), fid, par)
+    compare_solve(got, ref, f"sparse long rows F{fid}", mat.dense(), fid, par, X0=X0n,
+                  stepper=gpu_stepper(spca.am_solve_sparse, D, fid, par, X0, tol=1e-8))
     g = spca.am_solve_sparse(D, fid, par, X0, tol=1e-8, maxit=300, return_X=True,
                              flags=spca.FLAG_GRAPH)
     assert g["objective"] == got["objective"] and torch.equal(g["X_final"], got["X_final"])
@@ -129,13 +131,16 @@ def test_sparse_chunk_boundaries(spca, r, panels):
     flags = spca.FLAG_SPARSE_PANELS if panels else spca.FLAG_SPARSE_NO_PANELS
     dense = mat.dense()
     for fid, par in ((1, 10.0), (6, workloads.s_or_gamma_for(6, dense, 10, "scaled"))):
-        got = spca.am_solve_sparse(D, fid, par, to_device_rows(X0n), tol=1e-8, maxit=200,
+        X0d = to_device_rows(X0n)
+        got = spca.am_solve_sparse(D, fid, par, X0d, tol=1e-8, maxit=200,
                                    flags=flags, return_X=True)
         ref = oracle.am_multi_csc(mat.col_ptr, mat.row_idx, mat.col_val.astype(np.float64),
                                   mat.n, mat.p, fid, par, X0n.astype(np.float64), 1e-8, 200,
                                   nthreads=8)
         compare_solve(got, ref, f"sparse boundaries F{fid} r={r} panels={panels}", dense,
-                      fid, par)
+                      fid, par, X0=X0n,
+                      stepper=gpu_stepper(spca.am_solve_sparse, D, fid, par, X0d, tol=1e-8,
+                                          flags=flags))
 
 
 def test_sparse_heavy_column(spca):
@@ -153,9 +158,12 @@ def test_sparse_heavy_column(spca):
                           to_device_rows(X0n), tol=1e-8, maxit=300)
     for flags in (spca.FLAG_SPARSE_NO_PANELS, spca.FLAG_SPARSE_PANELS,
                   spca.FLAG_SPARSE_PANELS | spca.FLAG_GRAPH):
-        got = spca.am_solve_sparse(D, 1, 5.0, to_device_rows(X0n), tol=1e-8, maxit=300,
+        X0d = to_device_rows(X0n)
+        got = spca.am_solve_sparse(D, 1, 5.0, X0d, tol=1e-8, maxit=300,
                                    flags=flags, return_X=True)
-        compare_solve(got, ref, f"sparse heavy column flags={flags}", dense_np, 1, 5.0)
+        compare_solve(got, ref, f"sparse heavy column flags={flags}", dense_np, 1, 5.0,
+                      X0=X0n, stepper=gpu_stepper(spca.am_solve_sparse, D, 1, 5.0, X0d,
+                                                  tol=1e-8, flags=flags))
         assert rel_err(got["objective"], dense["objective"]) <= 1e-5
         if flags & spca.FLAG_GRAPH:
             assert torch.equal(got["X_final"], eager["X_final"])

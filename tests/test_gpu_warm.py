@@ -8,7 +8,8 @@ import pytest
 
 import oracle
 import workloads
-from gpu_helpers import per_start_parity, rel_err, to_device_colmajor, to_device_rows
+from gpu_helpers import (gpu_stepper, per_start_parity, rel_err, support_near_tie_margin,
+                         to_device_colmajor, to_device_rows, y_tie_margin)
 
 pytestmark = pytest.mark.gpu
 
@@ -25,7 +26,34 @@ def spca():
     return m
 
 
-def _check(got, ref, fid, label, A64):
+def _warm_step_fns(A64, fid, par, K, s, frozen):
+    """(step, margin) of the warm-up iteration for one start: during
+    x-updates 1..K the oracle's warm-up step (the parameter re-targeted to s
+    nonzeros, or lambda_s recomputed), afterwards the plain map with the
+    start's frozen parameter (the soft threshold at lambda for the L1
+    constraints); at x-update K the frozen value must be the FP64 one."""
+    plain = fid + 4 if fid <= 4 else fid
+    ts_fid = 1 if fid % 2 == 1 else 2
+
+    def step(prev, k):
+        if k <= K:
+            w = oracle.am_multi_warm(A64, fid, par, prev[None, :], -1.0, 1, 1, s)
+            if k == K:
+                assert rel_err(frozen, w["param"][0]) <= 1e-5, (frozen, w["param"][0])
+            return w["X"][0]
+        return oracle.am_single(A64, plain, frozen, prev, -1.0, 1)["x"]
+
+    def margin(prev, k):
+        if k <= K:
+            m = (support_near_tie_margin(A64, prev, fid, par) if fid <= 4
+                 else support_near_tie_margin(A64, prev, ts_fid, s))
+        else:
+            m = support_near_tie_margin(A64, prev, plain, frozen)
+        return min(m, y_tie_margin(A64, fid, prev))
+    return step, margin
+
+
+def _check(got, ref, fid, label, A64, stepper=None, K=6, s=15, par=0.0):
     # a start whose frozen parameter differs from the oracle's (the warm-up
     # took another (s+1)-th element at a near-tie) is certified like a start
     # whose objective differs: after the freeze the iteration is the plain
@@ -35,9 +63,10 @@ def _check(got, ref, fid, label, A64):
                                                           ref["param"])])
     ref2 = dict(ref)
     ref2["f"] = np.where(p_ok, ref["f"], np.nan)
-    match, n_cert = per_start_parity(got, ref2, label, A64, fid, None,
-                                     params=got["param_per_start"],
-                                     cert_fid=fid + 4 if fid <= 4 else fid)
+    match, n_cert = per_start_parity(
+        got, ref2, label, A64, fid, None, params=got["param_per_start"],
+        cert_fid=fid + 4 if fid <= 4 else fid, X0=ref["X0"], stepper=stepper,
+        step_fns=lambda j: _warm_step_fns(A64, fid, par, K, s, got["param_per_start"][j]))
     print(label, match, p_ok.mean(), n_cert, got["objective"], flush=True)
     if fid >= 5:
         # the best start has the largest explained variance
@@ -66,7 +95,10 @@ def test_warmup_matches_oracle(spca, fid, p):
                         return_X=True)
     ref = oracle.am_multi_warm(A64, fid, par, X0n.astype(np.float64), -1.0, 40, 6, s,
                                nthreads=8)
-    _check(got, ref, fid, f"warm F{fid} p={p} fixed work", A64)
+    ref["X0"] = X0n.astype(np.float64)
+    _check(got, ref, fid, f"warm F{fid} p={p} fixed work", A64,
+           stepper=gpu_stepper(spca.am_solve, A, fid, par, X0, tol=-1.0, warmup_iters=6,
+                               target_nnz=s), K=6, s=s, par=par)
     got = spca.am_solve(A, fid, par, X0, tol=1e-8, maxit=300, warmup_iters=6, target_nnz=s)
     ref = oracle.am_multi_warm(A64, fid, par, X0n.astype(np.float64), 1e-8, 300, 6, s,
                                nthreads=8)

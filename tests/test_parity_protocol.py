@@ -126,3 +126,105 @@ def test_per_start_parity_counts(case):
     got = _as_got(ref)
     match, n_cert = per_start_parity(got, ref, "counts", A, 2, 8)
     assert match == 1.0 and n_cert == 0
+
+
+def test_early_stop_on_the_same_trajectory_passes(case):
+    """A start reported CONVERGED a few x-updates before the oracle stops
+    (as when the FP32 ratio test meets a tolerance below its resolution):
+    its iterate is the oracle's after the same number of x-updates, so it
+    passes; the same iterate reported with another iteration count fails."""
+    A, X0 = case
+    ref = oracle.am_multi(A, 5, 2.0, X0, 1e-12, 1000)
+    j = int(np.argmax(ref["iters"]))
+    k = int(ref["iters"][j])
+    while True:  # the last x-update count whose iterate is clearly short of the end
+        k -= 1
+        early = oracle.am_single(A, 5, 2.0, X0[j], -1.0, k)
+        if ref["f"][j] - early["f"] > 1e-4 * ref["f"][j]:
+            break
+    assert not fixed_point_certificate(A, 5, 2.0, early["x"], early["f"])["ok"]
+    got = _as_got(ref)
+    got["iters_per_start"] = ref["iters"].copy()
+    got["iters_per_start"][j] = k
+    got["f_per_start"][j] = early["f"]
+    got["X_final"][j] = early["x"]
+    got["status_per_start"][j] = 0
+    info = compare_solve(got, ref, "early stop", A, 5, 2.0, X0=X0)
+    assert info["certified"] == 1
+    got["iters_per_start"][j] = k + 3
+    with pytest.raises(AssertionError):
+        compare_solve(got, ref, "early stop, wrong count", A, 5, 2.0, X0=X0)
+
+
+def _trajectory(A, fid, par, x0, K):
+    xs, x = [], np.asarray(x0, np.float64)
+    for _ in range(K):
+        x = oracle.am_single(A, fid, par, x, -1.0, 1)["x"]
+        xs.append(x.copy())
+    return xs
+
+
+def test_stepwise_check_accepts_a_valid_trajectory_and_rejects_a_wrong_step(case):
+    """Step-by-step certificate: a trajectory whose every step is the FP64
+    map of its predecessor (here from a start perturbed at rounding level,
+    and not yet converged) passes; the same trajectory with one step taken
+    by a wrong operator (T_s with s - 1) fails at that step."""
+    from gpu_helpers import plain_step, stepwise_check
+
+    A, X0 = case
+    fid, par, K = 1, 8, 12
+    x0 = X0[3] * (1 + 1e-9 * np.random.default_rng(0).standard_normal(X0.shape[1]))
+    xs = _trajectory(A, fid, par, x0, K)
+    step, margin = plain_step(A, fid, par)
+    assert stepwise_check(A, X0[3], xs, step, margin)["ok"]
+    bad = list(xs)
+    w, _ = oracle.x_operator(fid, A.T @ (A @ xs[4] / np.linalg.norm(A @ xs[4])), par - 1)
+    bad[5] = w / np.linalg.norm(w)
+    r = stepwise_check(A, X0[3], bad, step, margin)
+    assert not r["ok"] and r["k"] == 6
+
+
+def test_unconverged_differing_start_needs_the_stepwise_check(case, monkeypatch):
+    """Fixed work too short to converge, and a start reported at the end of
+    another valid trajectory (as after a split at a near-tie): the
+    fixed-point certificate does not cover it and, with the oracle's
+    trajectory check made to miss (a split), only the stepwise check
+    does; a planted wrong step then fails."""
+    import gpu_helpers
+
+    A, X0 = case
+    fid, par, K = 3, 6.0, 4
+    ref = oracle.am_multi(A, fid, par, X0, -1.0, K)
+    j = 5
+    X0b = X0.copy()
+    X0b[j] = X0[(j + 1) % len(X0)]
+    xs = _trajectory(A, fid, par, X0b[j], K)
+    got = _as_got(ref)
+    got["iters_per_start"] = ref["iters"].copy()
+    got["f_per_start"][j] = oracle.objective(fid, A, xs[-1], par)[0]
+    got["X_final"][j] = xs[-1]
+    got["objective"] = float(np.max(got["f_per_start"]))
+    if got["objective"] > ref["f"][ref["best"]]:
+        pytest.skip("the planted trajectory beats the oracle's best")
+    assert not fixed_point_certificate(A, fid, par, xs[-1], got["f_per_start"][j])["ok"]
+    monkeypatch.setattr(gpu_helpers, "trajectory_check",
+                        lambda *a, **k: {"ok": False, "why": "split"})
+    with pytest.raises(AssertionError):
+        compare_solve(got, ref, "unconverged, no stepper", A, fid, par, X0=X0b)
+
+    def stepper(k):
+        Xk = oracle.am_multi(A, fid, par, X0, -1.0, k)["X"]
+        Xk[j] = xs[k - 1]
+        return Xk
+    info = compare_solve(got, ref, "unconverged, stepwise", A, fid, par, X0=X0b,
+                         stepper=stepper)
+    assert info["certified"] == 1
+
+    def bad_stepper(k):
+        Xk = stepper(k)
+        if k == 2:
+            Xk[j] = np.roll(Xk[j], 1)
+        return Xk
+    with pytest.raises(AssertionError):
+        compare_solve(got, ref, "unconverged, wrong step", A, fid, par, X0=X0b,
+                      stepper=bad_stepper)
