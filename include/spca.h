@@ -356,6 +356,25 @@ int spca_x_update(void* stream, int formulation, const float* V, int64_t ldv,
                   int64_t r, int64_t p, double s_or_gamma, float* X,
                   int64_t ldx, double* phi, int32_t* nnz);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops that forbid allocation): spca_x_update with the
+ * same arguments, checks and results, whose chunked kernels (rows longer
+ * than 12288) take their scratch from a fixed array of
+ * SPCA_X_UPDATE_NOALLOC_SCRATCH bytes that every device the library runs
+ * on holds until the process ends, instead of allocating it.  The call
+ * neither allocates, frees nor synchronizes: it enqueues kernels on the
+ * stream and returns.  SPCA_EINVAL (nothing launched) when r rows of
+ * length p need more scratch than that (about 19 KB per row at p = 200000;
+ * split the rows into batches).  Every call on one device shares that
+ * device's array: calls that overlap in time on one device (different
+ * streams, or host threads) race and must be serialized by the caller.
+ * The call clears what must start at zero itself.  The first call on a
+ * device looks up the array's address there (a one-time set-up).        */
+#define SPCA_X_UPDATE_NOALLOC_SCRATCH (64ull << 20)
+int spca_x_update_noalloc(void* stream, int formulation, const float* V,
+                          int64_t ldv, int64_t r, int64_t p, double s_or_gamma,
+                          float* X, int64_t ldx, double* phi, int32_t* nnz);
+
 /* ---------------------------------------------------------------------- */
 /* Serving: continuous batching of independent solves on one GPU.         */
 

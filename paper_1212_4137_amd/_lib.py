@@ -30,7 +30,7 @@ EXPORTED = ("spca_am_solve", "spca_am_solve_ex", "spca_ctx_create",
             "spca_server_submit", "spca_server_poll", "spca_server_stats",
             "spca_server_destroy", "spca_tune_table_export", "spca_tune_table_import",
             "spca_tune_table_clear", "spca_gemm_nt_bf16_shape", "spca_am_components",
-            "spca_am_solve_sparse", "spca_am_components_sparse")
+            "spca_am_solve_sparse", "spca_am_components_sparse", "spca_x_update_noalloc")
 
 
 class SpcaError(RuntimeError):
@@ -157,6 +157,9 @@ def load():
         lib.spca_gemm_nt_f32_plan.restype = ctypes.c_int
         lib.spca_x_update.argtypes = [P, ctypes.c_int, P, i64, i64, i64, d, P, i64, P, P]
         lib.spca_x_update.restype = ctypes.c_int
+        lib.spca_x_update_noalloc.argtypes = [P, ctypes.c_int, P, i64, i64, i64, d, P, i64,
+                                              P, P]
+        lib.spca_x_update_noalloc.restype = ctypes.c_int
         lib.spca_tune_table_export.argtypes = [ctypes.c_char_p, ctypes.c_size_t,
                                                ctypes.POINTER(ctypes.c_size_t)]
         lib.spca_tune_table_export.restype = ctypes.c_int
@@ -463,19 +466,28 @@ def gemm_plan(M, N, K, max_splits=1):
     return sh.value, sp.value
 
 
-def x_update(formulation, V, s_or_gamma, stream=None):
-    """The x-update operator on each row of V (``spca_x_update``); returns
-    (X, phi, nnz) as GPU tensors."""
+def x_update(formulation, V, s_or_gamma, stream=None, out=None, noalloc=False):
+    """The x-update operator on each row of V (``spca_x_update``, or
+    ``spca_x_update_noalloc`` with noalloc=True); returns (X, phi, nnz) as
+    GPU tensors, written into ``out`` when given."""
     import torch
 
     _require_gpu_tensor(V, "V", torch.float32)
     r, p = V.shape
     if V.stride(1) != 1:
         raise ValueError("V must be row-major")
-    X = torch.empty((r, p), dtype=torch.float32, device=V.device)
-    phi = torch.empty(r, dtype=torch.float64, device=V.device)
-    nnz = torch.empty(r, dtype=torch.int32, device=V.device)
-    _check(load().spca_x_update(_stream_ptr(stream), int(formulation),
+    if out is None:
+        X = torch.empty((r, p), dtype=torch.float32, device=V.device)
+        phi = torch.empty(r, dtype=torch.float64, device=V.device)
+        nnz = torch.empty(r, dtype=torch.int32, device=V.device)
+    else:
+        X, phi, nnz = out
+        if (X.shape != (r, p) or X.dtype != torch.float32 or not X.is_contiguous()
+                or phi.dtype != torch.float64 or phi.numel() < r
+                or nnz.dtype != torch.int32 or nnz.numel() < r):
+            raise ValueError("out must be (X (r, p) float32, phi float64 >= r, nnz int32 >= r)")
+    fn = load().spca_x_update_noalloc if noalloc else load().spca_x_update
+    _check(fn(_stream_ptr(stream), int(formulation),
                                 ctypes.c_void_p(V.data_ptr()), V.stride(0), r, p,
                                 float(s_or_gamma), ctypes.c_void_p(X.data_ptr()), p,
                                 ctypes.c_void_p(phi.data_ptr()),

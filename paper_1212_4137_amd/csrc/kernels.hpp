@@ -268,6 +268,12 @@ constexpr int64_t kWideMinP = 12288;
 // p <= kWideMinP); the size is the same for every other formulation
 size_t x_update_wide_bytes(int fid, int64_t r, int64_t p);
 hipError_t x_update_wide_reset(hipStream_t st, void* scratch, int64_t r);
+// 32-bit words at the start of that scratch which x_update_wide_reset clears
+int64_t x_update_wide_clear_words(int64_t r);
+
+// Argument checks shared by the entry points (SPCA_EINVAL with a message).
+int check_problem(int64_t n, int64_t p, int64_t lda, int fid, double sg,
+                  int64_t r, double tol, int32_t maxit);
 // launches the chunked x-update; false (nothing launched) when it does not
 // apply
 bool x_update_wide(hipStream_t st, int fid, double s_or_gamma, const float* V,

@@ -29,6 +29,28 @@ static thread_local std::string g_last_error;
 void set_error(const std::string& msg) { g_last_error = msg; }
 const char* last_error() { return g_last_error.c_str(); }
 
+int check_problem(int64_t n, int64_t p, int64_t lda, int fid, double sg,
+                  int64_t r, double tol, int32_t maxit) {
+  (void)tol;
+  SPCA_REQUIRE(n >= 1 && p >= 1, "n and p must be >= 1");
+  SPCA_REQUIRE(r >= 1, "r (number of starts) must be >= 1");
+  SPCA_REQUIRE(lda >= n, "lda must be >= n");
+  SPCA_REQUIRE(fid >= 1 && fid <= 8, "formulation must be in 1..8 (Table 1)");
+  SPCA_REQUIRE(maxit >= 1, "maxit must be >= 1");
+  SPCA_REQUIRE(p <= INT32_MAX && n <= INT32_MAX && r <= INT32_MAX,
+               "n, p and r must fit in int32");
+  SPCA_REQUIRE(isfinite(sg), "s_or_gamma must be finite");
+  if (fid <= 2) {
+    SPCA_REQUIRE(sg >= 1.0 && sg <= (double)p && sg == floor(sg),
+                 "L0 constraint needs an integral s in [1, p]");
+  } else if (fid <= 4) {
+    SPCA_REQUIRE(sg >= 1.0, "L1 constraint needs s >= 1");
+  } else {
+    SPCA_REQUIRE(sg >= 0.0, "penalty gamma must be >= 0");
+  }
+  return SPCA_OK;
+}
+
 namespace {
 
 // The list-based A x is possible when every running start has at most
@@ -173,28 +195,6 @@ Otf carve_otf(char* base, int64_t r, int64_t p, int64_t l) {
   o.x_all = nullptr;
   o.total = l;
   return o;
-}
-
-int check_problem(int64_t n, int64_t p, int64_t lda, int fid, double sg,
-                  int64_t r, double tol, int32_t maxit) {
-  (void)tol;
-  SPCA_REQUIRE(n >= 1 && p >= 1, "n and p must be >= 1");
-  SPCA_REQUIRE(r >= 1, "r (number of starts) must be >= 1");
-  SPCA_REQUIRE(lda >= n, "lda must be >= n");
-  SPCA_REQUIRE(fid >= 1 && fid <= 8, "formulation must be in 1..8 (Table 1)");
-  SPCA_REQUIRE(maxit >= 1, "maxit must be >= 1");
-  SPCA_REQUIRE(p <= INT32_MAX && n <= INT32_MAX && r <= INT32_MAX,
-               "n, p and r must fit in int32");
-  SPCA_REQUIRE(isfinite(sg), "s_or_gamma must be finite");
-  if (fid <= 2) {
-    SPCA_REQUIRE(sg >= 1.0 && sg <= (double)p && sg == floor(sg),
-                 "L0 constraint needs an integral s in [1, p]");
-  } else if (fid <= 4) {
-    SPCA_REQUIRE(sg >= 1.0, "L1 constraint needs s >= 1");
-  } else {
-    SPCA_REQUIRE(sg >= 0.0, "penalty gamma must be >= 0");
-  }
-  return SPCA_OK;
 }
 
 struct DeviceGuard {

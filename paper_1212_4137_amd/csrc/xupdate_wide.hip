@@ -821,6 +821,8 @@ hipError_t x_update_wide_reset(hipStream_t st, void* scratch, int64_t r) {
   return hipMemsetAsync(scratch, 0, sizeof(uint32_t) * kWBins * r, st);
 }
 
+int64_t x_update_wide_clear_words(int64_t r) { return (int64_t)kWBins * r; }
+
 bool x_update_wide(hipStream_t st, int fid, double s_or_gamma, const float* V,
                    int64_t ldv, int64_t r, int64_t p, float* X, int64_t ldx,
                    int32_t* list_idx, float* list_val, int64_t ldl, int list_cap,

@@ -83,6 +83,15 @@ def test_x_update_argument_validation():
     assert rc == _lib.SPCA_EINVAL
     rc = lib.spca_x_update(None, 9, FAKE, 20, 3, 20, 1.0, FAKE, 20, FAKE, FAKE)
     assert rc == _lib.SPCA_EINVAL
+    # the allocation-free variant: same checks, and a batch whose chunked
+    # scratch exceeds its fixed array is refused before anything is launched
+    rc = lib.spca_x_update_noalloc(None, 1, FAKE, 20, 3, 20, 0.0, FAKE, 20, FAKE, FAKE)
+    assert rc == _lib.SPCA_EINVAL
+    rc = lib.spca_x_update_noalloc(None, 9, FAKE, 20, 3, 20, 1.0, FAKE, 20, FAKE, FAKE)
+    assert rc == _lib.SPCA_EINVAL
+    rc = lib.spca_x_update_noalloc(None, 1, FAKE, 200000, 100000, 200000, 5.0, FAKE,
+                                   200000, FAKE, FAKE)
+    assert rc == _lib.SPCA_EINVAL and "scratch" in lib.spca_last_error().decode()
 
 
 def test_workspace_bytes_is_monotone():
