@@ -11,8 +11,12 @@ starts are resident in HBM before timing starts.
 
 Metric: AM iterations x starts per second over the timed steps.  Also
 reported: the roofline position of the dominant kernel (the FP32 MFMA
-product V = A^T Y, timed with HIP events on the solve's stream) and the
-FP64 CPU oracle's throughput on a bounded sample of the same workload.
+product V = A^T Y, timed with HIP events on the solve's stream around its
+launches in every 8th iteration of the timed steps: an event pair costs the
+stream a few microseconds, so events around every launch would slow the
+step), the whole step against the FP32 MFMA bound of its algorithmic work
+(running starts and iterate nonzeros counted on the device), and the FP64
+CPU oracle's throughput on a bounded sample of the same workload.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
@@ -94,7 +98,7 @@ def _roofline_aty(kt, r, n, p, peak, unit_flops_name="TFLOP/s"):
     launches = kt["aty_launches"]
     avg_ms = kt["aty_ms"] / launches
     achieved = 2.0 * r * n * p / (avg_ms * 1e-3) / 1e12
-    return {"kernel": "gemm_nt (V = A^T Y)", "bound": "mfma",
+    return {"kernel": "gemm_nt (V = A^T Y), the dominant kernel", "bound": "mfma",
             "achieved": round(achieved, 2), "peak": peak, "unit": unit_flops_name,
             "frac": round(achieved / peak, 4), "traffic": None,
             "avg_launch_ms": round(avg_ms, 5), "launches": int(launches)}
@@ -143,7 +147,7 @@ def bench_all8(args, spca, torch):
         for fid in fids:
             res = spca.am_solve(A, fid, params[fid], X0, tol=-1.0, maxit=maxit,
                                 ctx=ctx, stream=stream, kernel_times=timing,
-                                flags=args.flags)
+                                flags=args.flags | (spca.FLAG_TIME_SAMPLED if timing else 0))
             work += res["iters_x_starts"]
             nnz[fid] = float(np.mean(res["nnz_per_start"]))
             if timing:
@@ -163,6 +167,24 @@ def bench_all8(args, spca, torch):
     work = sum(o["work"] for o in outs)
     kt_all = _sum_kt(outs)
     roofline = _roofline_aty(kt_all, r, n, p, PEAK_FP32_MFMA_TFLOPS)
+    # the whole iteration against its algorithmic bound: per running start
+    # and iteration 2 n p flops for A^T Y, and 2 n flops per nonzero of the
+    # iterate for A x, with the running starts and the nonzeros counted on
+    # the device at every iteration; beside it the dense-equivalent count
+    # (both products dense, 4 n p per start and iteration)
+    alg_flops = (2.0 * n * p * kt_all["active_starts_sum"] +
+                 2.0 * n * kt_all["ax_nnz_sum"]) / args.steps
+    dense_flops = 4.0 * n * p * kt_all["active_starts_sum"] / args.steps
+    t_step = dt / args.steps
+    path = {"bound": "mfma", "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
+            "algorithmic_flop_per_step": alg_flops,
+            "t_bound_ms": alg_flops / (PEAK_FP32_MFMA_TFLOPS * 1e12) * 1e3,
+            "achieved": round(alg_flops / t_step / 1e12, 2),
+            "frac": round(alg_flops / (PEAK_FP32_MFMA_TFLOPS * 1e12) / t_step, 4),
+            "dense_equivalent_flop_per_step": dense_flops,
+            "dense_equivalent_frac": round(dense_flops / (PEAK_FP32_MFMA_TFLOPS * 1e12) / t_step, 4),
+            "note": "whole AM step (all 8 formulations) against the FP32 MFMA bound of its "
+                    "algorithmic work; 'roofline' above is the A^T Y kernel alone"}
     tr = traffic_aty()
     if tr is not None:
         tr["algorithmic_bytes"] = 4.0 * (n * p + r * n + r * p)
@@ -194,6 +216,7 @@ def bench_all8(args, spca, torch):
                    "s": cfg["s"], "gamma": "0.1*max_i ||a_i||_2",
                    "spikes": list(cfg["thetas"]), "spike_nnz": cfg["spike_nnz"]},
         "roofline": roofline,
+        "path_roofline": path,
         "kernels": other,
     }
     if not args.no_cpu_baseline:
@@ -222,7 +245,8 @@ def bench_large(args, spca, torch):
 
     def step(timing):
         res = spca.am_solve(A, cfg["fid"], float(cfg["s"]), X0, tol=-1.0, maxit=maxit,
-                            ctx=ctx, stream=stream, kernel_times=timing, flags=args.flags)
+                            ctx=ctx, stream=stream, kernel_times=timing,
+                            flags=args.flags | (spca.FLAG_TIME_SAMPLED if timing else 0))
         res_last.update(res)
         return {"work": res["iters_x_starts"], "kt": res["kernel_times"] if timing else {}}
 

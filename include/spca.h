@@ -201,6 +201,12 @@ typedef struct {
  * the unpanelled product only in the order of the sums.                   */
 #define SPCA_FLAG_SPARSE_PANELS 32
 #define SPCA_FLAG_SPARSE_NO_PANELS 64
+/* SPCA_FLAG_TIME_SAMPLED: with kernel_times, record the HIP events only
+ * around the launches of every 8th iteration (iterations 0, 8, 16, ...);
+ * each event pair costs the stream a few microseconds, so timing every
+ * launch slows a long solve measurably.  The times and launch counts in
+ * kernel_times are then those of the sampled launches.                    */
+#define SPCA_FLAG_TIME_SAMPLED 128
 
 typedef struct {
   double* x;           /* host, p doubles (see spca_am_solve), or NULL      */
@@ -215,15 +221,18 @@ typedef struct {
   int32_t* nnz_per_start;
   float* X_final;      /* optional device r x p (l x p with total_starts > r):
                           final iterates (FP32)                             */
-  /* optional host array of 10 doubles: HIP-event times of the launches of
+  /* optional host array of 12 doubles: HIP-event times of the launches of
    * this solve, [0] total ms and [1] count of the V = A^T Y products,
    * [2] ms and [3] count of the x-updates, [4] ms and [5] count of the
    * dense U = A X products (including launches that found another product
    * selected and returned at once); [6], [7], [8] the iterations whose A x
    * used the dense product, the per-start lists (both list kernels), and
    * the product over the union of the supports; [9] of the list
-   * iterations, those that used the row-block list kernel.  NULL disables
-   * the events.                                                            */
+   * iterations, those that used the row-block list kernel; [10] the
+   * running starts summed over iterations (the A^T Y work is 2 n p per
+   * unit) and [11] the nonzeros of the iterates that entered A x, summed
+   * over iterations and starts (the algorithmic A x work is 2 n per unit).
+   * NULL disables the events.                                              */
   double* kernel_times;
   /* optional host array (per start): the final lambda (formulations 3, 4)
    * or gamma (5..8) of each start under the warm-up; untouched otherwise */

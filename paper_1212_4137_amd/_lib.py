@@ -20,7 +20,7 @@ SPCA_OK, SPCA_EINVAL, SPCA_ENOMEM, SPCA_EHIP = 0, -1, -2, -3
 CONVERGED, MAXIT, DEGENERATE, ZERO = 0, 1, 2, 3
 PREC_FP32, PREC_BF16_POLISH = 0, 1
 FLAG_GRAPH, FLAG_CHECK_FINITE, FLAG_DENSE_ONLY, FLAG_AUTOTUNE, FLAG_NO_UNION = 1, 2, 4, 8, 16
-FLAG_SPARSE_PANELS, FLAG_SPARSE_NO_PANELS = 32, 64
+FLAG_SPARSE_PANELS, FLAG_SPARSE_NO_PANELS, FLAG_TIME_SAMPLED = 32, 64, 128
 
 EXPORTED = ("spca_am_solve", "spca_am_solve_ex", "spca_ctx_create",
             "spca_ctx_destroy", "spca_workspace_bytes", "spca_last_error",
@@ -317,7 +317,7 @@ def am_solve(A, formulation, s_or_gamma, X0=None, tol=1e-8, maxit=200, *,
     status = np.zeros(total, dtype=np.int32)
     nnz = np.zeros(total, dtype=np.int32)
     Xf = torch.empty((total, p), dtype=torch.float32, device=A.device) if return_X else None
-    kt = np.zeros(10) if kernel_times else None
+    kt = np.zeros(12) if kernel_times else None
     prob = Problem(A.data_ptr(), n, p, lda, int(formulation), float(s_or_gamma))
     opts = SolveOpts(X0.data_ptr() if X0 is not None else None, r, float(tol), int(maxit),
                      int(precision), int(polish_maxit), int(check_every), int(flags),
@@ -342,7 +342,8 @@ def am_solve(A, formulation, s_or_gamma, X0=None, tol=1e-8, maxit=200, *,
                 "x_update_launches": int(kt[3]), "ax_dense_ms": kt[4],
                 "ax_dense_launches": int(kt[5]), "iters_dense": int(kt[6]),
                 "iters_list": int(kt[7]), "iters_union": int(kt[8]),
-                "iters_list_rows": int(kt[9])}}
+                "iters_list_rows": int(kt[9]), "active_starts_sum": float(kt[10]),
+                "ax_nnz_sum": float(kt[11])}}
 
 
 def am_solve_simple(A, formulation, s_or_gamma, X0=None, tol=1e-8, maxit=200):
@@ -729,7 +730,7 @@ def am_solve_sparse(D, formulation, s_or_gamma, X0, tol=1e-8, maxit=200, *, chec
                          float(s_or_gamma))
     opts = SolveOpts(X0.data_ptr(), r, float(tol), int(maxit), PREC_FP32, 0, int(check_every),
                      int(flags), 0, int(warmup_iters), int(target_nnz), None, 0)
-    kt = np.zeros(10) if kernel_times else None
+    kt = np.zeros(12) if kernel_times else None
     out = Outputs(_np_ptr(x), _np_ptr(sup), ctypes.pointer(res), _np_ptr(f), _np_ptr(ev),
                   _np_ptr(phi), _np_ptr(iters), _np_ptr(status), _np_ptr(nnz),
                   Xf.data_ptr() if Xf is not None else None,
@@ -746,4 +747,5 @@ def am_solve_sparse(D, formulation, s_or_gamma, X0, tol=1e-8, maxit=200, *, chec
                 "aty_ms": kt[0], "aty_launches": int(kt[1]), "x_update_ms": kt[2],
                 "x_update_launches": int(kt[3]), "ax_dense_ms": kt[4],
                 "ax_dense_launches": int(kt[5]), "iters_dense": int(kt[6]),
-                "iters_list": int(kt[7] - kt[9]), "iters_list_rows": int(kt[9])}}
+                "iters_list": int(kt[7] - kt[9]), "iters_list_rows": int(kt[9]),
+                "active_starts_sum": float(kt[10]), "ax_nnz_sum": float(kt[11])}}

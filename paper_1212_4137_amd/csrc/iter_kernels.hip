@@ -363,6 +363,8 @@ __global__ __launch_bounds__(1024) void plan_kernel(
     plan->mode = mode;
     plan->ax_splits = mode == kAxDense ? dense_splits : 1;
     plan->mode_count[mode] += v[0] > 0 ? 1 : 0;
+    plan->active_sum += (double)v[0];
+    plan->nnz_sum += (double)v[1];
     plan->epoch = epoch + 1;
     const int32_t it = plan->iter + 1;
     plan->iter = it;
@@ -385,6 +387,8 @@ __global__ void init_plan_kernel(Plan* plan, int dense_splits) {
   plan->iter = 0;
   plan->mode_count[0] = plan->mode_count[1] = plan->mode_count[2] = 0;
   plan->mode_count[3] = 0;
+  plan->active_sum = 0.0;
+  plan->nnz_sum = 0.0;
 }
 
 // Union gathers: the blocks copy the union columns of the rows of X, then

@@ -51,6 +51,12 @@ struct Plan {
   int32_t iter;         // planner calls so far
   int32_t mode_count[4];  // iterations run in each mode (statistics)
   int32_t last_union;   // most recent measured union size (0: none yet)
+  // work counters: summed over planner calls, each of which precedes the
+  // iteration it plans (a stopped start is not counted), so they are the
+  // sums over iterations of the running starts and of the nonzeros of the
+  // iterates that enter A x
+  double active_sum;
+  double nnz_sum;
 };
 
 // Sparsity-targeted warm-up (Section 4.1): during x-updates 1..K the

@@ -62,6 +62,7 @@ inline int list_cap_of(int64_t p) {
 }
 
 constexpr int kMaxSplits = 16;  // K splits of the dense A x product
+constexpr int kTimeSample = 8;  // SPCA_FLAG_TIME_SAMPLED: events every 8th iteration
 constexpr int kPolishMax = 32;      // starts polished in FP32 (BF16 mode)
 constexpr double kPolishBand = 2e-3;  // relative band of polished starts
 
@@ -715,6 +716,7 @@ int spca_am_solve_ex(spca_ctx* ctx, void* stream, const spca_problem* prob,
 
   const int32_t maxit = opts->maxit;
   const bool timed = out->kernel_times != nullptr;
+  const bool sampled = (opts->flags & SPCA_FLAG_TIME_SAMPLED) != 0;
   ctx->t_aty.reset();
   ctx->t_xup.reset();
   ctx->t_ax.reset();
@@ -851,7 +853,7 @@ int spca_am_solve_ex(spca_ctx* ctx, void* stream, const spca_problem* prob,
     if (loop_rc != SPCA_OK) return loop_rc;
   }
   for (; !done && it < loop_max; ++it) {
-    rc = iteration(st, timed);
+    rc = iteration(st, timed && (!sampled || it % kTimeSample == 0));
     if (rc != SPCA_OK) return rc;
     if ((it + 1) % every == 0 && it + 1 < loop_max) {
       rc = none_active(&done);
@@ -937,6 +939,8 @@ int spca_am_solve_ex(spca_ctx* ctx, void* stream, const spca_problem* prob,
     kt[8] = hplan.mode_count[kAxUnion];
     kt[7] += hplan.mode_count[kAxListRows];
     kt[9] = hplan.mode_count[kAxListRows];
+    kt[10] = hplan.active_sum;
+    kt[11] = hplan.nnz_sum;
   }
   double total_iters = 0.0;
   for (int64_t j = 0; j < l; ++j) total_iters += it_all[j];
@@ -1178,6 +1182,7 @@ int spca_am_solve_sparse(spca_ctx* ctx, void* stream, const spca_sparse_problem*
   SPCA_LAUNCH_CHECK("sparse staging");
   const int32_t maxit = opts->maxit;
   const bool timed = out->kernel_times != nullptr;
+  const bool sampled = (opts->flags & SPCA_FLAG_TIME_SAMPLED) != 0;
   ctx->t_aty.reset();
   ctx->t_xup.reset();
   ctx->t_ax.reset();
@@ -1247,7 +1252,7 @@ int spca_am_solve_sparse(spca_ctx* ctx, void* stream, const spca_sparse_problem*
     if (loop_rc != SPCA_OK) return loop_rc;
   }
   for (; !done && it < maxit; ++it) {
-    rc = iteration(st, timed);
+    rc = iteration(st, timed && (!sampled || it % kTimeSample == 0));
     if (rc != SPCA_OK) return rc;
     if ((it + 1) % every == 0 && it + 1 < maxit) {
       rc = none_active(&done);
@@ -1292,6 +1297,8 @@ int spca_am_solve_sparse(spca_ctx* ctx, void* stream, const spca_sparse_problem*
     kt[7] = hplan.mode_count[kAxList] + hplan.mode_count[kAxListRows];
     kt[8] = hplan.mode_count[kAxUnion];
     kt[9] = hplan.mode_count[kAxListRows];
+    kt[10] = hplan.active_sum;
+    kt[11] = hplan.nnz_sum;
   }
   const int32_t jb = hb[0], nnzb = hb[1];
   if (out->x)

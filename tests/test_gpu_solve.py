@@ -324,3 +324,27 @@ def test_union_product_returns_when_supports_converge(spca):
     g = spca.am_solve(A, 1, 20.0, X0, flags=spca.FLAG_GRAPH, **kw)
     assert np.array_equal(g["f_per_start"], got["f_per_start"])
     assert torch.equal(g["X_final"], got["X_final"])
+
+
+def test_work_counters_and_sampled_events(spca):
+    """The device's work counters (running starts and iterate nonzeros per
+    iteration, the algorithmic work of the two products) and the sampled
+    event timing: fixed work gives r maxit running-start iterations and,
+    for T_s, nonzeros r p (the dense starts) plus r s per later iteration;
+    with the stop test the running starts sum to the iterations done."""
+    sp = workloads.spiked_matrix(81, 200, 900, thetas=(40.0, 20.0), spike_nnz=10)
+    A = to_device_colmajor(sp.A)
+    X0 = to_device_rows(workloads.random_unit_starts(82, 40, 900))
+    got = spca.am_solve(A, 1, 12.0, X0, tol=-1.0, maxit=20, kernel_times=True)
+    kt = got["kernel_times"]
+    assert kt["active_starts_sum"] == 40 * 20
+    assert kt["ax_nnz_sum"] == 40 * 900 + 40 * 19 * 12
+    assert kt["aty_launches"] == 20
+    got = spca.am_solve(A, 1, 12.0, X0, tol=-1.0, maxit=20, kernel_times=True,
+                        flags=spca.FLAG_TIME_SAMPLED)
+    kt = got["kernel_times"]
+    assert kt["aty_launches"] == 3 and kt["x_update_launches"] == 3  # iterations 0, 8, 16
+    assert kt["active_starts_sum"] == 40 * 20
+    got = spca.am_solve(A, 3, 8.0, X0, tol=1e-6, maxit=300, kernel_times=True)
+    assert got["kernel_times"]["active_starts_sum"] == got["iters_per_start"].sum()
+    assert got["kernel_times"]["ax_nnz_sum"] >= 40 * 900
