@@ -246,6 +246,7 @@ __global__ void init_state_kernel(StartState s, int64_t r) {
   s.phi_prev[j] = 0.0;
   s.iters[j] = 0;
   s.status[j] = kRunning;
+  if (s.thr != nullptr) s.thr[j] = 0.f;
 }
 
 // One block: count running starts and their nonzeros, gather the union of

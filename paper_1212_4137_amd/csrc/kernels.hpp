@@ -25,6 +25,13 @@ struct StartState {
   int32_t* nnz;      // nonzeros of the current x
   int32_t* iters;    // x-updates done
   int32_t* status;   // kRunning or a SPCA_* status
+  // the last x-update's selection threshold (T_s: the s-th largest |v_i|;
+  // lambda_s: lambda), 0 when unknown; a starting guess for the next
+  // x-update's exact selection (it never changes the result).  May be null.
+  float* thr = nullptr;
+  // per start, set by the candidate x-update: 1 when the row still needs
+  // the full selection kernel, 0 when it was settled.  Null: every row.
+  int32_t* redo = nullptr;
 };
 
 // How the next product A x is formed (chosen on the device by the planner):

@@ -107,6 +107,7 @@ __global__ __launch_bounds__(256) void otf_copy_kernel(
     s.iters[j] = 0;
     s.nnz[j] = (int32_t)p;
     s.status[j] = kRunning;
+    if (s.thr != nullptr) s.thr[j] = 0.f;
   }
 }
 

@@ -76,7 +76,7 @@ struct Layout {
   int ax_split_cap, aty_split_cap;
   size_t off_At, off_Ac, off_X, off_U, off_Y, off_V, off_li, off_lv;
   size_t off_phi, off_phip, off_nnz, off_it, off_st, off_plan, off_part,
-      off_f, off_ev, off_xn, off_best, off_xout, off_sup, off_colsq, off_bad;
+      off_f, off_ev, off_xn, off_best, off_xout, off_sup, off_colsq, off_bad, off_thr, off_redo;
   size_t off_mark, off_ulist, off_Xc, off_Qc, off_wide, off_gam;
   size_t wide_bytes;
   int64_t ucap;  // largest support union the union product can hold
@@ -142,6 +142,8 @@ Layout make_layout(int64_t n, int64_t p, int64_t r, bool copy_a, bool bf16) {
   L.off_nnz = carve(&c, sizeof(int32_t) * r);
   L.off_it = carve(&c, sizeof(int32_t) * r);
   L.off_st = carve(&c, sizeof(int32_t) * r);
+  L.off_thr = carve(&c, sizeof(float) * r);
+  L.off_redo = carve(&c, sizeof(int32_t) * r);
   L.off_plan = carve(&c, sizeof(Plan));
   L.off_part = carve(&c, sizeof(double) * 2 * (size_t)r * L.nchunks);
   L.off_f = carve(&c, sizeof(double) * r);
@@ -580,7 +582,8 @@ int spca_am_solve_ex(spca_ctx* ctx, void* stream, const spca_problem* prob,
   Plan* plan = (Plan*)(base + L.off_plan);
   StartState s{(double*)(base + L.off_phi), (double*)(base + L.off_phip),
                (int32_t*)(base + L.off_nnz), (int32_t*)(base + L.off_it),
-               (int32_t*)(base + L.off_st)};
+               (int32_t*)(base + L.off_st), (float*)(base + L.off_thr),
+               (int32_t*)(base + L.off_redo)};
   double* partial = (double*)(base + L.off_part);
   double* fj = (double*)(base + L.off_f);
   double* evj = (double*)(base + L.off_ev);
@@ -1071,6 +1074,8 @@ int spca_am_solve_sparse(spca_ctx* ctx, void* stream, const spca_sparse_problem*
   const size_t o_nnz = carve(&c, sizeof(int32_t) * r);
   const size_t o_it = carve(&c, sizeof(int32_t) * r);
   const size_t o_st = carve(&c, sizeof(int32_t) * r);
+  const size_t o_thr = carve(&c, sizeof(float) * r);
+  const size_t o_redo = carve(&c, sizeof(int32_t) * r);
   const size_t o_plan = carve(&c, sizeof(Plan));
   const size_t o_part = carve(&c, sizeof(double) * 2 * r * nfin);
   const size_t o_f = carve(&c, sizeof(double) * r);
@@ -1101,7 +1106,8 @@ int spca_am_solve_sparse(spca_ctx* ctx, void* stream, const spca_sparse_problem*
   int32_t* li = (int32_t*)(base + o_li);
   float* lv = (float*)(base + o_lv);
   StartState s{(double*)(base + o_phi), (double*)(base + o_phip), (int32_t*)(base + o_nnz),
-               (int32_t*)(base + o_it), (int32_t*)(base + o_st)};
+               (int32_t*)(base + o_it), (int32_t*)(base + o_st), (float*)(base + o_thr),
+               (int32_t*)(base + o_redo)};
   Plan* plan = (Plan*)(base + o_plan);
   double* partial = (double*)(base + o_part);
   double* fj = (double*)(base + o_f);

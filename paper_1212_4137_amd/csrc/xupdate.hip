@@ -716,6 +716,8 @@ __global__ __launch_bounds__(kRT, (KIND == kTopS || WARM) ? 2 : 4) void x_update
   const int64_t j = blockIdx.x;
   const bool full = s.status != nullptr;
   if (full && s.status[j] != kRunning) return;
+  // after the candidate kernel: only the rows it could not settle
+  if (s.redo != nullptr && s.redo[j] == 0) return;
   const int tid = threadIdx.x;
   const int lane = tid % kWave;
   // Striped rows: element 4 (q kRT + tid) + e is v[4 q + e], so that each
@@ -1075,6 +1077,11 @@ __global__ __launch_bounds__(kRT, (KIND == kTopS || WARM) ? 2 : 4) void x_update
 
   if (tid == 0) {
     if (WARM && warming && KIND != kTopS) wm.gam[j] = lam;
+    // the selection threshold, a first guess for the next x-update
+    if (full && s.thr != nullptr) {
+      if (KIND == kTopS) s.thr[j] = zero ? 0.f : __uint_as_float(thr_key);
+      if (KIND == kLambdaS) s.thr[j] = zero ? 0.f : (float)lam;
+    }
     if (!full) {
       s.phi[j] = phi;
       s.nnz[j] = zero ? 0 : total;
@@ -1096,11 +1103,456 @@ __global__ __launch_bounds__(kRT, (KIND == kTopS || WARM) ? 2 : 4) void x_update
   }
 }
 
+// ---------------------------------------------------------------------------
+// Candidate x-update for T_s and V_{lambda_s} (register-resident rows,
+// inside a solve).  Near convergence the selection threshold moves little
+// between x-updates, so the entries with |v_i| at least 90% of the last
+// threshold (the s-th largest |v_i|, or lambda) are few, and they contain
+// every entry the operator keeps:
+//   T_s       when at least s of them exist, the s largest |v_i| (ties to
+//             the lower index) are the s first candidates in (|v| desc,
+//             index asc) order;
+//   lambda_s  when rho(t) = ||(|v| - t)_+||_1 / ||(|v| - t)_+||_2 >= sqrt(s)
+//             at the guess t, the root lies above t (rho is non-increasing),
+//             and the segment scan over the sorted candidates finds it.
+// The candidates (at most kCandCap) are sorted in registers (a bitonic
+// network: shuffles within a wave, LDS across waves, register swaps within
+// a thread), and the norm, phi, list (sorted again, by index) and column
+// marks all come from them; one more pass over the registers writes x.  A
+// row whose guess does not hold (the first x-update, or a threshold that
+// moved by more than 10%) is flagged in s.redo and left to
+// x_update_reg_kernel, launched right after.  Reductions run in a fixed
+// order, so results are deterministic.
+// ---------------------------------------------------------------------------
+constexpr int kCandCap = 1024;
+constexpr int kCandPer = kCandCap / kRT;  // sorted positions per thread
+constexpr float kGuessLow = 0.9f;
+constexpr float kGuessRetry = 0.7f;  // the next guesses: this factor lower
+constexpr uint32_t kIdxMask = 0x3fffu;    // row indices below 16384
+
+struct CSmem {
+  // candidate sort keys, (|v| bits) << 32 | (kIdxMask - index) << 1 | sign:
+  // descending order is |v| descending, then index ascending
+  uint64_t k64[kCandCap];
+  int scan[kRW + 1];
+  double dscan[2 * (kRW + 1)];
+  double red[2];
+  int kbest;
+  double seg[4];
+};
+
+__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t x, int m) {
+  const uint32_t lo = __shfl_xor((uint32_t)x, m, kWave);
+  const uint32_t hi = __shfl_xor((uint32_t)(x >> 32), m, kWave);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// Ascending bitonic sort of kRT E keys: x[e] is element tid + kRT e.
+// Partners fewer than 64 apart are in the same wave (shuffles), 64 and 128
+// apart in another wave (through buf, kRT E keys of LDS), kRT and more
+// apart in the same thread.
+template <int E>
+__device__ __forceinline__ void block_sort_asc(uint64_t (&x)[E], uint64_t* buf) {
+  const int tid = threadIdx.x;
+  constexpr int N = kRT * E;
+#pragma unroll
+  for (int size = 2; size <= N; size <<= 1) {
+#pragma unroll
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      if (stride >= kRT) {
+        const int d = stride / kRT;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          const int e2 = e ^ d;
+          if (e2 > e) {
+            const bool asc = ((tid + kRT * e) & size) == 0;
+            const uint64_t a = x[e], b = x[e2];
+            const bool sw = asc ? a > b : a < b;
+            x[e] = sw ? b : a;
+            x[e2] = sw ? a : b;
+          }
+        }
+      } else {
+        if (stride >= kWave) {
+#pragma unroll
+          for (int e = 0; e < E; ++e) buf[tid + kRT * e] = x[e];
+          __syncthreads();
+        }
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          const int i = tid + kRT * e;
+          const uint64_t b = stride >= kWave ? buf[i ^ stride] : shfl_xor_u64(x[e], stride);
+          const bool lower = (i & stride) == 0;
+          const bool asc = (i & size) == 0;
+          const uint64_t mn = x[e] < b ? x[e] : b;
+          const uint64_t mx = x[e] < b ? b : x[e];
+          x[e] = lower == asc ? mn : mx;
+        }
+        if (stride >= kWave) __syncthreads();
+      }
+    }
+  }
+}
+
+// Sorts arr[0, n) ascending in place (n <= kCandCap), padding with pad.
+// Entries may have been written by any thread before the call.
+template <int E>
+__device__ __forceinline__ void sort_in_lds(uint64_t* arr, int n, uint64_t pad) {
+  __syncthreads();
+  uint64_t x[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int i = threadIdx.x + kRT * e;
+    x[e] = i < n ? arr[i] : pad;
+  }
+  __syncthreads();
+  block_sort_asc<E>(x, arr);
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int i = threadIdx.x + kRT * e;
+    if (i < n) arr[i] = x[e];
+  }
+  __syncthreads();
+}
+
+// The same for n <= 64: the first wave sorts with shuffles alone.
+__device__ __forceinline__ void sort_wave_lds(uint64_t* arr, int n, uint64_t pad) {
+  __syncthreads();
+  if (threadIdx.x < kWave) {
+    const int lane = threadIdx.x;
+    uint64_t x = lane < n ? arr[lane] : pad;
+#pragma unroll
+    for (int size = 2; size <= kWave; size <<= 1) {
+#pragma unroll
+      for (int stride = size >> 1; stride > 0; stride >>= 1) {
+        const uint64_t b = shfl_xor_u64(x, stride);
+        const bool lower = (lane & stride) == 0;
+        const bool asc = (lane & size) == 0;
+        const uint64_t mn = x < b ? x : b;
+        const uint64_t mx = x < b ? b : x;
+        x = lower == asc ? mn : mx;
+      }
+    }
+    if (lane < n) arr[lane] = x;
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ void sort_lds(uint64_t* arr, int n, uint64_t pad) {
+  if (n <= kWave)
+    sort_wave_lds(arr, n, pad);
+  else if (n <= kRT)
+    sort_in_lds<1>(arr, n, pad);
+  else if (n <= 2 * kRT)
+    sort_in_lds<2>(arr, n, pad);
+  else
+    sort_in_lds<4>(arr, n, pad);
+}
+
+// Sum over positions [0, m) of f(q), FP64, in a fixed order: lane l of the
+// first wave adds positions l, l + 64, ..., then an xor butterfly.  The
+// result is returned to every thread of the block.
+template <typename F>
+__device__ __forceinline__ double fixed_sum(int m, F f, double* slot) {
+  if (threadIdx.x < kWave) {
+    double a = 0.0;
+    for (int q = threadIdx.x; q < m; q += kWave) a += f(q);
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) a += __shfl_xor(a, o, kWave);
+    if (threadIdx.x == 0) *slot = a;
+  }
+  __syncthreads();
+  const double r = *slot;
+  __syncthreads();
+  return r;
+}
+
+template <int KIND, int NPT>
+__global__ __launch_bounds__(kRT, 4) void x_update_cand_kernel(
+    const float* __restrict__ V, int64_t ldv, int p, double param,
+    float* __restrict__ X, int64_t ldx, int32_t* __restrict__ list_idx,
+    float* __restrict__ list_val, int64_t ldl, int list_cap, StartState s,
+    double tol, int maxit, int32_t* __restrict__ colmark, const Plan* plan) {
+  static_assert(KIND == kTopS || KIND == kLambdaS, "T_s and lambda_s only");
+  static_assert(kRT * NPT <= (int)kIdxMask + 1, "row indices must fit the sort key");
+  __shared__ CSmem sm;
+  const int64_t j = blockIdx.x;
+  if (s.status[j] != kRunning) return;
+  const int tid = threadIdx.x;
+  const uint32_t t0 = key_of(s.thr[j] * kGuessLow);
+  if (t0 == 0u) {  // no guess yet
+    if (tid == 0) s.redo[j] = 1;
+    return;
+  }
+  auto gidx = [&](int k) { return 4 * ((k / 4) * kRT + tid) + k % 4; };
+  const float* vg = V + j * ldv;
+  float v[NPT];
+#pragma unroll
+  for (int q = 0; q < NPT; q += 4) {
+    const int i = gidx(q);
+    if (i + 3 < p) {
+      const floatx4 w4 = *reinterpret_cast<const floatx4*>(vg + i);
+      v[q] = w4.x;
+      v[q + 1] = w4.y;
+      v[q + 2] = w4.z;
+      v[q + 3] = w4.w;
+    } else {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) v[q + e] = i + e < p ? vg[i + e] : 0.f;
+    }
+  }
+  // the candidate at sorted position q
+  auto cval = [&](int q) -> float {  // signed value
+    const uint64_t k = ~sm.k64[q];
+    const uint32_t bits = (uint32_t)(k >> 32) | ((uint32_t)k << 31);
+    return __uint_as_float(bits);
+  };
+  auto cidx = [&](int q) -> int {
+    return (int)(kIdxMask - (((uint32_t)~sm.k64[q] >> 1) & kIdxMask));
+  };
+  const uint32_t s_int =
+      (uint32_t)((int64_t)param < (int64_t)p ? (int64_t)param : (int64_t)p);
+
+  // the guess t: accepted when it brackets the threshold (at least s keys
+  // at or above it for T_s; for lambda_s more than s keys and
+  // rho(t) >= sqrt(s), i.e. the root at or above t) with at most kCandCap
+  // candidates; otherwise lowered twice by a factor 0.7 (too many
+  // candidates leave the row to the full kernel at once)
+  const double rs = sqrt(param);
+  uint32_t t = t0;
+  bool ok = false;
+  int mine = 0;
+#pragma unroll 1
+  for (int attempt = 0; attempt < 3; ++attempt) {
+    if (attempt > 0) t = key_of(__uint_as_float(t) * kGuessRetry);
+    if (t == 0u) break;
+    // (the rho test only picks the guess, so FP32 sums do: a guess
+    // accepted by rounding finds no root segment below and is left to the
+    // full kernel)
+    mine = 0;
+    float a[2] = {0.f, 0.f};
+    const float tf = __uint_as_float(t);
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) {
+      const bool in = key_of(v[k]) >= t;
+      mine += in;
+      if (KIND == kLambdaS) {
+        const float d = in ? fabsf(v[k]) - tf : 0.f;
+        a[0] += d;
+        a[1] += d * d;
+      }
+    }
+    const int n_in = block_sum(mine, sm.scan);
+    if (KIND == kLambdaS) block_sum_n<float, 2>(a, reinterpret_cast<float*>(sm.dscan));
+    if (n_in > kCandCap) break;
+    if (KIND == kTopS ? n_in >= (int)s_int
+                      : (double)n_in > param && a[1] > 0.f &&
+                            (double)a[0] >= rs * sqrt((double)a[1])) {
+      ok = true;
+      break;
+    }
+  }
+  if (!ok) {
+    if (tid == 0) s.redo[j] = 1;
+    return;
+  }
+  int nc;
+  int off = block_exclusive_scan(mine, sm.scan, &nc);
+  // sort keys, complemented so that an ascending sort gives (|v| desc,
+  // index asc); the pads (all ones) go last
+#pragma unroll
+  for (int k = 0; k < NPT; ++k) {
+    const uint32_t key = key_of(v[k]);
+    if (key >= t) {
+      const uint32_t lo = ((kIdxMask - (uint32_t)gidx(k)) << 1) | (__float_as_uint(v[k]) >> 31);
+      sm.k64[off++] = ~(((uint64_t)key << 32) | lo);
+    }
+  }
+  sort_lds(sm.k64, nc, ~0ull);
+
+  uint32_t thr_key = 0;
+  int64_t cut = -1;
+  double lam = 0.0;
+  int nkept;
+  if (KIND == kTopS) {
+    thr_key = key_of(cval(s_int - 1));
+    cut = cidx(s_int - 1);
+    nkept = (int)s_int;
+  } else {
+    const double s_par = param;
+    const double tf = (double)__uint_as_float(t);
+    // prefix sums of c and c^2 over the sorted candidates; thread t owns
+    // positions kCandPer t onward; the segment holding the root
+    double cv[kCandPer], pre[2] = {0.0, 0.0};
+#pragma unroll
+    for (int e = 0; e < kCandPer; ++e) {
+      const int q = kCandPer * tid + e;
+      cv[e] = q < nc ? fabs((double)cval(q)) : 0.0;
+      pre[0] += cv[e];
+      pre[1] += cv[e] * cv[e];
+    }
+    rscan2(pre, sm.dscan);
+    if (tid == 0) sm.kbest = INT32_MAX;
+    __syncthreads();
+    double S1 = pre[0], S2 = pre[1];
+    int myk = INT32_MAX;
+    double seg[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int e = 0; e < kCandPer; ++e) {
+      const int q = kCandPer * tid + e;
+      S1 += cv[e];
+      S2 += cv[e] * cv[e];
+      const int k = q + 1;
+      if (q >= nc || (double)k <= s_par || myk != INT32_MAX) continue;
+      const double lo = k < nc ? fabs((double)cval(k)) : tf;
+      const double l1 = S1 - (double)k * lo;
+      const double l2 = S2 - 2.0 * lo * S1 + (double)k * lo * lo;
+      if (l2 > 0.0 && l1 >= rs * sqrt(l2)) {
+        myk = k;
+        seg[0] = S1;
+        seg[1] = S2;
+        seg[2] = lo;
+        seg[3] = cv[e];
+      }
+    }
+    if (myk != INT32_MAX) atomicMin(&sm.kbest, myk);
+    __syncthreads();
+    const int kb = sm.kbest;
+    if (myk == kb && kb != INT32_MAX) {
+      sm.seg[0] = seg[0];
+      sm.seg[1] = seg[1];
+      sm.seg[2] = seg[2];
+      sm.seg[3] = seg[3];
+    }
+    __syncthreads();
+    if (kb == INT32_MAX) {  // rounding at the lower end: leave it to the full kernel
+      if (tid == 0) s.redo[j] = 1;
+      return;
+    }
+    const double k = (double)kb, S1b = sm.seg[0], S2b = sm.seg[1];
+    double disc = k * S2b - S1b * S1b;
+    disc = disc > 0.0 ? disc : 0.0;
+    double l = (S1b - sqrt(s_par * disc / (k - s_par))) / k;
+    l = l < sm.seg[2] ? sm.seg[2] : l;
+    l = l > sm.seg[3] ? sm.seg[3] : l;
+    lam = l;
+    // kept: |v| > lambda, a prefix of the sorted candidates
+    int cnt = 0;
+    for (int q = tid; q < nc; q += kRT) cnt += fabs((double)cval(q)) > lam;
+    nkept = block_sum(cnt, sm.scan);
+  }
+  // w of the kept candidate at sorted position q
+  auto wsorted = [&](int q) -> double {
+    const float x = cval(q);
+    if (KIND == kTopS) return (double)x;
+    const double a = fabs((double)x);
+    return x > 0.f ? a - lam : lam - a;
+  };
+  const double nrm2 = fixed_sum(nkept, [&](int q) {
+    const double w = wsorted(q);
+    return w * w;
+  }, &sm.red[0]);
+  const double nrm = sqrt(nrm2);
+  const double phi = KIND == kLambdaS ? lam * sqrt(param) + nrm : nrm;
+  const bool zero = !(nrm > 0.0);
+  const double inv = zero ? 0.0 : 1.0 / nrm;
+  // list (index order) and column marks, from the kept candidates: their
+  // (index, x value) pairs sorted by index
+  const bool listed = list_idx != nullptr && !zero && nkept <= list_cap;
+  const bool marking = colmark != nullptr && !zero && plan->mark != 0;
+  const int32_t epoch = marking ? plan->epoch : 0;
+  if (listed || marking) {
+    uint64_t pr[kCandPer];
+#pragma unroll
+    for (int e = 0; e < kCandPer; ++e) {
+      const int q = tid + kRT * e;
+      pr[e] = q < nkept ? ((uint64_t)(uint32_t)cidx(q) << 32) |
+                              __float_as_uint((float)(wsorted(q) * inv))
+                        : 0ull;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < kCandPer; ++e) {
+      const int q = tid + kRT * e;
+      if (q < nkept) sm.k64[q] = pr[e];
+    }
+    sort_lds(sm.k64, nkept, ~0ull);
+    for (int q = tid; q < nkept; q += kRT) {
+      const uint64_t k = sm.k64[q];
+      const int iq = (int)(k >> 32);
+      if (listed) {
+        list_idx[j * ldl + q] = iq;
+        list_val[j * ldl + q] = __uint_as_float((uint32_t)k);
+      }
+      if (marking) colmark[iq] = epoch;
+    }
+  }
+  // x, from the registers
+  float* x = X + j * ldx;
+#pragma unroll
+  for (int q = 0; q < NPT; q += 4) {
+    float xo[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const float vv = v[q + e];
+      const uint32_t kk = key_of(vv);
+      bool kp;
+      double w;
+      if (KIND == kTopS) {
+        w = (double)vv;
+        kp = kk != 0u && (kk > thr_key || (kk == thr_key && (int64_t)gidx(q + e) <= cut));
+      } else {
+        const double a = fabs((double)vv);
+        w = vv > 0.f ? a - lam : lam - a;
+        kp = a > lam;
+      }
+      xo[e] = (kp && !zero) ? (float)(w * inv) : 0.f;
+    }
+    const int i = gidx(q);
+    if (i + 3 < p) {
+      floatx4 w4 = {xo[0], xo[1], xo[2], xo[3]};
+      *reinterpret_cast<floatx4*>(x + i) = w4;
+    } else {
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        if (i + e < p) x[i + e] = xo[e];
+    }
+  }
+  if (tid == 0) {
+    s.redo[j] = 0;
+    s.thr[j] = zero ? 0.f : (KIND == kTopS ? __uint_as_float(thr_key) : (float)lam);
+    const int it = s.iters[j] + 1;
+    const double prev = s.phi[j];
+    s.iters[j] = it;
+    s.phi_prev[j] = prev;
+    s.phi[j] = phi;
+    s.nnz[j] = zero ? 0 : nkept;
+    if (zero)
+      s.status[j] = SPCA_ZERO;
+    else if (it >= 2 && tol >= 0.0 && phi <= (1.0 + tol) * prev)
+      s.status[j] = SPCA_CONVERGED;
+    else if (it >= maxit)
+      s.status[j] = SPCA_MAXIT;
+  }
+}
+
 template <int KIND, int NPT>
 void launch_reg(hipStream_t st, double param, const float* V, int64_t ldv,
                 int64_t r, int64_t p, float* X, int64_t ldx, int32_t* li,
                 float* lv, int64_t ldl, int list_cap, StartState s, double tol,
                 int maxit, int32_t* colmark, const Plan* plan, Warm wm) {
+  // inside a solve, T_s and lambda_s first try the candidate kernel; the
+  // full kernel then takes only the rows it flagged
+  constexpr bool kCand = KIND == kTopS || KIND == kLambdaS;
+  const bool cand = kCand && wm.K == 0 && s.status != nullptr && s.thr != nullptr &&
+                    s.redo != nullptr;
+  if (!cand) s.redo = nullptr;
+  if constexpr (kCand) {
+    if (cand)
+      hipLaunchKernelGGL((x_update_cand_kernel<KIND, NPT>), dim3((unsigned)r), dim3(kRT),
+                         0, st, V, ldv, (int)p, param, X, ldx, li, lv, ldl, list_cap, s,
+                         tol, maxit, colmark, plan);
+  }
   if (KIND != kTopS && wm.K > 0)
     hipLaunchKernelGGL((x_update_reg_kernel<KIND, NPT, true>), dim3((unsigned)r),
                        dim3(kRT), 0, st, V, ldv, (int)p, param, X, ldx, li, lv,
