@@ -59,12 +59,25 @@ enum {
 #define SPCA_DEGENERATE 2 /* A x = 0 (excluded by Theorem 1): x = 0, f = 0  */
 #define SPCA_ZERO 3       /* the x-operator returned 0: x = 0, f = 0         */
 
+/* spca_result.warning: a property of the whole solve (all its starts), 0 or
+ * positive; the solve itself succeeded (return code SPCA_OK) */
+#define SPCA_WARN_NONE 0
+#define SPCA_WARN_ALL_DEGENERATE 1 /* every start ended DEGENERATE (A x = 0) */
+#define SPCA_WARN_ALL_ZERO 2       /* every start ended DEGENERATE or ZERO,
+                                      at least one ZERO: x_out is 0, f = 0   */
+#define SPCA_WARN_NO_CONVERGED 3   /* tol >= 0 and no start met the stop test
+                                      within maxit (some ended MAXIT)        */
+
 /* Arithmetic of the iterations */
 #define SPCA_PREC_FP32 0        /* A, X, Y in FP32, FP32 MFMA accumulation   */
 #define SPCA_PREC_BF16_POLISH 1 /* A, X, Y operands in BF16, FP32 accumulation,
                                    then up to polish_maxit FP32 AM iterations
-                                   on the caller's FP32 A from the best
-                                   start's iterate ("polish"); objective and
+                                   on the caller's FP32 A ("polish"): every
+                                   start continues from its BF16-phase
+                                   iterate for up to 8 iterations, then the
+                                   16 best still-running ones to the end;
+                                   the per-start results and the best start
+                                   are those after the polish; objective and
                                    explained variance in FP64 on the FP32 A */
 
 typedef struct {
@@ -76,11 +89,11 @@ typedef struct {
   int32_t nnz;           /* |support|                                       */
   int32_t iters;         /* x-updates done by the best start                */
   int32_t status;        /* SPCA_CONVERGED .. SPCA_ZERO of the best start   */
-  double objective_pre_polish; /* BF16 mode: f of the best start before the
-                                  FP32 polish (FP64, on the FP32 A); equal to
-                                  objective otherwise                        */
-  int32_t polish_iters;  /* FP32 polish iterations run (BF16 mode)          */
-  int32_t reserved;
+  double objective_pre_polish; /* BF16 mode: the best f over the starts
+                                  before the FP32 polish (FP64, on the FP32
+                                  A); equal to objective otherwise          */
+  int32_t polish_iters;  /* FP32 polish iterations of the best start (BF16) */
+  int32_t warning;       /* SPCA_WARN_* over all starts of the solve        */
 } spca_result;
 
 /* ---------------------------------------------------------------------- */
@@ -220,7 +233,8 @@ typedef struct {
   int32_t* status_per_start;
   int32_t* nnz_per_start;
   float* X_final;      /* optional device r x p (l x p with total_starts > r):
-                          final iterates (FP32)                             */
+                          final iterates (FP32; with SPCA_PREC_BF16_POLISH
+                          those of the BF16 phase, before the polish)      */
   /* optional host array of 12 doubles: HIP-event times of the launches of
    * this solve, [0] total ms and [1] count of the V = A^T Y products,
    * [2] ms and [3] count of the x-updates, [4] ms and [5] count of the
@@ -295,6 +309,33 @@ int spca_am_components_sparse(spca_ctx* ctx, void* stream, const spca_sparse_pro
  * SPCA_FLAG_CHECK_FINITE, a non-finite entry of A.                         */
 int spca_am_solve_ex(spca_ctx* ctx, void* stream, const spca_problem* prob,
                      const spca_solve_opts* opts, spca_outputs* out);
+
+/* Grouped solve: `count` independent requests (probs[q], opts[q],
+ * outs[q]; each its own A, formulation, parameter, starts, tol and maxit)
+ * iterated together, so that every kernel launch of an AM iteration
+ * (Algorithm 2, from every start of every request, Section 4) covers the
+ * starts of all of them.  Meant for requests too small to fill the GPU,
+ * whose cost is the launch count: products are always dense, with a K split
+ * that follows from each request's own n and p, and the iteration runs
+ * until every start of every request has stopped.  A request's results are
+ * bit-identical alone (count = 1) and in any group; they are those of
+ * spca_am_solve up to the order of the sums in the products.
+ * Restrictions (SPCA_EINVAL, the message names the request): FP32
+ * precision, no total_starts > r, warm-up or deflation; p at most
+ * SPCA_GROUP_MAX_P (the register-resident x-update); at most
+ * SPCA_GROUP_MAX_REQUESTS requests and SPCA_GROUP_MAX_STARTS starts in all;
+ * each request is checked as in spca_am_solve_ex.  Flags are ignored; the
+ * host polls every min(check_every) iterations.  outs[q] as in
+ * spca_am_solve_ex (kernel_times and param_per_start are not written).
+ * Workspace: spca_group_workspace_bytes of the same arguments, taken from
+ * ctx (SPCA_ENOMEM beyond its budget).  Synchronizes the stream.          */
+#define SPCA_GROUP_MAX_REQUESTS 1024
+#define SPCA_GROUP_MAX_P 12288
+#define SPCA_GROUP_MAX_STARTS 65536
+size_t spca_group_workspace_bytes(int32_t count, const spca_problem* probs,
+                                  const spca_solve_opts* opts);
+int spca_am_solve_group(spca_ctx* ctx, void* stream, int32_t count, const spca_problem* probs,
+                        const spca_solve_opts* opts, spca_outputs* outs);
 
 /* Thread-local message of the last failure ("" if none).                 */
 const char* spca_last_error(void);
@@ -445,14 +486,27 @@ typedef struct {
 typedef struct spca_server spca_server;
 
 /* Bytes of server memory a request holds while it runs: its generated A,
- * spike factors, starts and spca_workspace_bytes of the solve.            */
+ * spike factors, starts and spca_workspace_bytes of the solve (for a
+ * request served in groups, see below, the grouped workspace of the request
+ * alone; its group's workspace is shared).                                */
 size_t spca_request_footprint(const spca_request* req);
 /* Allocates an arena of hbm_bytes on the device and starts `workers` worker
  * threads, each with its own stream and context.  Requests are admitted in
  * arrival order when a worker is free and their footprint fits in the free
- * part of the arena (first fit); admitted requests run concurrently.       */
+ * part of the arena (first fit); admitted requests run concurrently.
+ * Small requests (FP32, p <= SPCA_GROUP_MAX_P, n p r <= 5.4e8, no flag but
+ * SPCA_FLAG_GRAPH, valid arguments) are served in groups: the worker that
+ * admits one also admits the small requests queued right behind it (up to
+ * 32 requests and 4096 starts, as far as the arena allows) and solves them
+ * with spca_am_solve_group; their completions are posted together.  A
+ * request's result is the same alone and in any mix.                      */
 int spca_server_create(spca_server** srv, int device, size_t hbm_bytes,
                        int32_t workers);
+/* Largest number of requests served as one group (default 32); 0 serves
+ * every request alone with spca_am_solve_ex, 1 serves small requests alone
+ * with spca_am_solve_group.  Only while no request is queued or running
+ * (EINVAL otherwise).                                                      */
+int spca_server_set_group_limit(spca_server* srv, int32_t max_requests);
 /* Queues a request; EINVAL when its footprint exceeds the whole arena. */
 int spca_server_submit(spca_server* srv, const spca_request* req, int64_t* id);
 /* Moves up to max completions (in completion order) to out; waits up to

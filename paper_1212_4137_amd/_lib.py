@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(PKG, "libspca.so")
 
 SPCA_OK, SPCA_EINVAL, SPCA_ENOMEM, SPCA_EHIP = 0, -1, -2, -3
 CONVERGED, MAXIT, DEGENERATE, ZERO = 0, 1, 2, 3
+WARN_NONE, WARN_ALL_DEGENERATE, WARN_ALL_ZERO, WARN_NO_CONVERGED = 0, 1, 2, 3
 PREC_FP32, PREC_BF16_POLISH = 0, 1
 FLAG_GRAPH, FLAG_CHECK_FINITE, FLAG_DENSE_ONLY, FLAG_AUTOTUNE, FLAG_NO_UNION = 1, 2, 4, 8, 16
 FLAG_SPARSE_PANELS, FLAG_SPARSE_NO_PANELS, FLAG_TIME_SAMPLED = 32, 64, 128
@@ -30,7 +31,9 @@ EXPORTED = ("spca_am_solve", "spca_am_solve_ex", "spca_ctx_create",
             "spca_server_submit", "spca_server_poll", "spca_server_stats",
             "spca_server_destroy", "spca_tune_table_export", "spca_tune_table_import",
             "spca_tune_table_clear", "spca_gemm_nt_bf16_shape", "spca_am_components",
-            "spca_am_solve_sparse", "spca_am_components_sparse", "spca_x_update_noalloc")
+            "spca_am_solve_sparse", "spca_am_components_sparse", "spca_x_update_noalloc",
+            "spca_am_solve_group", "spca_group_workspace_bytes", "spca_server_set_group_limit")
+GROUP_MAX_REQUESTS, GROUP_MAX_P, GROUP_MAX_STARTS = 1024, 12288, 65536
 
 
 class SpcaError(RuntimeError):
@@ -45,7 +48,7 @@ class Result(ctypes.Structure):
                 ("best_start", ctypes.c_int32), ("nnz", ctypes.c_int32),
                 ("iters", ctypes.c_int32), ("status", ctypes.c_int32),
                 ("objective_pre_polish", ctypes.c_double),
-                ("polish_iters", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("polish_iters", ctypes.c_int32), ("warning", ctypes.c_int32)]
 
 
 class Problem(ctypes.Structure):
@@ -138,6 +141,14 @@ def load():
         lib.spca_am_solve_ex.argtypes = [P, P, ctypes.POINTER(Problem),
                                          ctypes.POINTER(SolveOpts), ctypes.POINTER(Outputs)]
         lib.spca_am_solve_ex.restype = ctypes.c_int
+        lib.spca_am_solve_group.argtypes = [P, P, i32, ctypes.POINTER(Problem),
+                                            ctypes.POINTER(SolveOpts), ctypes.POINTER(Outputs)]
+        lib.spca_am_solve_group.restype = ctypes.c_int
+        lib.spca_group_workspace_bytes.argtypes = [i32, ctypes.POINTER(Problem),
+                                                   ctypes.POINTER(SolveOpts)]
+        lib.spca_group_workspace_bytes.restype = ctypes.c_size_t
+        lib.spca_server_set_group_limit.argtypes = [P, i32]
+        lib.spca_server_set_group_limit.restype = ctypes.c_int
         lib.spca_gemm_nt_f32.argtypes = [P, P, i64, P, i64, P, i64, i64, i64, i64]
         lib.spca_gemm_nt_f32.restype = ctypes.c_int
         lib.spca_gemm_nt_bf16.argtypes = [P, P, i64, P, i64, P, i64, i64, i64, i64]
@@ -331,7 +342,7 @@ def am_solve(A, formulation, s_or_gamma, X0=None, tol=1e-8, maxit=200, *,
     return {"x": x, "support": sup[: res.nnz].copy(), "objective": res.objective,
             "explained_variance": res.explained_var, "phi": res.phi,
             "best_start": res.best_start, "nnz": res.nnz, "iters": res.iters,
-            "status": res.status, "iters_x_starts": res.iters_x_starts,
+            "status": res.status, "warning": res.warning, "iters_x_starts": res.iters_x_starts,
             "objective_pre_polish": res.objective_pre_polish,
             "polish_iters": res.polish_iters,
             "f_per_start": f, "ev_per_start": ev, "phi_per_start": phi,
@@ -344,6 +355,78 @@ def am_solve(A, formulation, s_or_gamma, X0=None, tol=1e-8, maxit=200, *,
                 "iters_list": int(kt[7]), "iters_union": int(kt[8]),
                 "iters_list_rows": int(kt[9]), "active_starts_sum": float(kt[10]),
                 "ax_nnz_sum": float(kt[11])}}
+
+
+def _group_args(requests):
+    import torch
+
+    count = len(requests)
+    probs = (Problem * count)()
+    opts = (SolveOpts * count)()
+    for q, rq in enumerate(requests):
+        A, X0 = rq["A"], rq.get("X0")
+        _require_gpu_tensor(A, "A", torch.float32)
+        n, p, lda = colmajor_view(A)
+        if X0 is not None:
+            _require_gpu_tensor(X0, "X0", torch.float32)
+            if X0.dim() != 2 or X0.shape[1] != p or not X0.is_contiguous():
+                raise ValueError("X0 must be a contiguous (r, p) tensor")
+        r = 1 if X0 is None else X0.shape[0]
+        probs[q] = Problem(A.data_ptr(), n, p, lda, int(rq["formulation"]),
+                           float(rq["s_or_gamma"]))
+        opts[q] = SolveOpts(X0.data_ptr() if X0 is not None else None, r,
+                            float(rq.get("tol", 1e-8)), int(rq.get("maxit", 200)), PREC_FP32, 0,
+                            int(rq.get("check_every", 8)), 0, 0, 0, 0)
+    return probs, opts
+
+
+def group_workspace_bytes(requests):
+    probs, opts = _group_args(requests)
+    return int(load().spca_group_workspace_bytes(len(requests), probs, opts))
+
+
+def am_solve_group(requests, *, ctx=None, stream=None, return_X=False):
+    """Grouped solve (``spca_am_solve_group``): the requests iterate together,
+    every launch of an iteration covering all of them.
+
+    requests: list of dicts with A (column-major float32 GPU tensor), X0
+        ((r, p) float32 GPU tensor or None for r = 1), formulation,
+        s_or_gamma and optionally tol, maxit, check_every.
+    Returns one result dict per request (the keys of ``am_solve``)."""
+    import torch
+
+    count = len(requests)
+    probs, opts = _group_args(requests)
+    outs = (Outputs * count)()
+    keep = []
+    for q, rq in enumerate(requests):
+        p, r = probs[q].p, opts[q].r
+        d = {"x": np.zeros(p), "sup": np.zeros(p, dtype=np.int32), "res": Result(),
+             "f": np.zeros(r), "ev": np.zeros(r), "phi": np.zeros(r),
+             "iters": np.zeros(r, dtype=np.int32), "status": np.zeros(r, dtype=np.int32),
+             "nnz": np.zeros(r, dtype=np.int32),
+             "Xf": torch.empty((r, p), dtype=torch.float32, device=rq["A"].device)
+             if return_X else None}
+        keep.append(d)
+        outs[q] = Outputs(_np_ptr(d["x"]), _np_ptr(d["sup"]), ctypes.pointer(d["res"]),
+                          _np_ptr(d["f"]), _np_ptr(d["ev"]), _np_ptr(d["phi"]),
+                          _np_ptr(d["iters"]), _np_ptr(d["status"]), _np_ptr(d["nnz"]),
+                          d["Xf"].data_ptr() if d["Xf"] is not None else None, None, None)
+    ctx = ctx or default_context(requests[0]["A"].device.index or 0)
+    _check(load().spca_am_solve_group(ctx.handle, _stream_ptr(stream), count, probs, opts, outs))
+    results = []
+    for d in keep:
+        res = d["res"]
+        results.append({
+            "x": d["x"], "support": d["sup"][: res.nnz].copy(), "objective": res.objective,
+            "explained_variance": res.explained_var, "phi": res.phi,
+            "best_start": res.best_start, "nnz": res.nnz, "iters": res.iters,
+            "status": res.status, "warning": res.warning,
+            "iters_x_starts": res.iters_x_starts, "f_per_start": d["f"],
+            "ev_per_start": d["ev"], "phi_per_start": d["phi"],
+            "iters_per_start": d["iters"], "status_per_start": d["status"],
+            "nnz_per_start": d["nnz"], "X_final": d["Xf"]})
+    return results
 
 
 def am_solve_simple(A, formulation, s_or_gamma, X0=None, tol=1e-8, maxit=200):
@@ -365,7 +448,7 @@ def am_solve_simple(A, formulation, s_or_gamma, X0=None, tol=1e-8, maxit=200):
                                 ctypes.byref(res)))
     return {"x": x, "support": sup[: res.nnz].copy(), "objective": res.objective,
             "explained_variance": res.explained_var, "best_start": res.best_start,
-            "nnz": res.nnz, "iters": res.iters, "status": res.status}
+            "nnz": res.nnz, "iters": res.iters, "status": res.status, "warning": res.warning}
 
 
 def gemm_nt(P, Q, stream=None):
@@ -549,11 +632,18 @@ class Server:
     dict with the fields of spca_request (``want_x=True`` asks for x and
     the support); ``poll`` returns finished requests as dicts."""
 
-    def __init__(self, hbm_bytes, workers=4, device=0):
+    def __init__(self, hbm_bytes, workers=4, device=0, group_limit=None):
         self.handle = ctypes.c_void_p()
         _check(load().spca_server_create(ctypes.byref(self.handle), device,
                                          int(hbm_bytes), int(workers)))
         self._keep = {}
+        if group_limit is not None:
+            # 0: every request alone (spca_am_solve_ex); k: groups of <= k
+            try:
+                _check(load().spca_server_set_group_limit(self.handle, int(group_limit)))
+            except Exception:
+                self.close()
+                raise
 
     def submit(self, spec):
         q, keep = _request(spec)
@@ -573,7 +663,7 @@ class Server:
             d = {"id": c.id, "rc": c.rc, "error": c.error.decode(errors="replace"),
                  "objective": c.res.objective, "explained_variance": c.res.explained_var,
                  "objective_pre_polish": c.res.objective_pre_polish,
-                 "nnz": c.res.nnz, "iters": c.res.iters, "status": c.res.status,
+                 "nnz": c.res.nnz, "iters": c.res.iters, "status": c.res.status, "warning": c.res.warning,
                  "best_start": c.res.best_start, "iters_x_starts": c.res.iters_x_starts,
                  "polish_iters": c.res.polish_iters, "s_or_gamma": c.s_or_gamma,
                  "t_submit": c.t_submit, "t_admit": c.t_admit, "t_solve": c.t_solve,
@@ -739,7 +829,7 @@ def am_solve_sparse(D, formulation, s_or_gamma, X0, tol=1e-8, maxit=200, *, chec
                                        ctypes.byref(opts), ctypes.byref(out)))
     return {"x": x, "support": sup[: res.nnz].copy(), "objective": res.objective,
             "explained_variance": res.explained_var, "best_start": res.best_start,
-            "nnz": res.nnz, "iters": res.iters, "status": res.status,
+            "nnz": res.nnz, "iters": res.iters, "status": res.status, "warning": res.warning,
             "iters_x_starts": res.iters_x_starts, "f_per_start": f, "ev_per_start": ev,
             "iters_per_start": iters, "status_per_start": status, "nnz_per_start": nnz,
             "param_per_start": par, "X_final": Xf,

@@ -94,42 +94,18 @@ __device__ __forceinline__ floatx4 load_chunk(const T* __restrict__ base,
   return v;
 }
 
+// One BM x BN tile of C = P * Q^T over K range [kbeg, kend): rows m0.. of P
+// and C, rows n0.. of Q (columns of C); lds holds 2 * kStage floats.
 template <typename T, int BM, int BN, int WM, int WN>
-__global__ __launch_bounds__(WM* WN* kWave) void gemm_nt_kernel(
-    const T* __restrict__ P, int64_t ldp, const T* __restrict__ Q,
-    int64_t ldq, float* __restrict__ C, int64_t ldc, int M, int N, int K,
-    int tiles_m, int tiles_mn, int splits, int kslabs_per_split,
-    int64_t split_stride, const int32_t* __restrict__ gate, int32_t gate_run,
-    const int32_t* __restrict__ kdev) {
+__device__ __forceinline__ void gemm_tile(const T* __restrict__ P, int64_t ldp,
+                                          const T* __restrict__ Q, int64_t ldq,
+                                          float* __restrict__ Cs, int64_t ldc, int M,
+                                          int N, int m0, int n0, int kbeg, int kend,
+                                          float* lds) {
   using Cfg = GemmCfg<BM, BN, WM, WN>;
   constexpr int E = Elem<T>::kPerChunk;
   constexpr int SK = kChunks * E;  // K elements per slab
-  if (gate != nullptr && *gate != gate_run) return;
-  if (kdev != nullptr) {
-    K = *kdev;
-    kslabs_per_split = (K + SK - 1) / SK;
-  }
-
-  __shared__ __attribute__((aligned(16))) float lds[2 * Cfg::kStage];
-
-  // Blocks are dealt to the 8 XCDs round-robin; renumber so that runs of
-  // consecutive tiles (the M tiles and K splits sharing one Q tile) stay on
-  // one XCD and reuse its L2.
-  int b = blockIdx.x;
-  const int total = tiles_mn * splits;
-  const int per_xcd = total / 8;
-  if (b < per_xcd * 8) b = (b % 8) * per_xcd + b / 8;
-  const int split = b % splits;
-  const int t = b / splits;
-  const int tm = t % tiles_m;
-  const int tn = t / tiles_m;
-  const int m0 = tm * BM;
-  const int n0 = tn * BN;
-  const int kbeg = split * kslabs_per_split * SK;
-  int kend = kbeg + kslabs_per_split * SK;
-  kend = kend < K ? kend : K;
   const int nslabs = kend > kbeg ? (kend - kbeg + SK - 1) / SK : 0;
-  float* Cs = C + (int64_t)split * split_stride;
 
   const int tid = threadIdx.x;
   const int lane = tid % kWave;
@@ -273,6 +249,72 @@ __global__ __launch_bounds__(WM* WN* kWave) void gemm_nt_kernel(
       }
     }
   }
+}
+
+template <typename T, int BM, int BN, int WM, int WN>
+__global__ __launch_bounds__(WM* WN* kWave) void gemm_nt_kernel(
+    const T* __restrict__ P, int64_t ldp, const T* __restrict__ Q,
+    int64_t ldq, float* __restrict__ C, int64_t ldc, int M, int N, int K,
+    int tiles_m, int tiles_mn, int splits, int kslabs_per_split,
+    int64_t split_stride, const int32_t* __restrict__ gate, int32_t gate_run,
+    const int32_t* __restrict__ kdev) {
+  using Cfg = GemmCfg<BM, BN, WM, WN>;
+  constexpr int SK = kChunks * Elem<T>::kPerChunk;  // K elements per slab
+  if (gate != nullptr && *gate != gate_run) return;
+  if (kdev != nullptr) {
+    K = *kdev;
+    kslabs_per_split = (K + SK - 1) / SK;
+  }
+
+  __shared__ __attribute__((aligned(16))) float lds[2 * Cfg::kStage];
+
+  // Blocks are dealt to the 8 XCDs round-robin; renumber so that runs of
+  // consecutive tiles (the M tiles and K splits sharing one Q tile) stay on
+  // one XCD and reuse its L2.
+  int b = blockIdx.x;
+  const int total = tiles_mn * splits;
+  const int per_xcd = total / 8;
+  if (b < per_xcd * 8) b = (b % 8) * per_xcd + b / 8;
+  const int split = b % splits;
+  const int t = b / splits;
+  const int tm = t % tiles_m;
+  const int tn = t / tiles_m;
+  const int kbeg = split * kslabs_per_split * SK;
+  int kend = kbeg + kslabs_per_split * SK;
+  kend = kend < K ? kend : K;
+  gemm_tile<T, BM, BN, WM, WN>(P, ldp, Q, ldq, C + (int64_t)split * split_stride, ldc,
+                               M, N, tm * BM, tn * BN, kbeg, kend, lds);
+}
+
+// Grouped products: one launch over the tiles of several independent
+// products (GemmGroupDesc), each tile owned by the product whose tile range
+// holds its block index.  The products of a request none of whose starts
+// still runs (running[req] == 0) are skipped.
+template <int BM, int BN, int WM, int WN>
+__global__ __launch_bounds__(WM* WN* kWave) void gemm_group_kernel(
+    const GemmGroupDesc* __restrict__ d, int count, const int32_t* __restrict__ running) {
+  using Cfg = GemmCfg<BM, BN, WM, WN>;
+  constexpr int SK = kChunks * Elem<float>::kPerChunk;
+  __shared__ __attribute__((aligned(16))) float lds[2 * Cfg::kStage];
+  const int b = blockIdx.x;
+  // the last product whose first tile is at or below b (tile0 ascending)
+  int lo = 0, hi = count - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) / 2;
+    if (d[mid].tile0 <= b) lo = mid; else hi = mid - 1;
+  }
+  const GemmGroupDesc g = d[lo];
+  if (running != nullptr && running[g.req] == 0) return;
+  const int local = b - g.tile0;
+  const int split = local % g.splits;
+  const int t = local / g.splits;
+  const int tm = t % g.tiles_m;
+  const int tn = t / g.tiles_m;
+  const int kbeg = split * g.kslabs_per_split * SK;
+  int kend = kbeg + g.kslabs_per_split * SK;
+  kend = kend < g.K ? kend : g.K;
+  gemm_tile<float, BM, BN, WM, WN>(g.P, g.ldp, g.Q, g.ldq, g.C + (int64_t)split * g.split_stride,
+                                   g.ldc, g.M, g.N, tm * BM, tn * BN, kbeg, kend, lds);
 }
 
 // Compiled tile shapes.  occ = workgroups a CU holds at once (LDS and
@@ -524,6 +566,28 @@ void gemm_nt_bf16(hipStream_t st, const uint16_t* P, int64_t ldp,
   if (M <= 0 || N <= 0) return;
   dispatch<uint16_t>(plan.shape, st, P, ldp, Q, ldq, C, ldc, M, N, K,
                      plan.splits, split_stride, gate, gate_run, nullptr);
+}
+
+void gemm_group_tiles(GemmGroupDesc* d, int count, int* total_tiles) {
+  int t = 0;
+  for (int q = 0; q < count; ++q) {
+    d[q].tiles_m = (int32_t)ceil_div((int64_t)d[q].M, (int64_t)kGroupBM);
+    const int tiles_n = (int)ceil_div((int64_t)d[q].N, (int64_t)kGroupBN);
+    const int kslabs = (int)ceil_div((int64_t)d[q].K, (int64_t)kChunks * 4);
+    if (d[q].splits < 1) d[q].splits = 1;
+    d[q].kslabs_per_split = (int32_t)ceil_div((int64_t)kslabs, (int64_t)d[q].splits);
+    d[q].tile0 = t;
+    t += d[q].tiles_m * tiles_n * d[q].splits;
+  }
+  *total_tiles = t;
+}
+
+void gemm_nt_f32_group(hipStream_t st, const GemmGroupDesc* d_dev, int count, int total_tiles,
+                       const int32_t* running) {
+  if (count <= 0 || total_tiles <= 0) return;
+  static_assert(kGroupBM == 64 && kGroupBN == 128, "group tile shape");
+  hipLaunchKernelGGL((gemm_group_kernel<64, 128, 2, 2>), dim3((unsigned)total_tiles),
+                     dim3(4 * kWave), 0, st, d_dev, count, running);
 }
 
 }  // namespace spca

@@ -464,6 +464,80 @@ __global__ __launch_bounds__(256) void y_update_kernel(
   }
 }
 
+// Grouped solves: y_update_kernel with the variance type and the partial
+// count taken per start from its request.
+__global__ __launch_bounds__(256) void group_y_update_kernel(
+    const float* __restrict__ U, int64_t split_stride, float* __restrict__ Y,
+    int64_t ldu, int64_t n, StartState s) {
+  __shared__ double red[8];
+  const int64_t j = blockIdx.x;
+  if (s.status[j] != kRunning) return;
+  const int splits = s.cfg[j].splits;
+  const bool l1 = s.cfg[j].l1 != 0;
+  const float* u = U + j * ldu;
+  float* y = Y + j * ldu;
+  double sq = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 256) {
+    float t = u[i];
+    for (int sp = 1; sp < splits; ++sp) t += u[i + sp * split_stride];
+    y[i] = t;
+    double td = t;
+    sq += td * td;
+  }
+  sq = block_sum(sq, red);
+  if (sq == 0.0) {
+    if (threadIdx.x == 0) s.status[j] = SPCA_DEGENERATE;
+    return;
+  }
+  const double inv = 1.0 / sqrt(sq);
+  for (int64_t i = threadIdx.x; i < n; i += 256) {
+    const float t = y[i];
+    y[i] = l1 ? (float)((t > 0.f) - (t < 0.f)) : (float)((double)t * inv);
+  }
+}
+
+// Grouped solves: one block per start sums its A^T y partials in order.
+__global__ __launch_bounds__(256) void group_sum_splits_kernel(float* __restrict__ V,
+                                                               int64_t stride, int64_t ldv,
+                                                               int64_t p, StartState s) {
+  const int64_t j = blockIdx.x;
+  if (s.status[j] != kRunning) return;
+  const int splits = s.cfg[j].aty_splits;
+  if (splits <= 1) return;
+  float* v = V + j * ldv;
+  for (int64_t i = threadIdx.x; i < p; i += 256) {
+    float a = v[i];
+    for (int sp = 1; sp < splits; ++sp) a += v[sp * stride + i];
+    v[i] = a;
+  }
+}
+
+// Running starts per request and in total; one block of 16 waves, a wave
+// per request at a time.
+__global__ __launch_bounds__(1024) void group_count_kernel(const int32_t* __restrict__ status,
+                                                           const int64_t* __restrict__ first,
+                                                           int count,
+                                                           int32_t* __restrict__ running) {
+  __shared__ int32_t tot[16];
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  int32_t mine = 0;
+  for (int q = wave; q < count; q += 16) {
+    int32_t c = 0;
+    for (int64_t j = first[q] + lane; j < first[q + 1]; j += kWave) c += status[j] == kRunning;
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) c += __shfl_xor(c, o);
+    if (lane == 0) running[q] = c;
+    mine += c;
+  }
+  if (lane == 0) tot[wave] = mine;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int32_t t = 0;
+    for (int w = 0; w < 16; ++w) t += tot[w];
+    running[count] = t;
+  }
+}
+
 // Sparse A x (x given by its list) fused with the y-update; one block per
 // start.  Thread t owns groups of 4 consecutive rows (one 16-byte load per
 // list entry and group), so a column of A is read with 16-byte loads; list
@@ -796,6 +870,24 @@ void y_update(hipStream_t st, int fid, const float* U, int64_t split_stride,
   else
     hipLaunchKernelGGL(y_update_kernel<false>, dim3((unsigned)r), dim3(256), 0,
                        st, U, split_stride, Y, ldu, n, s, plan, Yb, ldyb);
+}
+
+void group_y_update(hipStream_t st, const float* U, int64_t split_stride, float* Y,
+                    int64_t ldu, int64_t r, int64_t n, StartState s) {
+  hipLaunchKernelGGL(group_y_update_kernel, dim3((unsigned)r), dim3(256), 0, st, U,
+                     split_stride, Y, ldu, n, s);
+}
+
+void group_sum_splits(hipStream_t st, float* V, int64_t split_stride, int64_t ldv,
+                      int64_t r, int64_t p, StartState s) {
+  hipLaunchKernelGGL(group_sum_splits_kernel, dim3((unsigned)r), dim3(256), 0, st, V,
+                     split_stride, ldv, p, s);
+}
+
+void group_count(hipStream_t st, const int32_t* status, const int64_t* first, int count,
+                 int32_t* running) {
+  hipLaunchKernelGGL(group_count_kernel, dim3(1), dim3(1024), 0, st, status, first, count,
+                     running);
 }
 
 void to_bf16_colmajor(hipStream_t st, const float* A, int64_t lda, int64_t n,

@@ -18,6 +18,18 @@ inline XKind xkind_of(int fid) {
 }
 inline bool l1_variance(int fid) { return fid % 2 == 0; }
 
+// Per-start settings of a grouped solve (starts of several requests in one
+// set of launches): the request's operator, parameter and stop rule.
+struct RowCfg {
+  double param;    // s or gamma of the start's request
+  double tol;      // its stop tolerance (< 0: off)
+  int32_t maxit;   // its iteration limit
+  int32_t kind;    // XKind of its formulation
+  int32_t l1;      // 1: L1 variance (y = sgn u), 0: L2 (y = u / ||u||)
+  int32_t splits;  // K partials of its A x product that the y-update sums
+  int32_t aty_splits;  // K partials of its A^T y product
+};
+
 // Per-start iteration state, device arrays of length r.
 struct StartState {
   double* phi;       // phi after the last x-update (Table 3 optimum)
@@ -32,6 +44,10 @@ struct StartState {
   // per start, set by the candidate x-update: 1 when the row still needs
   // the full selection kernel, 0 when it was settled.  Null: every row.
   int32_t* redo = nullptr;
+  // grouped solves: per-start settings; the x-update kernels then take
+  // param, tol and maxit from here and skip the starts of other operator
+  // kinds.  Null: the launch arguments hold for every start.
+  const RowCfg* cfg = nullptr;
 };
 
 // How the next product A x is formed (chosen on the device by the planner):
@@ -151,6 +167,27 @@ void gemm_nt_bf16(hipStream_t st, const uint16_t* P, int64_t ldp,
                   int64_t M, int64_t N, int64_t K, const int32_t* gate,
                   int32_t gate_run, GemmPlan plan, int64_t split_stride);
 
+// Grouped products (requests sharing one launch): product q computes
+// C = P * Q^T (M x N x K, leading dimensions ldp, ldq, ldc) with its own K
+// split, split partials split_stride floats apart; req is the request it
+// belongs to.  tiles_m, kslabs_per_split and tile0 are filled in by
+// gemm_group_tiles, which also returns the launch's tile count.
+struct GemmGroupDesc {
+  const float* P;
+  const float* Q;
+  float* C;
+  int64_t ldp, ldq, ldc, split_stride;
+  int32_t M, N, K, splits, req;
+  int32_t tiles_m, kslabs_per_split, tile0;
+};
+constexpr int kGroupBM = 64;   // tile of the grouped products
+constexpr int kGroupBN = 128;
+void gemm_group_tiles(GemmGroupDesc* d, int count, int* total_tiles);
+// the products of d_dev (device copy of gemm_group_tiles' output); products
+// of requests with running[req] == 0 are skipped (running may be null)
+void gemm_nt_f32_group(hipStream_t st, const GemmGroupDesc* d_dev, int count, int total_tiles,
+                       const int32_t* running);
+
 // Row-major copy: At[i * ldat + k] = A[i + k * lda] (i < n, k < p).
 void transpose_f32(hipStream_t st, const float* A, int64_t lda, float* At,
                    int64_t ldat, int64_t n, int64_t p);
@@ -236,6 +273,19 @@ void sum_splits(hipStream_t st, float* V, int64_t stride, int splits, int64_t co
 void y_update(hipStream_t st, int fid, const float* U, int64_t split_stride,
               float* Y, int64_t ldu, int64_t r, int64_t n, StartState s,
               const Plan* plan, uint16_t* Yb = nullptr, int64_t ldyb = 0);
+
+// Grouped solves (s.cfg set): the y-update of every running start, with the
+// variance type and the A x partial count of its request; the A^T y
+// partials of every running start summed in split order into the first
+// (split_stride floats apart, cfg.aty_splits of them, rows of p entries);
+// and the running starts of each request (rows first[q] .. first[q+1]) into
+// running[q], their total into running[count].
+void group_y_update(hipStream_t st, const float* U, int64_t split_stride, float* Y,
+                    int64_t ldu, int64_t r, int64_t n, StartState s);
+void group_sum_splits(hipStream_t st, float* V, int64_t split_stride, int64_t ldv,
+                      int64_t r, int64_t p, StartState s);
+void group_count(hipStream_t st, const int32_t* status, const int64_t* first, int count,
+                 int32_t* running);
 
 // Sparse A x from the lists followed by the y-update, one block per start.
 // Runs only in list mode.

@@ -21,6 +21,7 @@
 
 #include "../../include/spca.h"
 #include "common.hpp"
+#include "context.hpp"
 #include "kernels.hpp"
 
 namespace spca {
@@ -63,8 +64,6 @@ inline int list_cap_of(int64_t p) {
 
 constexpr int kMaxSplits = 16;  // K splits of the dense A x product
 constexpr int kTimeSample = 8;  // SPCA_FLAG_TIME_SAMPLED: events every 8th iteration
-constexpr int kPolishMax = 32;      // starts polished in FP32 (BF16 mode)
-constexpr double kPolishBand = 2e-3;  // relative band of polished starts
 
 struct Layout {
   int64_t n, p, r;
@@ -122,7 +121,7 @@ Layout make_layout(int64_t n, int64_t p, int64_t r, bool copy_a, bool bf16) {
   L.off_Atb = carve(&c, bf16 ? sizeof(uint16_t) * (size_t)n * L.ldatb : 0);
   L.off_Yb = carve(&c, bf16 ? sizeof(uint16_t) * (size_t)r * L.ldyb : 0);
   L.off_Xb = carve(&c, bf16 ? sizeof(uint16_t) * (size_t)r * L.ldxb : 0);
-  L.off_Xp = carve(&c, bf16 ? sizeof(float) * (size_t)kPolishMax * p : 0);
+  L.off_Xp = carve(&c, bf16 ? sizeof(float) * (size_t)r * p : 0);
 
   L.off_Ac = carve(&c, copy_a ? sizeof(float) * (size_t)p * L.ldac : 0);
   L.off_X = carve(&c, sizeof(float) * (size_t)r * L.ldx);
@@ -200,67 +199,8 @@ Otf carve_otf(char* base, int64_t r, int64_t p, int64_t l) {
   return o;
 }
 
-struct DeviceGuard {
-  int prev = -1;
-  explicit DeviceGuard(int dev) {
-    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-    if (prev != dev) (void)hipSetDevice(dev);
-  }
-  ~DeviceGuard() {
-    int cur = -1;
-    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev)
-      (void)hipSetDevice(prev);
-  }
-};
-
 }  // namespace
 }  // namespace spca
-
-// Pool of HIP events recorded in begin/end pairs around selected launches.
-struct EventPairs {
-  std::vector<hipEvent_t> ev;
-  size_t used = 0;
-  hipError_t mark(hipStream_t st) {
-    if (used == ev.size()) {
-      hipEvent_t e;
-      hipError_t rc = hipEventCreate(&e);
-      if (rc != hipSuccess) return rc;
-      ev.push_back(e);
-    }
-    return hipEventRecord(ev[used++], st);
-  }
-  // sum of (end - begin) over the recorded pairs, in ms
-  hipError_t total_ms(double* ms) {
-    double t = 0.0;
-    for (size_t i = 0; i + 1 < used; i += 2) {
-      float x = 0.f;
-      hipError_t rc = hipEventElapsedTime(&x, ev[i], ev[i + 1]);
-      if (rc != hipSuccess) return rc;
-      t += x;
-    }
-    *ms = t;
-    return hipSuccess;
-  }
-  void reset() { used = 0; }
-  void destroy() {
-    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
-    ev.clear();
-    used = 0;
-  }
-};
-
-struct spca_ctx {
-  int device = 0;
-  size_t budget = 0;
-  void* ws = nullptr;
-  size_t ws_cap = 0;
-  bool ws_external = false;  // ws belongs to the caller
-  int32_t* host_poll = nullptr;  // pinned
-  EventPairs t_aty, t_xup, t_ax;
-  spca_ctx* polish = nullptr;  // context of the FP32 polish sub-solves
-  hipStream_t capture = nullptr;  // stream that graphs are captured on
-  std::mutex mu;
-};
 
 static int ensure_capture_stream(spca_ctx* ctx) {
   if (ctx->capture == nullptr)
@@ -363,18 +303,61 @@ static int components_loop(spca_ctx* ctx, void* stream, const Prob* prob,
   return rc;
 }
 
+int ensure_workspace(spca_ctx* ctx, hipStream_t st, size_t bytes) {
+  if (ctx->budget != 0 && bytes > ctx->budget) {
+    set_error("workspace of " + std::to_string(bytes) +
+              " bytes exceeds the context budget of " +
+              std::to_string(ctx->budget));
+    return SPCA_ENOMEM;
+  }
+  if (bytes <= ctx->ws_cap) return SPCA_OK;
+  if (ctx->ws_external) {
+    set_error("workspace of " + std::to_string(bytes) +
+              " bytes exceeds the caller-provided " + std::to_string(ctx->ws_cap));
+    return SPCA_ENOMEM;
+  }
+  if (ctx->ws) {
+    SPCA_HIP_TRY(hipStreamSynchronize(st));
+    SPCA_HIP_TRY(hipFree(ctx->ws));
+    ctx->ws = nullptr;
+    ctx->ws_cap = 0;
+  }
+  hipError_t e = hipMalloc(&ctx->ws, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    set_error("hipMalloc of " + std::to_string(bytes) + " bytes: " +
+              hipGetErrorString(e));
+    return e == hipErrorOutOfMemory ? SPCA_ENOMEM : SPCA_EHIP;
+  }
+  ctx->ws_cap = bytes;
+  return SPCA_OK;
+}
+
+// The solve-wide warning from the final per-start statuses (spca_result
+// .warning): all starts degenerate, all ended with x = 0, or (with the stop
+// test on) none converged.
+int32_t solve_warning(const std::vector<int32_t>& st, int64_t l, double tol) {
+  int64_t deg = 0, zero = 0, conv = 0;
+  for (int64_t j = 0; j < l; ++j) {
+    deg += st[j] == SPCA_DEGENERATE;
+    zero += st[j] == SPCA_ZERO;
+    conv += st[j] == SPCA_CONVERGED;
+  }
+  if (l > 0 && deg == l) return SPCA_WARN_ALL_DEGENERATE;
+  if (l > 0 && deg + zero == l) return SPCA_WARN_ALL_ZERO;
+  if (tol >= 0.0 && conv == 0) return SPCA_WARN_NO_CONVERGED;
+  return SPCA_WARN_NONE;
+}
+
 extern "C" {
 
 const char* spca_last_error(void) { return spca::last_error(); }
 
 // Workspace of one solve: its layout, and for BF16 storage the layout of the
-// FP32 polish sub-solve after it (at most kPolishMax starts).
+// FP32 polish sub-solve of all r starts after it.
 static size_t solve_bytes(const Layout& L, int64_t n, int64_t p, int64_t r) {
   size_t b = L.total;
-  if (L.bf16) {
-    const int64_t rp = r < kPolishMax ? r : kPolishMax;
-    b = (size_t)round_up((int64_t)b, 256) + make_layout(n, p, rp, true, false).total;
-  }
+  if (L.bf16) b = (size_t)round_up((int64_t)b, 256) + make_layout(n, p, r, true, false).total;
   return b;
 }
 
@@ -442,49 +425,26 @@ int spca_ctx_destroy(spca_ctx* ctx) {
   return SPCA_OK;
 }
 
-static int ensure_workspace(spca_ctx* ctx, hipStream_t st, size_t bytes) {
-  if (ctx->budget != 0 && bytes > ctx->budget) {
-    set_error("workspace of " + std::to_string(bytes) +
-              " bytes exceeds the context budget of " +
-              std::to_string(ctx->budget));
-    return SPCA_ENOMEM;
-  }
-  if (bytes <= ctx->ws_cap) return SPCA_OK;
-  if (ctx->ws_external) {
-    set_error("workspace of " + std::to_string(bytes) +
-              " bytes exceeds the caller-provided " + std::to_string(ctx->ws_cap));
-    return SPCA_ENOMEM;
-  }
-  if (ctx->ws) {
-    SPCA_HIP_TRY(hipStreamSynchronize(st));
-    SPCA_HIP_TRY(hipFree(ctx->ws));
-    ctx->ws = nullptr;
-    ctx->ws_cap = 0;
-  }
-  hipError_t e = hipMalloc(&ctx->ws, bytes);
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    set_error("hipMalloc of " + std::to_string(bytes) + " bytes: " +
-              hipGetErrorString(e));
-    return e == hipErrorOutOfMemory ? SPCA_ENOMEM : SPCA_EHIP;
-  }
-  ctx->ws_cap = bytes;
-  return SPCA_OK;
-}
 
-// a7 polish: FP32 AM of the same formulation on the caller's FP32 A, run
-// as one batched solve from the BF16-phase iterates of the candidate starts
-// (rows of Xp), for at most polish_maxit iterations with the same stop
-// test.  Candidates are the starts whose BF16-phase objective lies within
-// the BF16 error band (2e-3 relative) of the best, since BF16 iterates
-// cannot rank starts closer than that.  Working on all of A (not only on
-// the BF16-phase supports) lets a column that BF16 rounding moved across a
-// selection threshold come back.  The best polished start replaces the
-// result when its FP64 objective does not decrease.
+// a7 polish: FP32 AM of the same formulation on the caller's FP32 A,
+// continued from the BF16-phase iterates, in two batched sub-solves with the
+// same stop test:
+//   1. every start, for at most kPolishRank iterations: BF16 rounding moves
+//      each trajectory by up to about 1e-3 relative, enough to reorder the
+//      starts' objectives, so the starts are ranked only after some FP32
+//      iterations;
+//   2. the kPolishKeep best starts of that ranking (FP64 objective), for the
+//      remaining polish_maxit - kPolishRank iterations.
+// Working on all of A lets a column that BF16 rounding moved across a
+// selection threshold come back.  The sub-solves' results (per start and
+// best) are the solve's results.
+constexpr int kPolishRank = 8;   // FP32 iterations of every start
+constexpr int kPolishKeep = 16;  // starts polished to the end
 
-static int polish_best(spca_ctx* ctx, hipStream_t st, const spca_problem* prob,
-                       const spca_solve_opts* opts, const float* Xp,
-                       int32_t nc, size_t ws_off, spca_outputs* out) {
+
+static int polish_subsolve(spca_ctx* ctx, hipStream_t st, const spca_problem* prob,
+                           const spca_solve_opts* opts, const float* Xp, int32_t r,
+                           int32_t maxit, size_t ws_off, spca_outputs* sub_out) {
   if (ctx->polish == nullptr) {
     int rc = spca_ctx_create(&ctx->polish, ctx->device, 0);
     if (rc != SPCA_OK) return rc;
@@ -496,26 +456,9 @@ static int polish_best(spca_ctx* ctx, hipStream_t st, const spca_problem* prob,
     if (rc != SPCA_OK) return rc;
   }
   spca_problem sub = *prob;
-  spca_solve_opts so{Xp, nc, opts->tol, opts->polish_maxit, SPCA_PREC_FP32, 0,
-                     opts->check_every, opts->flags};
-  std::vector<double> xsub(prob->p);
-  std::vector<int32_t> ssub(prob->p);
-  spca_result rsub{};
-  spca_outputs o{};
-  o.x = xsub.data();
-  o.support = ssub.data();
-  o.res = &rsub;
-  int rc = spca_am_solve_ex(ctx->polish, st, &sub, &so, &o);
-  if (rc != SPCA_OK) return rc;
-  spca_result* res = out->res;
-  if (!(rsub.objective >= res->objective_pre_polish)) return SPCA_OK;
-  res->objective = rsub.objective;
-  res->explained_var = rsub.explained_var;
-  res->nnz = rsub.nnz;
-  res->polish_iters = rsub.iters;
-  if (out->x) std::copy(xsub.begin(), xsub.end(), out->x);
-  if (out->support) std::copy(ssub.begin(), ssub.begin() + rsub.nnz, out->support);
-  return SPCA_OK;
+  spca_solve_opts so{Xp, r, opts->tol, maxit, SPCA_PREC_FP32, 0, opts->check_every,
+                     opts->flags & ~(SPCA_FLAG_AUTOTUNE | SPCA_FLAG_TIME_SAMPLED)};
+  return spca_am_solve_ex(ctx->polish, st, &sub, &so, sub_out);
 }
 
 int spca_am_solve_ex(spca_ctx* ctx, void* stream, const spca_problem* prob,
@@ -959,24 +902,114 @@ int spca_am_solve_ex(spca_ctx* ctx, void* stream, const spca_problem* prob,
   res->iters = it_all[jb];
   res->status = st_all[jb];
   if (bf16 && opts->polish_maxit > 0 && nnzb > 0) {
-    // candidates: best first, then by decreasing objective inside the band
-    std::vector<int32_t> order;
-    const double fb = f_all[jb];
-    const double floor_f = fb - kPolishBand * fabs(fb);
-    for (int64_t j = 0; j < r; ++j)
-      if (j != jb && nnz_all[j] > 0 && f_all[j] >= floor_f) order.push_back((int32_t)j);
-    std::stable_sort(order.begin(), order.end(),
-                     [&](int32_t a, int32_t b) { return f_all[a] > f_all[b]; });
-    order.insert(order.begin(), jb);
-    if ((int)order.size() > kPolishMax) order.resize(kPolishMax);
+    // 1. every start, kPolishRank FP32 iterations from its BF16-phase iterate
     float* Xp = (float*)(base + L.off_Xp);
-    for (size_t c = 0; c < order.size(); ++c)
-      SPCA_HIP_TRY(hipMemcpyAsync(Xp + c * p, X + (int64_t)order[c] * L.ldx,
-                                  sizeof(float) * p, hipMemcpyDeviceToDevice, st));
+    SPCA_HIP_TRY(hipMemcpy2DAsync(Xp, sizeof(float) * p, X, sizeof(float) * L.ldx,
+                                  sizeof(float) * p, r, hipMemcpyDeviceToDevice, st));
+    const size_t ws_off = (size_t)round_up((int64_t)L.total, 256);
+    const int32_t m1 = opts->polish_maxit < kPolishRank ? opts->polish_maxit : kPolishRank;
+    std::vector<double> pf(r), pev(r), pphi(r), xa(p);
+    std::vector<int32_t> pit(r), pst(r), pnnz(r), sa(p);
+    spca_result r1{};
+    spca_outputs so{};
+    so.x = xa.data();
+    so.support = sa.data();
+    so.res = &r1;
+    so.f_per_start = pf.data();
+    so.ev_per_start = pev.data();
+    so.phi_per_start = pphi.data();
+    so.iters_per_start = pit.data();
+    so.status_per_start = pst.data();
+    so.nnz_per_start = pnnz.data();
+    so.X_final = Xp;  // the ranked iterates, read again by the second sub-solve
     // the context lock is held, so the workspace stays valid meanwhile
-    rc = polish_best(ctx, st, prob, opts, Xp, (int32_t)order.size(),
-                     (size_t)round_up((int64_t)L.total, 256), out);
+    rc = polish_subsolve(ctx, st, prob, opts, Xp, (int32_t)r, m1, ws_off, &so);
     if (rc != SPCA_OK) return rc;
+    std::vector<int32_t> polish_it(r);
+    for (int64_t j = 0; j < r; ++j) {
+      f_all[j] = pf[j];
+      ev_all[j] = pev[j];
+      phi_all[j] = pphi[j];
+      polish_it[j] = pit[j];
+      st_all[j] = pst[j];
+      nnz_all[j] = pnnz[j];
+    }
+    double polish_work = r1.iters_x_starts;
+    // 2. the kPolishKeep best still-running starts of that ranking, to the end
+    std::vector<int32_t> keep;
+    if (opts->polish_maxit > m1) {
+      for (int64_t j = 0; j < r; ++j)
+        if (pst[j] == SPCA_MAXIT && pnnz[j] > 0) keep.push_back((int32_t)j);
+      std::stable_sort(keep.begin(), keep.end(),
+                       [&](int32_t a, int32_t b) { return pf[a] > pf[b]; });
+      if ((int)keep.size() > kPolishKeep) keep.resize(kPolishKeep);
+      std::sort(keep.begin(), keep.end());
+    }
+    // the result: stage 1's best, unless stage 2 improves on it
+    int32_t jbest = r1.best_start;
+    spca_result rb = r1;
+    const double* xbest = xa.data();
+    const int32_t* sbest = sa.data();
+    bool best_kept = false;
+    for (int32_t k : keep) best_kept = best_kept || k == jbest;
+    std::vector<double> xb(keep.empty() ? 0 : p);
+    std::vector<int32_t> sb(keep.empty() ? 0 : p);
+    if (!keep.empty()) {
+      // gather the kept rows to the front of Xp (ascending indices, so no
+      // source row is overwritten before it is read)
+      for (size_t c = 0; c < keep.size(); ++c)
+        if ((int32_t)c != keep[c])
+          SPCA_HIP_TRY(hipMemcpyAsync(Xp + c * p, Xp + (int64_t)keep[c] * p,
+                                      sizeof(float) * p, hipMemcpyDeviceToDevice, st));
+      const int32_t mk = (int32_t)keep.size();
+      std::vector<double> qf(mk), qev(mk), qphi(mk);
+      std::vector<int32_t> qit(mk), qst(mk), qnnz(mk);
+      spca_result r2{};
+      spca_outputs o2{};
+      o2.x = xb.data();
+      o2.support = sb.data();
+      o2.res = &r2;
+      o2.f_per_start = qf.data();
+      o2.ev_per_start = qev.data();
+      o2.phi_per_start = qphi.data();
+      o2.iters_per_start = qit.data();
+      o2.status_per_start = qst.data();
+      o2.nnz_per_start = qnnz.data();
+      rc = polish_subsolve(ctx, st, prob, opts, Xp, mk, opts->polish_maxit - m1, ws_off, &o2);
+      if (rc != SPCA_OK) return rc;
+      for (int32_t c = 0; c < mk; ++c) {
+        const int32_t j = keep[c];
+        f_all[j] = qf[c];
+        ev_all[j] = qev[c];
+        phi_all[j] = qphi[c];
+        polish_it[j] += qit[c];
+        st_all[j] = qst[c];
+        nnz_all[j] = qnnz[c];
+      }
+      polish_work += r2.iters_x_starts;
+      const int32_t jb2 = keep[r2.best_start];
+      // stage 1's best stands only if it was not continued and is not
+      // beaten (ties to the lower start index)
+      if (best_kept || r2.objective > rb.objective ||
+          (r2.objective == rb.objective && jb2 < jbest)) {
+        jbest = jb2;
+        rb = r2;
+        xbest = xb.data();
+        sbest = sb.data();
+      }
+    }
+    res->objective = rb.objective;
+    res->explained_var = rb.explained_var;
+    res->phi = rb.phi;
+    res->iters_x_starts = total_iters + polish_work;
+    res->best_start = jbest;
+    res->nnz = rb.nnz;
+    res->iters = it_all[jbest] + polish_it[jbest];
+    res->status = rb.status;
+    res->polish_iters = polish_it[jbest];
+    for (int64_t j = 0; j < r; ++j) it_all[j] += polish_it[j];
+    if (out->x) std::copy(xbest, xbest + p, out->x);
+    if (out->support) std::copy(sbest, sbest + rb.nnz, out->support);
   }
   for (int64_t j = 0; j < l; ++j) {
     if (out->f_per_start) out->f_per_start[j] = f_all[j];
@@ -986,6 +1019,7 @@ int spca_am_solve_ex(spca_ctx* ctx, void* stream, const spca_problem* prob,
     if (out->status_per_start) out->status_per_start[j] = st_all[j];
     if (out->nnz_per_start) out->nnz_per_start[j] = nnz_all[j];
   }
+  out->res->warning = solve_warning(st_all, l, opts->tol);
   return SPCA_OK;
 }
 
@@ -1340,6 +1374,7 @@ int spca_am_solve_sparse(spca_ctx* ctx, void* stream, const spca_sparse_problem*
     if (out->status_per_start) out->status_per_start[j] = st_all[j];
     if (out->nnz_per_start) out->nnz_per_start[j] = nnz_all[j];
   }
+  out->res->warning = solve_warning(st_all, r, opts->tol);
   return SPCA_OK;
 }
 

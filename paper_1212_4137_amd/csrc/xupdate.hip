@@ -189,6 +189,12 @@ __global__ __launch_bounds__(kXT) void x_update_kernel(
   const int64_t j = blockIdx.x;
   const bool full = s.status != nullptr;
   if (full && s.status[j] != kRunning) return;
+  if (s.cfg != nullptr) {  // grouped solve: this start's request
+    if (s.cfg[j].kind != KIND) return;
+    param = s.cfg[j].param;
+    tol = s.cfg[j].tol;
+    maxit = s.cfg[j].maxit;
+  }
   const int tid = threadIdx.x;
   const int lane = tid % kWave;
   const float* vg = V + j * ldv;
@@ -716,6 +722,12 @@ __global__ __launch_bounds__(kRT, (KIND == kTopS || WARM) ? 2 : 4) void x_update
   const int64_t j = blockIdx.x;
   const bool full = s.status != nullptr;
   if (full && s.status[j] != kRunning) return;
+  if (s.cfg != nullptr) {  // grouped solve: this start's request
+    if (s.cfg[j].kind != KIND) return;
+    param = s.cfg[j].param;
+    tol = s.cfg[j].tol;
+    maxit = s.cfg[j].maxit;
+  }
   // after the candidate kernel: only the rows it could not settle
   if (s.redo != nullptr && s.redo[j] == 0) return;
   const int tid = threadIdx.x;
@@ -1278,6 +1290,12 @@ __global__ __launch_bounds__(kRT, 4) void x_update_cand_kernel(
   __shared__ CSmem sm;
   const int64_t j = blockIdx.x;
   if (s.status[j] != kRunning) return;
+  if (s.cfg != nullptr) {  // grouped solve: this start's request
+    if (s.cfg[j].kind != KIND) return;
+    param = s.cfg[j].param;
+    tol = s.cfg[j].tol;
+    maxit = s.cfg[j].maxit;
+  }
   const int tid = threadIdx.x;
   const uint32_t t0 = key_of(s.thr[j] * kGuessLow);
   if (t0 == 0u) {  // no guess yet

@@ -26,6 +26,22 @@ def test_header_declares_the_binding_names():
     assert sorted(_declared()) == sorted(_lib.EXPORTED)
 
 
+def test_header_constants_match_the_binding():
+    """Status, warning, precision and flag values: the binding's constants are
+    the header's #defines."""
+    defs = dict(re.findall(r"#define\s+SPCA_([A-Z0-9_]+)\s+\(?(-?\d+)", open(HEADER).read()))
+    names = {"CONVERGED": "CONVERGED", "MAXIT": "MAXIT", "DEGENERATE": "DEGENERATE",
+             "ZERO": "ZERO", "WARN_NONE": "WARN_NONE",
+             "WARN_ALL_DEGENERATE": "WARN_ALL_DEGENERATE", "WARN_ALL_ZERO": "WARN_ALL_ZERO",
+             "WARN_NO_CONVERGED": "WARN_NO_CONVERGED", "PREC_FP32": "PREC_FP32",
+             "PREC_BF16_POLISH": "PREC_BF16_POLISH", "FLAG_TIME_SAMPLED": "FLAG_TIME_SAMPLED",
+             "FLAG_GRAPH": "FLAG_GRAPH", "FLAG_AUTOTUNE": "FLAG_AUTOTUNE",
+             "GROUP_MAX_REQUESTS": "GROUP_MAX_REQUESTS", "GROUP_MAX_P": "GROUP_MAX_P",
+             "GROUP_MAX_STARTS": "GROUP_MAX_STARTS"}
+    for h, b in names.items():
+        assert int(defs[h]) == getattr(spca, b), h
+
+
 def test_library_exports_every_declared_symbol():
     out = subprocess.run(["nm", "-D", "--defined-only", spca.LIB_PATH],
                          capture_output=True, text=True, check=True).stdout
@@ -67,6 +83,56 @@ def test_argument_validation(kw, msg):
     rc, err = _solve(**kw)
     assert rc == _lib.SPCA_EINVAL
     assert msg in err
+
+
+def _group(reqs, count=None):
+    """spca_am_solve_group on fake device pointers (validation only)."""
+    count = len(reqs) if count is None else count
+    probs = (_lib.Problem * max(len(reqs), 1))()
+    opts = (_lib.SolveOpts * max(len(reqs), 1))()
+    for q, kw in enumerate(reqs):
+        a = dict(A=FAKE.value, n=10, p=20, lda=12, fid=1, sg=3.0, X0=FAKE.value, r=2, tol=1e-6,
+                 maxit=10, precision=0, check_every=8, total=0, warm=0)
+        a.update(kw)
+        probs[q] = _lib.Problem(a["A"], a["n"], a["p"], a["lda"], a["fid"], a["sg"])
+        opts[q] = _lib.SolveOpts(a["X0"], a["r"], a["tol"], a["maxit"], a["precision"], 0,
+                                 a["check_every"], 0, a["total"], a["warm"], 0)
+    outs = (_lib.Outputs * max(len(reqs), 1))()
+    lib = spca.load()
+    rc = lib.spca_am_solve_group(None, None, count, probs, opts, outs)
+    return rc, lib.spca_last_error().decode()
+
+
+@pytest.mark.parametrize("bad,msg", [
+    (dict(p=12289, lda=12, sg=3.0), "SPCA_GROUP_MAX_P"), (dict(precision=1), "FP32"),
+    (dict(total=5), "replacement"), (dict(warm=2, fid=3), "warm-up"),
+    (dict(X0=None), "X0 may be NULL"), (dict(fid=9), "formulation"),
+    (dict(check_every=0), "check_every"), (dict(A=None), "A must not be NULL"),
+])
+def test_group_argument_validation(bad, msg):
+    """Each request of a group is checked, and the message names it."""
+    rc, err = _group([{}, bad])
+    assert rc == _lib.SPCA_EINVAL
+    assert msg in err and "(request 1)" in err
+
+
+def test_group_count_and_start_limits():
+    rc, err = _group([{}], count=0)
+    assert rc == _lib.SPCA_EINVAL and "count" in err
+    rc, err = _group([dict(r=40000), dict(r=30000)])
+    assert rc == _lib.SPCA_EINVAL and "SPCA_GROUP_MAX_STARTS" in err
+    # well-formed requests pass the checks and fail only on the missing
+    # context (no device work is reached)
+    rc, err = _group([{}, dict(fid=8, sg=0.5, p=12288, lda=12)])
+    assert rc == _lib.SPCA_EINVAL and "ctx" in err
+    lib = spca.load()
+    probs = (_lib.Problem * 2)(_lib.Problem(FAKE.value, 10, 20, 12, 1, 3.0),
+                               _lib.Problem(FAKE.value, 30, 100, 32, 5, 0.1))
+    opts = (_lib.SolveOpts * 2)(_lib.SolveOpts(FAKE.value, 2, 1e-6, 10, 0, 0, 8, 0, 0, 0, 0),
+                                _lib.SolveOpts(FAKE.value, 5, 1e-6, 10, 0, 0, 8, 0, 0, 0, 0))
+    b2 = lib.spca_group_workspace_bytes(2, probs, opts)
+    b1 = lib.spca_group_workspace_bytes(1, probs, opts)
+    assert b2 > b1 > 0
 
 
 def test_gemm_argument_validation():

@@ -43,9 +43,9 @@ SPECS = [(0, 120, 1500, 1, 16, "fp32"), (1, 300, 2000, 2, 64, "fp32"),
          (8, 180, 2500, 4, 16, "bf16"), (9, 260, 1800, 1, 64, "bf16")]
 
 
-def _run(spca, specs, workers, one_at_a_time, arena=2 << 30):
+def _run(spca, specs, workers, one_at_a_time, arena=2 << 30, group_limit=None):
     out = {}
-    with spca.Server(arena, workers=workers) as srv:
+    with spca.Server(arena, workers=workers, group_limit=group_limit) as srv:
         ids = {}
         for k, sp in enumerate(specs):
             ids[srv.submit(sp)] = k
@@ -81,6 +81,27 @@ def test_alone_and_in_the_mix_are_identical(spca):
         assert a["iters"] == m["iters"] and a["best_start"] == m["best_start"]
         assert np.array_equal(a["support"], m["support"])
         assert np.array_equal(a["x"], m["x"])
+
+
+def test_small_requests_are_served_in_groups(spca):
+    """Small FP32 requests queued together share one grouped solve (one
+    worker, several requests running at once); each result is bit-identical
+    to the request served alone, and close to its ungrouped solve."""
+    specs = [_spec(90 + k, 150 + 20 * k, 1000 + 400 * k, 1 + k % 8, 16, "fp32")
+             for k in range(10)]
+    grouped, stats = _run(spca, specs, workers=1, one_at_a_time=False)
+    assert stats["peak_running"] >= 2, stats
+    alone, stats1 = _run(spca, specs, workers=1, one_at_a_time=True, group_limit=1)
+    assert stats1["peak_running"] == 1
+    plain, _ = _run(spca, specs, workers=1, one_at_a_time=True, group_limit=0)
+    for k in range(len(specs)):
+        g, a, c = grouped[k], alone[k], plain[k]
+        print("request", k, g["objective"], a["objective"], c["objective"], flush=True)
+        assert g["rc"] == 0 and a["rc"] == 0 and c["rc"] == 0
+        assert g["objective"] == a["objective"] and np.array_equal(g["x"], a["x"])
+        assert g["iters"] == a["iters"] and g["best_start"] == a["best_start"]
+        # the ungrouped solve differs only in the order of the sums
+        assert abs(g["objective"] - c["objective"]) <= 1e-4 * abs(c["objective"])
 
 
 @pytest.mark.parametrize("fid", [1, 4, 6, 7])

@@ -174,15 +174,26 @@ def test_degenerate_and_zero_starts(spca):
     assert got["f_per_start"][0] == 0.0 and got["iters_per_start"][0] == 0
     ref = oracle.am_multi(A_np, 1, 3, X0, 1e-9, 50)
     assert rel_err(got["objective"], ref["f"][ref["best"]]) <= 1e-5
-    # gamma above the zero-solution threshold: every start ends ZERO
+    assert got["warning"] == spca.WARN_NONE  # the others converged
+    # the same with one x-update: no start can meet the stop test
+    got = spca.am_solve(A, 1, 3, to_device_rows(X0), tol=1e-9, maxit=1)
+    assert got["warning"] == spca.WARN_NO_CONVERGED
+    got = spca.am_solve(A, 1, 3, to_device_rows(X0), tol=-1.0, maxit=1)
+    assert got["warning"] == spca.WARN_NONE  # stop test off: no warning
+    # gamma above the zero-solution threshold: every start ends ZERO (one
+    # DEGENERATE start among them)
     thr = float(np.max(np.linalg.norm(A_np.astype(np.float64), axis=0)))
     got = spca.am_solve(A, 7, thr * 1.01, to_device_rows(X0[1:]), tol=1e-9, maxit=50)
     assert np.all(got["status_per_start"] == spca.ZERO)
     assert got["objective"] == 0.0 and got["nnz"] == 0 and not np.any(got["x"])
+    assert got["warning"] == spca.WARN_ALL_ZERO
+    got = spca.am_solve(A, 7, thr * 1.01, to_device_rows(X0), tol=1e-9, maxit=50)
+    assert got["warning"] == spca.WARN_ALL_ZERO
     # an all-zero matrix: every start DEGENERATE
     got = spca.am_solve(to_device_colmajor(np.zeros((8, 9), np.float32)), 2, 2,
                         to_device_rows(np.ones((2, 9), np.float32)), tol=1e-9, maxit=5)
     assert np.all(got["status_per_start"] == spca.DEGENERATE)
+    assert got["warning"] == spca.WARN_ALL_DEGENERATE
 
 
 def test_check_finite_flag_rejects_nan(spca):
