@@ -1,14 +1,16 @@
 """BF16-storage path (A, X, Y operands in BF16, FP32 accumulation) with FP32
 polish on the final support and FP64 objective: kernel parity of the BF16
 product and solve parity against the FP64 oracle at the tolerances of the
-precision study (relative objective error <= 1e-3 before polish, <= 1e-5
-after)."""
+precision study: the BF16-phase best within 1e-3 of the oracle's best, and
+after the FP32 polish an FP64 stationary point no worse than the oracle's
+best by more than 1e-5 (a better stationary point is allowed), except at a
+documented near-tie of the oracle's own top stationary points."""
 import numpy as np
 import pytest
 
 import oracle
 import workloads
-from gpu_helpers import rel_err, to_device_colmajor, to_device_rows
+from gpu_helpers import fixed_point_certificate, rel_err, to_device_colmajor, to_device_rows
 
 pytestmark = pytest.mark.gpu
 
@@ -93,24 +95,29 @@ def test_bf16_polish_solve_matches_oracle(spca, fid):
                         maxit=200, precision=spca.PREC_BF16_POLISH, polish_maxit=200)
     ref = oracle.am_multi(A_np, fid, par, X0, 1e-8, 200, nthreads=8, want_x=False)
     f_ref = ref["f"][ref["best"]]
-    pre = rel_err(got["objective_pre_polish"], f_ref)
-    post = rel_err(got["objective"], f_ref)
+    scale = abs(f_ref)
+    # signed: positive when the GPU result is above the oracle's best
+    pre = (got["objective_pre_polish"] - f_ref) / scale
+    post = (got["objective"] - f_ref) / scale
     srt = np.sort(ref["f"])[::-1]
     gap = (srt[0] - srt[1]) / abs(srt[0]) if len(srt) > 1 else 1.0
-    print(f"F{fid}: pre-polish rel err {pre:.2e}, post-polish {post:.2e}, "
+    print(f"F{fid}: pre-polish rel gap {pre:+.2e}, post-polish {post:+.2e}, "
           f"polish iters {got['polish_iters']}, oracle top-2 gap {gap:.2e}", flush=True)
-    assert pre <= 1e-3
-    if gap >= 1e-3:
-        assert post <= 1e-5
-    else:
-        # Rugged landscape: the oracle's best stationary point is reached by
-        # few starts and the next ones lie within 1e-3, so BF16 rounding may
-        # steer every start elsewhere.  The result must then be an FP64 fixed
-        # point of Algorithm 2 and rank with the oracle's top decile.
-        cert = oracle.am_single(A_np, fid, par, got["x"], 1e-12, 50)
-        assert rel_err(cert["f"], got["objective"]) <= 1e-6
-        assert np.array_equal(np.flatnonzero(cert["x"]), np.flatnonzero(got["x"]))
-        assert got["objective"] >= np.quantile(ref["f"], 0.9) * (1 - 1e-9)
+    # before the polish: within BF16 resolution of the oracle's best
+    assert abs(pre) <= 1e-3
+    # the result is an FP64 stationary point of Algorithm 2
+    cert = fixed_point_certificate(A_np, fid, par, got["x"], got["objective"])
+    assert cert["ok"], cert
+    # after the polish: no worse than the oracle's best by more than 1e-5,
+    # except at a documented near-tie of the oracle's own stationary points
+    # (top-2 gap below the BF16 resolution 1e-3, where BF16 rounding can
+    # steer every start to the second one): then at least the oracle's
+    # second best
+    if post < -1e-5:
+        assert gap < 1e-3, (post, gap)
+        assert got["objective"] >= srt[1] * (1 - 1e-9), (got["objective"], srt[:3])
+        print(f"F{fid}: near-tie of the oracle's top stationary points (gap {gap:.2e}); "
+              f"the result lies between its best and second best", flush=True)
     # the returned vector is unit norm and its objective is the reported one
     x = got["x"]
     assert abs(np.linalg.norm(x) - 1.0) < 1e-12 or not x.any()
