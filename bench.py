@@ -18,6 +18,12 @@ step), the whole step against the FP32 MFMA bound of its algorithmic work
 (running starts and iterate nonzeros counted on the device), and the FP64
 CPU oracle's throughput on a bounded sample of the same workload.
 
+The default run adds, under "secondary", short runs of the other
+configurations (about two minutes in all): the BF16 + polish precision study
+at 5000 x 50000, the 16 GB instance at 20000 x 200000, and a 2000-request
+serving stream at 40 requests/s, batched against one request at a time
+(--no-secondary skips them; --workload selects one of them alone, in full).
+
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
 import argparse
@@ -729,6 +735,68 @@ def bench_sparse(args, spca, torch):
     }
 
 
+def bench_secondary(args, spca, torch):
+    """The other configurations, short, beside the headline line: the BF16 +
+    polish precision study (5000 x 50000, 2 steps), the 16 GB instance (2
+    steps of 30 iterations) and a 2000-request serving stream at a fixed
+    offered load, batched with mixed precision and the one-request-at-a-time
+    FP32 baseline.  A failing part records its error instead of ending the
+    run."""
+    import copy
+    import gc
+
+    out = {}
+
+    def part(name, fn):
+        t0 = time.monotonic()
+        try:
+            out[name] = fn()
+        except Exception as e:  # recorded, the headline line still prints
+            out[name] = {"error": f"{type(e).__name__}: {e}"}
+        out[name]["wall_s"] = round(time.monotonic() - t0, 1)
+        gc.collect()
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        print(json.dumps({name: out[name]})[:400], file=sys.stderr, flush=True)
+
+    a = copy.copy(args)
+    a.steps, a.warmup, a.maxit = 2, 1, 0
+
+    def precision():
+        r = bench_precision(a, spca, torch)
+        return {k: r[k] for k in ("metric", "value", "unit", "ms_per_step", "fp32_solves_per_s",
+                                  "speedup_vs_fp32", "signed_rel_gap_to_fp32_post_polish",
+                                  "signed_rel_gap_to_fp32_pre_polish", "post_polish_not_below_fp32",
+                                  "signed_rel_gap_to_fp64_oracle_best", "config")}
+
+    def large():
+        r = bench_large(a, spca, torch)
+        return {k: r[k] for k in ("metric", "value", "unit", "ms_per_step", "roofline", "config")}
+
+    def serve():
+        count, qps = args.serve_requests, args.serve_qps
+        seed = workloads.SEED_BASE + 5
+        arena = int(args.arena_gb * (1 << 30))
+        run_stream(spca, serve_requests(4, seed + 999, "mixed"), float("inf"), args.workers,
+                   arena, seed)
+        batched, _ = run_stream(spca, serve_requests(count, seed, "mixed"), qps, args.workers,
+                                arena, seed)
+        base, _ = run_stream(spca, serve_requests(count, seed, "fp32"), qps, 1, arena, seed, 0)
+        return {"metric": "solves/s with p50/p99 latency at a fixed offered load",
+                "requests": count, "offered_qps": qps,
+                "batched_mixed": batched, "one_at_a_time_fp32": base,
+                "speedup_solves_per_s": batched["solves_per_s"] / base["solves_per_s"],
+                "config": {"workload": f"serve-poisson-{count}req-{qps:g}qps",
+                           "n": "U[200,5000]", "p": "U[1000,50000]", "formulation": "U{1..8}",
+                           "r": [16, 64, 256], "precision": "50% fp32, 50% bf16+polish (batched); "
+                           "fp32 (baseline)", "workers": args.workers, "tol": 1e-6, "maxit": 200}}
+
+    part("precision", precision)
+    part("large", large)
+    part("serve", serve)
+    return out
+
+
 WORKLOADS = {"spiked-all8": bench_all8, "otf": bench_otf, "hunt": bench_hunt,
              "sparse": bench_sparse,
              "components": bench_components, "large": bench_large, "precision": bench_precision,
@@ -761,6 +829,12 @@ def main():
                     help="keep the planner off the union-of-supports product")
     ap.add_argument("--graph", action="store_true",
                     help="replay the iterations from a captured HIP graph")
+    ap.add_argument("--no-secondary", action="store_true",
+                    help="spiked-all8: skip the short runs of the other configurations")
+    ap.add_argument("--serve-requests", type=int, default=2000,
+                    help="secondary serving stream: requests")
+    ap.add_argument("--serve-qps", type=float, default=40.0,
+                    help="secondary serving stream: offered load (requests/s)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported: "
@@ -774,6 +848,8 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     args.flags = (spca.FLAG_GRAPH if args.graph else 0) | (spca.FLAG_NO_UNION if args.no_union else 0)
     rec = WORKLOADS[args.workload](args, spca, torch)
+    if args.workload == "spiked-all8" and not args.no_secondary and args.fids == "1,2,3,4,5,6,7,8":
+        rec["secondary"] = bench_secondary(args, spca, torch)
     print(json.dumps(rec), flush=True)
 
 
