@@ -457,7 +457,7 @@ static int polish_subsolve(spca_ctx* ctx, hipStream_t st, const spca_problem* pr
   }
   spca_problem sub = *prob;
   spca_solve_opts so{Xp, r, opts->tol, maxit, SPCA_PREC_FP32, 0, opts->check_every,
-                     opts->flags & ~(SPCA_FLAG_AUTOTUNE | SPCA_FLAG_TIME_SAMPLED)};
+                     opts->flags & ~SPCA_FLAG_TIME_SAMPLED};
   return spca_am_solve_ex(ctx->polish, st, &sub, &so, sub_out);
 }
 
