@@ -245,9 +245,13 @@ def bench_large(args, spca, torch):
     ctx = spca.Context(0)
     stream = torch.cuda.current_stream()
     res_last = {}
-    if args.autotune:
+    tuned = not args.no_autotune
+    if tuned:
+        # a8: the configuration asks for autotuned tiles: one short tuned
+        # solve fills the table for both products before the timed steps
         spca.am_solve(A, cfg["fid"], float(cfg["s"]), X0, tol=-1.0, maxit=2, ctx=ctx,
                       stream=stream, flags=args.flags | spca.FLAG_AUTOTUNE)
+    plans = {"aty": spca.gemm_plan(r, p, n, 16), "ax_dense": spca.gemm_plan(r, n, p, 16)}
 
     def step(timing):
         res = spca.am_solve(A, cfg["fid"], float(cfg["s"]), X0, tol=-1.0, maxit=maxit,
@@ -278,6 +282,7 @@ def bench_large(args, spca, torch):
                                                   kt["iters_union"])},
         "result": {"objective": res_last["objective"], "nnz": int(res_last["nnz"]),
                    "support_overlap_with_spikes": recovered},
+        "autotuned": tuned, "gemm_plans_shape_splits": plans,
     }
 
 
@@ -771,7 +776,9 @@ def bench_secondary(args, spca, torch):
 
     def large():
         r = bench_large(a, spca, torch)
-        return {k: r[k] for k in ("metric", "value", "unit", "ms_per_step", "roofline", "config")}
+        spca.tune_table_clear()  # its entries are for this instance's products only
+        return {k: r[k] for k in ("metric", "value", "unit", "ms_per_step", "roofline", "config",
+                                  "autotuned", "gemm_plans_shape_splits")}
 
     def serve():
         count, qps = args.serve_requests, args.serve_qps
@@ -824,7 +831,9 @@ def main():
     ap.add_argument("--workers", type=int, default=4, help="serve: concurrent solves")
     ap.add_argument("--arena-gb", type=float, default=64.0, help="serve: HBM arena")
     ap.add_argument("--autotune", action="store_true",
-                    help="time every tile shape and split first (spiked-all8, large)")
+                    help="spiked-all8: time every tile shape and split first")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="large: plan the tiles from the model instead of tuning them first")
     ap.add_argument("--no-union", action="store_true",
                     help="keep the planner off the union-of-supports product")
     ap.add_argument("--graph", action="store_true",
