@@ -89,9 +89,10 @@ typedef struct {
   int32_t nnz;           /* |support|                                       */
   int32_t iters;         /* x-updates done by the best start                */
   int32_t status;        /* SPCA_CONVERGED .. SPCA_ZERO of the best start   */
-  double objective_pre_polish; /* BF16 mode: the best f over the starts
-                                  before the FP32 polish (FP64, on the FP32
-                                  A); equal to objective otherwise          */
+  double objective_pre_polish; /* BF16 mode: f before the FP32 polish
+                                  (FP64, on the FP32 A) of the start whose
+                                  BF16-phase in-loop objective phi is the
+                                  largest; equal to objective otherwise     */
   int32_t polish_iters;  /* FP32 polish iterations of the best start (BF16) */
   int32_t warning;       /* SPCA_WARN_* over all starts of the solve        */
 } spca_result;

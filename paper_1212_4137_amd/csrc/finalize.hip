@@ -95,6 +95,10 @@ __global__ __launch_bounds__(kFT) void final_matvec_kernel(
 // B[l / 16][l % 16]; result element e of lane l: D[4 e + l / 16][l % 16]).
 // The columns advance 16 at a time through LDS, the next 16 already in
 // registers.  Partial pairs per (start, 64-row tile), summed in a fixed order.
+// With a column split (blockIdx.z of gridDim.z splits, pc columns each) the
+// workgroups write their part of u to upart[(z r + j) n + i] instead, and
+// final_pairs_kernel sums the splits in order before forming the pairs:
+// more workgroups than the (row, start) tiles alone give.
 typedef double double4_t __attribute__((ext_vector_type(4)));
 constexpr int kGT = 64;  // rows and starts per workgroup tile
 constexpr int kGK = 16;  // columns per stage
@@ -102,7 +106,8 @@ constexpr int kGK = 16;  // columns per stage
 __global__ __launch_bounds__(256) void final_gemm64_kernel(
     const float* __restrict__ A, int64_t lda, int64_t n, int64_t p,
     const float* __restrict__ X, int64_t ldx, StartState s, int64_t r,
-    const double* __restrict__ xnorm, double* partial, int ntiles, Defl defl) {
+    const double* __restrict__ xnorm, double* partial, int ntiles, Defl defl, int64_t pc,
+    double* __restrict__ upart) {
   __shared__ double sA[kGK][kGT];  // A[row][col] by column
   __shared__ double sB[kGK][kGT];  // Xs[col][start] by column
   __shared__ double scale[kGT];
@@ -125,13 +130,15 @@ __global__ __launch_bounds__(256) void final_gemm64_kernel(
   const int ar = tid % kGT, ac = 4 * (tid / kGT);
   const int xj = tid / 4, xc = 4 * (tid % 4);
   float pa[4], px[4];
+  const int64_t cbeg = (int64_t)blockIdx.z * pc;
+  const int64_t cend = cbeg + pc < p ? cbeg + pc : p;
   auto fetch = [&](int64_t c0) {
     const int64_t i = i0 + ar, j = j0 + xj;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const int64_t ca = c0 + ac + e, cx = c0 + xc + e;
-      pa[e] = (i < n && ca < p) ? A[i + ca * lda] : 0.f;
-      px[e] = (j < r && cx < p) ? X[j * ldx + cx] : 0.f;
+      pa[e] = (i < n && ca < cend) ? A[i + ca * lda] : 0.f;
+      px[e] = (j < r && cx < cend) ? X[j * ldx + cx] : 0.f;
     }
   };
   double4_t acc[2][2];
@@ -139,16 +146,16 @@ __global__ __launch_bounds__(256) void final_gemm64_kernel(
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = {0.0, 0.0, 0.0, 0.0};
-  fetch(0);
+  fetch(cbeg);
   __syncthreads();  // scale
-  for (int64_t c0 = 0; c0 < p; c0 += kGK) {
+  for (int64_t c0 = cbeg; c0 < cend; c0 += kGK) {
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       sA[ac + e][ar] = (double)pa[e];
       sB[xc + e][xj] = (double)px[e] * scale[xj];
     }
     __syncthreads();
-    if (c0 + kGK < p) fetch(c0 + kGK);
+    if (c0 + kGK < cend) fetch(c0 + kGK);
 #pragma unroll
     for (int k0 = 0; k0 < kGK; k0 += 4) {
       const int k = k0 + lane / 16, q = lane % 16;
@@ -167,6 +174,20 @@ __global__ __launch_bounds__(256) void final_gemm64_kernel(
   }
   // epilogue: lane holds rows wm 32 + a 16 + 4 e + lane / 16 of start
   // wn 32 + b 16 + lane % 16
+  if (gridDim.z > 1) {  // this split's part of u
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const int64_t j = j0 + wn * 32 + b * 16 + lane % 16;
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int64_t i = i0 + wm * 32 + a * 16 + 4 * e + lane / 16;
+          if (i < n && j < r) upart[((int64_t)blockIdx.z * r + j) * n + i] = acc[a][b][e];
+        }
+    }
+    return;
+  }
 #pragma unroll
   for (int b = 0; b < 2; ++b) {
     const int jl = wn * 32 + b * 16 + lane % 16;
@@ -199,6 +220,44 @@ __global__ __launch_bounds__(256) void final_gemm64_kernel(
       }
     partial[((j0 + tid) * ntiles + blockIdx.x) * 2] = sq;
     partial[((j0 + tid) * ntiles + blockIdx.x) * 2 + 1] = ab;
+  }
+}
+
+// The split parts of u summed in split order, the deflation correction,
+// then the partial pairs (sum u_i^2, sum |u_i|) of each (start, 64-row
+// tile): thread t sums rows 16 (t / 64) .. + 15 of start t % 64, and the
+// four row groups are added in order.
+__global__ __launch_bounds__(256) void final_pairs_kernel(const double* __restrict__ upart,
+                                                          int splits, int64_t n, int64_t r,
+                                                          double* partial, int ntiles,
+                                                          Defl defl) {
+  __shared__ double red[4][kGT][2];
+  const int tid = threadIdx.x, jl = tid % kGT, g = tid / kGT;
+  const int64_t i0 = (int64_t)blockIdx.x * kGT, j = (int64_t)blockIdx.y * kGT + jl;
+  double sq = 0.0, ab = 0.0;
+  if (j < r) {
+    for (int q = 0; q < kGT / 4; ++q) {
+      const int64_t i = i0 + 16 * g + q;
+      if (i >= n) break;
+      double u = 0.0;
+      for (int z = 0; z < splits; ++z) u += upart[((int64_t)z * r + j) * n + i];
+      if (defl.k > 0)
+        for (int l = 0; l < defl.k; ++l)
+          u -= defl.alpha[j * kMaxDefl + l] * defl.scores[i * kMaxDefl + l];
+      sq += u * u;
+      ab += fabs(u);
+    }
+  }
+  red[g][jl][0] = sq;
+  red[g][jl][1] = ab;
+  __syncthreads();
+  if (g == 0 && j < r) {
+    for (int h = 1; h < 4; ++h) {
+      sq += red[h][jl][0];
+      ab += red[h][jl][1];
+    }
+    partial[(j * ntiles + blockIdx.x) * 2] = sq;
+    partial[(j * ntiles + blockIdx.x) * 2 + 1] = ab;
   }
 }
 
@@ -327,23 +386,38 @@ void objective_and_best(hipStream_t st, int fid, double s_or_gamma, StartState s
                      list_idx, list_val, ldl, xnorm, best, x_out, support_out);
 }
 
+int final_gemm64_splits(int64_t n, int64_t p, int64_t r) {
+  const int64_t base = ceil_div(n, (int64_t)kGT) * ceil_div(r, (int64_t)kGT);
+  int sp = 1;
+  // at least 512 workgroups where the columns allow, each split at least
+  // 256 columns, and the parts of u (splits r n doubles) within r p floats
+  while (sp < 8 && base * sp < 512 && p / (2 * sp) >= 256 && 2 * sp * 2 * n <= p) sp *= 2;
+  return sp;
+}
+
 void finalize(hipStream_t st, int fid, double s_or_gamma, const float* A,
               int64_t lda, int64_t n, int64_t p, const int32_t* list_idx,
               const float* list_val, int64_t ldl, StartState s, int64_t r,
               double* partial, double* f, double* ev, double* xnorm,
               int32_t* best, double* x_out, int32_t* support_out,
               const double* gam, bool by_ev, Defl defl, const float* X_dense,
-              int64_t ldx) {
+              int64_t ldx, double* upart) {
   if (X_dense == nullptr) {
     evaluate_rows(st, fid, s_or_gamma, A, lda, n, list_idx, list_val, ldl, s, r,
                   partial, f, ev, xnorm, nullptr, gam, defl);
   } else {
     const int ntiles = (int)ceil_div(n, (int64_t)kGT);
+    const int rtiles = (int)ceil_div(r, (int64_t)kGT);
+    const int splits = upart != nullptr ? final_gemm64_splits(n, p, r) : 1;
+    const int64_t pc = round_up(ceil_div(p, (int64_t)splits), (int64_t)kGK);
     hipLaunchKernelGGL(x_norms_kernel, dim3((unsigned)r), dim3(256), 0, st, list_val, ldl, s,
                        r, xnorm, nullptr);
-    hipLaunchKernelGGL(final_gemm64_kernel,
-                       dim3((unsigned)ntiles, (unsigned)ceil_div(r, (int64_t)kGT)), dim3(256),
-                       0, st, A, lda, n, p, X_dense, ldx, s, r, xnorm, partial, ntiles, defl);
+    hipLaunchKernelGGL(final_gemm64_kernel, dim3((unsigned)ntiles, (unsigned)rtiles,
+                       (unsigned)splits), dim3(256), 0, st, A, lda, n, p, X_dense, ldx, s, r,
+                       xnorm, partial, ntiles, defl, pc, upart);
+    if (splits > 1)
+      hipLaunchKernelGGL(final_pairs_kernel, dim3((unsigned)ntiles, (unsigned)rtiles),
+                         dim3(256), 0, st, upart, splits, n, r, partial, ntiles, defl);
     hipLaunchKernelGGL(objective_kernel, dim3((unsigned)ceil_div(r, 256)), dim3(256), 0, st,
                        fid, s_or_gamma, s, r, partial, ntiles, xnorm, f, ev, nullptr, gam);
   }

@@ -340,7 +340,9 @@ int spca_am_solve_group(spca_ctx* ctx, void* stream, int32_t count, const spca_p
   }
 
   // a6 per request: lists of the final iterates, FP64 objective and
-  // explained variance, best start, output vector
+  // explained variance, best start, output vector (the FP64 product may
+  // split its columns over the V buffer: at most r p floats per request,
+  // and the requests' evaluations run one after another on the stream)
   compact_rows(st, X, ldx, R, L.p_max, li, lv, ldx, s.nnz, nullptr, nullptr, nullptr);
   std::vector<int32_t> nnz_h((size_t)R);
   SPCA_HIP_TRY(hipMemcpyAsync(nnz_h.data(), s.nnz, sizeof(int32_t) * (size_t)R,
@@ -358,7 +360,7 @@ int spca_am_solve_group(spca_ctx* ctx, void* stream, int32_t count, const spca_p
              lv + f0 * ldx, ldx, sq, r, (double*)(base + L.off_part[q]), fj + f0, evj + f0,
              xnorm + 2 * f0, best + 2 * q, (double*)(base + L.off_xout[q]),
              (int32_t*)(base + L.off_sup[q]), nullptr, false, Defl{},
-             dense_eval ? X + f0 * ldx : nullptr, ldx);
+             dense_eval ? X + f0 * ldx : nullptr, ldx, (double*)V);
   }
   SPCA_LAUNCH_CHECK("group finalize");
   std::vector<int32_t> hb(2 * (size_t)count), it_h((size_t)R), st_h((size_t)R);

@@ -351,14 +351,18 @@ bool x_update_wide(hipStream_t st, int fid, double s_or_gamma, const float* V,
 // by_ev: pick the best start by explained variance instead of f
 // X_dense (r x ldx FP32 iterates, the lists' dense twin): for mostly dense
 // iterates, U = A X^T in FP64 on the matrix cores (partial needs
-// 2 r ceil(n / 64) doubles) instead of per-start sums over the lists
+// 2 r ceil(n / 64) doubles) instead of per-start sums over the lists; with
+// upart (final_gemm64_splits(n, p, r) r n doubles, at most r p floats' worth)
+// that product is split over the columns for more workgroups
 void finalize(hipStream_t st, int fid, double s_or_gamma, const float* A,
               int64_t lda, int64_t n, int64_t p, const int32_t* list_idx,
               const float* list_val, int64_t ldl, StartState s, int64_t r,
               double* partial, double* f, double* ev, double* xnorm,
               int32_t* best, double* x_out, int32_t* support_out,
               const double* gam = nullptr, bool by_ev = false, Defl defl = Defl{},
-              const float* X_dense = nullptr, int64_t ldx = 0);
+              const float* X_dense = nullptr, int64_t ldx = 0, double* upart = nullptr);
+// column splits of that product: a function of the shape only
+int final_gemm64_splits(int64_t n, int64_t p, int64_t r);
 // The FP64 objective and explained variance of the rows with only[j] != 0
 // (the first three steps of finalize); other rows are left untouched.
 void evaluate_rows(hipStream_t st, int fid, double s_or_gamma, const float* A,

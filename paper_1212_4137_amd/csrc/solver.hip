@@ -814,24 +814,53 @@ int spca_am_solve_ex(spca_ctx* ctx, void* stream, const spca_problem* prob,
     otf_step(st, fid, sg, A, ldA, n, p, X, L.ldx, opts->X0, li, lv, L.ldx, s, r,
              partial, fj, evj, xnorm, o, 1);
     otf_output(st, o, p, best, xout, sup);
-  } else {
+  }
+  // the FP64 product of the evaluation may split its columns over the
+  // V buffer, free once the loop is done
+  double* upart = (double*)(base + L.off_V);
+  // BF16 + polish: the polish re-evaluates every start after its FP32
+  // iterations, so the BF16 phase's own result is needed for one start only
+  // (objective_pre_polish): the one with the largest in-loop objective phi
+  int32_t pre_best = -1;
+  if (!otf) {
     compact_rows(st, X, L.ldx, r, p, li, lv, L.ldx, s.nnz, nullptr, nullptr, nullptr);
     // under the penalty warm-up every start has its own gamma: f uses it,
     // and the best start is the one with the largest explained variance
     const bool per_start_gamma = warm && fid >= 5;
     if (dk > 0) deflate_final_alpha(st, X, L.ldx, p, r, defl);
-    // mostly dense iterates (a quarter of all entries or more): one FP64
-    // product on the matrix cores instead of per-start sums over the lists
-    std::vector<int32_t> nnz_h(r);
+    std::vector<int32_t> nnz_h(r), st_h(r);
+    std::vector<double> phi_h(r);
     SPCA_HIP_TRY(hipMemcpyAsync(nnz_h.data(), s.nnz, sizeof(int32_t) * r,
                                 hipMemcpyDeviceToHost, st));
+    SPCA_HIP_TRY(hipMemcpyAsync(st_h.data(), s.status, sizeof(int32_t) * r,
+                                hipMemcpyDeviceToHost, st));
+    SPCA_HIP_TRY(hipMemcpyAsync(phi_h.data(), s.phi, sizeof(double) * r,
+                                hipMemcpyDeviceToHost, st));
     SPCA_HIP_TRY(hipStreamSynchronize(st));
-    double tot_nnz = 0.0;
-    for (int64_t j = 0; j < r; ++j) tot_nnz += nnz_h[j];
-    const bool dense_eval = r >= 16 && tot_nnz * 4.0 >= (double)r * (double)p;
-    finalize(st, fid, sg, A, ldA, n, p, li, lv, L.ldx, s, r, partial, fj, evj,
-             xnorm, best, xout, sup, per_start_gamma ? gam : nullptr, per_start_gamma,
-             defl, dense_eval ? X : nullptr, L.ldx);
+    if (bf16 && opts->polish_maxit > 0) {
+      for (int64_t j = 0; j < r; ++j) {
+        const bool live = st_h[j] != SPCA_DEGENERATE && st_h[j] != SPCA_ZERO && nnz_h[j] > 0;
+        if (live && (pre_best < 0 || phi_h[j] > phi_h[pre_best])) pre_best = (int32_t)j;
+      }
+    }
+    if (pre_best >= 0) {
+      const int64_t jp = pre_best;
+      StartState s1{s.phi + jp, s.phi_prev + jp, s.nnz + jp, s.iters + jp, s.status + jp,
+                    s.thr + jp, s.redo + jp};
+      const bool dense1 = (double)nnz_h[jp] * 4.0 >= (double)p;
+      finalize(st, fid, sg, A, ldA, n, p, li + jp * L.ldx, lv + jp * L.ldx, L.ldx, s1, 1,
+               partial, fj + jp, evj + jp, xnorm, best, xout, sup, nullptr, false, defl,
+               dense1 ? X + jp * L.ldx : nullptr, L.ldx, upart);
+    } else {
+      // mostly dense iterates (a quarter of all entries or more): one FP64
+      // product on the matrix cores instead of per-start sums over the lists
+      double tot_nnz = 0.0;
+      for (int64_t j = 0; j < r; ++j) tot_nnz += nnz_h[j];
+      const bool dense_eval = r >= 16 && tot_nnz * 4.0 >= (double)r * (double)p;
+      finalize(st, fid, sg, A, ldA, n, p, li, lv, L.ldx, s, r, partial, fj, evj,
+               xnorm, best, xout, sup, per_start_gamma ? gam : nullptr, per_start_gamma,
+               defl, dense_eval ? X : nullptr, L.ldx, upart);
+    }
   }
   SPCA_LAUNCH_CHECK("finalize");
 
@@ -840,7 +869,7 @@ int spca_am_solve_ex(spca_ctx* ctx, void* stream, const spca_problem* prob,
   SPCA_HIP_TRY(hipMemcpyAsync(hb, best, sizeof(hb), hipMemcpyDeviceToHost, st));
   SPCA_HIP_TRY(hipMemcpyAsync(&hplan, plan, sizeof(Plan), hipMemcpyDeviceToHost, st));
   SPCA_HIP_TRY(hipStreamSynchronize(st));
-  const int32_t jb = hb[0], nnzb = hb[1];
+  const int32_t jb = pre_best >= 0 ? pre_best : hb[0], nnzb = hb[1];
   // per-start results: the slots themselves, or with replacement the
   // records of all l starts
   std::vector<double> f_all(l), ev_all(l), phi_all(l);
