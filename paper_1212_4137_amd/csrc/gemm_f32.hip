@@ -322,7 +322,10 @@ __global__ __launch_bounds__(WM* WN* kWave) void gemm_group_kernel(
 // MI355X (larger per-wave tiles reuse each LDS read for more MFMAs); eff16
 // the same for BF16 operands, where a tile's operand bytes per MFMA (global
 // and LDS) limit it long before the matrix cores do, so the largest tiles
-// win (measured on 256 x 50000 x 5000 and 256 x 5000 x 50000).
+// win (measured on 256 x 50000 x 5000 and 256 x 5000 x 50000); with one
+// workgroup per CU, 8 waves (two per SIMD) hide more of its load latency
+// than 4.  A shape with eff (eff16) 0 is never planned for FP32 (BF16) by
+// the model, only by the autotuner.
 struct Shape {
   int bm, bn, occ;
   double eff, eff16;
@@ -337,6 +340,8 @@ constexpr Shape kShapes[] = {
     {64, 256, 2, 0.85, 0.57},   // 1x4 waves of 64x64
     {256, 128, 1, 0.90, 0.85},  // 2x2 waves of 128x64
     {256, 256, 1, 0.90, 1.25},  // 2x2 waves of 128x128
+    {256, 256, 1, 0.0, 1.36},   // 2x4 waves of 128x64: BF16 only (2 waves per SIMD)
+    {256, 256, 1, 0.0, 0.0},    // 4x2 waves of 64x128: tuning candidate only
 };
 constexpr int kNumShapes = (int)(sizeof(kShapes) / sizeof(kShapes[0]));
 
@@ -386,8 +391,14 @@ void dispatch(int shape, hipStream_t st, const T* P, int64_t ldp,
     case 7:
       launch<T, 256, 128, 2, 2>(st, P, ldp, Q, ldq, C, ldc, M, N, K, splits, split_stride, gate, gate_run, kdev);
       break;
-    default:
+    case 8:
       launch<T, 256, 256, 2, 2>(st, P, ldp, Q, ldq, C, ldc, M, N, K, splits, split_stride, gate, gate_run, kdev);
+      break;
+    case 9:
+      launch<T, 256, 256, 2, 4>(st, P, ldp, Q, ldq, C, ldc, M, N, K, splits, split_stride, gate, gate_run, kdev);
+      break;
+    default:
+      launch<T, 256, 256, 4, 2>(st, P, ldp, Q, ldq, C, ldc, M, N, K, splits, split_stride, gate, gate_run, kdev);
       break;
   }
 }
