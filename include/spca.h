@@ -74,7 +74,7 @@ enum {
                                    then up to polish_maxit FP32 AM iterations
                                    on the caller's FP32 A ("polish"): every
                                    start continues from its BF16-phase
-                                   iterate for up to 8 iterations, then the
+                                   iterate for up to 4 iterations, then the
                                    16 best still-running ones to the end;
                                    the per-start results and the best start
                                    are those after the polish; objective and

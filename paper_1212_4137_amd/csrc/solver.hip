@@ -438,7 +438,7 @@ int spca_ctx_destroy(spca_ctx* ctx) {
 // Working on all of A lets a column that BF16 rounding moved across a
 // selection threshold come back.  The sub-solves' results (per start and
 // best) are the solve's results.
-constexpr int kPolishRank = 8;   // FP32 iterations of every start
+constexpr int kPolishRank = 4;   // FP32 iterations of every start
 constexpr int kPolishKeep = 16;  // starts polished to the end
 
 
