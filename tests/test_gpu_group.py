@@ -9,7 +9,8 @@ together, every launch of an iteration covering all of them.
 * A request gives the same bits alone and in a group (its K splits follow
   from its own n and p and the padding only adds exact zeros).
 * The widest rows (p = 12288), a start e_i (X0 NULL), degenerate and zero
-  starts, per-request limits, and the solve-wide warnings."""
+  starts, per-request limits, the solve-wide warnings, and an A whose
+  leading dimension and address need the aligned copy."""
 import numpy as np
 import pytest
 
@@ -178,3 +179,29 @@ def test_group_rejects_wide_rows(spca):
     A = to_device_colmajor(np.ones((4, 12289), np.float32))
     with pytest.raises(spca.SpcaError, match="SPCA_GROUP_MAX_P"):
         spca.am_solve_group([dict(A=A, X0=None, formulation=1, s_or_gamma=3)])
+
+
+def test_unaligned_matrix_in_a_group(spca):
+    """A request whose A has lda = 41 and a 4-byte offset (not 16-byte
+    aligned): the group copies it to an aligned layout; its result matches
+    the oracle and is the same with the matrix aligned."""
+    n, p, lda = 37, 500, 41
+    sp = workloads.spiked_matrix(workloads.SEED_BASE + 911, n, p, thetas=(25.0,), spike_nnz=12)
+    base = torch.zeros(p * lda + 1, dtype=torch.float32)
+    view = base[1:1 + p * lda].view(p, lda)
+    view[:, :n] = torch.from_numpy(np.ascontiguousarray(sp.A.T))
+    A_odd = base.cuda()[1:1 + p * lda].view(p, lda)[:, :n].t()
+    assert A_odd.stride() == (1, lda) and A_odd.data_ptr() % 16 != 0
+    X0 = workloads.random_unit_starts(workloads.SEED_BASE + 912, 12, p)
+    other = _device(_requests(13)[0])
+    req = dict(A=A_odd, X0=to_device_rows(X0), formulation=3, s_or_gamma=6.0, tol=1e-9,
+               maxit=150)
+    got = spca.am_solve_group([other, req], return_X=True)[1]
+    aligned = spca.am_solve_group([dict(req, A=to_device_colmajor(sp.A))], return_X=True)[0]
+    assert np.array_equal(got["f_per_start"], aligned["f_per_start"])
+    assert torch.equal(got["X_final"], aligned["X_final"])
+    ref = oracle.am_multi(sp.A, 3, 6.0, X0, 1e-9, 150)
+    g = dict(got)
+    g["X_final"] = g["X_final"].cpu().numpy()
+    compare_solve(g, ref, "group unaligned A", sp.A, 3, 6.0, X0=X0,
+                  stepper=_group_stepper(spca, req))
