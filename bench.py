@@ -130,7 +130,7 @@ def _sum_kt(outs):
     return kt
 
 
-def bench_all8(args, spca, torch):
+def bench_all8(args, spca, torch, timed_events=True):
     dev = torch.device("cuda:0")
     cfg = workloads.SPIKED_ALL8
     n, p, r, maxit = cfg["n"], cfg["p"], cfg["r"], cfg["maxit"]
@@ -142,18 +142,50 @@ def bench_all8(args, spca, torch):
 
     A = torch.from_numpy(np.ascontiguousarray(A_np.T)).to(dev).t()  # column-major
     X0 = torch.from_numpy(X0_np).to(dev)
-    ctx = spca.Context(0)
-    stream = torch.cuda.current_stream()
+    # the 8 solves of a step are independent: with --streams K they run on K
+    # streams at once (a context and a host thread each), so that one solve's
+    # memory-bound kernels overlap another's matrix-core products; the
+    # formulations are dealt to the streams by their measured cost
+    ns = max(1, min(args.streams, len(fids)))
+    ctxs = [spca.Context(0) for _ in range(ns)]
+    streams = ([torch.cuda.current_stream()] if ns == 1 else
+               [torch.cuda.Stream() for _ in range(ns)])
+    cost = {1: 50, 2: 50, 3: 63, 4: 62, 5: 82, 6: 82, 7: 45, 8: 82}
+    lanes = [[] for _ in range(ns)]
+    load = [0] * ns
+    for fid in sorted(fids, key=lambda f: (-cost[f], f)):
+        w = load.index(min(load))
+        lanes[w].append(fid)
+        load[w] += cost[fid]
     modes = {}
 
     def step(timing):
+        results = {}
+
+        def run_lane(w):
+            for fid in lanes[w]:
+                results[fid] = spca.am_solve(
+                    A, fid, params[fid], X0, tol=-1.0, maxit=maxit, ctx=ctxs[w],
+                    stream=streams[w], kernel_times=timing,
+                    flags=args.flags | (spca.FLAG_TIME_SAMPLED if timing else 0))
+
+        if ns == 1:
+            run_lane(0)
+        else:
+            import threading
+
+            threads = [threading.Thread(target=run_lane, args=(w,)) for w in range(ns)]
+            for t in threads:
+                t.start()
+            for t in threads:
+                t.join()
+            if len(results) != len(fids):
+                raise RuntimeError("a solve of the step failed")
         work = 0.0
         kt = {}
         nnz = {}
         for fid in fids:
-            res = spca.am_solve(A, fid, params[fid], X0, tol=-1.0, maxit=maxit,
-                                ctx=ctx, stream=stream, kernel_times=timing,
-                                flags=args.flags | (spca.FLAG_TIME_SAMPLED if timing else 0))
+            res = results[fid]
             work += res["iters_x_starts"]
             nnz[fid] = float(np.mean(res["nnz_per_start"]))
             if timing:
@@ -163,12 +195,21 @@ def bench_all8(args, spca, torch):
                 modes[fid] = (t["iters_dense"], t["iters_list"], t["iters_union"])
         return {"work": work, "kt": kt, "nnz": nnz}
 
+    ctx, stream = ctxs[0], streams[0]
+
     if args.autotune:
         # a8: one tuned solve per formulation fills the tuning table before
         # the timed steps (which then plan from it)
         for fid in fids:
             spca.am_solve(A, fid, params[fid], X0, tol=-1.0, maxit=2, ctx=ctx,
                           stream=stream, flags=args.flags | spca.FLAG_AUTOTUNE)
+    if not timed_events:
+        # throughput only: no kernel events on any iteration
+        dt, outs = _timed_steps(lambda timing: step(False), args.steps, args.warmup)
+        return {"metric": "AM iters x starts/sec",
+                "value": sum(o["work"] for o in outs) / dt, "unit": "iter*start/s",
+                "ms_per_step": dt / args.steps * 1e3,
+                "config": {"concurrent_solves": ns, "solves_per_stream": lanes}}
     dt, outs = _timed_steps(step, args.steps, args.warmup)
     work = sum(o["work"] for o in outs)
     kt_all = _sum_kt(outs)
@@ -220,7 +261,8 @@ def bench_all8(args, spca, torch):
         "config": {"workload": cfg["name"], "n": n, "p": p, "starts": r,
                    "formulations": fids, "maxit": maxit, "tol": "disabled (fixed work)",
                    "s": cfg["s"], "gamma": "0.1*max_i ||a_i||_2",
-                   "spikes": list(cfg["thetas"]), "spike_nnz": cfg["spike_nnz"]},
+                   "spikes": list(cfg["thetas"]), "spike_nnz": cfg["spike_nnz"],
+                   "concurrent_solves": ns, "solves_per_stream": lanes},
         "roofline": roofline,
         "path_roofline": path,
         "kernels": other,
@@ -740,13 +782,14 @@ def bench_sparse(args, spca, torch):
     }
 
 
-def bench_secondary(args, spca, torch):
-    """The other configurations, short, beside the headline line: the BF16 +
-    polish precision study (5000 x 50000, 2 steps), the 16 GB instance (2
-    steps of 30 iterations) and a 2000-request serving stream at a fixed
-    offered load, batched with mixed precision and the one-request-at-a-time
-    FP32 baseline.  A failing part records its error instead of ending the
-    run."""
+def bench_secondary(args, spca, torch, main_rec):
+    """The other configurations, short, beside the headline line: the
+    headline step with its solves on 4 streams at once (throughput only),
+    the BF16 + polish precision study (5000 x 50000, 2 steps), the 16 GB
+    instance (2 steps of 30 iterations) and a 2000-request serving stream at
+    a fixed offered load, batched with mixed precision and the
+    one-request-at-a-time FP32 baseline.  A failing part records its error
+    instead of ending the run."""
     import copy
     import gc
 
@@ -798,6 +841,21 @@ def bench_secondary(args, spca, torch):
                            "r": [16, 64, 256], "precision": "50% fp32, 50% bf16+polish (batched); "
                            "fp32 (baseline)", "workers": args.workers, "tol": 1e-6, "maxit": 200}}
 
+    def concurrent():
+        # the headline step with its 8 solves on 4 streams at once, no
+        # kernel events (events of overlapping kernels measure time shared
+        # with the other streams, so the kernel roofline stays with the
+        # sequential line above)
+        b = copy.copy(args)
+        b.streams, b.steps, b.warmup, b.no_cpu_baseline = 4, 3, 1, True
+        r = bench_all8(b, spca, torch, timed_events=False)
+        t_bound = main_rec["path_roofline"]["t_bound_ms"]  # the same work
+        return {"metric": r["metric"], "value": r["value"], "unit": r["unit"],
+                "ms_per_step": r["ms_per_step"],
+                "path_roofline_frac": round(t_bound / r["ms_per_step"], 4),
+                "concurrent_solves": 4, "solves_per_stream": r["config"]["solves_per_stream"]}
+
+    part("headline_concurrent", concurrent)
     part("precision", precision)
     part("large", large)
     part("serve", serve)
@@ -838,6 +896,8 @@ def main():
                     help="keep the planner off the union-of-supports product")
     ap.add_argument("--graph", action="store_true",
                     help="replay the iterations from a captured HIP graph")
+    ap.add_argument("--streams", type=int, default=1,
+                    help="spiked-all8: run the step's solves on this many streams at once")
     ap.add_argument("--no-secondary", action="store_true",
                     help="spiked-all8: skip the short runs of the other configurations")
     ap.add_argument("--serve-requests", type=int, default=2000,
@@ -858,7 +918,7 @@ def main():
     args.flags = (spca.FLAG_GRAPH if args.graph else 0) | (spca.FLAG_NO_UNION if args.no_union else 0)
     rec = WORKLOADS[args.workload](args, spca, torch)
     if args.workload == "spiked-all8" and not args.no_secondary and args.fids == "1,2,3,4,5,6,7,8":
-        rec["secondary"] = bench_secondary(args, spca, torch)
+        rec["secondary"] = bench_secondary(args, spca, torch, rec)
     print(json.dumps(rec), flush=True)
 
 
