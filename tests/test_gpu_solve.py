@@ -359,3 +359,36 @@ def test_work_counters_and_sampled_events(spca):
     got = spca.am_solve(A, 3, 8.0, X0, tol=1e-6, maxit=300, kernel_times=True)
     assert got["kernel_times"]["active_starts_sum"] == got["iters_per_start"].sum()
     assert got["kernel_times"]["ax_nnz_sum"] >= 40 * 900
+
+
+def test_concurrent_solves_on_several_streams_are_identical(spca):
+    """Independent solves on 4 streams at once (a context and a host thread
+    each, as bench.py --streams runs them) give the same bits as one after
+    another on one stream."""
+    import threading
+
+    sp = workloads.spiked_matrix(workloads.SEED_BASE + 77, 300, 3000, thetas=(40.0, 20.0),
+                                 spike_nnz=20)
+    A = to_device_colmajor(sp.A)
+    X0 = to_device_rows(workloads.random_unit_starts(workloads.SEED_BASE + 78, 96, 3000))
+    fids = list(range(1, 9))
+    par = {f: _param(f, sp.A, 20, "literal") for f in fids}
+    seq = {f: spca.am_solve(A, f, par[f], X0, tol=-1.0, maxit=60, return_X=True) for f in fids}
+    ctxs = [spca.Context(0) for _ in range(4)]
+    streams = [torch.cuda.Stream() for _ in range(4)]
+    conc = {}
+
+    def lane(w):
+        for f in fids[w::4]:
+            conc[f] = spca.am_solve(A, f, par[f], X0, tol=-1.0, maxit=60, ctx=ctxs[w],
+                                    stream=streams[w], return_X=True)
+    threads = [threading.Thread(target=lane, args=(w,)) for w in range(4)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    torch.cuda.synchronize()
+    for f in fids:
+        assert np.array_equal(seq[f]["f_per_start"], conc[f]["f_per_start"]), f
+        assert torch.equal(seq[f]["X_final"], conc[f]["X_final"]), f
+        assert np.array_equal(seq[f]["x"], conc[f]["x"]), f
