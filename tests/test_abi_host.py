@@ -135,6 +135,12 @@ def test_group_count_and_start_limits():
     assert b2 > b1 > 0
 
 
+def test_server_group_limit_validation():
+    lib = spca.load()
+    assert lib.spca_server_set_group_limit(None, 4) == _lib.SPCA_EINVAL
+    assert "server" in lib.spca_last_error().decode()
+
+
 def test_gemm_argument_validation():
     lib = spca.load()
     rc = lib.spca_gemm_nt_f32(None, FAKE, 6, FAKE, 8, FAKE, 8, 4, 4, 6)
