@@ -44,6 +44,7 @@ namespace {
 
 constexpr int64_t kGroupSplitK = 1024;  // target K per split of a product
 constexpr int kGroupMaxSplits = 12;
+static_assert(kGroupMaxSplits <= kSplitsMax, "the grouped sums add at most kSplitsMax partials");
 
 size_t gcarve(size_t* cur, size_t bytes) {
   size_t o = (*cur + 255) / 256 * 256;

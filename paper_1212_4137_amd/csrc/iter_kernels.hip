@@ -428,6 +428,78 @@ __global__ __launch_bounds__(256) void union_gather_kernel(
 // y-update (Algorithm 2; Table 3, S1 for L2 variance, S2 for L1 variance)
 // ---------------------------------------------------------------------------
 
+typedef float yvec4 __attribute__((ext_vector_type(4)));
+
+// u = the split partials summed in split order, for the four consecutive
+// entries i .. i + 3 of a row (entries at n and beyond read as 0).  The
+// loads of all partials are issued before the first add, so a thread waits
+// for memory once per group instead of once per partial.  Rows and split
+// strides are multiples of 4 floats and 16-byte aligned.
+__device__ __forceinline__ yvec4 sum_partials4(const float* __restrict__ u, int64_t i,
+                                               int64_t n, int splits, int64_t stride) {
+  yvec4 part[kSplitsMax];
+#pragma unroll
+  for (int sp = 0; sp < kSplitsMax; ++sp)
+    if (sp < splits) part[sp] = *reinterpret_cast<const yvec4*>(u + i + sp * stride);
+  yvec4 t = part[0];
+#pragma unroll
+  for (int sp = 1; sp < kSplitsMax; ++sp)
+    if (sp < splits) t += part[sp];
+  if (i + 3 >= n) {
+    if (i + 1 >= n) t.y = 0.f;
+    if (i + 2 >= n) t.z = 0.f;
+    if (i + 3 >= n) t.w = 0.f;
+  }
+  return t;
+}
+
+__device__ __forceinline__ void store4(float* __restrict__ y, int64_t i, int64_t n, yvec4 t) {
+  if (i + 3 < n) {
+    *reinterpret_cast<yvec4*>(y + i) = t;
+  } else {
+    y[i] = t.x;
+    if (i + 1 < n) y[i + 1] = t.y;
+    if (i + 2 < n) y[i + 2] = t.z;
+  }
+}
+
+// One block per start.  Thread t owns the groups of four entries starting
+// at 4 (t + 256 k), in increasing order whatever the row length; it keeps
+// its sums in y until the FP64 norm (entries squared in index order per
+// thread, then the block sum) is known.
+template <bool L1VAR>
+__device__ __forceinline__ void y_update_row(const float* __restrict__ u, int64_t stride,
+                                             int splits, float* __restrict__ y, int64_t n,
+                                             int32_t* status, uint16_t* __restrict__ yb,
+                                             double* red) {
+  double sq = 0.0;
+  for (int64_t i = 4 * (int64_t)threadIdx.x; i < n; i += 4 * 256) {
+    const yvec4 t = sum_partials4(u, i, n, splits, stride);
+    store4(y, i, n, t);
+    const double t0 = t.x, t1 = t.y, t2 = t.z, t3 = t.w;
+    sq += t0 * t0;
+    sq += t1 * t1;
+    sq += t2 * t2;
+    sq += t3 * t3;
+  }
+  sq = block_sum(sq, red);
+  if (sq == 0.0) {
+    if (threadIdx.x == 0) *status = SPCA_DEGENERATE;
+    return;
+  }
+  const double inv = 1.0 / sqrt(sq);
+  for (int64_t i = 4 * (int64_t)threadIdx.x; i < n; i += 4 * 256) {
+    const yvec4 t = *reinterpret_cast<const yvec4*>(y + i);
+    yvec4 o;
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      o[e] = L1VAR ? (float)((t[e] > 0.f) - (t[e] < 0.f)) : (float)((double)t[e] * inv);
+    store4(y, i, n, o);
+    if (yb != nullptr)
+      for (int e = 0; e < 4 && i + e < n; ++e) yb[i + e] = f32_to_bf16(o[e]);
+  }
+}
+
 template <bool L1VAR>
 __global__ __launch_bounds__(256) void y_update_kernel(
     const float* __restrict__ U, int64_t split_stride, float* __restrict__ Y,
@@ -438,30 +510,8 @@ __global__ __launch_bounds__(256) void y_update_kernel(
   const int splits = plan->ax_splits;
   const int64_t j = blockIdx.x;
   if (s.status[j] != kRunning) return;
-  const float* u = U + j * ldu;
-  float* y = Y + j * ldu;
-  // u_i = sum of the split partials in split order; each thread keeps the
-  // values it owns in y until the norm is known
-  double sq = 0.0;
-  for (int64_t i = threadIdx.x; i < n; i += 256) {
-    float t = u[i];
-    for (int sp = 1; sp < splits; ++sp) t += u[i + sp * split_stride];
-    y[i] = t;
-    double td = t;
-    sq += td * td;
-  }
-  sq = block_sum(sq, red);
-  if (sq == 0.0) {
-    if (threadIdx.x == 0) s.status[j] = SPCA_DEGENERATE;
-    return;
-  }
-  const double inv = 1.0 / sqrt(sq);
-  for (int64_t i = threadIdx.x; i < n; i += 256) {
-    float t = y[i];
-    const float o = L1VAR ? (float)((t > 0.f) - (t < 0.f)) : (float)((double)t * inv);
-    y[i] = o;
-    if (Yb != nullptr) Yb[j * ldyb + i] = f32_to_bf16(o);
-  }
+  y_update_row<L1VAR>(U + j * ldu, split_stride, splits, Y + j * ldu, n, s.status + j,
+                      Yb != nullptr ? Yb + j * ldyb : nullptr, red);
 }
 
 // Grouped solves: y_update_kernel with the variance type and the partial
@@ -473,27 +523,12 @@ __global__ __launch_bounds__(256) void group_y_update_kernel(
   const int64_t j = blockIdx.x;
   if (s.status[j] != kRunning) return;
   const int splits = s.cfg[j].splits;
-  const bool l1 = s.cfg[j].l1 != 0;
-  const float* u = U + j * ldu;
-  float* y = Y + j * ldu;
-  double sq = 0.0;
-  for (int64_t i = threadIdx.x; i < n; i += 256) {
-    float t = u[i];
-    for (int sp = 1; sp < splits; ++sp) t += u[i + sp * split_stride];
-    y[i] = t;
-    double td = t;
-    sq += td * td;
-  }
-  sq = block_sum(sq, red);
-  if (sq == 0.0) {
-    if (threadIdx.x == 0) s.status[j] = SPCA_DEGENERATE;
-    return;
-  }
-  const double inv = 1.0 / sqrt(sq);
-  for (int64_t i = threadIdx.x; i < n; i += 256) {
-    const float t = y[i];
-    y[i] = l1 ? (float)((t > 0.f) - (t < 0.f)) : (float)((double)t * inv);
-  }
+  if (s.cfg[j].l1 != 0)
+    y_update_row<true>(U + j * ldu, split_stride, splits, Y + j * ldu, n, s.status + j,
+                       nullptr, red);
+  else
+    y_update_row<false>(U + j * ldu, split_stride, splits, Y + j * ldu, n, s.status + j,
+                        nullptr, red);
 }
 
 // Grouped solves: one block per start sums its A^T y partials in order.
@@ -505,11 +540,8 @@ __global__ __launch_bounds__(256) void group_sum_splits_kernel(float* __restrict
   const int splits = s.cfg[j].aty_splits;
   if (splits <= 1) return;
   float* v = V + j * ldv;
-  for (int64_t i = threadIdx.x; i < p; i += 256) {
-    float a = v[i];
-    for (int sp = 1; sp < splits; ++sp) a += v[sp * stride + i];
-    v[i] = a;
-  }
+  for (int64_t i = 4 * (int64_t)threadIdx.x; i < p; i += 4 * 256)
+    store4(v, i, p, sum_partials4(v, i, p, splits, stride));
 }
 
 // Running starts per request and in total; one block of 16 waves, a wave

@@ -18,6 +18,10 @@ inline XKind xkind_of(int fid) {
 }
 inline bool l1_variance(int fid) { return fid % 2 == 0; }
 
+// The most K-split partials of one product that its consumer (the y-update,
+// the grouped partial sums) adds up.
+constexpr int kSplitsMax = 16;
+
 // Per-start settings of a grouped solve (starts of several requests in one
 // set of launches): the request's operator, parameter and stop rule.
 struct RowCfg {

@@ -63,6 +63,7 @@ inline int list_cap_of(int64_t p) {
 }
 
 constexpr int kMaxSplits = 16;  // K splits of the dense A x product
+static_assert(kMaxSplits <= kSplitsMax, "the y-update sums at most kSplitsMax partials");
 constexpr int kTimeSample = 8;  // SPCA_FLAG_TIME_SAMPLED: events every 8th iteration
 
 struct Layout {
