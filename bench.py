@@ -47,8 +47,8 @@ PEAK_HBM_GBS = 8000.0
 # counters on a 1 GiB copy (fetch x 2.0, write x 1.0); valid only for the
 # GEMM source they were taken on.
 TRAFFIC_ATY = {"gemm_kernel_sha256":
-               "7b4066d3a3dc8e4cefa5a8981d5938b3debf88837b57d0f59907b450c21a6987",
-               "read_bytes": 3.917e4 * 1024 * 2.0, "write_bytes": 4.237e4 * 1024 * 1.0,
+               "8ca7c3a38ab4cacc471144a5492dc5e8cbb0053638feb307c9367f81c7005cc1",
+               "read_bytes": 3.917e4 * 1024 * 2.0, "write_bytes": 4.244e4 * 1024 * 1.0,
                "profile": "profiles/traffic_spiked-1000x10000-F1-r1024_fetch_write.md"}
 
 
