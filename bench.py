@@ -47,8 +47,8 @@ PEAK_HBM_GBS = 8000.0
 # counters on a 1 GiB copy (fetch x 2.0, write x 1.0); valid only for the
 # GEMM source they were taken on.
 TRAFFIC_ATY = {"gemm_kernel_sha256":
-               "8ca7c3a38ab4cacc471144a5492dc5e8cbb0053638feb307c9367f81c7005cc1",
-               "read_bytes": 3.917e4 * 1024 * 2.0, "write_bytes": 4.244e4 * 1024 * 1.0,
+               "5f5e9c75553825e3076bdeeafe9b0b6daac79865826051a58bc420f182d9c765",
+               "read_bytes": 3.919e4 * 1024 * 2.0, "write_bytes": 4.257e4 * 1024 * 1.0,
                "profile": "profiles/traffic_spiked-1000x10000-F1-r1024_fetch_write.md"}
 
 

@@ -28,6 +28,7 @@
 #include <mutex>
 #include <sstream>
 #include <string>
+#include <type_traits>
 
 #include "common.hpp"
 #include "kernels.hpp"
@@ -96,7 +97,9 @@ __device__ __forceinline__ floatx4 load_chunk(const T* __restrict__ base,
 
 // One BM x BN tile of C = P * Q^T over K range [kbeg, kend): rows m0.. of P
 // and C, rows n0.. of Q (columns of C); lds holds 2 * kStage floats.
-template <typename T, int BM, int BN, int WM, int WN>
+// DEPTH = slabs in flight between global memory and LDS: 1 (one register
+// set), or 2 (two register sets, the slab loop taken two at a time).
+template <typename T, int BM, int BN, int WM, int WN, int DEPTH = 1>
 __device__ __forceinline__ void gemm_tile(const T* __restrict__ P, int64_t ldp,
                                           const T* __restrict__ Q, int64_t ldq,
                                           float* __restrict__ Cs, int64_t ldc, int M,
@@ -128,8 +131,9 @@ __device__ __forceinline__ void gemm_tile(const T* __restrict__ P, int64_t ldp,
 #pragma unroll
       for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.f;
 
-  floatx4 pre_p[Cfg::kPVec];
-  floatx4 pre_q[Cfg::kQVec];
+  static_assert(DEPTH == 1 || DEPTH == 2, "one or two slabs in flight");
+  floatx4 pre_p[DEPTH][Cfg::kPVec];
+  floatx4 pre_q[DEPTH][Cfg::kQVec];
 
   // Small wave tiles (at most two MFMA blocks) load interior slabs of full
   // tiles without per-row or per-K guards, and read the operands of the
@@ -138,18 +142,19 @@ __device__ __forceinline__ void gemm_tile(const T* __restrict__ P, int64_t ldp,
   // cover its latency, and measured slower with either change.
   constexpr bool kPrefetch = Cfg::kFM * Cfg::kFN <= 2;
   const bool full_rows = mrows >= BM && nrows >= BN;
-  auto fetch = [&](int k0) {
+  auto fetch = [&](auto set_tag, int k0) {
+    constexpr int R = decltype(set_tag)::value;
     if (kPrefetch && full_rows && k0 + SK <= kend) {
 #pragma unroll
       for (int v = 0; v < Cfg::kPVec; ++v) {
         const int f = tid + v * Cfg::kThreads;
-        pre_p[v] = *reinterpret_cast<const floatx4*>(
+        pre_p[R][v] = *reinterpret_cast<const floatx4*>(
             Pblk + (int64_t)(f / kChunks) * ldp + k0 + (f % kChunks) * E);
       }
 #pragma unroll
       for (int v = 0; v < Cfg::kQVec; ++v) {
         const int f = tid + v * Cfg::kThreads;
-        pre_q[v] = *reinterpret_cast<const floatx4*>(
+        pre_q[R][v] = *reinterpret_cast<const floatx4*>(
             Qblk + (int64_t)(f / kChunks) * ldq + k0 + (f % kChunks) * E);
       }
       return;
@@ -157,37 +162,33 @@ __device__ __forceinline__ void gemm_tile(const T* __restrict__ P, int64_t ldp,
 #pragma unroll
     for (int v = 0; v < Cfg::kPVec; ++v) {
       int f = tid + v * Cfg::kThreads;
-      pre_p[v] = load_chunk<T>(Pblk, ldp, f / kChunks, mrows, k0 + (f % kChunks) * E, kend);
+      pre_p[R][v] = load_chunk<T>(Pblk, ldp, f / kChunks, mrows, k0 + (f % kChunks) * E, kend);
     }
 #pragma unroll
     for (int v = 0; v < Cfg::kQVec; ++v) {
       int f = tid + v * Cfg::kThreads;
-      pre_q[v] = load_chunk<T>(Qblk, ldq, f / kChunks, nrows, k0 + (f % kChunks) * E, kend);
+      pre_q[R][v] = load_chunk<T>(Qblk, ldq, f / kChunks, nrows, k0 + (f % kChunks) * E, kend);
     }
   };
-  auto stash = [&](float* st) {
+  auto stash = [&](auto set_tag, float* st) {
+    constexpr int R = decltype(set_tag)::value;
 #pragma unroll
     for (int v = 0; v < Cfg::kPVec; ++v) {
       int f = tid + v * Cfg::kThreads;
-      *reinterpret_cast<floatx4*>(&st[swz(f / kChunks, f % kChunks)]) = pre_p[v];
+      *reinterpret_cast<floatx4*>(&st[swz(f / kChunks, f % kChunks)]) = pre_p[R][v];
     }
     float* sq = st + BM * kBK;
 #pragma unroll
     for (int v = 0; v < Cfg::kQVec; ++v) {
       int f = tid + v * Cfg::kThreads;
-      *reinterpret_cast<floatx4*>(&sq[swz(f / kChunks, f % kChunks)]) = pre_q[v];
+      *reinterpret_cast<floatx4*>(&sq[swz(f / kChunks, f % kChunks)]) = pre_q[R][v];
     }
   };
 
-  if (nslabs > 0) {
-    fetch(kbeg);
-    stash(lds);
-  }
-  __syncthreads();
-  for (int ks = 0; ks < nslabs; ++ks) {
+  // the MFMAs of slab ks, from LDS stage ks & 1
+  auto compute = [&](int ks) {
     const float* sp = lds + (ks & 1) * Cfg::kStage;
     const float* sq = sp + BM * kBK;
-    if (ks + 1 < nslabs) fetch(kbeg + (ks + 1) * SK);
     floatx4 a[2][Cfg::kFM];
     floatx4 bq[2][Cfg::kFN];
     auto read_ops = [&](int buf, int c8) {
@@ -231,8 +232,42 @@ __device__ __forceinline__ void gemm_tile(const T* __restrict__ P, int64_t ldp,
                 acc[i][j], 0, 0, 0);
       }
     }
-    if (ks + 1 < nslabs) stash(lds + ((ks + 1) & 1) * Cfg::kStage);
+  };
+  using S0 = std::integral_constant<int, 0>;
+  if constexpr (DEPTH == 1) {
+    if (nslabs > 0) {
+      fetch(S0{}, kbeg);
+      stash(S0{}, lds);
+    }
     __syncthreads();
+    for (int ks = 0; ks < nslabs; ++ks) {
+      if (ks + 1 < nslabs) fetch(S0{}, kbeg + (ks + 1) * SK);
+      compute(ks);
+      if (ks + 1 < nslabs) stash(S0{}, lds + ((ks + 1) & 1) * Cfg::kStage);
+      __syncthreads();
+    }
+  } else {
+    // slab ks + 2 loads into the register set that slab ks left while
+    // slab ks is multiplied and slab ks + 1 waits in the other set
+    using S1 = std::integral_constant<int, 1>;
+    if (nslabs > 0) {
+      fetch(S0{}, kbeg);
+      stash(S0{}, lds);
+    }
+    if (nslabs > 1) fetch(S1{}, kbeg + SK);
+    __syncthreads();
+    int ks = 0;
+    for (; ks + 1 < nslabs; ks += 2) {
+      if (ks + 2 < nslabs) fetch(S0{}, kbeg + (ks + 2) * SK);
+      compute(ks);
+      stash(S1{}, lds + Cfg::kStage);
+      __syncthreads();
+      if (ks + 3 < nslabs) fetch(S1{}, kbeg + (ks + 3) * SK);
+      compute(ks + 1);
+      if (ks + 2 < nslabs) stash(S0{}, lds);
+      __syncthreads();
+    }
+    if (ks < nslabs) compute(ks);
   }
 
   // Accumulator layout of the 32x32 block: register e of lane l holds
@@ -251,8 +286,10 @@ __device__ __forceinline__ void gemm_tile(const T* __restrict__ P, int64_t ldp,
   }
 }
 
-template <typename T, int BM, int BN, int WM, int WN>
-__global__ __launch_bounds__(WM* WN* kWave) void gemm_nt_kernel(
+// DEPTH 2 holds two register sets of slabs; its one compiled shape
+// (64 x 128) is held to 168 registers so that a CU keeps three workgroups.
+template <typename T, int BM, int BN, int WM, int WN, int DEPTH = 1>
+__global__ __launch_bounds__(WM* WN* kWave, DEPTH == 2 ? 3 : 1) void gemm_nt_kernel(
     const T* __restrict__ P, int64_t ldp, const T* __restrict__ Q,
     int64_t ldq, float* __restrict__ C, int64_t ldc, int M, int N, int K,
     int tiles_m, int tiles_mn, int splits, int kslabs_per_split,
@@ -286,7 +323,7 @@ __global__ __launch_bounds__(WM* WN* kWave) void gemm_nt_kernel(
   const int kbeg = split * kslabs_per_split * SK;
   int kend = kbeg + kslabs_per_split * SK;
   kend = kend < K ? kend : K;
-  gemm_tile<T, BM, BN, WM, WN>(P, ldp, Q, ldq, C + (int64_t)split * split_stride, ldc,
+  gemm_tile<T, BM, BN, WM, WN, DEPTH>(P, ldp, Q, ldq, C + (int64_t)split * split_stride, ldc,
                                M, N, tm * BM, tn * BN, kbeg, kend, lds);
 }
 
@@ -346,10 +383,11 @@ constexpr Shape kShapes[] = {
     {256, 256, 1, 0.90, 1.25},  // 2x2 waves of 128x128
     {256, 256, 1, 0.0, 1.36},   // 2x4 waves of 128x64: BF16 only (2 waves per SIMD)
     {256, 256, 1, 0.0, 0.0},    // 4x2 waves of 64x128: tuning candidate only
+    {64, 128, 3, 0.0, 0.0},     // 2x2 waves of 32x64, two slabs in flight: tuning candidate only
 };
 constexpr int kNumShapes = (int)(sizeof(kShapes) / sizeof(kShapes[0]));
 
-template <typename T, int BM, int BN, int WM, int WN>
+template <typename T, int BM, int BN, int WM, int WN, int DEPTH = 1>
 void launch(hipStream_t st, const T* P, int64_t ldp, const T* Q,
             int64_t ldq, float* C, int64_t ldc, int64_t M, int64_t N,
             int64_t K, int splits, int64_t split_stride, const int32_t* gate,
@@ -359,7 +397,7 @@ void launch(hipStream_t st, const T* P, int64_t ldp, const T* Q,
   const int kslabs = (int)ceil_div(K, kChunks * Elem<T>::kPerChunk);
   const int per_split = (int)ceil_div(kslabs, splits);
   const int total = tiles_m * tiles_n * splits;
-  hipLaunchKernelGGL((gemm_nt_kernel<T, BM, BN, WM, WN>), dim3(total),
+  hipLaunchKernelGGL((gemm_nt_kernel<T, BM, BN, WM, WN, DEPTH>), dim3(total),
                      dim3(WM * WN * kWave), 0, st, P, ldp, Q, ldq, C, ldc,
                      (int)M, (int)N, (int)K, tiles_m, tiles_m * tiles_n, splits,
                      per_split, split_stride, gate, gate_run, kdev);
@@ -401,8 +439,11 @@ void dispatch(int shape, hipStream_t st, const T* P, int64_t ldp,
     case 9:
       launch<T, 256, 256, 2, 4>(st, P, ldp, Q, ldq, C, ldc, M, N, K, splits, split_stride, gate, gate_run, kdev);
       break;
-    default:
+    case 10:
       launch<T, 256, 256, 4, 2>(st, P, ldp, Q, ldq, C, ldc, M, N, K, splits, split_stride, gate, gate_run, kdev);
+      break;
+    default:
+      launch<T, 64, 128, 2, 2, 2>(st, P, ldp, Q, ldq, C, ldc, M, N, K, splits, split_stride, gate, gate_run, kdev);
       break;
   }
 }

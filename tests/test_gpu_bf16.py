@@ -53,7 +53,7 @@ def test_gemm_bf16_matches_fp64(spca, M, N, K):
     assert np.all(np.abs(C.cpu().numpy().astype(np.float64) - ref) <= bound)
 
 
-@pytest.mark.parametrize("shape", range(11))
+@pytest.mark.parametrize("shape", range(12))
 @pytest.mark.parametrize("M,N,K,splits", [(130, 333, 1001, 1), (300, 290, 4100, 4)])
 def test_gemm_bf16_every_shape_and_split(spca, shape, M, N, K, splits):
     print(f"bf16 gemm shape={shape} M={M} N={N} K={K} splits={splits}", flush=True)

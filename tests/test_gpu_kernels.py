@@ -50,7 +50,7 @@ def test_gemm_nt_matches_fp64(spca, M, N, K):
     assert np.all(err <= bound), float(np.max(err / bound))
 
 
-@pytest.mark.parametrize("shape", range(11))
+@pytest.mark.parametrize("shape", range(12))
 @pytest.mark.parametrize("M,N,K,splits", [(130, 333, 1001, 1), (37, 161, 517, 4),
                                           (256, 100, 4100, 16)])
 def test_gemm_every_shape_and_split(spca, shape, M, N, K, splits):
