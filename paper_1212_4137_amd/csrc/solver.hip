@@ -603,9 +603,16 @@ int spca_am_solve_ex(spca_ctx* ctx, void* stream, const spca_problem* prob,
   }
   if (opts->flags & SPCA_FLAG_AUTOTUNE) {
     // a8: measure every tile shape and split on this solve's own operands
-    // for the products that have no entry in the tuning table yet
+    // for the products that have no entry in the tuning table yet.  Y holds
+    // the leading entries of the starts (zero beyond p): with Y = 0 the chip
+    // draws less power and clocks higher than on real operands (2.4 against
+    // 1.9 GHz for the 16 GB instance's A^T Y), which would time every plan
+    // too fast.
     SPCA_HIP_TRY(hipMemsetAsync(Y, 0, sizeof(float) * r * L.ldu, st));
-    if (bf16) SPCA_HIP_TRY(hipMemsetAsync(Yb, 0, sizeof(uint16_t) * r * L.ldyb, st));
+    SPCA_HIP_TRY(hipMemcpy2DAsync(Y, sizeof(float) * L.ldu, X, sizeof(float) * L.ldx,
+                                  sizeof(float) * (size_t)(n < p ? n : p), r,
+                                  hipMemcpyDeviceToDevice, st));
+    if (bf16) rows_to_bf16(st, Y, L.ldu, r, n, Yb, L.ldyb, nullptr);
     const int eb = bf16 ? 2 : 4;
     GemmPlan tmp;
     if (!tuned_plan(r, n, p, kMaxSplits, eb, &tmp)) {
