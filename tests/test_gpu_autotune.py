@@ -72,32 +72,39 @@ def _bucket(x):
     return int(round(2.0 * np.log2(x)))
 
 
-@pytest.mark.parametrize("fid", [1, 6])
-def test_every_tile_shape_gives_the_same_solve(spca, fid):
+@pytest.mark.parametrize("fid,prec", [(1, "fp32"), (6, "fp32"), (1, "bf16"), (6, "bf16")])
+def test_every_tile_shape_gives_the_same_solve(spca, fid, prec):
     """A tuning-table entry forces each compiled tile shape on both products
     of a dense-only solve (one K split each, fixed work): each tile sums its
     K range in the same order whatever its shape, so every shape gives the
-    same bits; the shape-0 result keeps parity with the oracle."""
+    same bits; the FP32 shape-0 result keeps parity with the oracle.  With
+    BF16 storage the forced products are the BF16 phase's (the polish keeps
+    its model plans), and the BF16-phase iterates and the polished results
+    are the same bits for every shape."""
     n, p, r = 300, 2000, 64
     sp = workloads.spiked_matrix(53 + fid, n, p, thetas=(60.0, 30.0), spike_nnz=20)
     X0n = workloads.random_unit_starts(54 + fid, r, p)
     A, X0 = to_device_colmajor(sp.A), to_device_rows(X0n)
     par = workloads.s_or_gamma_for(fid, sp.A, 20, "literal")
-    kw = dict(tol=-1.0, maxit=25, return_X=True, flags=spca.FLAG_DENSE_ONLY)
+    kw = dict(tol=-1.0, maxit=25, return_X=True, flags=spca.FLAG_DENSE_ONLY, precision=prec,
+              polish_maxit=25 if prec == "bf16" else 0)
+    eb = 2 if prec == "bf16" else 4
     first = None
     shape = 0
     while True:
         spca.tune_table_clear()
         try:
             # U^T = X^T A^T: M = r, N = n, K = p; V^T = Y^T A: M = r, N = p, K = n
-            spca.tune_table_import(f"4 16 {_bucket(r)} {_bucket(n)} {_bucket(p)} {shape} 1\n"
-                                   f"4 16 {_bucket(r)} {_bucket(p)} {_bucket(n)} {shape} 1\n")
+            spca.tune_table_import(f"{eb} 16 {_bucket(r)} {_bucket(n)} {_bucket(p)} {shape} 1\n"
+                                   f"{eb} 16 {_bucket(r)} {_bucket(p)} {_bucket(n)} {shape} 1\n")
         except spca.SpcaError:
             break  # past the last compiled shape
         got = spca.am_solve(A, fid, par, X0, **kw)
         assert spca.tune_table_export().split()[5] == str(shape)
         print(f"F{fid} shape {shape}: objective {got['objective']!r}", flush=True)
-        if first is None:
+        if first is None and prec == "bf16":
+            first = got
+        elif first is None:
             first = got
             ref = oracle.am_multi(sp.A.astype(np.float64), fid, par, X0n.astype(np.float64),
                                   -1.0, 25, nthreads=8)
