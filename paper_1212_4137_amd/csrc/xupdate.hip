@@ -1135,11 +1135,18 @@ __global__ __launch_bounds__(kRT, (KIND == kTopS || WARM) ? 2 : 4) void x_update
 // moved by more than 10%) is flagged in s.redo and left to
 // x_update_reg_kernel, launched right after.  Reductions run in a fixed
 // order, so results are deterministic.
+// lambda_s first tries the last x-update's kept set S = {|v_i| > lambda'}:
+// restricted to S, the root condition sum (|v| - l) = sqrt(s) ||(|v| - l)||_2
+// is a quadratic in l whose smaller root is (S1 - sqrt(s (k S2 - S1^2) /
+// (k - s))) / k (k = |S|, S1 = sum |v|, S2 = sum v^2 over S); when exactly
+// the entries of S lie above that l, it is the root of the whole row, and
+// the row is finished from registers without candidates or sorts.
 // ---------------------------------------------------------------------------
 constexpr int kCandCap = 1024;
 constexpr int kCandPer = kCandCap / kRT;  // sorted positions per thread
 constexpr float kGuessLow = 0.9f;
 constexpr float kGuessRetry = 0.7f;  // the next guesses: this factor lower
+constexpr int kLamRounds = 6;        // closed-form rounds of lambda_s before the candidates
 constexpr uint32_t kIdxMask = 0x3fffu;    // row indices below 16384
 
 struct CSmem {
@@ -1317,6 +1324,130 @@ __global__ __launch_bounds__(kRT, 4) void x_update_cand_kernel(
     } else {
 #pragma unroll
       for (int e = 0; e < 4; ++e) v[q + e] = i + e < p ? vg[i + e] : 0.f;
+    }
+  }
+  if constexpr (KIND == kLambdaS) {
+    // closed-form root on the last kept set (every branch below depends on
+    // block totals only, so all threads take it together)
+    constexpr int R = NPT / 4;
+    // S_0 = {|v| > lambda'}; each round takes the root l of S_t's quadratic
+    // and S_{t+1} = {|v| > l}, until S_{t+1} = S_t (l is then the root of the
+    // row) or kLamRounds rounds; a row that does not settle takes the
+    // candidate path below
+    const double lprev = (double)s.thr[j];
+    double set3[3] = {0.0, 0.0, 0.0};  // |S|, sum |v| and sum v^2 over S
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) {
+      reload(v[k]);  // each pass derives its doubles afresh (no copies held across passes)
+      const double a = fabs((double)v[k]);
+      if (a > lprev) {
+        set3[0] += 1.0;
+        set3[1] += a;
+        set3[2] += a * a;
+      }
+    }
+    block_sum_n<double, 3>(set3, reinterpret_cast<double*>(sm.k64));
+    double lam = -1.0;
+    int cnt[R], off[R];
+    double acc[2] = {0.0, 0.0};
+    bool settled = false;
+#pragma unroll 1
+    for (int round = 0; round < kLamRounds; ++round) {
+      const double kk = set3[0];
+      if (!(kk > param)) break;
+      double disc = kk * set3[2] - set3[1] * set3[1];
+      disc = disc > 0.0 ? disc : 0.0;
+      lam = (set3[1] - sqrt(param * disc / (kk - param))) / kk;
+      if (!(lam > 0.0)) break;
+      // the set above lam: its size and sums (the next round's), and the
+      // squared distances to lam (the norm, if the set is unchanged)
+      double b4[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        cnt[q] = 0;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          reload(v[4 * q + e]);
+          const double a = fabs((double)v[4 * q + e]);
+          if (a > lam) {
+            ++cnt[q];
+            b4[0] += 1.0;
+            b4[1] += a;
+            b4[2] += a * a;
+            b4[3] += (a - lam) * (a - lam);
+          }
+        }
+      }
+      block_sum_n<double, 4>(b4, reinterpret_cast<double*>(sm.k64));
+      if (b4[0] == kk) {  // nested sets of equal size: unchanged
+        acc[0] = b4[3];
+        acc[1] = b4[0];
+        settled = true;
+        break;
+      }
+      set3[0] = b4[0];
+      set3[1] = b4[1];
+      set3[2] = b4[2];
+    }
+    if (settled) {  // {|v| > lam} is the set lam came from: lam is the root
+      const int total = rank_rows<R>(cnt, off, sm.k64);
+      const double nrm = sqrt(acc[0]);
+      const double phi = lam * sqrt(param) + nrm;
+      const bool zero = !(nrm > 0.0);
+      const double inv = zero ? 0.0 : 1.0 / nrm;
+      const bool listed = list_idx != nullptr && !zero && total <= list_cap;
+      const bool marking = colmark != nullptr && !zero && plan->mark != 0;
+      const int32_t epoch = marking ? plan->epoch : 0;
+      int32_t* li = listed ? list_idx + j * ldl : nullptr;
+      float* lv = listed ? list_val + j * ldl : nullptr;
+      float* x = X + j * ldx;
+#pragma unroll
+      for (int q = 0; q < NPT; q += 4) {
+        float xo[4];
+        int o = off[q / 4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          reload(v[q + e]);
+          const float vv = v[q + e];
+          const double a = fabs((double)vv);
+          const bool kp = a > lam && !zero;
+          const double w = vv > 0.f ? a - lam : lam - a;
+          xo[e] = kp ? (float)(w * inv) : 0.f;
+          const int gi = gidx(q + e);
+          if (kp && li != nullptr) {
+            li[o] = gi;
+            lv[o] = xo[e];
+            ++o;
+          }
+          if (kp && marking) colmark[gi] = epoch;
+        }
+        const int i = gidx(q);
+        if (i + 3 < p) {
+          floatx4 w4 = {xo[0], xo[1], xo[2], xo[3]};
+          *reinterpret_cast<floatx4*>(x + i) = w4;
+        } else {
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            if (i + e < p) x[i + e] = xo[e];
+        }
+      }
+      if (tid == 0) {
+        s.redo[j] = 0;
+        s.thr[j] = zero ? 0.f : (float)lam;
+        const int it = s.iters[j] + 1;
+        const double prev = s.phi[j];
+        s.iters[j] = it;
+        s.phi_prev[j] = prev;
+        s.phi[j] = phi;
+        s.nnz[j] = zero ? 0 : total;
+        if (zero)
+          s.status[j] = SPCA_ZERO;
+        else if (it >= 2 && tol >= 0.0 && phi <= (1.0 + tol) * prev)
+          s.status[j] = SPCA_CONVERGED;
+        else if (it >= maxit)
+          s.status[j] = SPCA_MAXIT;
+      }
+      return;
     }
   }
   // the candidate at sorted position q
